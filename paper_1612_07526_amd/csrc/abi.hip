@@ -1,0 +1,731 @@
+// C-ABI entry points and the host-side planner of libphdc.so.
+//
+// The planner lays out the Cuppen split tree (Eq. (2)) of every matrix: blocks
+// are halved (first half floor(m/2)) until they have at most leaf_size rows.
+// Leaves are solved in one launch; merges are grouped by height (a leaf has
+// height 0, a merge one more than its taller child) and each height is one
+// batched launch per kernel.  A node at depth t writes its eigenvectors to the
+// caller's buffers when t is even and to the workspace twin when t is odd, so
+// a merge always reads its children from the other buffer than it writes.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "phdc_internal.h"
+#include "profile.h"
+#include "hss.h"
+
+namespace phdc {
+
+void launch_canonical_sign(const void* descs, const int32_t* pfx, int nmat, int total, hipStream_t s);
+void launch_clear_status(int32_t* status, hipStream_t s);
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Node {
+  int32_t b;      // matrix
+  int64_t r0;     // first row within the matrix
+  int32_t m, n1;  // size, first half (merges)
+  int32_t depth, height;
+};
+
+struct Tree {
+  std::vector<Node> leaves;
+  std::vector<Node> merges;  // sorted by height, stable
+  std::vector<int32_t> hstart;  // merges of height h: [hstart[h-1], hstart[h]) for h >= 1
+  int32_t root_merge = -1;      // id of matrix 0's root merge (or -1)
+};
+
+int build_node(Tree& T, int32_t b, int64_t r0, int32_t m, int32_t depth, int leaf) {
+  if (m <= leaf) {
+    T.leaves.push_back(Node{b, r0, m, 0, depth, 0});
+    return 0;
+  }
+  const int32_t k = m / 2;
+  const int h1 = build_node(T, b, r0, k, depth + 1, leaf);
+  const int h2 = build_node(T, b, r0 + k, m - k, depth + 1, leaf);
+  const int h = 1 + std::max(h1, h2);
+  T.merges.push_back(Node{b, r0, m, k, depth, h});
+  return h;
+}
+
+Tree build_tree(const std::vector<int64_t>& n, int leaf) {
+  Tree T;
+  for (size_t b = 0; b < n.size(); ++b)
+    if (n[b] > 0) build_node(T, (int32_t)b, 0, (int32_t)n[b], 0, leaf);
+  std::stable_sort(T.merges.begin(), T.merges.end(),
+                   [](const Node& a, const Node& c) { return a.height < c.height; });
+  int H = T.merges.empty() ? 0 : T.merges.back().height;
+  T.hstart.assign(H + 1, 0);
+  for (int h = 1; h <= H; ++h) {
+    T.hstart[h] = T.hstart[h - 1];
+    while (T.hstart[h] < (int)T.merges.size() && T.merges[T.hstart[h]].height == h) ++T.hstart[h];
+  }
+  for (size_t i = 0; i < T.merges.size(); ++i)
+    if (T.merges[i].b == 0 && T.merges[i].depth == 0) T.root_merge = (int32_t)i;
+  return T;
+}
+
+// Sizes that determine the workspace.
+struct Sizes {
+  int64_t n_total = 0;     // rows over all matrices (scratch arrays)
+  int64_t q_total = 0;     // elements of the eigenvector twin buffer
+  int64_t nmerges = 0, nleaves = 0, nmats = 0;
+  int64_t uhat = 0;        // elements of the Uhat arena
+  int64_t map_ints = 0;    // block-map prefix entries
+  int H = 0;
+  size_t hss_arena = 0;    // HSS working storage (largest HSS-eligible merge)
+  size_t hss_desc = 0;     // HSS descriptor staging area
+};
+
+struct Layout {
+  size_t status, hdr, counters, mparam, descs, leaves, canon, canon_pfx, maps, scratch, uhat, qtwin, ltwin, hss,
+      hss_desc, total;
+};
+
+constexpr int kScratchD = 12, kScratchI = 22;
+
+int32_t hss_threshold(const phdc_opts* o) {
+  if (!o || o->gemm_mode != PHDC_GEMM_HSS) return 0;
+  return (int32_t)std::min<int64_t>(std::max<int64_t>(o->hss_min_K, 1), 1 << 30);
+}
+
+int hss_dmax(const phdc_opts* o) {
+  return std::min(512, std::max(16, o->hss_samples) + 2 * std::max(16, o->hss_samples_inc));
+}
+
+Sizes sizes_of(const Tree& T, const std::vector<int64_t>& n, int64_t q_total, const phdc_opts* o) {
+  Sizes z;
+  for (auto x : n) z.n_total += x;
+  z.q_total = q_total;
+  z.nmerges = (int64_t)T.merges.size();
+  z.nleaves = (int64_t)T.leaves.size();
+  z.nmats = (int64_t)n.size();
+  z.H = (int)T.hstart.size() - 1;
+  for (int h = 1; h <= z.H; ++h) {
+    int64_t u = 0;
+    for (int i = T.hstart[h - 1]; i < T.hstart[h]; ++i) u += (int64_t)T.merges[i].m * T.merges[i].m;
+    z.uhat = std::max(z.uhat, u);
+    z.map_ints += (int64_t)MAP_COUNT * (T.hstart[h] - T.hstart[h - 1] + 1);
+  }
+  const int32_t thr = hss_threshold(o);
+  if (thr > 0) {
+    int64_t mh = 0;
+    for (auto& nd : T.merges)
+      if (nd.m >= thr) mh = std::max<int64_t>(mh, nd.m);
+    if (mh > 0) {
+      z.hss_arena = hss_arena_bytes(mh, mh, o->hss_leaf, hss_dmax(o));
+      z.hss_desc = (size_t)16 << 20;
+    }
+  }
+  return z;
+}
+
+Layout layout_of(const Sizes& z) {
+  Layout L;
+  size_t p = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = p;
+    p = align_up(p + std::max<size_t>(bytes, 1));
+    return at;
+  };
+  L.status = take(256);
+  L.hdr = take(256);
+  L.counters = take((size_t)std::max<int64_t>(z.nmerges, 1) * kCounters * 4);
+  L.mparam = take((size_t)std::max<int64_t>(z.nmerges, 1) * 4 * 8);
+  L.descs = take((size_t)z.nmerges * sizeof(MergeDesc));
+  L.leaves = take((size_t)z.nleaves * sizeof(LeafArgs));
+  L.canon = take((size_t)z.nmats * sizeof(CanonDesc));
+  L.canon_pfx = take((size_t)(z.nmats + 1) * 4);
+  L.maps = take((size_t)z.map_ints * 4);
+  L.scratch = take((size_t)z.n_total * (kScratchD * 8 + kScratchI * 4) + kScratchD * kAlign + kScratchI * kAlign);
+  L.uhat = take((size_t)z.uhat * 8);
+  L.qtwin = take((size_t)z.q_total * 8);
+  L.ltwin = take((size_t)z.n_total * 8);
+  L.hss = take(z.hss_arena);
+  L.hss_desc = take(z.hss_desc);
+  L.total = p;
+  return L;
+}
+
+Scratch scratch_of(char* base, const Layout& L, const Sizes& z) {
+  Scratch S;
+  char* p = base + L.scratch;
+  auto dtake = [&]() {
+    double* r = (double*)p;
+    p += align_up((size_t)z.n_total * 8);
+    return r;
+  };
+  auto itake = [&]() {
+    int32_t* r = (int32_t*)p;
+    p += align_up((size_t)z.n_total * 4);
+    return r;
+  };
+  S.dv = dtake(); S.zv = dtake(); S.ds = dtake(); S.zs = dtake(); S.rc = dtake(); S.rs = dtake();
+  S.dfv1 = dtake(); S.dfv2 = dtake(); S.tau = dtake(); S.dorg = dtake(); S.zhat = dtake(); S.cnorm = dtake();
+  S.col = itake(); S.part = itake(); S.flag = itake(); S.surv = itake(); S.grp = itake(); S.coltop = itake();
+  S.colbot = itake(); S.rcolp = itake(); S.rcolj = itake(); S.rpart = itake(); S.chain = itake();
+  S.dfc1 = itake(); S.dfp1 = itake(); S.dfc2 = itake(); S.dfp2 = itake(); S.org = itake(); S.dest = itake();
+  S.destd1 = itake(); S.destd2 = itake(); S.grpsrc = itake(); S.csort = itake(); S.psort = itake();
+  S.mparam = (double*)(base + L.mparam);
+  S.uhat = (double*)(base + L.uhat);
+  S.counters = (int32_t*)(base + L.counters);
+  S.status = (int32_t*)(base + L.status);
+  return S;
+}
+
+// Pinned staging buffer for the plan upload, one per workspace pointer.  The
+// next call on the same workspace waits for the previous upload to finish
+// before reusing the buffer.
+struct Staging {
+  void* host = nullptr;
+  size_t cap = 0;
+  hipEvent_t done = nullptr;
+  bool pending = false;
+};
+std::mutex g_mu;
+std::unordered_map<const void*, Staging> g_staging;
+
+int upload(const void* work, void* dst, const std::vector<char>& bytes, hipStream_t s) {
+  if (bytes.empty()) return 0;
+  std::lock_guard<std::mutex> lk(g_mu);
+  Staging& st = g_staging[work];
+  if (st.pending) {
+    hipEventSynchronize(st.done);
+    st.pending = false;
+  }
+  if (st.cap < bytes.size()) {
+    if (st.host) hipHostFree(st.host);
+    st.host = nullptr;
+    st.cap = 0;
+    if (hipHostMalloc(&st.host, bytes.size(), hipHostMallocDefault) != hipSuccess) return -1;
+    st.cap = bytes.size();
+  }
+  if (!st.done && hipEventCreateWithFlags(&st.done, hipEventDisableTiming) != hipSuccess) return -1;
+  std::memcpy(st.host, bytes.data(), bytes.size());
+  if (hipMemcpyAsync(dst, st.host, bytes.size(), hipMemcpyHostToDevice, s) != hipSuccess) return -1;
+  hipEventRecord(st.done, s);
+  st.pending = true;
+  return 0;
+}
+
+template <class T>
+void put(std::vector<char>& buf, size_t at, const T* src, size_t count) {
+  if (count == 0) return;
+  if (buf.size() < at + count * sizeof(T)) buf.resize(at + count * sizeof(T));
+  std::memcpy(buf.data() + at, src, count * sizeof(T));
+}
+
+bool opts_ok(const phdc_opts* o) {
+  return o->leaf_size >= 2 && o->leaf_size <= kMaxLeaf && o->gemm_mode >= 0 && o->gemm_mode <= 2;
+}
+
+// Everything one solve needs: tree, sizes and layout.
+struct Setup {
+  Tree T;
+  Sizes z;
+  Layout L;
+};
+
+Setup setup_for(const std::vector<int64_t>& n, int64_t q_total, const phdc_opts* o) {
+  Setup S;
+  S.T = build_tree(n, o->leaf_size);
+  S.z = sizes_of(S.T, n, q_total, o);
+  S.L = layout_of(S.z);
+  return S;
+}
+
+struct Buffers {
+  const double* d;
+  const double* e;
+  double* lam[2];
+  double* q[2];
+  std::vector<int64_t> off, eoff, qoff;  // per matrix
+  std::vector<int64_t> ld[2];            // per matrix
+};
+
+// HSS update of the merges of one level that kept K >= hss_min_K poles.  The
+// path was chosen on the device; reading K back is the one host
+// synchronisation of this path (per level that has eligible merges).
+int run_hss_level(const MergeDesc* hdescs, int nm, const Scratch& S, char* arena, size_t arena_bytes, char* descarea,
+                  size_t desc_bytes, const phdc_opts* o, hipStream_t s) {
+  const int32_t thr = hss_threshold(o);
+  if (thr <= 0) return 0;
+  std::vector<int> cand;
+  for (int i = 0; i < nm; ++i)
+    if (hdescs[i].m >= thr) cand.push_back(i);
+  if (cand.empty()) return 0;
+  if (hipStreamSynchronize(s) != hipSuccess) return -110;
+  for (int i : cand) {
+    int32_t c[kCounters];
+    if (hipMemcpy(c, S.counters + (int64_t)hdescs[i].id * kCounters, sizeof(c), hipMemcpyDeviceToHost) != hipSuccess)
+      return -111;
+    if (c[C_PATH] != 2) continue;
+    int rc = run_hss_merge(hdescs[i], c[C_K], S, arena, arena_bytes, descarea, desc_bytes, o,
+                           S.counters + (int64_t)hdescs[i].id * kCounters, s);
+    if (rc != 0) return rc;
+  }
+  return 0;
+}
+
+// Build the device plan (descriptors, leaves, block maps), upload it and
+// launch every kernel of the solve.
+int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n, void* work, const phdc_opts* o,
+              hipStream_t s) {
+  const Tree& T = SU.T;
+  const Sizes& z = SU.z;
+  const Layout& L = SU.L;
+  char* base = (char*)work;
+  Scratch S = scratch_of(base, L, z);
+
+  std::vector<char> plan;
+  const size_t plan0 = L.hdr;  // plan region spans hdr .. maps (contiguous)
+  plan.resize(L.scratch - plan0, 0);
+  put(plan, 0, &T.root_merge, 1);
+  const int32_t nmerges32 = (int32_t)T.merges.size();
+  put(plan, 4, &nmerges32, 1);
+
+  std::vector<MergeDesc> descs(T.merges.size());
+  std::vector<int64_t> uoff(T.merges.size(), 0);
+  for (int h = 1; h <= z.H; ++h) {
+    int64_t u = 0;
+    for (int i = T.hstart[h - 1]; i < T.hstart[h]; ++i) {
+      uoff[i] = u;
+      u += (int64_t)T.merges[i].m * T.merges[i].m;
+    }
+  }
+  for (size_t i = 0; i < T.merges.size(); ++i) {
+    const Node& nd = T.merges[i];
+    const int pout = nd.depth & 1, pin = pout ^ 1;
+    MergeDesc& D = descs[i];
+    std::memset(&D, 0, sizeof(D));
+    const int64_t b = nd.b;
+    D.ldin = BF.ld[pin][b];
+    D.ldout = BF.ld[pout][b];
+    D.qin = BF.q[pin] + BF.qoff[b] + nd.r0 + nd.r0 * D.ldin;
+    D.qout = BF.q[pout] + BF.qoff[b] + nd.r0 + nd.r0 * D.ldout;
+    D.lin = BF.lam[pin] + BF.off[b] + nd.r0;
+    D.lout = BF.lam[pout] + BF.off[b] + nd.r0;
+    D.zgiven = nullptr;
+    D.ecoup = BF.e + BF.eoff[b] + nd.r0 + nd.n1 - 1;
+    D.rho = 0.0;
+    D.zsign = 1.0;
+    D.m = nd.m;
+    D.n1 = nd.n1;
+    D.s_off = BF.off[b] + nd.r0;
+    D.u_off = uoff[i];
+    D.id = (int32_t)i;
+    D.hss_min_k = hss_threshold(o);
+  }
+  put(plan, L.descs - plan0, descs.data(), descs.size());
+
+  std::vector<LeafArgs> leaves(T.leaves.size());
+  for (size_t i = 0; i < T.leaves.size(); ++i) {
+    const Node& nd = T.leaves[i];
+    const int p = nd.depth & 1;
+    const int64_t b = nd.b;
+    LeafArgs& A = leaves[i];
+    std::memset(&A, 0, sizeof(A));
+    A.d = BF.d + BF.off[b] + nd.r0;
+    A.e = BF.e + BF.eoff[b] + nd.r0;
+    A.ldq = BF.ld[p][b];
+    A.q = BF.q[p] + BF.qoff[b] + nd.r0 + nd.r0 * A.ldq;
+    A.lam = BF.lam[p] + BF.off[b] + nd.r0;
+    A.s = nd.m;
+    A.couple = (nd.r0 > 0 ? 1 : 0) | (nd.r0 + nd.m < n[b] ? 2 : 0);
+  }
+  put(plan, L.leaves - plan0, leaves.data(), leaves.size());
+
+  std::vector<CanonDesc> canon(n.size());
+  std::vector<int32_t> cpfx(n.size() + 1, 0);
+  for (size_t b = 0; b < n.size(); ++b) {
+    canon[b] = CanonDesc{BF.q[0] + BF.qoff[b], BF.ld[0][b], (int32_t)n[b], 0};
+    cpfx[b + 1] = cpfx[b] + (int32_t)n[b];
+  }
+  put(plan, L.canon - plan0, canon.data(), canon.size());
+  put(plan, L.canon_pfx - plan0, cpfx.data(), cpfx.size());
+
+  std::vector<int32_t> maps;
+  std::vector<LevelMaps> lm(z.H + 1);
+  for (int h = 1; h <= z.H; ++h) {
+    const int a = T.hstart[h - 1], e = T.hstart[h];
+    for (int k = 0; k < MAP_COUNT; ++k) {
+      const size_t at = maps.size();
+      int32_t acc = 0;
+      maps.push_back(0);
+      for (int i = a; i < e; ++i) {
+        acc += map_blocks(k, T.merges[i].m, T.merges[i].n1);
+        maps.push_back(acc);
+      }
+      lm[h].pfx[k] = (const int32_t*)(base + L.maps) + at;
+      lm[h].total[k] = acc;
+    }
+  }
+  put(plan, L.maps - plan0, maps.data(), maps.size());
+  plan.resize(L.scratch - plan0);
+
+  launch_clear_status(S.status, s);
+  if (upload(work, base + plan0, plan, s) != 0) return -101;
+
+  {
+    ProfScope p(PH_LEAF, s);
+    launch_leaf_ql((const LeafArgs*)(base + L.leaves), (int)T.leaves.size(), S.status, s);
+  }
+  const MergeDesc* dd = (const MergeDesc*)(base + L.descs);
+  for (int h = 1; h <= z.H; ++h) {
+    const int a = T.hstart[h - 1], e = T.hstart[h];
+    launch_merge_level(dd + a, e - a, lm[h], S, o->gemm_mode, s);
+    int rc = run_hss_level(descs.data() + a, e - a, S, base + L.hss, L.hss_desc - L.hss, base + L.hss_desc,
+                           z.hss_desc, o, s);
+    if (rc != 0) return rc;
+  }
+  if (o->canonical_sign && cpfx.back() > 0) {
+    ProfScope p(PH_CANON, s);
+    launch_canonical_sign(base + L.canon, (const int32_t*)(base + L.canon_pfx), (int)n.size(), cpfx.back(), s);
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -103;
+}
+
+}  // namespace
+
+int hss_upload(const void* key, void* dst, const std::vector<char>& bytes, hipStream_t s) {
+  return upload(key, dst, bytes, s);
+}
+
+}  // namespace phdc
+
+using namespace phdc;
+
+extern "C" {
+
+void phdc_opts_default(phdc_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->leaf_size = 32;
+  o->gemm_mode = PHDC_GEMM_FP64;
+  o->hss_min_K = 4096;
+  o->hss_rel_tol = 1e-14;
+  o->hss_leaf = 256;
+  o->hss_samples = 256;
+  o->hss_samples_inc = 128;
+  o->split_slices = 7;
+  o->seed = 0x9e3779b97f4a7c15ULL;
+  o->canonical_sign = 0;
+  o->check_finite = 0;
+}
+
+int phdc_version(void) { return 1; }
+
+int phdc_stedc_workspace(int64_t n, const phdc_opts* o, size_t* bytes) {
+  phdc_opts def;
+  if (!o) { phdc_opts_default(&def); o = &def; }
+  if (n < 0) return -1;
+  if (!opts_ok(o)) return -2;
+  if (!bytes) return -3;
+  Setup SU = setup_for({n}, n * n, o);
+  *bytes = SU.L.total;
+  return 0;
+}
+
+int phdc_stedc(int64_t n, const double* d, const double* e, double* lambda, double* Q, int64_t ldq, void* work,
+               size_t lwork, const phdc_opts* o, void* stream) {
+  phdc_opts def;
+  if (!o) { phdc_opts_default(&def); o = &def; }
+  if (n < 0) return -1;
+  if (n > 0 && !d) return -2;
+  if (n > 1 && !e) return -3;
+  if (n > 0 && !lambda) return -4;
+  if (n > 0 && !Q) return -5;
+  if (ldq < std::max<int64_t>(1, n)) return -6;
+  if (!work) return -7;
+  if (!opts_ok(o)) return -9;
+  if (n > (int64_t)1 << 30) return -1;
+  Setup SU = setup_for({n}, n * n, o);
+  if (lwork < SU.L.total) return -8;
+  if (((uintptr_t)work & (kAlign - 1)) != 0) return -7;
+  if (n == 0) {
+    launch_clear_status((int32_t*)work, (hipStream_t)stream);
+    return 0;
+  }
+  char* base = (char*)work;
+  Buffers BF;
+  BF.d = d;
+  BF.e = e;
+  BF.lam[0] = lambda;
+  BF.lam[1] = (double*)(base + SU.L.ltwin);
+  BF.q[0] = Q;
+  BF.q[1] = (double*)(base + SU.L.qtwin);
+  BF.off = {0};
+  BF.eoff = {0};
+  BF.qoff = {0};
+  BF.ld[0] = {ldq};
+  BF.ld[1] = {n};
+  return run_solve(SU, BF, {n}, work, o, (hipStream_t)stream);
+}
+
+int phdc_stedc_batched_workspace(int64_t B, const int64_t* n_host, const phdc_opts* o, size_t* bytes) {
+  phdc_opts def;
+  if (!o) { phdc_opts_default(&def); o = &def; }
+  if (B < 0) return -1;
+  if (B > 0 && !n_host) return -2;
+  if (!opts_ok(o)) return -3;
+  if (!bytes) return -4;
+  std::vector<int64_t> n(n_host, n_host + B);
+  int64_t q = 0;
+  for (auto x : n) {
+    if (x < 0) return -2;
+    q += x * x;
+  }
+  Setup SU = setup_for(n, q, o);
+  *bytes = SU.L.total;
+  return 0;
+}
+
+int phdc_stedc_batched(int64_t B, const int64_t* n_host, const int64_t* off_host, const int64_t* qoff_host,
+                       const double* d, const double* e, double* lambda, double* Q, void* work, size_t lwork,
+                       const phdc_opts* o, void* stream) {
+  phdc_opts def;
+  if (!o) { phdc_opts_default(&def); o = &def; }
+  if (B < 0) return -1;
+  if (B > 0 && (!n_host)) return -2;
+  if (B > 0 && (!off_host)) return -3;
+  if (B > 0 && (!qoff_host)) return -4;
+  std::vector<int64_t> n(n_host, n_host + B);
+  int64_t acc = 0, qacc = 0;
+  for (int64_t b = 0; b < B; ++b) {
+    if (n[b] < 0 || n[b] > (1 << 30)) return -2;
+    if (off_host[b] != acc) return -3;
+    if (qoff_host[b] != qacc) return -4;
+    acc += n[b];
+    qacc += n[b] * n[b];
+  }
+  if (acc > 0 && !d) return -5;
+  int64_t etot = 0;
+  for (int64_t b = 0; b < B; ++b) etot += std::max<int64_t>(n[b] - 1, 0);
+  if (etot > 0 && !e) return -6;
+  if (acc > 0 && !lambda) return -7;
+  if (acc > 0 && !Q) return -8;
+  if (!work) return -9;
+  if (!opts_ok(o)) return -11;
+  Setup SU = setup_for(n, qacc, o);
+  if (lwork < SU.L.total) return -10;
+  if (((uintptr_t)work & (kAlign - 1)) != 0) return -9;
+  if (acc == 0) {
+    launch_clear_status((int32_t*)work, (hipStream_t)stream);
+    return 0;
+  }
+  char* base = (char*)work;
+  Buffers BF;
+  BF.d = d;
+  BF.e = e;
+  BF.lam[0] = lambda;
+  BF.lam[1] = (double*)(base + SU.L.ltwin);
+  BF.q[0] = Q;
+  BF.q[1] = (double*)(base + SU.L.qtwin);
+  BF.off.assign(off_host, off_host + B);
+  BF.qoff.assign(qoff_host, qoff_host + B);
+  BF.eoff.resize(B);
+  int64_t eacc = 0;
+  for (int64_t b = 0; b < B; ++b) {
+    BF.eoff[b] = eacc;
+    eacc += std::max<int64_t>(n[b] - 1, 0);
+  }
+  BF.ld[0] = n;
+  BF.ld[1] = n;
+  return run_solve(SU, BF, n, work, o, (hipStream_t)stream);
+}
+
+int phdc_merge_workspace(int64_t n1, int64_t n2, const phdc_opts* o, size_t* bytes) {
+  phdc_opts def;
+  if (!o) { phdc_opts_default(&def); o = &def; }
+  if (n1 < 0) return -1;
+  if (n2 < 0) return -2;
+  if (!opts_ok(o)) return -3;
+  if (!bytes) return -4;
+  const int64_t m = n1 + n2;
+  Tree T;
+  if (m > 0) {
+    T.merges.push_back(Node{0, 0, (int32_t)m, (int32_t)n1, 0, 1});
+    T.hstart = {0, 1};
+  } else {
+    T.hstart = {0};
+  }
+  Sizes z = sizes_of(T, {m}, m * m, o);
+  *bytes = layout_of(z).total;
+  return 0;
+}
+
+int phdc_merge(int64_t n1, int64_t n2, const double* D, const double* z, double rho, const double* Q1,
+               int64_t ldq1, const double* Q2, int64_t ldq2, double* lambda, double* Q, int64_t ldq, void* work,
+               size_t lwork, const phdc_opts* o, void* stream) {
+  phdc_opts def;
+  if (!o) { phdc_opts_default(&def); o = &def; }
+  const int64_t m = n1 + n2;
+  if (n1 < 0) return -1;
+  if (n2 < 0) return -2;
+  if (m > 0 && !D) return -3;
+  if (m > 0 && !z) return -4;
+  if (!(rho >= 0.0) || !std::isfinite(rho)) return -5;
+  if (n1 > 0 && !Q1) return -6;
+  if (ldq1 < std::max<int64_t>(1, n1)) return -7;
+  if (n2 > 0 && !Q2) return -8;
+  if (ldq2 < std::max<int64_t>(1, n2)) return -9;
+  if (m > 0 && !lambda) return -10;
+  if (m > 0 && !Q) return -11;
+  if (ldq < std::max<int64_t>(1, m)) return -12;
+  if (!work) return -13;
+  if (!opts_ok(o)) return -15;
+  if (m > (int64_t)1 << 30) return -1;
+  Tree T;
+  if (m > 0) {
+    T.merges.push_back(Node{0, 0, (int32_t)m, (int32_t)n1, 0, 1});
+    T.hstart = {0, 1};
+    T.root_merge = 0;
+  } else {
+    T.hstart = {0};
+  }
+  Sizes zs = sizes_of(T, {m}, m * m, o);
+  Layout L = layout_of(zs);
+  if (lwork < L.total) return -14;
+  if (((uintptr_t)work & (kAlign - 1)) != 0) return -13;
+  hipStream_t s = (hipStream_t)stream;
+  char* base = (char*)work;
+  if (m == 0) {
+    launch_clear_status((int32_t*)(base + L.status), s);
+    return 0;
+  }
+  Scratch S = scratch_of(base, L, zs);
+  double* qin = (double*)(base + L.qtwin);
+  if (n1 > 0 && hipMemcpy2DAsync(qin, m * 8, Q1, ldq1 * 8, n1 * 8, n1, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return -100;
+  if (n2 > 0 && hipMemcpy2DAsync(qin + n1 + n1 * m, m * 8, Q2, ldq2 * 8, n2 * 8, n2, hipMemcpyDeviceToDevice, s) !=
+                    hipSuccess)
+    return -100;
+  MergeDesc Dd;
+  std::memset(&Dd, 0, sizeof(Dd));
+  Dd.qin = qin;
+  Dd.ldin = m;
+  Dd.qout = Q;
+  Dd.ldout = ldq;
+  Dd.lin = D;
+  Dd.lout = lambda;
+  Dd.zgiven = z;
+  Dd.ecoup = nullptr;
+  Dd.rho = rho;
+  Dd.zsign = 1.0;
+  Dd.m = (int32_t)m;
+  Dd.n1 = (int32_t)n1;
+  Dd.s_off = 0;
+  Dd.u_off = 0;
+  Dd.id = 0;
+  Dd.hss_min_k = hss_threshold(o);
+  std::vector<char> plan(L.scratch - L.hdr, 0);
+  const int32_t root_and_count[2] = {0, 1};
+  std::memcpy(plan.data(), root_and_count, 8);
+  std::memcpy(plan.data() + (L.descs - L.hdr), &Dd, sizeof(Dd));
+  CanonDesc c{Q, ldq, (int32_t)m, 0};
+  int32_t pf[2] = {0, (int32_t)m};
+  std::memcpy(plan.data() + (L.canon - L.hdr), &c, sizeof(c));
+  std::memcpy(plan.data() + (L.canon_pfx - L.hdr), pf, sizeof(pf));
+  std::vector<int32_t> maps;
+  LevelMaps lm;
+  for (int k = 0; k < MAP_COUNT; ++k) {
+    lm.pfx[k] = (const int32_t*)(base + L.maps) + maps.size();
+    lm.total[k] = map_blocks(k, (int)m, (int)n1);
+    maps.push_back(0);
+    maps.push_back(lm.total[k]);
+  }
+  std::memcpy(plan.data() + (L.maps - L.hdr), maps.data(), maps.size() * 4);
+  launch_clear_status(S.status, s);
+  if (upload(work, base + L.hdr, plan, s) != 0) return -101;
+  launch_merge_level((const MergeDesc*)(base + L.descs), 1, lm, S, o->gemm_mode, s);
+  {
+    int rc = run_hss_level(&Dd, 1, S, base + L.hss, L.hss_desc - L.hss, base + L.hss_desc, zs.hss_desc, o, s);
+    if (rc != 0) return rc;
+  }
+  if (o->canonical_sign) launch_canonical_sign(base + L.canon, (const int32_t*)(base + L.canon_pfx), 1, (int)m, s);
+  return hipGetLastError() == hipSuccess ? 0 : -103;
+}
+
+int phdc_secular(int64_t K, const double* d, const double* z, double rho, int32_t* org, double* tau, void* work,
+                 size_t lwork, void* stream) {
+  if (K < 0) return -1;
+  if (K > 0 && !d) return -2;
+  if (K > 0 && !z) return -3;
+  if (!(rho > 0.0) || !std::isfinite(rho)) return -4;
+  if (K > 0 && !org) return -5;
+  if (K > 0 && !tau) return -6;
+  if (!work) return -7;
+  if (lwork < 256) return -8;
+  hipStream_t s = (hipStream_t)stream;
+  launch_clear_status((int32_t*)work, s);
+  launch_secular_standalone(K, d, z, rho, org, tau, (int32_t*)work, s);
+  return hipGetLastError() == hipSuccess ? 0 : -103;
+}
+
+int phdc_status(const void* work, void* stream) {
+  if (!work) return -1;
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return -100;
+  int32_t v = 0;
+  if (hipMemcpy(&v, work, 4, hipMemcpyDeviceToHost) != hipSuccess) return -101;
+  return v;
+}
+
+int phdc_merge_stats(const void* work, int32_t* stats_host) {
+  if (!work || !stats_host) return -1;
+  int32_t root = -1;
+  if (hipMemcpy(&root, (const char*)work + 256, 4, hipMemcpyDeviceToHost) != hipSuccess) return -1;
+  if (root < 0) {
+    std::memset(stats_host, 0, 8 * 4);
+    return 0;
+  }
+  int32_t c[kCounters];
+  const char* cnt = (const char*)work + 512;  // counters follow the status and header blocks
+  if (hipMemcpy(c, cnt + (size_t)root * kCounters * 4, sizeof(c), hipMemcpyDeviceToHost) != hipSuccess) return -1;
+  stats_host[0] = c[C_K];
+  stats_host[1] = c[C_K1];
+  stats_host[2] = c[C_K2];
+  stats_host[3] = c[C_K3];
+  stats_host[4] = c[C_NT1];
+  stats_host[5] = c[C_NT2];
+  stats_host[6] = c[C_PATH];
+  stats_host[7] = c[C_HSSRANK];
+  return 0;
+}
+
+int phdc_merge_table(const void* work, int64_t max_rows, int32_t* table_host, int64_t* rows_out) {
+  if (!work || !rows_out) return -1;
+  int32_t hdr[2] = {-1, 0};
+  if (hipMemcpy(hdr, (const char*)work + 256, 8, hipMemcpyDeviceToHost) != hipSuccess) return -1;
+  const int64_t nm = hdr[1];
+  *rows_out = nm;
+  if (!table_host || max_rows <= 0 || nm <= 0) return 0;
+  const int64_t rows = std::min<int64_t>(nm, max_rows);
+  // counters start at 512; the descriptors follow counters and mparam (layout_of order)
+  Sizes z;
+  z.nmerges = nm;
+  const size_t counters = 512;
+  const size_t mparam = align_up(counters + (size_t)std::max<int64_t>(nm, 1) * kCounters * 4);
+  const size_t descs = align_up(mparam + (size_t)std::max<int64_t>(nm, 1) * 4 * 8);
+  std::vector<int32_t> c((size_t)rows * kCounters);
+  std::vector<MergeDesc> d((size_t)rows);
+  if (hipMemcpy(c.data(), (const char*)work + counters, c.size() * 4, hipMemcpyDeviceToHost) != hipSuccess) return -1;
+  if (hipMemcpy(d.data(), (const char*)work + descs, d.size() * sizeof(MergeDesc), hipMemcpyDeviceToHost) !=
+      hipSuccess)
+    return -1;
+  for (int64_t i = 0; i < rows; ++i) {
+    int32_t* r = table_host + i * 10;
+    r[0] = d[i].m;
+    r[1] = d[i].n1;
+    for (int k = 0; k < 8; ++k) r[2 + k] = c[i * kCounters + k];
+  }
+  return 0;
+}
+
+}  // extern "C"

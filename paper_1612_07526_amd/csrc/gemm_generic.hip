@@ -1,0 +1,257 @@
+// General FP64 matrix product on the gfx950 matrix cores, column-major
+// operands with optional transposition, a batch index in blockIdx.y and a
+// fused epilogue.  Same tiling as the merge update: 128x128 output tile per
+// 256-thread block, 4 waves of 4x4 v_mfma_f64_16x16x4 blocks, k-steps of 16
+// through double-buffered LDS.
+#include "gemm_generic.h"
+
+namespace phdc {
+
+typedef double d4g_t __attribute__((ext_vector_type(4)));
+
+constexpr int QT = 128, QK = 16, QLD = QT + 4;
+
+template <bool TA, bool TB, class Epi>
+__global__ void __launch_bounds__(256) k_gemm_f64(GemmArgs g, Epi epi) {
+  __shared__ double As[2][QK][QLD];
+  __shared__ double Bs[2][QK][QLD];
+  const int bz = blockIdx.y;
+  const double* A = g.A + (int64_t)bz * g.strideA;
+  const double* B = g.B + (int64_t)bz * g.strideB;
+  const int tmn = (g.m + QT - 1) / QT;
+  const int mt = blockIdx.x % tmn, nt = blockIdx.x / tmn;
+  const int i0 = mt * QT, j0 = nt * QT;
+  const int t = threadIdx.x;
+  double ra[8], rb[8];
+
+  auto gload = [&](int kt) {
+    const int kb = kt * QK;
+    if (!TA) {  // A(i,k) = A[i + k lda]: thread stages k = t/16, rows i0 + 8*(t%16) ..
+      const int k = kb + (t >> 4), i = i0 + (t & 15) * 8;
+      const double* src = A + (int64_t)k * g.lda + i;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) ra[e] = (k < g.k && i + e < g.m) ? src[e] : 0.0;
+    } else {    // op(A)(i,k) = A[k + i lda]: thread stages row i = t/2, k = kb + 8*(t%2) ..
+      const int i = i0 + (t >> 1), k = kb + (t & 1) * 8;
+      const double* src = A + (int64_t)i * g.lda + k;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) ra[e] = (i < g.m && k + e < g.k) ? src[e] : 0.0;
+    }
+    if (!TB) {  // B(k,j) = B[k + j ldb]: thread stages column j = t/2, k = kb + 8*(t%2) ..
+      const int j = j0 + (t >> 1), k = kb + (t & 1) * 8;
+      const double* src = B + (int64_t)j * g.ldb + k;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) rb[e] = (j < g.n && k + e < g.k) ? src[e] : 0.0;
+    } else {    // op(B)(k,j) = B[j + k ldb]
+      const int k = kb + (t >> 4), j = j0 + (t & 15) * 8;
+      const double* src = B + (int64_t)k * g.ldb + j;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) rb[e] = (k < g.k && j + e < g.n) ? src[e] : 0.0;
+    }
+  };
+  auto lstore = [&](int buf) {
+    if (!TA) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) As[buf][t >> 4][(t & 15) * 8 + e] = ra[e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) As[buf][(t & 1) * 8 + e][t >> 1] = ra[e];
+    }
+    if (!TB) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) Bs[buf][(t & 1) * 8 + e][t >> 1] = rb[e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) Bs[buf][t >> 4][(t & 15) * 8 + e] = rb[e];
+    }
+  };
+
+  const int w = t >> 6, lane = t & 63;
+  const int wm = (w & 1) * 64, wn = (w >> 1) * 64;
+  const int li = lane & 15, lk = lane >> 4;
+  d4g_t acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = d4g_t{0.0, 0.0, 0.0, 0.0};
+
+  const int nkt = (g.k + QK - 1) / QK;
+  if (nkt > 0) {
+    gload(0);
+    lstore(0);
+  }
+  __syncthreads();
+  for (int kt = 0; kt < nkt; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nkt) gload(kt + 1);
+#pragma unroll
+    for (int ks = 0; ks < QK / 4; ++ks) {
+      const int kr = ks * 4 + lk;
+      double av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = As[buf][kr][wm + i * 16 + li];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = Bs[buf][kr][wn + j * 16 + li];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    if (kt + 1 < nkt) lstore(buf ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int cj = j0 + wn + j * 16 + li;
+    if (cj >= g.n) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ri = i0 + wm + i * 16 + lk + 4 * r;  // element r of a lane sits at row lk + 4 r
+        if (ri < g.m) epi(bz, ri, cj, acc[i][j][r]);
+      }
+  }
+}
+
+template <bool TA, bool TB, class Epi>
+void launch_gemm(const GemmArgs& g, int batch, const Epi& epi, hipStream_t s) {
+  if (g.m <= 0 || g.n <= 0 || batch <= 0) return;
+  dim3 grid(((g.m + QT - 1) / QT) * ((g.n + QT - 1) / QT), batch);
+  hipLaunchKernelGGL((k_gemm_f64<TA, TB, Epi>), grid, dim3(256), 0, s, g, epi);
+}
+
+// C = op(A) op(B), plain store.
+void gemm_f64(bool ta, bool tb, const GemmArgs& g, int batch, double* C, int64_t ldc, int64_t strideC,
+              hipStream_t s) {
+  EpiStore e{C, ldc, strideC};
+  if (!ta && !tb) launch_gemm<false, false>(g, batch, e, s);
+  else if (ta && !tb) launch_gemm<true, false>(g, batch, e, s);
+  else if (!ta && tb) launch_gemm<false, true>(g, batch, e, s);
+  else launch_gemm<true, true>(g, batch, e, s);
+}
+
+// M' = diag(lbar) + F o (Q^T Qbar), F_ij = 1/(lambda_j - lambda_i) off the diagonal.
+void gemm_f64_adjoint_f(const GemmArgs& g, int batch, double* C, int64_t ldc, int64_t strideC, const double* lam,
+                        const double* lbar, int64_t strideL, hipStream_t s) {
+  EpiAdjointF e{C, ldc, strideC, lam, lbar, strideL};
+  launch_gemm<true, false>(g, batch, e, s);
+}
+
+}  // namespace phdc
+
+namespace phdc {
+
+int vgemm_tiles(int m, int n) {
+  if (m <= 0 || n <= 0) return 0;
+  return ((m + QT - 1) / QT) * ((n + QT - 1) / QT);
+}
+
+// Variable-size batch: every block finds its product by binary search in the
+// tile prefix and computes one 128 x 128 tile of it.
+__global__ void __launch_bounds__(256) k_vgemm(const VGemm* __restrict__ descs, const int32_t* __restrict__ pfx,
+                                               int nd) {
+  __shared__ double As[2][QK][QLD];
+  __shared__ double Bs[2][QK][QLD];
+  const int bid = blockIdx.x;
+  int lo = 0, hi = nd - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (pfx[mid] <= bid) lo = mid; else hi = mid - 1;
+  }
+  const VGemm g = descs[lo];
+  const int tile = bid - pfx[lo];
+  const int tmn = (g.m + QT - 1) / QT;
+  const int i0 = (tile % tmn) * QT, j0 = (tile / tmn) * QT;
+  const int t = threadIdx.x;
+  double ra[8], rb[8];
+  auto gload = [&](int kt) {
+    const int kb = kt * QK;
+    if (!g.ta) {
+      const int k = kb + (t >> 4), i = i0 + (t & 15) * 8;
+      const double* src = g.A + (int64_t)k * g.lda + i;
+      for (int e = 0; e < 8; ++e) ra[e] = (k < g.k && i + e < g.m) ? src[e] : 0.0;
+    } else {
+      const int i = i0 + (t >> 1), k = kb + (t & 1) * 8;
+      const double* src = g.A + (int64_t)i * g.lda + k;
+      for (int e = 0; e < 8; ++e) ra[e] = (i < g.m && k + e < g.k) ? src[e] : 0.0;
+    }
+    if (!g.tb) {
+      const int j = j0 + (t >> 1), k = kb + (t & 1) * 8;
+      const double* src = g.B + (int64_t)j * g.ldb + k;
+      for (int e = 0; e < 8; ++e) rb[e] = (j < g.n && k + e < g.k) ? src[e] : 0.0;
+    } else {
+      const int k = kb + (t >> 4), j = j0 + (t & 15) * 8;
+      const double* src = g.B + (int64_t)k * g.ldb + j;
+      for (int e = 0; e < 8; ++e) rb[e] = (k < g.k && j + e < g.n) ? src[e] : 0.0;
+    }
+  };
+  auto lstore = [&](int buf) {
+    if (!g.ta) {
+      for (int e = 0; e < 8; ++e) As[buf][t >> 4][(t & 15) * 8 + e] = ra[e];
+    } else {
+      for (int e = 0; e < 8; ++e) As[buf][(t & 1) * 8 + e][t >> 1] = ra[e];
+    }
+    if (!g.tb) {
+      for (int e = 0; e < 8; ++e) Bs[buf][(t & 1) * 8 + e][t >> 1] = rb[e];
+    } else {
+      for (int e = 0; e < 8; ++e) Bs[buf][t >> 4][(t & 15) * 8 + e] = rb[e];
+    }
+  };
+  const int w = t >> 6, lane = t & 63;
+  const int wm = (w & 1) * 64, wn = (w >> 1) * 64;
+  const int li = lane & 15, lk = lane >> 4;
+  d4g_t acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = d4g_t{0.0, 0.0, 0.0, 0.0};
+  const int nkt = (g.k + QK - 1) / QK;
+  if (nkt > 0) {
+    gload(0);
+    lstore(0);
+  }
+  __syncthreads();
+  for (int kt = 0; kt < nkt; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nkt) gload(kt + 1);
+#pragma unroll
+    for (int ks = 0; ks < QK / 4; ++ks) {
+      const int kr = ks * 4 + lk;
+      double av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = As[buf][kr][wm + i * 16 + li];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = Bs[buf][kr][wn + j * 16 + li];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    if (kt + 1 < nkt) lstore(buf ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int cj = j0 + wn + j * 16 + li;
+    if (cj >= g.n) continue;
+    double* col = g.C + (int64_t)(g.cmap ? g.cmap[cj] : cj) * g.ldc;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ri = i0 + wm + i * 16 + lk + 4 * r;
+        if (ri < g.m) {
+          const double v = g.alpha * acc[i][j][r];
+          col[ri] = (g.beta == 0.0) ? v : v + g.beta * col[ri];
+        }
+      }
+  }
+}
+
+void vgemm_launch(const VGemm* descs, const int32_t* pfx, int nd, int total, hipStream_t s) {
+  if (nd <= 0 || total <= 0) return;
+  hipLaunchKernelGGL(k_vgemm, dim3(total), dim3(256), 0, s, descs, pfx, nd);
+}
+
+}  // namespace phdc

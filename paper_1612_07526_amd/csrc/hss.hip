@@ -1,0 +1,655 @@
+// HSS path of the merge update (Sec. 2.2): when a merge keeps K >= hss_min_K
+// poles, the Cauchy-like eigenvector matrix Uhat (K x K) is compressed into
+// hierarchically semiseparable form by randomized sampling (Algorithm 1) and
+// the update U = X Uhat (Eq. (6), X = the merge's rotated input columns in
+// pole order, no Gu grouping) is applied in that form.
+//
+// HSS form (Eq. (7)): on a binary tree over the pole order with leaves of at
+// most hss_leaf poles, each leaf i has D_i = Uhat(t_i, t_i) and row / column
+// interpolation bases U_i, V_i; each parent has transfer matrices U_p, V_p
+// acting on its children's skeletons, and each sibling pair (c1, c2) has the
+// couplings B_c1 = Uhat(I_c1, J_c2), B_c2 = Uhat(I_c2, J_c1) where I, J are
+// skeleton row / column indices chosen by interpolative decompositions (IDs).
+//
+// Construction (Algorithm 1): Y = Uhat Omega1, Z = Uhat^T Omega2 with Gaussian
+// Omega (K x d); bottom-up, Phi_i = Y_i - D_i Omega1_i (leaf) or the stacked
+// child skeleton rows minus their couplings' contribution (parent), a row ID
+// Phi_i ~ U_i Phi_i(I_i, :) and likewise Theta_i ~ V_i Theta_i(J_i, :) for Z,
+// then Yhat_i = V_i^T Omega1_i (nested), Zhat_i = U_i^T Omega2_i (nested).
+//
+// Application of U = X Uhat (the transposed HSS product, all operands m rows):
+//   leaves   Xh_i = X(:, t_i) U_i,       U(:, t_i) = X(:, t_i) D_i
+//   up       Xh_p = [Xh_c1 Xh_c2] U_p
+//   couple   Yh_c2 = Xh_c1 B_c1,         Yh_c1 = Xh_c2 B_c2
+//   down     [Yh_c1 Yh_c2] += Yh_p V_p^T
+//   leaves   U(:, t_i) += Yh_i V_i^T
+// The IDs use column-pivoted Householder QR of Phi^T with the relative
+// truncation tolerance hss_rel_tol (|R_kk| <= tol |R_00| ends the rank).
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "gemm_generic.h"
+#include "hss.h"
+#include "profile.h"
+
+namespace phdc {
+
+// ------------------------------------------------------------ random samples
+// Counter-based Gaussian numbers: SplitMix64 (Steele, Lea, Flood 2014) on the
+// counter, then the Box-Muller transform.
+__device__ inline uint64_t splitmix64(uint64_t x) {
+  x += 0x9e3779b97f4a7c15ULL;
+  x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ULL;
+  x = (x ^ (x >> 27)) * 0x94d049bb133111ebULL;
+  return x ^ (x >> 31);
+}
+
+__global__ void __launch_bounds__(256) k_gauss(int64_t count, uint64_t seed, double* out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= count) return;
+  const uint64_t a = splitmix64(seed + 2 * (uint64_t)i), b = splitmix64(seed + 2 * (uint64_t)i + 1);
+  const double u1 = ((double)(a >> 11) + 0.5) * 1.1102230246251565e-16;  // (0, 1)
+  const double u2 = (double)(b >> 11) * 1.1102230246251565e-16;          // [0, 1)
+  out[i] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+}
+
+// ------------------------------------------------------------ gathers
+// X(:, k) = input column of survivor k (pole order), structurally zero half as 0.
+__global__ void __launch_bounds__(256) k_gather_x(const double* __restrict__ qin, int64_t ldin, int m, int n1, int K,
+                                                  const int32_t* __restrict__ csort,
+                                                  const int32_t* __restrict__ psort, double* X) {
+  const int k = blockIdx.y;
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (k >= K || r >= m) return;
+  const int p = psort[k];
+  const bool top = r < n1;
+  const bool valid = p == 2 || (top ? p == 1 : p == 3);
+  X[r + (int64_t)k * m] = valid ? qin[r + (int64_t)csort[k] * ldin] : 0.0;
+}
+
+// Entries of Uhat evaluated from the secular solution with the same arithmetic
+// as the dense writer: zhat_i / ((d_i - dorg_j) - tau_j) * cnorm_j.
+__global__ void __launch_bounds__(256) k_ugather(const UGather* __restrict__ g, const double* __restrict__ ds,
+                                                 const double* __restrict__ zh, const double* __restrict__ dorg,
+                                                 const double* __restrict__ tau, const double* __restrict__ cn) {
+  const UGather G = g[blockIdx.x];
+  for (int e = threadIdx.x; e < G.nr * G.nc; e += 256) {
+    const int a = e % G.nr, b = e / G.nr;
+    const int i = G.ri ? G.ri[a] : G.r0 + a;
+    const int j = G.cj ? G.cj[b] : G.c0 + b;
+    G.out[a + (int64_t)b * G.ld] = zh[i] / ((ds[i] - dorg[j]) - tau[j]) * cn[j];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_rows(const RowCopy* __restrict__ rc) {
+  const RowCopy R = rc[blockIdx.x];
+  for (int e = threadIdx.x; e < R.nr * R.ncol; e += 256) {
+    const int a = e % R.nr, b = e / R.nr;
+    const int src = R.idx ? R.idx[a] : a;
+    R.dst[R.dst_row0 + a + (int64_t)b * R.ldd] = R.src[src + (int64_t)b * R.lds];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_ints(const IntCopy* __restrict__ ic) {
+  const IntCopy C = ic[blockIdx.x];
+  for (int a = threadIdx.x; a < C.n; a += 256) C.dst[C.dst0 + a] = C.src[a];
+}
+
+__global__ void __launch_bounds__(256) k_skel(const SkelDesc* __restrict__ sd) {
+  const SkelDesc S = sd[blockIdx.x];
+  for (int a = threadIdx.x; a < S.rank; a += 256) {
+    const int p = S.perm[a];
+    S.out[a] = S.base ? S.base[p] : S.lo + p;
+  }
+}
+
+// ------------------------------------------------------------ interpolative decomposition
+// Row ID of Phi (p x d): Phi ~ U Phi(I, :), U (p x r) holding the identity on
+// the skeleton rows I = perm[0:r].  Computed as the column-pivoted Householder
+// QR of Phi^T, whose columns are Phi's rows: Phi^T P = Q [R11 R12]; the rank r
+// is the number of pivots with |R_kk| > tol |R_00|; T = R11^{-1} R12 and
+// U(perm[r + c], :) = T(:, c)^T.  One block per decomposition; the work copy
+// keeps Phi's layout, so row c of Phi (a column of Phi^T) is W(c, :).
+constexpr int kIdMax = 1024;
+
+__global__ void __launch_bounds__(256) k_row_id(const IdDesc* __restrict__ ids, double tol) {
+  __shared__ double cn[kIdMax], cn0[kIdMax], v[kIdMax];
+  __shared__ int pv[kIdMax];
+  __shared__ double redv[4];
+  __shared__ int redi[4];
+  __shared__ double sh_norm, sh_r00;
+  __shared__ int sh_piv, sh_stop;
+  const IdDesc D = ids[blockIdx.x];
+  const int p = D.p, d = D.d;
+  double* W = D.work;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  for (int e = t; e < p * d; e += 256) {
+    const int c = e % p, k = e / p;
+    W[c + (int64_t)k * p] = D.phi[c + (int64_t)k * D.ldphi];
+  }
+  __syncthreads();
+  for (int c = t; c < p; c += 256) {
+    double s = 0.0;
+    for (int k = 0; k < d; ++k) {
+      const double x = W[c + (int64_t)k * p];
+      s += x * x;
+    }
+    cn[c] = s;
+    cn0[c] = s;
+    pv[c] = c;
+  }
+  if (t == 0) {
+    sh_r00 = 0.0;
+    sh_stop = 0;
+  }
+  __syncthreads();
+  const int kmax = min(p, d);
+  int r = 0;
+  for (int j = 0; j < kmax; ++j) {
+    double bv = -1.0;
+    int bi = 0x7fffffff;
+    for (int c = j + t; c < p; c += 256)
+      if (cn[c] > bv) {
+        bv = cn[c];
+        bi = c;
+      }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ob = __shfl_xor(bv, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (ob > bv || (ob == bv && oi < bi)) {
+        bv = ob;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      redv[w] = bv;
+      redi[w] = bi;
+    }
+    __syncthreads();
+    if (t == 0) {
+      double b0 = redv[0];
+      int i0 = redi[0];
+      for (int q = 1; q < 4; ++q)
+        if (redv[q] > b0 || (redv[q] == b0 && redi[q] < i0)) {
+          b0 = redv[q];
+          i0 = redi[q];
+        }
+      sh_piv = i0;
+      const double nrm = sqrt(fmax(b0, 0.0));
+      if (j == 0) sh_r00 = nrm;
+      sh_stop = (i0 >= p || sh_r00 == 0.0 || nrm <= tol * sh_r00) ? 1 : 0;
+    }
+    __syncthreads();
+    if (sh_stop) break;
+    const int piv = sh_piv;
+    if (piv != j) {
+      for (int k = t; k < d; k += 256) {
+        const double a = W[j + (int64_t)k * p];
+        W[j + (int64_t)k * p] = W[piv + (int64_t)k * p];
+        W[piv + (int64_t)k * p] = a;
+      }
+      if (t == 0) {
+        double a = cn[j];
+        cn[j] = cn[piv];
+        cn[piv] = a;
+        a = cn0[j];
+        cn0[j] = cn0[piv];
+        cn0[piv] = a;
+        const int q = pv[j];
+        pv[j] = pv[piv];
+        pv[piv] = q;
+      }
+      __syncthreads();
+    }
+    // Householder reflector of x = W(j, j:d): v = x - alpha e_j, alpha = -sign(x_j) |x|
+    double s = 0.0;
+    for (int k = j + t; k < d; k += 256) {
+      const double x = W[j + (int64_t)k * p];
+      v[k] = x;
+      s += x * x;
+    }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) redv[w] = s;
+    __syncthreads();
+    if (t == 0) sh_norm = sqrt(redv[0] + redv[1] + redv[2] + redv[3]);
+    __syncthreads();
+    const double xn = sh_norm;
+    const double x0 = W[j + (int64_t)j * p];
+    const double alpha = (x0 >= 0.0) ? -xn : xn;
+    const double vtv = 2.0 * xn * (xn + fabs(x0));  // |x - alpha e_j|^2
+    __syncthreads();
+    if (t == 0) v[j] = x0 - alpha;
+    __syncthreads();
+    if (vtv > 0.0) {
+      for (int c = j + 1 + t; c < p; c += 256) {
+        double dot = 0.0;
+        for (int k = j; k < d; ++k) dot += v[k] * W[c + (int64_t)k * p];
+        const double f = 2.0 * dot / vtv;
+        for (int k = j; k < d; ++k) W[c + (int64_t)k * p] -= f * v[k];
+        const double rjc = W[c + (int64_t)j * p];
+        double nc = cn[c] - rjc * rjc;
+        if (nc <= 1e-2 * cn0[c]) {  // cancellation: recompute the remaining norm
+          nc = 0.0;
+          for (int k = j + 1; k < d; ++k) {
+            const double x = W[c + (int64_t)k * p];
+            nc += x * x;
+          }
+          cn0[c] = nc;
+        }
+        cn[c] = nc;
+      }
+    }
+    __syncthreads();
+    if (t == 0) W[j + (int64_t)j * p] = alpha;  // R_jj; R_{j c} sits at W(c, j)
+    __syncthreads();
+    r = j + 1;
+  }
+  double* U = D.U;
+  for (int e = t; e < p * r; e += 256) U[e % p + (int64_t)(e / p) * p] = 0.0;
+  __syncthreads();
+  for (int a = t; a < r; a += 256) U[pv[a] + (int64_t)a * p] = 1.0;
+  for (int c = r + t; c < p; c += 256) {
+    const int row = pv[c];
+    for (int a = r - 1; a >= 0; --a) {  // back substitution with R_ab = W(b, a)
+      double s = W[c + (int64_t)a * p];
+      for (int b = a + 1; b < r; ++b) s -= W[b + (int64_t)a * p] * U[row + (int64_t)b * p];
+      U[row + (int64_t)a * p] = s / W[a + (int64_t)a * p];
+    }
+  }
+  for (int c = t; c < p; c += 256) D.perm[c] = pv[c];
+  if (t == 0) *D.rank = r;
+}
+
+// ------------------------------------------------------------ host orchestration
+
+namespace {
+
+struct HNode {
+  int lo, hi, c1, c2, level;
+  bool leaf;
+};
+
+int build_hss_tree(std::vector<HNode>& T, int lo, int hi, int leaf, int level) {
+  const int id = (int)T.size();
+  T.push_back(HNode{lo, hi, -1, -1, level, hi - lo <= leaf});
+  if (hi - lo > leaf) {
+    const int mid = lo + (hi - lo) / 2;
+    const int a = build_hss_tree(T, lo, mid, leaf, level + 1);
+    const int b = build_hss_tree(T, mid, hi, leaf, level + 1);
+    T[id].c1 = a;
+    T[id].c2 = b;
+  }
+  return id;
+}
+
+// Descriptors of one stage, staged into the device descriptor area and
+// uploaded once (kernels of the stage are launched after the upload).
+struct Stage {
+  char* dev;
+  size_t cap;
+  std::vector<char> host;
+  template <class T>
+  const T* push(const std::vector<T>& v) {
+    if (v.empty()) return nullptr;
+    const size_t at = (host.size() + 255) / 256 * 256;
+    host.resize(at + v.size() * sizeof(T));
+    std::memcpy(host.data() + at, v.data(), v.size() * sizeof(T));
+    return (const T*)(dev + at);
+  }
+  int flush(const void* key, hipStream_t s) {
+    if (host.empty()) return 0;
+    if (host.size() > cap) return -1;
+    int rc = hss_upload(key, dev, host, s);
+    host.clear();
+    return rc;
+  }
+};
+
+struct VBatch {
+  std::vector<VGemm> g;
+  std::vector<int32_t> pf{0};
+  void add(const VGemm& x) {
+    if (x.m <= 0 || x.n <= 0) return;
+    g.push_back(x);
+    pf.push_back(pf.back() + vgemm_tiles(x.m, x.n));
+  }
+};
+
+VGemm mk(const double* A, int64_t lda, int ta, const double* B, int64_t ldb, int tb, double* C, int64_t ldc, int m,
+         int n, int k, double alpha, double beta, const int32_t* cmap = nullptr) {
+  VGemm g;
+  std::memset(&g, 0, sizeof(g));
+  g.A = A; g.B = B; g.C = C; g.cmap = cmap;
+  g.lda = lda; g.ldb = ldb; g.ldc = ldc;
+  g.alpha = alpha; g.beta = beta;
+  g.m = m; g.n = n; g.k = k; g.ta = ta; g.tb = tb;
+  return g;
+}
+
+}  // namespace
+
+size_t hss_arena_bytes(int64_t m, int64_t K, int leaf, int dmax) {
+  if (K <= 0 || m <= 0) return 0;
+  std::vector<HNode> T;
+  build_hss_tree(T, 0, (int)K, std::max(8, leaf), 0);
+  const int64_t pmax = std::max<int64_t>(std::max(8, leaf), 2 * (int64_t)dmax);
+  size_t b = 0;
+  auto take = [&](int64_t bytes) { b += ((size_t)bytes + 255) / 256 * 256; };
+  take(m * K * 8);
+  for (int q = 0; q < 4; ++q) take(K * dmax * 8);
+  take((int64_t)(2 * T.size() + 2) * 4);
+  for (auto& h : T) {
+    const int64_t p = h.leaf ? h.hi - h.lo : pmax;
+    if (h.leaf) take(p * p * 8);
+    for (int q = 0; q < 6; ++q) take(p * dmax * 8);
+    for (int q = 0; q < 4; ++q) take((int64_t)dmax * dmax * 8);
+    if (!h.leaf) { take((int64_t)dmax * dmax * 8); take((int64_t)dmax * dmax * 8); }
+    take(m * dmax * 8);
+    take(m * dmax * 8);
+    take(p * 4); take(p * 4); take(dmax * 4); take(dmax * 4); take(2 * dmax * 4); take(2 * dmax * 4);
+  }
+  return b + 4096;
+}
+
+// One HSS merge; called with K known on the host.  Returns 0 or a negative code.
+int run_hss_merge(const MergeDesc& M, int K, const Scratch& S, char* arena, size_t arena_bytes, char* descarea,
+                  size_t desc_bytes, const phdc_opts* o, int32_t* counters_dev, hipStream_t s) {
+  const int m = M.m;
+  const int leaf = std::max(8, o->hss_leaf);
+  const int dmax = std::min(512, std::max(16, o->hss_samples) + 2 * std::max(16, o->hss_samples_inc));
+  int d = std::min(std::max(16, o->hss_samples), 512);
+  const int64_t so = M.s_off;
+  const double* ds = S.ds + so;
+  const double* zh = S.zhat + so;
+  const double* dorg = S.dorg + so;
+  const double* tau = S.tau + so;
+  const double* cn = S.cnorm + so;
+  const double* Shat = S.uhat + M.u_off;  // row-major K x K: Uhat(i, j) at i K + j
+  std::vector<HNode> T;
+  build_hss_tree(T, 0, K, leaf, 0);
+  const int nn = (int)T.size();
+  int maxlevel = 0;
+  for (auto& h : T) maxlevel = std::max(maxlevel, h.level);
+  const void* key = arena;
+
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    const int pmax = std::max(leaf, 2 * dmax);
+    size_t off = 0;
+    auto dtake = [&](int64_t count) {
+      double* p = (double*)(arena + off);
+      off += ((size_t)count * 8 + 255) / 256 * 256;
+      return p;
+    };
+    auto itake = [&](int64_t count) {
+      int32_t* p = (int32_t*)(arena + off);
+      off += ((size_t)count * 4 + 255) / 256 * 256;
+      return p;
+    };
+    double* X = dtake((int64_t)m * K);
+    double* Om1 = dtake((int64_t)K * dmax);
+    double* Om2 = dtake((int64_t)K * dmax);
+    double* Y = dtake((int64_t)K * dmax);
+    double* Z = dtake((int64_t)K * dmax);
+    int32_t* ranks = itake(2 * nn + 2);  // [2 i] row-ID rank, [2 i + 1] column-ID rank
+    std::vector<double*> Dl(nn, nullptr), Phi(nn), Theta(nn), Wk(nn), Wk2(nn), Ub(nn), Vb(nn), Phisk(nn), Thsk(nn),
+        Yhat(nn), Zhat(nn), B1(nn, nullptr), B2(nn, nullptr), Xh(nn), Yh(nn);
+    std::vector<int32_t*> permU(nn), permV(nn), skI(nn), skJ(nn), stI(nn), stJ(nn);
+    for (int i = 0; i < nn; ++i) {
+      const int p = T[i].leaf ? T[i].hi - T[i].lo : pmax;
+      if (T[i].leaf) Dl[i] = dtake((int64_t)p * p);
+      Phi[i] = dtake((int64_t)p * dmax);
+      Theta[i] = dtake((int64_t)p * dmax);
+      Wk[i] = dtake((int64_t)p * dmax);
+      Wk2[i] = dtake((int64_t)p * dmax);
+      Ub[i] = dtake((int64_t)p * dmax);
+      Vb[i] = dtake((int64_t)p * dmax);
+      Phisk[i] = dtake((int64_t)dmax * dmax);
+      Thsk[i] = dtake((int64_t)dmax * dmax);
+      Yhat[i] = dtake((int64_t)dmax * dmax);
+      Zhat[i] = dtake((int64_t)dmax * dmax);
+      if (!T[i].leaf) {
+        B1[i] = dtake((int64_t)dmax * dmax);
+        B2[i] = dtake((int64_t)dmax * dmax);
+      }
+      Xh[i] = dtake((int64_t)m * dmax);
+      Yh[i] = dtake((int64_t)m * dmax);
+      permU[i] = itake(p);
+      permV[i] = itake(p);
+      skI[i] = itake(dmax);
+      skJ[i] = itake(dmax);
+      stI[i] = itake(2 * dmax);
+      stJ[i] = itake(2 * dmax);
+    }
+    if (off > arena_bytes) return -200;
+    Stage st{descarea, desc_bytes, {}};
+
+    {
+      ProfScope ps(PH_HSS_SAMPLE, s);
+      hipLaunchKernelGGL(k_gather_x, dim3((m + 255) / 256, K), dim3(256), 0, s, M.qin, M.ldin, m, M.n1, K,
+                         S.csort + so, S.psort + so, X);
+      const int64_t cnt = (int64_t)K * d;
+      const uint64_t sd = o->seed + 0x9e3779b97f4a7c15ULL * (uint64_t)(attempt + 1);
+      hipLaunchKernelGGL(k_gauss, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, cnt, sd, Om1);
+      hipLaunchKernelGGL(k_gauss, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, cnt, sd ^ 0x5bd1e9955bd1e995ULL,
+                         Om2);
+      // Shat read column-major (ld K) is Uhat^T: Y = Uhat Omega1, Z = Uhat^T Omega2
+      GemmArgs gy{Shat, Om1, K, K, 0, 0, K, d, K, 0};
+      gemm_f64(true, false, gy, 1, Y, K, 0, s);
+      GemmArgs gz{Shat, Om2, K, K, 0, 0, K, d, K, 0};
+      gemm_f64(false, false, gz, 1, Z, K, 0, s);
+    }
+
+    std::vector<int32_t> hr(2 * nn + 2, 0), hp(2 * nn + 2, 0);
+    int maxrank = 0;
+    bool too_large = false;
+    {
+      ProfScope pc(PH_HSS_COMPRESS, s);
+      for (int lev = maxlevel; lev >= 0 && !too_large; --lev) {
+        std::vector<int> nodes;
+        for (int i = 0; i < nn; ++i)
+          if (T[i].level == lev) nodes.push_back(i);
+        std::vector<UGather> ug;
+        std::vector<RowCopy> rc;
+        VBatch g1;
+        std::vector<IdDesc> idd;
+        const bool root_only = (lev == 0 && !T[0].leaf);
+        for (int i : nodes) {
+          const HNode& h = T[i];
+          if (h.leaf) {
+            const int p = h.hi - h.lo;
+            hp[2 * i] = hp[2 * i + 1] = p;
+            ug.push_back(UGather{nullptr, nullptr, Dl[i], p, h.lo, h.lo, p, p});
+            rc.push_back(RowCopy{Y + h.lo, nullptr, Phi[i], K, p, p, d, 0, 0});
+            rc.push_back(RowCopy{Z + h.lo, nullptr, Theta[i], K, p, p, d, 0, 0});
+            g1.add(mk(Dl[i], p, 0, Om1 + h.lo, K, 0, Phi[i], p, p, d, p, -1.0, 1.0));
+            g1.add(mk(Dl[i], p, 1, Om2 + h.lo, K, 0, Theta[i], p, p, d, p, -1.0, 1.0));
+          } else {
+            const int a = h.c1, b = h.c2;
+            const int ra = hr[2 * a], rb = hr[2 * b], ca = hr[2 * a + 1], cb = hr[2 * b + 1];
+            const int p = ra + rb, q = ca + cb;
+            hp[2 * i] = p;
+            hp[2 * i + 1] = q;
+            // couplings of the children: B1 = Uhat(I_a, J_b), B2 = Uhat(I_b, J_a)
+            ug.push_back(UGather{skI[a], skJ[b], B1[i], dmax, 0, 0, ra, cb});
+            ug.push_back(UGather{skI[b], skJ[a], B2[i], dmax, 0, 0, rb, ca});
+            if (root_only) continue;
+            rc.push_back(RowCopy{Phisk[a], nullptr, Phi[i], dmax, p, ra, d, 0, 0});
+            rc.push_back(RowCopy{Phisk[b], nullptr, Phi[i], dmax, p, rb, d, ra, 0});
+            rc.push_back(RowCopy{Thsk[a], nullptr, Theta[i], dmax, q, ca, d, 0, 0});
+            rc.push_back(RowCopy{Thsk[b], nullptr, Theta[i], dmax, q, cb, d, ca, 0});
+          }
+        }
+        // the coupling products need B1/B2 and the stacked rows first: two stages
+        const UGather* dug = st.push(ug);
+        const RowCopy* drc = st.push(rc);
+        const VGemm* dg1 = st.push(g1.g);
+        const int32_t* dp1 = st.push(g1.pf);
+        if (st.flush(key, s)) return -201;
+        if (dug) hipLaunchKernelGGL(k_ugather, dim3((unsigned)ug.size()), dim3(256), 0, s, dug, ds, zh, dorg, tau, cn);
+        if (root_only) break;
+        if (drc) hipLaunchKernelGGL(k_rows, dim3((unsigned)rc.size()), dim3(256), 0, s, drc);
+        if (dg1) vgemm_launch(dg1, dp1, (int)g1.g.size(), g1.pf.back(), s);
+        VBatch g2;
+        for (int i : nodes) {
+          const HNode& h = T[i];
+          if (h.leaf) continue;
+          const int a = h.c1, b = h.c2;
+          const int ra = hr[2 * a], rb = hr[2 * b], ca = hr[2 * a + 1], cb = hr[2 * b + 1];
+          const int p = ra + rb, q = ca + cb;
+          // Phi rows of a -= B1 Yhat_b, rows of b -= B2 Yhat_a (Algorithm 1)
+          g2.add(mk(B1[i], dmax, 0, Yhat[b], dmax, 0, Phi[i], p, ra, d, cb, -1.0, 1.0));
+          g2.add(mk(B2[i], dmax, 0, Yhat[a], dmax, 0, Phi[i] + ra, p, rb, d, ca, -1.0, 1.0));
+          // Theta rows of a -= B2^T Zhat_b, rows of b -= B1^T Zhat_a
+          g2.add(mk(B2[i], dmax, 1, Zhat[b], dmax, 0, Theta[i], q, ca, d, rb, -1.0, 1.0));
+          g2.add(mk(B1[i], dmax, 1, Zhat[a], dmax, 0, Theta[i] + ca, q, cb, d, ra, -1.0, 1.0));
+        }
+        for (int i : nodes) {
+          idd.push_back(IdDesc{Phi[i], Wk[i], Ub[i], permU[i], &ranks[2 * i], hp[2 * i], hp[2 * i], d});
+          idd.push_back(IdDesc{Theta[i], Wk2[i], Vb[i], permV[i], &ranks[2 * i + 1], hp[2 * i + 1], hp[2 * i + 1], d});
+        }
+        const VGemm* dg2 = st.push(g2.g);
+        const int32_t* dp2 = st.push(g2.pf);
+        const IdDesc* did = st.push(idd);
+        if (st.flush(key, s)) return -202;
+        if (dg2) vgemm_launch(dg2, dp2, (int)g2.g.size(), g2.pf.back(), s);
+        hipLaunchKernelGGL(k_row_id, dim3((unsigned)idd.size()), dim3(256), 0, s, did, o->hss_rel_tol);
+        if (hipMemcpyAsync(hr.data(), ranks, hr.size() * 4, hipMemcpyDeviceToHost, s) != hipSuccess) return -203;
+        if (hipStreamSynchronize(s) != hipSuccess) return -204;
+        for (int i : nodes) {
+          maxrank = std::max(maxrank, std::max(hr[2 * i], hr[2 * i + 1]));
+          if ((hr[2 * i] >= d - 8 && hr[2 * i] < hp[2 * i]) || (hr[2 * i + 1] >= d - 8 && hr[2 * i + 1] < hp[2 * i + 1]))
+            too_large = true;
+        }
+        if (too_large) break;
+        // skeleton rows and indices, nested Yhat / Zhat
+        std::vector<RowCopy> rs;
+        std::vector<IntCopy> ic;
+        std::vector<SkelDesc> sk;
+        VBatch g3, g4;
+        for (int i : nodes) {
+          const HNode& h = T[i];
+          const int p = hp[2 * i], q = hp[2 * i + 1], r = hr[2 * i], c = hr[2 * i + 1];
+          rs.push_back(RowCopy{Phi[i], permU[i], Phisk[i], p, dmax, r, d, 0, 0});
+          rs.push_back(RowCopy{Theta[i], permV[i], Thsk[i], q, dmax, c, d, 0, 0});
+          if (h.leaf) {
+            sk.push_back(SkelDesc{permU[i], nullptr, skI[i], r, h.lo});
+            sk.push_back(SkelDesc{permV[i], nullptr, skJ[i], c, h.lo});
+            g3.add(mk(Vb[i], q, 1, Om1 + h.lo, K, 0, Yhat[i], dmax, c, d, q, 1.0, 0.0));
+            g3.add(mk(Ub[i], p, 1, Om2 + h.lo, K, 0, Zhat[i], dmax, r, d, p, 1.0, 0.0));
+          } else {
+            const int a = h.c1, b = h.c2;
+            const int ra = hr[2 * a], rb = hr[2 * b], ca = hr[2 * a + 1], cb = hr[2 * b + 1];
+            ic.push_back(IntCopy{skI[a], stI[i], ra, 0});
+            ic.push_back(IntCopy{skI[b], stI[i], rb, ra});
+            ic.push_back(IntCopy{skJ[a], stJ[i], ca, 0});
+            ic.push_back(IntCopy{skJ[b], stJ[i], cb, ca});
+            sk.push_back(SkelDesc{permU[i], stI[i], skI[i], r, 0});
+            sk.push_back(SkelDesc{permV[i], stJ[i], skJ[i], c, 0});
+            g3.add(mk(Vb[i], q, 1, Yhat[a], dmax, 0, Yhat[i], dmax, c, d, ca, 1.0, 0.0));
+            g4.add(mk(Vb[i] + ca, q, 1, Yhat[b], dmax, 0, Yhat[i], dmax, c, d, cb, 1.0, ca ? 1.0 : 0.0));
+            g3.add(mk(Ub[i], p, 1, Zhat[a], dmax, 0, Zhat[i], dmax, r, d, ra, 1.0, 0.0));
+            g4.add(mk(Ub[i] + ra, p, 1, Zhat[b], dmax, 0, Zhat[i], dmax, r, d, rb, 1.0, ra ? 1.0 : 0.0));
+          }
+        }
+        const RowCopy* drs = st.push(rs);
+        const IntCopy* dic = st.push(ic);
+        const SkelDesc* dsk = st.push(sk);
+        const VGemm* dg3 = st.push(g3.g);
+        const int32_t* dp3 = st.push(g3.pf);
+        const VGemm* dg4 = st.push(g4.g);
+        const int32_t* dp4 = st.push(g4.pf);
+        if (st.flush(key, s)) return -205;
+        hipLaunchKernelGGL(k_rows, dim3((unsigned)rs.size()), dim3(256), 0, s, drs);
+        if (dic) hipLaunchKernelGGL(k_ints, dim3((unsigned)ic.size()), dim3(256), 0, s, dic);
+        hipLaunchKernelGGL(k_skel, dim3((unsigned)sk.size()), dim3(256), 0, s, dsk);
+        if (dg3) vgemm_launch(dg3, dp3, (int)g3.g.size(), g3.pf.back(), s);
+        if (dg4) vgemm_launch(dg4, dp4, (int)g4.g.size(), g4.pf.back(), s);
+      }
+    }
+    if (too_large) {
+      if (d >= dmax || attempt == 2) return -206;
+      d = std::min(dmax, d + std::max(16, o->hss_samples_inc));  // adaptive sampling: more columns, start over
+      continue;
+    }
+    {
+      static thread_local int32_t mr;
+      mr = maxrank;
+      hipMemcpyAsync(counters_dev + C_HSSRANK, &mr, 4, hipMemcpyHostToDevice, s);
+      hipStreamSynchronize(s);
+    }
+
+    // ------------------------------------------------------------ apply U = X Uhat
+    ProfScope pa(PH_HSS_APPLY, s);
+    const int32_t* dest = S.dest + so;
+    double* out = M.qout;
+    const int64_t ldo = M.ldout;
+    std::vector<VBatch> stages;
+    {
+      VBatch g;
+      for (int i = 0; i < nn; ++i) {
+        const HNode& h = T[i];
+        if (!h.leaf) continue;
+        const int p = h.hi - h.lo, r = hr[2 * i];
+        if (nn > 1) g.add(mk(X + (int64_t)h.lo * m, m, 0, Ub[i], p, 0, Xh[i], m, m, r, p, 1.0, 0.0));
+        g.add(mk(X + (int64_t)h.lo * m, m, 0, Dl[i], p, 0, out, ldo, m, p, p, 1.0, 0.0, dest + h.lo));
+      }
+      stages.push_back(g);
+    }
+    for (int lev = maxlevel - 1; lev >= 1; --lev) {  // up-sweep
+      VBatch ga, gb;
+      for (int i = 0; i < nn; ++i) {
+        const HNode& h = T[i];
+        if (h.leaf || h.level != lev) continue;
+        const int a = h.c1, b = h.c2, ra = hr[2 * a], rb = hr[2 * b], p = ra + rb, r = hr[2 * i];
+        ga.add(mk(Xh[a], m, 0, Ub[i], p, 0, Xh[i], m, m, r, ra, 1.0, 0.0));
+        gb.add(mk(Xh[b], m, 0, Ub[i] + ra, p, 0, Xh[i], m, m, r, rb, 1.0, ra ? 1.0 : 0.0));
+      }
+      stages.push_back(ga);
+      stages.push_back(gb);
+    }
+    {
+      VBatch g;  // couplings of every sibling pair
+      for (int i = 0; i < nn; ++i) {
+        const HNode& h = T[i];
+        if (h.leaf) continue;
+        const int a = h.c1, b = h.c2, ra = hr[2 * a], rb = hr[2 * b], ca = hr[2 * a + 1], cb = hr[2 * b + 1];
+        g.add(mk(Xh[a], m, 0, B1[i], dmax, 0, Yh[b], m, m, cb, ra, 1.0, 0.0));
+        g.add(mk(Xh[b], m, 0, B2[i], dmax, 0, Yh[a], m, m, ca, rb, 1.0, 0.0));
+      }
+      stages.push_back(g);
+    }
+    for (int lev = 1; lev <= maxlevel - 1; ++lev) {  // down-sweep
+      VBatch g;
+      for (int i = 0; i < nn; ++i) {
+        const HNode& h = T[i];
+        if (h.leaf || h.level != lev) continue;
+        const int a = h.c1, b = h.c2, ca = hr[2 * a + 1], cb = hr[2 * b + 1], q = ca + cb, c = hr[2 * i + 1];
+        if (!c) continue;
+        g.add(mk(Yh[i], m, 0, Vb[i], q, 1, Yh[a], m, m, ca, c, 1.0, 1.0));
+        g.add(mk(Yh[i], m, 0, Vb[i] + ca, q, 1, Yh[b], m, m, cb, c, 1.0, 1.0));
+      }
+      stages.push_back(g);
+    }
+    if (nn > 1) {
+      VBatch g;  // leaves: out(:, t) += Yh V^T
+      for (int i = 0; i < nn; ++i) {
+        const HNode& h = T[i];
+        if (!h.leaf) continue;
+        const int p = h.hi - h.lo, c = hr[2 * i + 1];
+        if (c) g.add(mk(Yh[i], m, 0, Vb[i], p, 1, out, ldo, m, p, c, 1.0, 1.0, dest + h.lo));
+      }
+      stages.push_back(g);
+    }
+    std::vector<std::pair<const VGemm*, const int32_t*>> dptr;
+    for (auto& g : stages) dptr.emplace_back(st.push(g.g), st.push(g.pf));
+    if (st.flush(key, s)) return -207;
+    for (size_t q = 0; q < stages.size(); ++q)
+      if (!stages[q].g.empty())
+        vgemm_launch(dptr[q].first, dptr[q].second, (int)stages[q].g.size(), stages[q].pf.back(), s);
+    return 0;
+  }
+  return -208;
+}
+
+}  // namespace phdc

@@ -1,0 +1,726 @@
+// Merge step of the divide-and-conquer eigensolver (Sec. 1, Eq. (3)-(6)):
+// deflation, secular roots, Loewner z, the eigenvector matrix Uhat, the final
+// ordering and the copy of deflated columns.  All merges of one level run in
+// one launch per kernel; every kernel reads the data-dependent sizes (K, type
+// counts) from device counters, so no host round trip is needed.
+#include "phdc_internal.h"
+#include "profile.h"
+
+namespace phdc {
+
+__device__ inline int cdiv_d(int a, int b) { return (a + b - 1) / b; }
+
+// ------------------------------------------------------------ block utilities
+
+template <int NT>
+__device__ double block_sum(double v, double* sh) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  for (int i = 0; i < NT / 64; ++i) r += sh[i];  // fixed order: deterministic
+  return r;
+}
+
+template <int NT>
+__device__ double block_max(double v, double* sh) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  for (int i = 0; i < NT / 64; ++i) r = fmax(r, sh[i]);
+  return r;
+}
+
+// Exclusive scan of a 64-bit value over the block (used with packed counters).
+template <int NT>
+__device__ int64_t block_excl_scan(int64_t x, int64_t* total, int64_t* sh) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int64_t v = x;
+  for (int o = 1; o < 64; o <<= 1) {
+    int64_t y = __shfl_up(v, o, 64);
+    if (lane >= o) v += y;
+  }
+  __syncthreads();
+  if (lane == 63) sh[w] = v;
+  __syncthreads();
+  int64_t before = 0, tot = 0;
+  for (int i = 0; i < NT / 64; ++i) {
+    if (i < w) before += sh[i];
+    tot += sh[i];
+  }
+  *total = tot;
+  return before + v - x;
+}
+
+// # of a[0:n) strictly below x / at most x (a ascending).
+__device__ inline int count_lt(const double* a, int n, double x) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (a[mid] < x) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+__device__ inline int count_le(const double* a, int n, double x) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (a[mid] <= x) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// Part codes: which halves of a merge column can be nonzero.
+__device__ inline bool part_valid(int part, bool top) {
+  return part == 2 || (top ? part == 1 : part == 3);
+}
+
+// Type-2 deflation test for consecutive survivors p < j (Sec. 1, after Remark 1):
+// the rotation that zeroes z_p leaves the off-diagonal residue (d_j - d_p) c s.
+__device__ inline bool pair_deflates(double dp, double zp, double dj, double zj, double tol, double* c,
+                                     double* s, double* tau) {
+  double t = hypot(zp, zj);
+  *c = zj / t;
+  *s = -zp / t;
+  *tau = t;
+  return fabs((dj - dp) * (*c) * (*s)) <= tol;
+}
+
+// ------------------------------------------------------------ deflation
+// One 1024-thread workgroup per merge.
+constexpr int kDefThreads = 1024;
+
+__global__ void __launch_bounds__(kDefThreads) k_deflate(const MergeDesc* __restrict__ descs, Scratch S) {
+  __shared__ double shd[kDefThreads / 64];
+  __shared__ int64_t shl[kDefThreads / 64];
+  __shared__ int shi[4];
+  const MergeDesc M = descs[blockIdx.x];
+  const int m = M.m, n1 = M.n1, t = threadIdx.x;
+  const int64_t so = M.s_off;
+  int32_t* cnt = S.counters + (int64_t)M.id * kCounters;
+  double* dv = S.dv + so;
+  double* zv = S.zv + so;
+  int32_t* col = S.col + so;
+  int32_t* part = S.part + so;
+  int32_t* flag = S.flag + so;
+  int32_t* surv = S.surv + so;
+
+  double rho0 = M.rho, zsign = M.zsign;
+  if (M.ecoup != nullptr) {
+    // stedc: the coupling b_k of the split (Eq. (2)) lives in the off-diagonal
+    // array: rho = |b_k| and the Q2 half of z carries sign(b_k).
+    const double bk = *M.ecoup;
+    rho0 = fabs(bk);
+    zsign = (bk < 0.0) ? -1.0 : 1.0;
+  }
+
+  // 1. z (Eq. (3): last row of Q1, first row of Q2), |z|^2, max |D|, sortedness.
+  double zz = 0.0, dmx = 0.0;
+  int uns = 0;
+  for (int i = t; i < m; i += kDefThreads) {
+    double zi;
+    if (M.zgiven) zi = M.zgiven[i];
+    else zi = (i < n1) ? M.qin[(n1 - 1) + (int64_t)i * M.ldin] : zsign * M.qin[n1 + (int64_t)i * M.ldin];
+    S.zs[so + i] = zi;
+    double di = M.lin[i];
+    zz += zi * zi;
+    dmx = fmax(dmx, fabs(di));
+    // NaN or a descending step inside either run makes the merge of the two
+    // runs ill-defined; such input is reported and merged without sorting.
+    if (!(di == di) || (i > 0 && i != n1 && !(di >= M.lin[i - 1]))) uns = 1;
+  }
+  zz = block_sum<kDefThreads>(zz, shd);
+  dmx = block_max<kDefThreads>(dmx, shd);
+  __syncthreads();
+  if (t == 0) shi[0] = 0;
+  __syncthreads();
+  if (uns) shi[0] = 1;
+  __syncthreads();
+  uns = shi[0];
+  const double rho = rho0 * zz;
+  const double zn = sqrt(zz);
+  const double tol = 8.0 * kUnitRoundoff * fmax(dmx, rho);
+  if (t == 0) {
+    S.mparam[(int64_t)M.id * 4 + 0] = rho;
+    S.mparam[(int64_t)M.id * 4 + 1] = tol;
+    if (uns) set_status(S.status, PHDC_ERR_UNSORTED);
+  }
+
+  // 2. merge the two ascending runs (ties: D1 first) and normalise z.  For
+  // valid input the positions form a permutation of [0, m); otherwise keep the
+  // input order so every slot is still written exactly once.
+  for (int i = t; i < m; i += kDefThreads) {
+    double di = M.lin[i];
+    int pos = uns ? i
+                  : (i < n1) ? i + count_lt(M.lin + n1, m - n1, di) : (i - n1) + count_le(M.lin, n1, di);
+    dv[pos] = di;
+    zv[pos] = (zn > 0.0) ? S.zs[so + i] / zn : 0.0;
+    col[pos] = i;
+    part[pos] = (i < n1) ? 1 : 3;
+  }
+  __syncthreads();
+
+  // 3. type-1 deflation (rho |z_i| <= tol) and compaction of both lists in pole order.
+  int base_s = 0, base_d = 0;
+  for (int c0 = 0; c0 < m; c0 += kDefThreads) {
+    int k = c0 + t;
+    int isS = 0, isD = 0;
+    if (k < m) {
+      bool dfl = rho * fabs(zv[k]) <= tol;
+      isD = dfl;
+      isS = !dfl;
+      flag[k] = dfl ? 1 : 0;
+    }
+    int64_t tot;
+    int64_t ex = block_excl_scan<kDefThreads>((int64_t)isS | ((int64_t)isD << 32), &tot, shl);
+    if (isS) surv[base_s + (int)(ex & 0xffffffffLL)] = k;
+    if (isD) {
+      int q = base_d + (int)(ex >> 32);
+      S.dfv1[so + q] = dv[k];
+      S.dfc1[so + q] = col[k];
+      S.dfp1[so + q] = part[k];
+    }
+    base_s += (int)(tot & 0xffffffffLL);
+    base_d += (int)(tot >> 32);
+  }
+  __syncthreads();
+  const int ns = base_s, nd1 = base_d;
+
+  // 4. type-2 deflation: scan consecutive survivors in pole order.  Wave 0 tests
+  // 64 survivors at a time speculatively (each against its unmodified
+  // predecessor) and then replays the chunk in order, jumping straight to the
+  // next pair that passes whenever the current predecessor is unmodified.
+  if (t < 64) {
+    const int lane = t;
+    int nrot = 0, nchain = 0;
+    bool have_p = false, pmod = false;
+    int pk = -1, pp = 0;
+    double pd = 0.0, pz = 0.0;
+    for (int b0 = 0; b0 < ns; b0 += 64) {
+      const int nv = min(64, ns - b0);
+      int k = -1, kp = 0;
+      double dk = 0.0, zk = 0.0;
+      if (lane < nv) {
+        k = surv[b0 + lane];
+        dk = dv[k];
+        zk = zv[k];
+        kp = part[k];
+      }
+      double dprev = __shfl_up(dk, 1, 64), zprev = __shfl_up(zk, 1, 64);
+      double c_, s_, t_;
+      bool spec = (lane > 0) && (lane < nv) && pair_deflates(dprev, zprev, dk, zk, tol, &c_, &s_, &t_);
+      const uint64_t mask = __ballot(spec);
+      int L = 0;
+      while (L < nv) {
+        const double dL = __shfl(dk, L, 64), zL = __shfl(zk, L, 64);
+        const int kL = __shfl(k, L, 64), partL = __shfl(kp, L, 64);
+        if (!have_p) {
+          have_p = true;
+          pk = kL; pd = dL; pz = zL; pp = partL; pmod = false;
+          ++L;
+        } else {
+          double c, s, tau;
+          if (pair_deflates(pd, pz, dL, zL, tol, &c, &s, &tau)) {
+            const double dpn = pd * c * c + dL * s * s;
+            const double djn = pd * s * s + dL * c * c;
+            const int np = (pp == partL) ? pp : 2;
+            if (lane == 0) {
+              if (!pmod) S.chain[so + nchain] = nrot;
+              S.rcolp[so + nrot] = col[pk];
+              S.rcolj[so + nrot] = col[kL];
+              S.rc[so + nrot] = c;
+              S.rs[so + nrot] = s;
+              S.rpart[so + nrot] = pp | (partL << 8);
+              dv[pk] = dpn;
+              zv[pk] = 0.0;
+              flag[pk] = 2;
+              part[pk] = np;
+              dv[kL] = djn;
+              zv[kL] = tau;
+              part[kL] = np;
+            }
+            if (!pmod) ++nchain;
+            ++nrot;
+            pk = kL; pd = djn; pz = tau; pp = np; pmod = true;
+            ++L;
+            continue;
+          }
+          pk = kL; pd = dL; pz = zL; pp = partL; pmod = false;
+          ++L;
+        }
+        // The predecessor is an unmodified survivor of this chunk: the
+        // speculative results are exact until the next passing pair.
+        const uint64_t rem = (L < 64) ? (mask & (~0ULL << L)) : 0ULL;
+        if (rem == 0ULL) {
+          if (L < nv) {
+            const int q = nv - 1;
+            pk = __shfl(k, q, 64); pd = __shfl(dk, q, 64); pz = __shfl(zk, q, 64); pp = __shfl(kp, q, 64);
+            pmod = false;
+          }
+          L = nv;
+        } else {
+          const int h = __ffsll((unsigned long long)rem) - 1;
+          if (h > L) {
+            const int q = h - 1;
+            pk = __shfl(k, q, 64); pd = __shfl(dk, q, 64); pz = __shfl(zk, q, 64); pp = __shfl(kp, q, 64);
+            pmod = false;
+          }
+          L = h;
+        }
+      }
+    }
+    if (lane == 0) {
+      cnt[C_NROT] = nrot;
+      cnt[C_NCHAIN] = nchain;
+    }
+  }
+  __syncthreads();
+
+  // 5. final survivors in pole order, Gu's grouping by part (Sec. 1): rows of
+  // Uhat ordered [part 1 | part 2 | part 3]; the Q1-row product uses columns of
+  // parts 1,2 and the Q2-row product those of parts 2,3.  Type-2 deflated list.
+  int c1 = 0, c2 = 0, c3 = 0, c4 = 0;
+  for (int k = t; k < m; k += kDefThreads) {
+    int f = flag[k];
+    if (f == 0) {
+      int p = part[k];
+      c1 += (p == 1); c2 += (p == 2); c3 += (p == 3);
+    } else if (f == 2) {
+      ++c4;
+    }
+  }
+  const int k1 = (int)block_sum<kDefThreads>((double)c1, shd);
+  const int k2 = (int)block_sum<kDefThreads>((double)c2, shd);
+  const int k3 = (int)block_sum<kDefThreads>((double)c3, shd);
+  const int nd2 = (int)block_sum<kDefThreads>((double)c4, shd);
+  const int K = k1 + k2 + k3;
+  int64_t b1 = 0, b2 = 0, b3 = 0, b4 = 0;
+  for (int c0 = 0; c0 < m; c0 += kDefThreads) {
+    int k = c0 + t;
+    int f = -1, p = 0;
+    if (k < m) {
+      f = flag[k];
+      p = part[k];
+    }
+    int64_t x = 0;
+    if (f == 0) x = (p == 1) ? 1LL : (p == 2) ? (1LL << 21) : (1LL << 42);
+    int64_t tot;
+    int64_t ex = block_excl_scan<kDefThreads>(x, &tot, shl);
+    int64_t tot4;
+    int64_t ex4 = block_excl_scan<kDefThreads>((int64_t)(f == 2), &tot4, shl);
+    const int64_t msk = (1LL << 21) - 1;
+    if (f == 0) {
+      int e1 = (int)(b1 + (ex & msk)), e2 = (int)(b2 + ((ex >> 21) & msk)), e3 = (int)(b3 + ((ex >> 42) & msk));
+      int ks = e1 + e2 + e3;
+      S.ds[so + ks] = dv[k];
+      S.zs[so + ks] = zv[k];
+      S.csort[so + ks] = col[k];
+      S.psort[so + ks] = p;
+      int g;
+      if (p == 1) {
+        g = e1;
+        S.coltop[so + e1] = col[k];
+      } else if (p == 2) {
+        g = k1 + e2;
+        S.coltop[so + k1 + e2] = col[k];
+        S.colbot[so + e2] = col[k];
+      } else {
+        g = k1 + k2 + e3;
+        S.colbot[so + k2 + e3] = col[k];
+      }
+      S.grp[so + ks] = g;
+      S.grpsrc[so + g] = ks;
+    } else if (f == 2) {
+      int q = (int)(b4 + ex4);
+      S.dfv2[so + q] = dv[k];
+      S.dfc2[so + q] = col[k];
+      S.dfp2[so + q] = p;
+    }
+    b1 += tot & msk;
+    b2 += (tot >> 21) & msk;
+    b3 += (tot >> 42) & msk;
+    b4 += tot4;
+  }
+  if (t == 0) {
+    cnt[C_K] = K;
+    cnt[C_K1] = k1;
+    cnt[C_K2] = k2;
+    cnt[C_K3] = k3;
+    cnt[C_NT1] = nd1;
+    cnt[C_NT2] = nd2;
+    cnt[C_ND1] = nd1;
+    cnt[C_ND2] = nd2;
+    cnt[C_PATH] = (M.hss_min_k > 0 && K >= M.hss_min_k) ? 2 : 0;
+    cnt[C_HSSRANK] = 0;
+  }
+}
+
+// ------------------------------------------------------------ rotations
+// Applies the recorded rotation chains to the columns of the merge's input
+// block, in place.  A chain's records share a column and run in order per row;
+// distinct chains touch disjoint columns and run in parallel.
+constexpr int kRotGroups = 16;
+
+__global__ void __launch_bounds__(256) k_rotate(BlockMap bm, Scratch S) {
+  const int b = blockIdx.x;
+  const int mi = find_merge(bm, b);
+  const int lb = b - bm.pfx[mi];
+  const MergeDesc M = bm.descs[mi];
+  const int m = M.m, n1 = M.n1;
+  const int RB = cdiv_d(m, 256);
+  const int G = (bm.pfx[mi + 1] - bm.pfx[mi]) / RB;
+  const int rb = lb % RB, g = lb / RB;
+  const int32_t* cnt = S.counters + (int64_t)M.id * kCounters;
+  const int nrot = cnt[C_NROT], nchain = cnt[C_NCHAIN];
+  const int r = rb * 256 + threadIdx.x;
+  if (r >= m) return;
+  const int64_t so = M.s_off;
+  const bool top = r < n1;
+  double* q = M.qin;
+  const int64_t ld = M.ldin;
+  for (int ci = g; ci < nchain; ci += G) {
+    const int a = S.chain[so + ci];
+    const int e = (ci + 1 < nchain) ? S.chain[so + ci + 1] : nrot;
+    for (int x = a; x < e; ++x) {
+      const int cp = S.rcolp[so + x], cj = S.rcolj[so + x];
+      const int pr = S.rpart[so + x];
+      const bool vp = part_valid(pr & 255, top), vj = part_valid(pr >> 8, top);
+      if (!vp && !vj) continue;
+      const double c = S.rc[so + x], s = S.rs[so + x];
+      const double xp = vp ? q[r + (int64_t)cp * ld] : 0.0;
+      const double xj = vj ? q[r + (int64_t)cj * ld] : 0.0;
+      q[r + (int64_t)cp * ld] = c * xp + s * xj;
+      q[r + (int64_t)cj * ld] = c * xj - s * xp;
+    }
+  }
+}
+
+// ------------------------------------------------------------ secular roots
+// One root per thread.  Root j of f(lambda) = 1 + rho sum_i z_i^2/(d_i - lambda)
+// (Sec. 1, after Eq. (4)) is bracketed in (d_j, d_{j+1}) (last root: (d_K,
+// d_K + rho|z|^2)); its origin is the bracket end nearer to the root (sign of f
+// at the midpoint).  tau is then refined by the two-pole rational model of f
+// (the "middle way" of R.-C. Li, 1993: psi = poles left of the bracket, phi =
+// poles right of it, each matched in value and slope at the current iterate),
+// with the bracket kept up to date and a bisection step whenever the model
+// step leaves it.  All differences are formed as (d_i - d_org) - tau.
+__device__ bool secular_root(int K, const double* __restrict__ d, const double* __restrict__ z, double rho, int j,
+                             int* org_out, double* tau_out) {
+  const double inv_rho = 1.0 / rho;
+  if (K == 1) {
+    *org_out = 0;
+    *tau_out = rho * z[0] * z[0];
+    return true;
+  }
+  int org;
+  double lo, hi;
+  if (j < K - 1) {
+    const double dj = d[j], dj1 = d[j + 1];
+    const double half = 0.5 * (dj1 - dj);
+    double w = inv_rho;
+    for (int i = 0; i < K; ++i) w += z[i] * z[i] / ((d[i] - dj) - half);
+    if (w >= 0.0) {
+      org = j; lo = 0.0; hi = half;
+    } else {
+      org = j + 1; lo = (dj - dj1) + half; hi = 0.0;
+    }
+  } else {
+    org = K - 1;
+    lo = 0.0;
+    double zz = 0.0;
+    for (int i = 0; i < K; ++i) zz += z[i] * z[i];
+    hi = rho * zz;
+    for (int guard = 0; guard < 64; ++guard) {
+      double w = inv_rho;
+      for (int i = 0; i < K; ++i) w += z[i] * z[i] / ((d[i] - d[org]) - hi);
+      if (w >= 0.0) break;
+      hi *= 2.0;
+    }
+  }
+  const double dorg = d[org];
+  const int jl = (j < K - 1) ? j : K - 2;
+  const int jr = jl + 1;
+  double tau = 0.5 * (lo + hi);
+  bool ok = false;
+  for (int it = 0; it < 120; ++it) {
+    double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0, eabs = 0.0;
+    for (int i = 0; i < K; ++i) {
+      const double del = (d[i] - dorg) - tau;
+      const double rcp = 1.0 / del;
+      const double tt = z[i] * z[i] * rcp;
+      const double dt = tt * rcp;
+      if (i <= jl) { psi += tt; dpsi += dt; } else { phi += tt; dphi += dt; }
+      eabs += fabs(tt);
+    }
+    const double w = inv_rho + psi + phi;
+    if (w > 0.0) hi = tau;
+    else if (w < 0.0) lo = tau;
+    else { ok = true; break; }
+    if (fabs(w) <= 8.0 * kUnitRoundoff * (inv_rho + eabs)) { ok = true; break; }
+    const double Dl = (d[jl] - dorg) - tau, Dr = (d[jr] - dorg) - tau;
+    const double a = (Dl + Dr) * w - Dl * Dr * (dpsi + dphi);
+    const double bb = Dl * Dr * w;
+    const double c = w - Dl * dpsi - Dr * dphi;
+    const double disc = sqrt(fabs(a * a - 4.0 * bb * c));
+    double eta;
+    if (c == 0.0) eta = bb / a;
+    else if (j < K - 1) eta = (a <= 0.0) ? (a - disc) / (2.0 * c) : 2.0 * bb / (a + disc);
+    else eta = (a >= 0.0) ? (a + disc) / (2.0 * c) : 2.0 * bb / (a - disc);
+    double tn = tau + eta;
+    if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+    if (tn == tau || !(hi > lo)) { ok = true; break; }
+    tau = tn;
+  }
+  *org_out = org;
+  *tau_out = tau;
+  return ok;
+}
+
+__global__ void __launch_bounds__(64) k_secular(BlockMap bm, Scratch S) {
+  const int b = blockIdx.x;
+  const int mi = find_merge(bm, b);
+  const int lb = b - bm.pfx[mi];
+  const MergeDesc M = bm.descs[mi];
+  const int K = S.counters[(int64_t)M.id * kCounters + C_K];
+  const int j = lb * 64 + threadIdx.x;
+  if (j >= K) return;
+  const int64_t so = M.s_off;
+  const double rho = S.mparam[(int64_t)M.id * 4 + 0];
+  int org;
+  double tau;
+  bool ok = secular_root(K, S.ds + so, S.zs + so, rho, j, &org, &tau);
+  S.org[so + j] = org;
+  S.tau[so + j] = tau;
+  S.dorg[so + j] = S.ds[so + org];
+  if (!ok) set_status(S.status, PHDC_ERR_SECULAR);
+}
+
+__global__ void __launch_bounds__(64) k_secular_raw(int K, const double* d, const double* z, double rho,
+                                                    int32_t* org, double* tau, int32_t* status) {
+  const int j = blockIdx.x * 64 + threadIdx.x;
+  if (j >= K) return;
+  int o;
+  double t;
+  bool ok = secular_root(K, d, z, rho, j, &o, &t);
+  org[j] = o;
+  tau[j] = t;
+  if (!ok) set_status(status, PHDC_ERR_SECULAR);
+}
+
+// ------------------------------------------------------------ Loewner z
+// rho zhat_i^2 = prod_j (lambda_j - d_i) / prod_{k != i} (d_k - d_i) (Remark 1),
+// paired so every factor is in (0, 1]: for j < i (d_i - lambda_j)/(d_i - d_j),
+// for i <= j < K-1 (d_i - lambda_j)/(d_i - d_{j+1}), times lambda_{K-1} - d_i.
+__global__ void __launch_bounds__(64) k_lowner(BlockMap bm, Scratch S) {
+  const int b = blockIdx.x;
+  const int mi = find_merge(bm, b);
+  const int lb = b - bm.pfx[mi];
+  const MergeDesc M = bm.descs[mi];
+  const int K = S.counters[(int64_t)M.id * kCounters + C_K];
+  const int i = lb * 64 + threadIdx.x;
+  if (i >= K) return;
+  const int64_t so = M.s_off;
+  const double* ds = S.ds + so;
+  const double* dorg = S.dorg + so;
+  const double* tau = S.tau + so;
+  const double rho = S.mparam[(int64_t)M.id * 4 + 0];
+  const double di = ds[i];
+  double w = -((di - dorg[K - 1]) - tau[K - 1]);
+  for (int j = 0; j < K - 1; ++j) {
+    const double num = (di - dorg[j]) - tau[j];
+    const double den = (j < i) ? (di - ds[j]) : (di - ds[j + 1]);
+    w *= num / den;
+  }
+  const double mag = sqrt(fabs(w) / rho);
+  S.zhat[so + i] = (S.zs[so + i] < 0.0) ? -mag : mag;
+}
+
+// ------------------------------------------------------------ Uhat
+// Column j of Uhat is (D - lambda_j)^{-1} zhat (Sec. 1, after Eq. (4)), scaled
+// to unit norm.  First the column norms (one thread per column) ...
+__global__ void __launch_bounds__(64) k_unorm(BlockMap bm, Scratch S) {
+  const int b = blockIdx.x;
+  const int mi = find_merge(bm, b);
+  const int lb = b - bm.pfx[mi];
+  const MergeDesc M = bm.descs[mi];
+  const int K = S.counters[(int64_t)M.id * kCounters + C_K];
+  const int j = lb * 64 + threadIdx.x;
+  if (j >= K) return;
+  const int64_t so = M.s_off;
+  const double* ds = S.ds + so;
+  const double* zh = S.zhat + so;
+  const double lj = S.dorg[so + j], tj = S.tau[so + j];
+  double s = 0.0;
+  for (int i = 0; i < K; ++i) {
+    const double v = zh[i] / ((ds[i] - lj) - tj);
+    s += v * v;
+  }
+  S.cnorm[so + j] = 1.0 / sqrt(s);
+}
+
+// ... then the entries, written row-major (row g = grouped row, ld = K) so that
+// the product's operand tiles are contiguous.  A block covers 256 columns and
+// strides over rows.
+constexpr int kUwRowGroups = 64;
+
+__global__ void __launch_bounds__(256) k_uwrite(BlockMap bm, Scratch S) {
+  const int b = blockIdx.x;
+  const int mi = find_merge(bm, b);
+  const int lb = b - bm.pfx[mi];
+  const MergeDesc M = bm.descs[mi];
+  const int K = S.counters[(int64_t)M.id * kCounters + C_K];
+  const int CB = cdiv_d(M.m, 256);
+  const int RG = (bm.pfx[mi + 1] - bm.pfx[mi]) / CB;
+  const int cb = lb % CB, rg = lb / CB;
+  const int j = cb * 256 + threadIdx.x;
+  if (j >= K) return;
+  const int64_t so = M.s_off;
+  const double* ds = S.ds + so;
+  const double* zh = S.zhat + so;
+  // HSS merges keep the pole order (Gu's grouping would break the low-rank
+  // structure of the off-diagonal blocks, Sec. 2.2); plain merges use it.
+  const bool pole_order = S.counters[(int64_t)M.id * kCounters + C_PATH] == 2;
+  const int32_t* src = S.grpsrc + so;
+  const double lj = S.dorg[so + j], tj = S.tau[so + j], sc = S.cnorm[so + j];
+  double* U = S.uhat + M.u_off;
+  for (int g = rg; g < K; g += RG) {
+    const int i = pole_order ? g : src[g];
+    U[(int64_t)g * K + j] = zh[i] / ((ds[i] - lj) - tj) * sc;
+  }
+}
+
+// ------------------------------------------------------------ final order
+// Output position of every eigenvalue of the merge: the ascending order of
+// {roots} u {type-1 deflated} u {type-2 deflated}, ties broken by (class,
+// index).  Roots and type-1 values are each non-decreasing (binary search);
+// type-2 values are counted directly.
+__global__ void __launch_bounds__(256) k_rank(BlockMap bm, Scratch S) {
+  const int b = blockIdx.x;
+  const int mi = find_merge(bm, b);
+  const int lb = b - bm.pfx[mi];
+  const MergeDesc M = bm.descs[mi];
+  const int x = lb * 256 + threadIdx.x;
+  if (x >= M.m) return;
+  const int32_t* cnt = S.counters + (int64_t)M.id * kCounters;
+  const int K = cnt[C_K], nd1 = cnt[C_ND1], nd2 = cnt[C_ND2];
+  const int64_t so = M.s_off;
+  const double* dorg = S.dorg + so;
+  const double* tau = S.tau + so;
+  const double* v1 = S.dfv1 + so;
+  const double* v2 = S.dfv2 + so;
+  int cls, idx;
+  double v;
+  if (x < K) { cls = 0; idx = x; v = dorg[x] + tau[x]; }
+  else if (x < K + nd1) { cls = 1; idx = x - K; v = v1[idx]; }
+  else { cls = 2; idx = x - K - nd1; v = v2[idx]; }
+  int r;
+  // roots
+  if (cls == 0) r = idx;
+  else {
+    int lo = 0, hi = K;
+    while (lo < hi) {
+      int mid = (lo + hi) >> 1;
+      if (dorg[mid] + tau[mid] <= v) lo = mid + 1; else hi = mid;
+    }
+    r = lo;
+  }
+  // type-1 deflated
+  if (cls == 1) r += idx;
+  else if (cls == 0) r += count_lt(v1, nd1, v);
+  else r += count_le(v1, nd1, v);
+  // type-2 deflated
+  for (int q = 0; q < nd2; ++q) {
+    const double u = v2[q];
+    r += (u < v) || (u == v && cls == 2 && q < idx);
+  }
+  M.lout[r] = v;
+  if (cls == 0) S.dest[so + idx] = r;
+  else if (cls == 1) S.destd1[so + idx] = r;
+  else S.destd2[so + idx] = r;
+}
+
+// ------------------------------------------------------------ deflated columns
+// Deflated columns of Q G P (Eq. (6), the identity block) go unchanged to
+// their output position; halves that are structurally zero are written as 0.
+constexpr int kCopyGroups = 64;
+
+__global__ void __launch_bounds__(256) k_copy_deflated(BlockMap bm, Scratch S) {
+  const int b = blockIdx.x;
+  const int mi = find_merge(bm, b);
+  const int lb = b - bm.pfx[mi];
+  const MergeDesc M = bm.descs[mi];
+  const int m = M.m;
+  const int RB = cdiv_d(m, 256);
+  const int G = (bm.pfx[mi + 1] - bm.pfx[mi]) / RB;
+  const int rb = lb % RB, g = lb / RB;
+  const int r = rb * 256 + threadIdx.x;
+  if (r >= m) return;
+  const int32_t* cnt = S.counters + (int64_t)M.id * kCounters;
+  const int nd1 = cnt[C_ND1], nd2 = cnt[C_ND2];
+  const int64_t so = M.s_off;
+  const bool top = r < M.n1;
+  for (int q = g; q < nd1 + nd2; q += G) {
+    int c, p, dst;
+    if (q < nd1) { c = S.dfc1[so + q]; p = S.dfp1[so + q]; dst = S.destd1[so + q]; }
+    else { const int q2 = q - nd1; c = S.dfc2[so + q2]; p = S.dfp2[so + q2]; dst = S.destd2[so + q2]; }
+    const double v = part_valid(p, top) ? M.qin[r + (int64_t)c * M.ldin] : 0.0;
+    M.qout[r + (int64_t)dst * M.ldout] = v;
+  }
+}
+
+// ------------------------------------------------------------ block maps
+constexpr int kGemmTile = 128;
+
+int map_blocks(int kind, int m, int n1) {
+  auto cdiv = [](int a, int b) { return (a + b - 1) / b; };
+  switch (kind) {
+    case MAP_ROOTS64: return cdiv(m, 64);
+    case MAP_ROWS256: return cdiv(m, 256);
+    case MAP_ROT: return cdiv(m, 256) * std::max(1, std::min(m / 2, kRotGroups));
+    case MAP_UWRITE: return cdiv(m, 256) * std::max(1, std::min(m, kUwRowGroups));
+    case MAP_GEMM: return (cdiv(n1, kGemmTile) + cdiv(m - n1, kGemmTile)) * cdiv(m, kGemmTile);
+    case MAP_COPY: return cdiv(m, 256) * std::max(1, std::min(m, kCopyGroups));
+  }
+  return 0;
+}
+
+void launch_merge_gemm_f64(const BlockMap& bm, int total, const Scratch& S, hipStream_t s);
+
+void launch_merge_level(const MergeDesc* descs, int nm, const LevelMaps& maps, const Scratch& S, int gemm_mode,
+                        hipStream_t s) {
+  if (nm <= 0) return;
+  (void)gemm_mode;
+  auto bmap = [&](int kind) { return BlockMap{descs, maps.pfx[kind], nm}; };
+  { ProfScope p(PH_DEFLATE, s);
+    hipLaunchKernelGGL(k_deflate, dim3(nm), dim3(kDefThreads), 0, s, descs, S); }
+  { ProfScope p(PH_ROTATE, s);
+    hipLaunchKernelGGL(k_rotate, dim3(maps.total[MAP_ROT]), dim3(256), 0, s, bmap(MAP_ROT), S); }
+  { ProfScope p(PH_SECULAR, s);
+    hipLaunchKernelGGL(k_secular, dim3(maps.total[MAP_ROOTS64]), dim3(64), 0, s, bmap(MAP_ROOTS64), S); }
+  { ProfScope p(PH_LOWNER, s);
+    hipLaunchKernelGGL(k_lowner, dim3(maps.total[MAP_ROOTS64]), dim3(64), 0, s, bmap(MAP_ROOTS64), S); }
+  { ProfScope p(PH_UNORM, s);
+    hipLaunchKernelGGL(k_unorm, dim3(maps.total[MAP_ROOTS64]), dim3(64), 0, s, bmap(MAP_ROOTS64), S); }
+  { ProfScope p(PH_UWRITE, s);
+    hipLaunchKernelGGL(k_uwrite, dim3(maps.total[MAP_UWRITE]), dim3(256), 0, s, bmap(MAP_UWRITE), S); }
+  { ProfScope p(PH_RANK, s);
+    hipLaunchKernelGGL(k_rank, dim3(maps.total[MAP_ROWS256]), dim3(256), 0, s, bmap(MAP_ROWS256), S); }
+  { ProfScope p(PH_GEMM, s);
+    launch_merge_gemm_f64(bmap(MAP_GEMM), maps.total[MAP_GEMM], S, s); }
+  { ProfScope p(PH_COPY, s);
+    hipLaunchKernelGGL(k_copy_deflated, dim3(maps.total[MAP_COPY]), dim3(256), 0, s, bmap(MAP_COPY), S); }
+}
+
+void launch_secular_standalone(int64_t K, const double* d, const double* z, double rho, int32_t* org, double* tau,
+                               int32_t* status, hipStream_t s) {
+  if (K <= 0) return;
+  hipLaunchKernelGGL(k_secular_raw, dim3((unsigned)((K + 63) / 64)), dim3(64), 0, s, (int)K, d, z, rho, org, tau,
+                     status);
+}
+
+}  // namespace phdc

@@ -1,0 +1,138 @@
+// Internal declarations shared by the HIP translation units of libphdc.so.
+// Not part of the public C-ABI (include/phdc.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/phdc.h"
+
+namespace phdc {
+
+constexpr double kUnitRoundoff = 1.1102230246251565e-16;  // 2^-53
+constexpr int kMaxLeaf = 64;
+constexpr int kCounters = 16;  // per-merge int32 counters
+
+// Counter slots (per merge).
+enum : int {
+  C_K = 0, C_K1 = 1, C_K2 = 2, C_K3 = 3, C_NT1 = 4, C_NT2 = 5, C_PATH = 6, C_HSSRANK = 7,
+  C_NROT = 8, C_NCHAIN = 9, C_ND1 = 10, C_ND2 = 11
+};
+
+// One rank-one merge of the divide-and-conquer tree.  All pointers are device pointers.
+struct MergeDesc {
+  double* qin;          // input block origin: rows/cols [0, m) hold diag(Q1, Q2); off-diagonal blocks are scratch
+  double* qout;         // output block origin (m x m)
+  int64_t ldin, ldout;  // leading dimensions
+  const double* lin;    // child eigenvalues D = [D1; D2] (m), each half ascending
+  double* lout;         // output eigenvalues (m)
+  const double* zgiven; // merge(): caller's z (m); stedc: nullptr (z gathered from qin)
+  const double* ecoup;  // stedc: the off-diagonal entry b_k coupling the halves; merge(): nullptr
+  double rho;           // merge(): coupling rho >= 0 (stedc: taken from *ecoup)
+  double zsign;         // merge(): 1 (stedc: sign of *ecoup)
+  int32_t m, n1;        // merge size and size of the first half
+  int64_t s_off;        // offset of this merge's m-long slot in the n-long scratch arrays
+  int64_t u_off;        // offset of this merge's m*m slot in the Uhat arena
+  int32_t id;           // row in the counters table
+  int32_t hss_min_k;    // HSS update for this merge when K >= hss_min_k (0: never)
+};
+
+// One leaf solve (one wavefront).
+struct LeafArgs {
+  const double* d;     // diagonal at the leaf's first row
+  const double* e;     // off-diagonal at the leaf's first row (e[-1] valid if coupled left)
+  double* q;           // eigenvector block origin
+  int64_t ldq;
+  double* lam;         // eigenvalue output
+  int32_t s;           // rows
+  int32_t couple;      // bit 0: coupled to the left, bit 1: coupled to the right
+};
+
+// One matrix for the eigenvector sign pass.
+struct CanonDesc {
+  double* q;
+  int64_t ld;
+  int32_t n;
+  int32_t pad;
+};
+
+// Scratch arrays (device pointers into the caller's workspace).  Unless noted
+// each is n_total long and merge i uses [s_off, s_off + m).
+struct Scratch {
+  double* dv;      // poles sorted ascending (modified in place by rotations)
+  double* zv;      // z in sorted order (normalised)
+  int32_t* col;    // merge column of sorted pole
+  int32_t* part;   // 1: rows of Q1 only, 3: rows of Q2 only, 2: both
+  int32_t* flag;   // 0 survivor, 1 type-1, 2 type-2
+  int32_t* surv;   // sorted indices of the type-1 survivors
+  double* ds;      // final survivors: pole
+  double* zs;      //                  z
+  int32_t* grp;    //                  row of Uhat in Gu's grouped order
+  int32_t* coltop; // GEMM column list for the Q1 rows (types 1, 2)
+  int32_t* colbot; // GEMM column list for the Q2 rows (types 2, 3)
+  int32_t* rcolp;  // rotation records: column p
+  int32_t* rcolj;  //                   column j
+  double* rc;      //                   cosine
+  double* rs;      //                   sine
+  int32_t* rpart;  //                   part of p (low byte) and j (next byte) before the rotation
+  int32_t* chain;  // first record of each rotation chain
+  double* dfv1;    // type-1 deflated: value (ascending)
+  int32_t* dfc1;   //                  column
+  int32_t* dfp1;   //                  part
+  double* dfv2;    // type-2 deflated: value
+  int32_t* dfc2;   //                  column
+  int32_t* dfp2;   //                  part
+  int32_t* org;    // secular root: origin pole
+  double* tau;     //                offset
+  double* dorg;    //                origin pole value d[org]
+  double* zhat;    // Loewner z
+  double* cnorm;   // 1 / column norm of Uhat
+  int32_t* dest;   // output column of root j (K), then of deflated items
+  int32_t* destd1; // output column of type-1 deflated item
+  int32_t* destd2; // output column of type-2 deflated item
+  int32_t* grpsrc; // survivor that fills grouped row g of Uhat
+  int32_t* csort;  // input column of survivor k (pole order)
+  int32_t* psort;  // part of survivor k
+  double* mparam;  // per merge (4 doubles): normalised rho, deflation tolerance
+  double* uhat;    // Uhat arena
+  int32_t* counters;
+  int32_t* status;
+};
+
+// Block map: launch of `total` blocks split over merges by prefix pfx[0..nm].
+struct BlockMap {
+  const MergeDesc* descs;
+  const int32_t* pfx;
+  int32_t nm;
+};
+
+__device__ inline int find_merge(const BlockMap& bm, int b) {
+  int lo = 0, hi = bm.nm - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (bm.pfx[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ inline void set_status(int32_t* status, int code) {
+  // First error wins; written with a vector atomic.
+  atomicCAS(status, 0, code);
+}
+
+// Kernel launchers (defined in the .hip files).
+void launch_leaf_ql(const LeafArgs* leaves, int nleaves, int32_t* status, hipStream_t s);
+
+// Block maps of one merge level (device prefix arrays, nm + 1 entries each).
+enum MapKind { MAP_ROOTS64 = 0, MAP_ROWS256, MAP_ROT, MAP_UWRITE, MAP_GEMM, MAP_COPY, MAP_COUNT };
+struct LevelMaps {
+  const int32_t* pfx[MAP_COUNT];
+  int32_t total[MAP_COUNT];
+};
+int map_blocks(int kind, int m, int n1);
+
+void launch_merge_level(const MergeDesc* descs, int nm, const LevelMaps& maps, const Scratch& S,
+                        int gemm_mode, hipStream_t s);
+void launch_secular_standalone(int64_t K, const double* d, const double* z, double rho, int32_t* org,
+                               double* tau, int32_t* status, hipStream_t s);
+
+}  // namespace phdc

@@ -1,0 +1,61 @@
+// Small utility kernels: status reset and the eigenvector sign convention.
+#include "phdc_internal.h"
+
+namespace phdc {
+
+
+// Zero the 256-byte status block with a kernel (not a memset node), so the
+// call sequence stays safe to capture in a HIP graph.
+__global__ void k_clear_status(int32_t* status) { status[threadIdx.x] = 0; }
+
+void launch_clear_status(int32_t* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, s, status);
+}
+
+// Eigenvectors are defined up to sign; this fixes it: in every column the entry
+// of largest magnitude (lowest row on ties) is made positive.  One block per
+// column, columns of all matrices of a batch in one launch.
+__global__ void __launch_bounds__(256) k_canonical_sign(const CanonDesc* __restrict__ descs,
+                                                       const int32_t* __restrict__ pfx, int nmat) {
+  __shared__ double sv[4];
+  __shared__ int si[4];
+  const int b = blockIdx.x;
+  int lo = 0, hi = nmat - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (pfx[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  const CanonDesc D = descs[lo];
+  const int col = b - pfx[lo];
+  double* q = D.q + (int64_t)col * D.ld;
+  double best = -1.0;
+  int bi = 0x7fffffff;
+  for (int r = threadIdx.x; r < D.n; r += 256) {
+    double a = fabs(q[r]);
+    if (a > best) { best = a; bi = r; }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    double ob = __shfl_xor(best, o, 64);
+    int oi = __shfl_xor(bi, o, 64);
+    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) { sv[w] = best; si[w] = bi; }
+  __syncthreads();
+  best = sv[0];
+  bi = si[0];
+  for (int i = 1; i < 4; ++i)
+    if (sv[i] > best || (sv[i] == best && si[i] < bi)) { best = sv[i]; bi = si[i]; }
+  if (bi >= D.n) return;
+  if (q[bi] < 0.0) {
+    __syncthreads();
+    for (int r = threadIdx.x; r < D.n; r += 256) q[r] = -q[r];
+  }
+}
+
+void launch_canonical_sign(const void* descs, const int32_t* pfx, int nmat, int total, hipStream_t s) {
+  if (total <= 0) return;
+  hipLaunchKernelGGL(k_canonical_sign, dim3(total), dim3(256), 0, s, (const CanonDesc*)descs, pfx, nmat);
+}
+
+}  // namespace phdc

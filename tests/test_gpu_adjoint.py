@@ -1,0 +1,161 @@
+"""Adjoint (gradients on d, e) through the C-ABI and the autograd wrapper, on the GPU.
+
+Checks: the library's backward against the oracle's adjoint on the same
+eigenpairs (elementwise), against the plain formula evaluated from the oracle's
+eigenpairs at full size, and against central finite differences of the solver
+itself (h = 1e-6; normwise relative error, see the reading of the
+differentiation workload).
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from checks import canon
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1612_07526_amd as P
+    P.load()
+    return P
+
+
+def _colstore(Q):
+    """column-major storage of square matrices (B, n, n) -> contiguous (B, n, n) with [b, j, i] = Q_b(i, j)."""
+    return torch.as_tensor(np.ascontiguousarray(np.transpose(Q, (0, 2, 1))), device="cuda")
+
+
+@pytest.mark.parametrize("n,batch", [(2, 1), (37, 2), (130, 3), (300, 1)])
+def test_backward_vs_oracle(P, orc, n, batch):
+    g = np.random.default_rng(n)
+    lam = np.zeros((batch, n))
+    Q = np.zeros((batch, n, n))
+    for b in range(batch):
+        d, e = W.ramp(n, seed=b)
+        lam[b], Q[b], _ = orc.stedc(d, e)
+    lbar = g.standard_normal((batch, n))
+    Qbar = g.standard_normal((batch, n, n))
+    db, eb = P.stedc_backward(torch.tensor(lam.reshape(-1), device="cuda"), _colstore(Q),
+                              torch.tensor(lbar.reshape(-1), device="cuda"), _colstore(Qbar), n, batch)
+    db, eb = db.cpu().numpy(), eb.cpu().numpy()
+    for b in range(batch):
+        dr, er = orc.adjoint(lam[b], Q[b], lbar[b], Qbar[b])
+        scale = max(np.abs(dr).max(), np.abs(er).max() if er.size else 0.0)
+        assert np.abs(db[b] - dr).max() <= 1e-11 * scale
+        if n > 1:
+            assert np.abs(eb[b] - er).max() <= 1e-11 * scale
+
+
+def test_backward_eigenvalue_only(P, orc):
+    n = 64
+    d, e = W.ramp(n, seed=3)
+    lam, Q, _ = orc.stedc(d, e)
+    w = np.random.default_rng(0).standard_normal(n)
+    db, eb = P.stedc_backward(torch.tensor(lam, device="cuda"), _colstore(Q[None]), torch.tensor(w, device="cuda"),
+                              None, n, 1)
+    assert np.allclose(db.cpu().numpy()[0], (Q ** 2) @ w, atol=1e-13)
+    assert np.allclose(eb.cpu().numpy()[0], 2 * (Q[:-1] * Q[1:]) @ w, atol=1e-13)
+
+
+def _loss(P, d, e, w, G):
+    lam, Q = P.eigh_tridiagonal(d, e)
+    return (w * lam).sum() + (G * Q).sum()
+
+
+def test_autograd_vs_fd_small(P):
+    n = 40
+    g = np.random.default_rng(1)
+    d0, e0 = W.ramp(n, seed=2)
+    w = torch.tensor(g.standard_normal(n), device="cuda")
+    G = torch.tensor(g.standard_normal((n, n)), device="cuda")
+    d = torch.tensor(d0, device="cuda", requires_grad=True)
+    e = torch.tensor(e0, device="cuda", requires_grad=True)
+    L = _loss(P, d, e, w, G)
+    L.backward()
+    gd, ge = d.grad.cpu().numpy(), e.grad.cpu().numpy()
+    h = 1e-6
+
+    def Lnp(dd, ee):
+        lam, V = np.linalg.eigh(np.diag(dd) + np.diag(ee, 1) + np.diag(ee, -1))
+        return float(w.cpu().numpy() @ lam + np.sum(G.cpu().numpy() * canon(V)))
+    fd_d = np.array([(Lnp(d0 + h * np.eye(n)[i], e0) - Lnp(d0 - h * np.eye(n)[i], e0)) / (2 * h) for i in range(n)])
+    fd_e = np.array([(Lnp(d0, e0 + h * np.eye(n - 1)[i]) - Lnp(d0, e0 - h * np.eye(n - 1)[i])) / (2 * h)
+                     for i in range(n - 1)])
+    g_all = np.concatenate([gd, ge])
+    fd = np.concatenate([fd_d, fd_e])
+    assert np.abs(g_all - fd).max() <= 1e-6 * np.abs(fd).max()
+
+
+@pytest.mark.parametrize("batch,n,ndir", [(4, 512, 4), (64, 4096, 4)])
+def test_autograd_batched_vs_solver_fd(P, batch, n, ndir):
+    # The differentiation workload: ramp matrices, loss = sum_k w_k lambda_k + <G, Q>,
+    # central differences of the GPU solver itself along random unit directions in (d, e).
+    d0, e0, w0, G0 = W.ramp_batch(batch, n, seed=0) if n <= 1024 else _ramp_big(batch, n)
+    dev = "cuda"
+    w = torch.tensor(w0, device=dev)
+    G = torch.tensor(G0, device=dev) if G0 is not None else torch.randn(batch, n, n, dtype=torch.float64,
+                                                                         device=dev, generator=_gen())
+    d = torch.tensor(d0, device=dev, requires_grad=True)
+    e = torch.tensor(e0, device=dev, requires_grad=True)
+    L = _loss(P, d, e, w, G)
+    L.backward()
+    gd, ge = d.grad.detach(), e.grad.detach()
+    g = torch.Generator(device=dev).manual_seed(7)
+    h = 1e-6
+    with torch.no_grad():
+        for k in range(ndir):
+            vd = torch.randn(batch, n, dtype=torch.float64, device=dev, generator=g)
+            ve = torch.randn(batch, n - 1, dtype=torch.float64, device=dev, generator=g)
+            nv = torch.sqrt((vd ** 2).sum() + (ve ** 2).sum())
+            vd, ve = vd / nv, ve / nv
+            Lp = _loss(P, d.detach() + h * vd, e.detach() + h * ve, w, G)
+            Lm = _loss(P, d.detach() - h * vd, e.detach() - h * ve, w, G)
+            fd = float((Lp - Lm) / (2 * h))
+            an = float((gd * vd).sum() + (ge * ve).sum())
+            # FD truncation and rounding: |L| u / h ~ 1e-8 relative, far below the 1e-6 bound
+            assert abs(an - fd) <= 1e-6 * max(abs(fd), 1.0) + 1e-6 * float(torch.sqrt((gd ** 2).sum() + (ge ** 2).sum())), \
+                (k, an, fd)
+
+
+def _gen():
+    return torch.Generator(device="cuda").manual_seed(11)
+
+
+def _ramp_big(batch, n):
+    g = np.random.default_rng(0)
+    d = 4.0 * np.arange(1, n + 1, dtype=np.float64)[None, :] / n + g.uniform(-0.01, 0.01, (batch, n))
+    e = g.uniform(0.1, 0.5, (batch, n - 1))
+    w = g.standard_normal((batch, n))
+    return d, e, w, None
+
+
+def test_backward_full_size_vs_formula_from_oracle(P, orc):
+    # one matrix of the differentiation workload (n = 4096): the library's gradient for the
+    # library's eigenpairs vs the plain formula (numpy products) on the oracle's eigenpairs
+    n = 4096
+    g = np.random.default_rng(5)
+    d, e = W.ramp(n, seed=5)
+    lr, Qr, _ = orc.stedc(d, e)
+    Qr = canon(Qr)
+    w = g.standard_normal(n)
+    G = g.standard_normal((n, n))
+    M = Qr.T @ G
+    F = lr[None, :] - lr[:, None]
+    np.fill_diagonal(F, 1.0)
+    Mp = M / F
+    np.fill_diagonal(Mp, w)
+    Wm = Qr @ Mp
+    dref = np.sum(Wm * Qr, axis=1)
+    eref = np.sum(Wm[:-1] * Qr[1:], axis=1) + np.sum(Wm[1:] * Qr[:-1], axis=1)
+    dt = torch.tensor(d, device="cuda", requires_grad=True)
+    et = torch.tensor(e, device="cuda", requires_grad=True)
+    L = _loss(P, dt, et, torch.tensor(w, device="cuda"), torch.tensor(G, device="cuda"))
+    L.backward()
+    gd, ge = dt.grad.cpu().numpy(), et.grad.cpu().numpy()
+    scale = max(np.abs(dref).max(), np.abs(eref).max())
+    # the two eigen-decompositions agree to ~1e-13; gradients amplify by 1/gap (min gap ~ 3e-7)
+    assert np.abs(gd - dref).max() <= 1e-5 * scale
+    assert np.abs(ge - eref).max() <= 1e-5 * scale

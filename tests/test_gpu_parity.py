@@ -1,0 +1,264 @@
+"""Parity of the HIP path (through the C-ABI) with the CPU oracle, on the GPU.
+
+Tolerances (fixed by the target of the build; relative to ||T|| = max |lambda|):
+  max |lambda - lambda_ref|      <= 1e-13 ||T||
+  ||Q^T Q - I||_max              <= 1e-12
+  ||T Q - Q Lambda||_F/(n ||T||) <= 1e-13
+Eigenvector columns are compared entry by entry only where the eigenvalue is
+separated from its neighbours (an eigenvector is determined up to sign, and
+only to about u ||T|| / gap); signs are aligned to the oracle's first.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from checks import align, isolated_columns, orth, residual, toeplitz_121_exact, tri_dense
+
+pytestmark = pytest.mark.gpu
+
+LAM_TOL = 1e-13
+ORTH_TOL = 1e-12
+RES_TOL = 1e-13
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1612_07526_amd as P
+    P.load()
+    assert torch.cuda.is_available()
+    return P
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _check_eig(d, e, lam, Q, lref=None, Qref=None, vec_tol=1e-9):
+    d = np.asarray(d, dtype=np.float64)
+    e = np.asarray(e, dtype=np.float64)
+    nrm = max(np.abs(lam).max(), 1e-300) if lam.size else 1.0
+    assert np.all(np.diff(lam) >= 0)
+    if lref is not None:
+        err = np.abs(lam - lref).max() if lam.size else 0.0
+        assert err <= LAM_TOL * nrm, f"eigenvalue error {err:.3e} > {LAM_TOL * nrm:.3e}"
+    assert orth(Q) <= ORTH_TOL
+    assert residual(d, e, lam, Q) <= RES_TOL
+    if Qref is not None and lam.size:
+        iso = isolated_columns(lref, 1e-3 * nrm)
+        if iso.any():
+            diff = np.abs(align(Q, Qref)[:, iso] - Qref[:, iso]).max()
+            assert diff <= vec_tol, f"eigenvector difference {diff:.3e}"
+
+
+# ---------------------------------------------------------------- secular roots
+
+
+@pytest.mark.parametrize("K,seed", [(1, 0), (2, 1), (17, 2), (300, 3), (2049, 4)])
+def test_secular_parity(P, orc, K, seed):
+    g = np.random.default_rng(seed)
+    d = np.sort(g.standard_normal(K))
+    z = g.standard_normal(K)
+    z /= np.linalg.norm(z)
+    rho = 0.7
+    o_ref, t_ref = orc.secular(d, z, rho)
+    org, tau = P.secular(d, z, rho)
+    org, tau = _np(org), _np(tau)
+    lam = d[org] + tau
+    lref = d[o_ref] + t_ref
+    scale = np.abs(d).max() + rho
+    assert np.abs(lam - lref).max() <= 1e-14 * scale
+    # distance to the origin pole has full relative accuracy where both sides chose the same origin
+    same = org == o_ref
+    assert same.mean() > 0.99
+    assert np.all(np.abs(tau[same] - t_ref[same]) <= 1e-13 * np.abs(t_ref[same]) + 1e-300)
+
+
+def test_secular_fig3_poles(P, orc):
+    D, z, rho, _, _ = W.fig3_merge(4096, seed=1, with_q=False)
+    o_ref, t_ref = orc.secular(D, z, rho)
+    org, tau = P.secular(D, z, rho)
+    lam = D[_np(org)] + _np(tau)
+    assert np.abs(lam - (D[o_ref] + t_ref)).max() <= 1e-14 * 2
+
+
+# ---------------------------------------------------------------- merge
+
+
+MERGE_CASES = [
+    (1, 1, 0, 0, 0), (3, 2, 0, 0, 1), (16, 16, 0, 0, 2), (31, 33, 4, 0, 3), (64, 64, 0, 9, 4),
+    (127, 129, 20, 20, 5), (128, 128, 0, 0, 6), (200, 57, 7, 0, 7), (300, 513, 0, 0, 8), (700, 650, 50, 40, 9),
+]
+
+
+@pytest.mark.parametrize("n1,n2,dup,tiny,seed", MERGE_CASES)
+def test_merge_parity(P, orc, n1, n2, dup, tiny, seed):
+    D, z, rho, Q1, Q2 = W.random_merge(n1, n2, seed=seed, dup=dup, tiny=tiny)
+    lref, Qref, st_ref = orc.merge(D, z, rho, Q1, Q2)
+    lam, Q, work = P.merge(D, z, rho, torch.tensor(Q1), torch.tensor(Q2), return_work=True)
+    st = P.merge_stats(work)
+    lam, Q = _np(lam), _np(Q)
+    m = n1 + n2
+    Qb = np.zeros((m, m))
+    Qb[:n1, :n1] = Q1
+    Qb[n1:, n1:] = Q2
+    A = Qb @ (np.diag(D) + rho * np.outer(z, z)) @ Qb.T
+    nrm = np.abs(lref).max()
+    assert np.abs(lam - lref).max() <= LAM_TOL * nrm
+    assert orth(Q) <= ORTH_TOL
+    assert np.linalg.norm(A @ Q - Q * lam) / (m * nrm) <= RES_TOL
+    iso = isolated_columns(lref, 1e-3 * nrm)
+    assert np.abs(align(Q, Qref)[:, iso] - Qref[:, iso]).max() <= 1e-9
+    # deflation decisions are integer results: identical to the oracle's
+    assert list(st[:6]) == list(st_ref[:6])
+
+
+def test_merge_fig3(P, orc):
+    # the rank-one merge of Sec. 2.2 (poles i/N, rho = 1, random unit z): no deflation
+    D, z, rho, Q1, Q2 = W.fig3_merge(1000, seed=3)
+    lref, Qref, st_ref = orc.merge(D, z, rho, Q1, Q2)
+    lam, Q, work = P.merge(D, z, rho, torch.tensor(Q1), torch.tensor(Q2), return_work=True)
+    lam, Q = _np(lam), _np(Q)
+    assert P.merge_stats(work)[0] == 1000 == st_ref[0]
+    assert np.abs(lam - lref).max() <= LAM_TOL * np.abs(lref).max()
+    assert orth(Q) <= ORTH_TOL
+    assert np.abs(align(Q, Qref) - Qref).max() <= 1e-9
+
+
+def test_merge_all_deflated(P):
+    g = np.random.default_rng(0)
+    D = np.concatenate([np.sort(g.standard_normal(40)), np.sort(g.standard_normal(30))])
+    Q1 = W.random_orthogonal(40, g)
+    Q2 = W.random_orthogonal(30, g)
+    lam, Q, work = P.merge(D, g.standard_normal(70), 0.0, torch.tensor(Q1), torch.tensor(Q2), return_work=True)
+    assert P.merge_stats(work)[0] == 0
+    assert np.array_equal(_np(lam), np.sort(D))
+    assert orth(_np(Q)) <= 1e-15
+
+
+def test_merge_unsorted_reports_status(P):
+    g = np.random.default_rng(1)
+    D = g.standard_normal(20)  # not sorted within the halves
+    Q1 = W.random_orthogonal(10, g)
+    Q2 = W.random_orthogonal(10, g)
+    lam, Q, work = P.merge(D, g.standard_normal(20), 1.0, torch.tensor(Q1), torch.tensor(Q2), check=False,
+                           return_work=True)
+    assert P.status(work) == 3
+
+
+# ---------------------------------------------------------------- whole solve
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 31, 32, 33, 64, 65, 100, 257, 1000])
+@pytest.mark.parametrize("off", [1.0, -1.0])
+def test_stedc_toeplitz_closed_form(P, n, off):
+    d, e = W.toeplitz_121(n, off)
+    lam, Q = P.stedc(d, e)
+    lr, Vr = toeplitz_121_exact(n, off)
+    _check_eig(d, e, _np(lam), _np(Q), lr, Vr)
+
+
+def test_stedc_toeplitz_2048_vs_oracle(P, orc):
+    # 1-2-1 Toeplitz, n = 2048, leaf 32: every merge deflates exactly half its poles by rotation
+    d, e = W.toeplitz_121(2048, -1.0)
+    lref, Qref, st_ref = orc.stedc(d, e, leaf=32)
+    lam, Q, work = P.stedc(d, e, return_work=True)
+    assert list(P.merge_stats(work)[:6]) == list(st_ref[:6]) == [1024, 0, 1024, 0, 0, 1024]
+    lr, Vr = toeplitz_121_exact(2048, -1.0)
+    _check_eig(d, e, _np(lam), _np(Q), lr, Vr, vec_tol=1e-8)
+
+
+@pytest.mark.parametrize("gen,n,seed", [("uniform", 500, 0), ("normal_pos", 777, 1), ("normal", 1024, 2),
+                                        ("ramp", 600, 3), ("clement", 301, 0), ("hermite", 200, 0)])
+def test_stedc_vs_oracle(P, orc, gen, n, seed):
+    d, e = W.tridiag(gen, n, seed)
+    lref, Qref, _ = orc.stedc(d, e)
+    lam, Q = P.stedc(d, e)
+    _check_eig(d, e, _np(lam), _np(Q), lref, Qref)
+
+
+@pytest.mark.parametrize("leaf", [2, 7, 16, 64])
+def test_stedc_leaf_sizes(P, orc, leaf):
+    d, e = W.normal(300, 5)
+    lref, Qref, _ = orc.stedc(d, e, leaf=leaf)
+    lam, Q = P.stedc(d, e, o=P.opts(leaf_size=leaf))
+    _check_eig(d, e, _np(lam), _np(Q), lref, Qref)
+
+
+def test_stedc_decoupled(P, orc):
+    d, e = W.normal(200, 6)
+    e[99] = 0.0
+    e[49] = 0.0
+    lref, _, _ = orc.stedc(d, e)
+    lam, Q = P.stedc(d, e)
+    _check_eig(d, e, _np(lam), _np(Q), lref)
+
+
+def test_stedc_uniform_16384_full_size(P, orc):
+    # the headline workload: n = 16384, d, e ~ U[-1, 1]; eigenvalues vs the oracle,
+    # orthogonality and residual of the full Q on the GPU, sampled columns vs the oracle
+    n = 16384
+    d, e = W.uniform(n, 0)
+    lref, Qref, st_ref = orc.stedc(d, e)
+    lam, Q, work = P.stedc(d, e, return_work=True)
+    assert list(P.merge_stats(work)[:6]) == list(st_ref[:6])
+    lam_h = _np(lam)
+    nrm = np.abs(lref).max()
+    assert np.abs(lam_h - lref).max() <= LAM_TOL * nrm
+    Qd = Q.contiguous()
+    I = torch.eye(n, dtype=torch.float64, device=Qd.device)
+    assert (Qd.T @ Qd - I).abs().max().item() <= ORTH_TOL
+    del I
+    dt = torch.tensor(d, device=Qd.device)
+    et = torch.tensor(e, device=Qd.device)
+    R = dt[:, None] * Qd - Qd * lam[None, :]
+    R[:-1] += et[:, None] * Qd[1:]
+    R[1:] += et[:, None] * Qd[:-1]
+    assert (torch.linalg.norm(R) / (n * nrm)).item() <= RES_TOL
+    del R
+    # eigenvector entries are determined to about u ||T|| / gap: compare columns whose
+    # eigenvalue is separated from both neighbours by at least 1e-5 ||T||
+    iso = np.flatnonzero(isolated_columns(lref, 1e-5 * nrm))
+    cols = np.random.default_rng(0).choice(iso, min(64, iso.size), replace=False)
+    assert cols.size >= 32
+    Qs = _np(Q[:, torch.tensor(cols, device=Q.device)])
+    assert np.abs(align(Qs, Qref[:, cols]) - Qref[:, cols]).max() <= 1e-9
+
+
+def test_stedc_canonical_sign(P):
+    d, e = W.normal(150, 7)
+    lam, Q = P.stedc(d, e, o=P.opts(canonical_sign=1))
+    Qh = _np(Q)
+    idx = np.argmax(np.abs(Qh), axis=0)
+    assert np.all(Qh[idx, np.arange(150)] > 0)
+
+
+def test_stedc_deterministic(P):
+    d, e = W.uniform(3000, 9)
+    l1, Q1 = P.stedc(d, e)
+    l2, Q2 = P.stedc(d, e)
+    assert torch.equal(l1, l2) and torch.equal(Q1, Q2)
+
+
+def test_stedc_empty(P):
+    lam, Q = P.stedc(np.zeros(0), np.zeros(0))
+    assert lam.numel() == 0
+
+
+# ---------------------------------------------------------------- batched
+
+
+def test_batched_vs_oracle(P, orc):
+    sizes = [1, 2, 33, 64, 100, 0, 257, 31, 500, 3]
+    g = np.random.default_rng(3)
+    ds = [g.standard_normal(n) for n in sizes]
+    es = [g.standard_normal(max(n - 1, 0)) for n in sizes]
+    lam, Q, off, qoff = P.stedc_batched(sizes, np.concatenate(ds), np.concatenate(es))
+    lam, Q = _np(lam), _np(Q)
+    for b, n in enumerate(sizes):
+        if n == 0:
+            continue
+        lb = lam[off[b]:off[b] + n]
+        Qb = Q[qoff[b]:qoff[b] + n * n].reshape(n, n).T
+        lref, Qref, _ = orc.stedc(ds[b], es[b])
+        _check_eig(ds[b], es[b], lb, Qb, lref, Qref)
