@@ -1,21 +1,22 @@
 #!/usr/bin/env python3
-"""Benchmark: n = 16384 tridiagonal eigensolve on one MI355X.
+"""Benchmark: n = 16384 tridiagonal eigensolve on one MI355X, plain vs chosen form.
 
-Workload (value): d, e iid Uniform[-1, 1] (seed 0), n = 16384, leaf 32.  One
-step = one complete divide-and-conquer solve (leaves, every merge level,
-eigenvalues and the full n x n eigenvector matrix) with inputs resident in HBM.
-The chosen form (HSS-compressed Uhat for merges with K >= 4096, FP64 MFMA
-otherwise) is timed for `value`; the plain FP64-MFMA form is timed beside it.
+value: d, e iid Uniform[-1, 1] (seed 0), n = 16384, leaf 32.  One step = one
+complete divide-and-conquer solve (leaves, every merge level, eigenvalues and
+the full n x n eigenvector matrix), inputs resident in HBM.  The chosen form
+(HSS-compressed Uhat for merges with K >= 4096, FP64 MFMA otherwise) is timed
+for `value`; the plain FP64-MFMA form is timed beside it.
 
-Also reported on the same JSON line:
-  roofline      -- the dominant kernel of the timed workload, measured live with
-                   HIP events on the launch stream (library profiling hooks);
-  merge_gemm    -- the merge update product on a large-K merge (the rank-one
-                   merge of Sec. 2.2 with poles i/N, N = 16384: K = N), TFLOP/s
-                   and fraction of the FP64 MFMA peak;
-  supplementary -- the Toeplitz-type matrix (diagonal 2, off-diagonal 1) at
-                   n = 16383, where no pole deflates at the top merge;
-  cpu_baseline  -- the CPU oracle solving the same matrix on the host cores.
+Also on the same JSON line (each section can be skipped with --skip):
+  roofline     -- dominant kernel of the timed workload, HIP events on the launch stream
+  merge_gemm   -- the large-K rank-one merge of Sec. 2.2 (poles i/N, N = 16384, K = N):
+                  FP64-MFMA update TFLOP/s vs peak; HSS and split-precision update times
+  toeplitz     -- diagonal 2 / off-diagonal 1 at n = 16383 (no deflation at the top)
+  split        -- n = 32768, d ~ N(0,1), e ~ U[0.1,1]: split precision vs FP64 MFMA
+  batch        -- 4096 matrices of sizes U{32..1024}: graph-replayed batched launches vs
+                  one solve call per matrix
+  adjoint      -- batch 64 x n = 4096 ramp matrices: forward + backward
+  cpu_baseline -- the CPU oracle solving the headline matrix on the host cores
 """
 from __future__ import annotations
 
@@ -42,60 +43,62 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def timed(fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    sync()
+    return (time.perf_counter() - t0) / steps
+
+
 def merge_table(P, work):
     lib = P.load()
-    rows = ctypes.c_int64()
     lib.phdc_merge_table.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]
+    rows = ctypes.c_int64()
     lib.phdc_merge_table(ctypes.c_void_p(work.data_ptr()), 0, None, ctypes.byref(rows))
     n = rows.value
     buf = (ctypes.c_int32 * max(n * 10, 1))()
     lib.phdc_merge_table(ctypes.c_void_p(work.data_ptr()), n, buf, ctypes.byref(rows))
-    return np.frombuffer(buf, dtype=np.int32)[: n * 10].reshape(n, 10)
+    return np.frombuffer(buf, dtype=np.int32)[: n * 10].reshape(n, 10).copy()
 
 
 def algorithmic(table):
-    """Per-phase algorithmic work of one solve from the merge table.
+    """Algorithmic work of one solve (or merge) from its merge table.
 
-    gemm: 2 [n1 (k1+k2) + n2 (k2+k3)] K flops (Gu's grouped products, Eq. (6));
-    copy: deflated columns read and written, 2 * 8 m bytes each;
-    uhat_write: 8 K^2 bytes written;
-    rotate: each rotation reads and writes two m-long columns, 32 m bytes.
+    gemm_flops: 2 [n1 (k1+k2) + n2 (k2+k3)] K over merges on the FP64 path (Gu's
+                grouped products, Eq. (6));
+    copy_bytes: every deflated column read and written once, 16 m bytes;
+    uhat_write_bytes: 8 K^2 bytes per merge;
+    secular_flops: K^2 pole terms (1 reciprocal + 8 flops) per iteration, 5 iterations.
     """
-    m, n1, K, k1, k2, k3, nt1, nt2 = (table[:, i].astype(np.float64) for i in range(8))
+    m, n1, K, k1, k2, k3, nt1, nt2, path = (table[:, i].astype(np.float64) for i in range(9))
     n2 = m - n1
-    path = table[:, 8]
     plain = path == 0
     return {
         "gemm_flops": float(np.sum((2 * (n1 * (k1 + k2) + n2 * (k2 + k3)) * K)[plain])),
         "copy_bytes": float(np.sum((nt1 + nt2) * m * 16)),
         "uhat_write_bytes": float(np.sum(K * K * 8)),
-        "rotate_bytes": float(np.sum(nt2 * m * 32)),
     }
 
 
-def timed(fn, steps, warmup):
-    import torch
-    for _ in range(warmup):
-        fn()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        fn()
-    torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / steps
-
-
 def profile_phases(P, fn, reps=2):
-    import torch
     lib = P.load()
     lib.phdc_profile_enable.argtypes = [ctypes.c_int]
     lib.phdc_profile_read.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
-    torch.cuda.synchronize()
+    sync()
     lib.phdc_profile_read((ctypes.c_double * 32)(), (ctypes.c_int64 * 32)(), 32)
     lib.phdc_profile_enable(1)
     for _ in range(reps):
         fn()
-    torch.cuda.synchronize()
+    sync()
     lib.phdc_profile_enable(0)
     ms = (ctypes.c_double * 32)()
     cnt = (ctypes.c_int64 * 32)()
@@ -103,198 +106,335 @@ def profile_phases(P, fn, reps=2):
     return {PHASES[i]: (ms[i] / reps, cnt[i] // reps) for i in range(len(PHASES)) if cnt[i]}
 
 
+class Solver:
+    """Preallocated single-matrix solves through the C-ABI (no allocation in the timed loop)."""
+
+    def __init__(self, P, d, e, o):
+        import torch
+        self.P, self.o = P, o
+        self.lib = P.load()
+        self.d = torch.as_tensor(d, dtype=torch.float64, device="cuda")
+        self.e = torch.as_tensor(e, dtype=torch.float64, device="cuda")
+        self.n = self.d.numel()
+        self.lam = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        self.q = torch.empty((self.n, self.n), dtype=torch.float64, device="cuda")
+        nb = ctypes.c_size_t()
+        self.lib.phdc_stedc_workspace(self.n, ctypes.byref(o), ctypes.byref(nb))
+        self.work = P.workspace(nb.value, "cuda")
+
+    def __call__(self):
+        P = self.P
+        rc = self.lib.phdc_stedc(self.n, P._ptr(self.d), P._ptr(self.e), P._ptr(self.lam), P._ptr(self.q), self.n,
+                                 P._ptr(self.work), self.work.numel(), ctypes.byref(self.o), P._stream())
+        if rc != 0:
+            raise RuntimeError(f"phdc_stedc returned {rc}")
+
+    def accuracy(self):
+        import torch
+        Qd = self.q.t()
+        n = self.n
+        nrm = float(self.lam.abs().max())
+        G = Qd.T @ Qd
+        G.diagonal().sub_(1.0)
+        orth = float(G.abs().max())
+        del G
+        R = self.d[:, None] * Qd - Qd * self.lam[None, :]
+        R[:-1] += self.e[:, None] * Qd[1:]
+        R[1:] += self.e[:, None] * Qd[:-1]
+        res = float(torch.linalg.norm(R) / (n * nrm))
+        del R
+        return orth, res
+
+
+def sec_value(P, W, args, out):
+    n = 16384
+    d, e = W.uniform(n, seed=0)
+    chosen = P.GEMM_FP64 if "hss" in args.skip_paths else P.GEMM_HSS
+    ch = Solver(P, d, e, P.opts(gemm_mode=chosen))
+    log(f"[bench] value: warmup {args.warmup}, timing {args.steps} solves of uniform n={n} (chosen form)")
+    t_ch = timed(ch, args.steps, args.warmup)
+    st = P.status(ch.work)
+    if st != 0:
+        raise RuntimeError(f"device status {st}")
+    table = merge_table(P, ch.work)
+    orth, res = ch.accuracy()
+    log(f"[bench] chosen form {t_ch * 1e3:.3f} ms/solve; top merge K={table[-1, 2]}; orth {orth:.2e} res {res:.2e}")
+    lam_gpu = ch.lam.cpu().numpy()
+    del ch
+    pl = Solver(P, d, e, P.opts(gemm_mode=P.GEMM_FP64))
+    t_pl = timed(pl, args.steps, 1)
+    log(f"[bench] plain FP64 {t_pl * 1e3:.3f} ms/solve")
+    phases = profile_phases(P, pl)
+    log("[bench] phases (ms/solve): " + ", ".join(f"{k}={v[0]:.3f}" for k, v in phases.items()))
+    alg = algorithmic(merge_table(P, pl.work))
+    del pl
+    out.update(t_ch=t_ch, t_pl=t_pl, orth=orth, res=res, phases=phases, alg=alg, table=table, lam=lam_gpu, d=d, e=e)
+
+
+def sec_merge_gemm(P, W, args):
+    import torch
+    N = 16384
+    D, z, rho, Q1, Q2 = W.fig3_merge(N, seed=0, with_q=True)
+    lib = P.load()
+    Dt = torch.tensor(D, device="cuda")
+    zt = torch.tensor(z, device="cuda")
+    Q1c, ld1 = P._colmajor(torch.tensor(Q1, device="cuda"))
+    Q2c, ld2 = P._colmajor(torch.tensor(Q2, device="cuda"))
+    del Q1, Q2
+    res = {"workload": f"rank-one merge of Sec. 2.2: poles i/N, rho=1, random unit z, N={N}"}
+    for name, o in (("fp64", P.opts(gemm_mode=P.GEMM_FP64)),
+                    ("hss", P.opts(gemm_mode=P.GEMM_HSS, hss_min_K=4096)),
+                    ("split", P.opts(gemm_mode=P.GEMM_SPLIT))):
+        if name in args.skip_paths:
+            continue
+        lam = torch.empty(N, dtype=torch.float64, device="cuda")
+        qm = torch.empty((N, N), dtype=torch.float64, device="cuda")
+        nb = ctypes.c_size_t()
+        lib.phdc_merge_workspace(N // 2, N - N // 2, ctypes.byref(o), ctypes.byref(nb))
+        wm = P.workspace(nb.value, "cuda")
+
+        def mg():
+            rc = lib.phdc_merge(N // 2, N - N // 2, P._ptr(Dt), P._ptr(zt), rho, P._ptr(Q1c), ld1, P._ptr(Q2c), ld2,
+                                P._ptr(lam), P._ptr(qm), N, P._ptr(wm), wm.numel(), ctypes.byref(o), P._stream())
+            if rc != 0:
+                raise RuntimeError(f"phdc_merge returned {rc}")
+        log(f"[bench] merge N={N} via {name}")
+        t = timed(mg, 2, 1)
+        ph = profile_phases(P, mg, reps=1)
+        tab = merge_table(P, wm)
+        G = qm.t()
+        Gm = G.T @ G
+        Gm.diagonal().sub_(1.0)
+        orth = float(Gm.abs().max())
+        del Gm
+        entry = {"merge_s": round(t, 5), "orth": orth, "K": int(tab[0, 2]), "path": int(tab[0, 8]),
+                 "hss_rank": int(tab[0, 9])}
+        if name == "fp64":
+            alg = algorithmic(tab)
+            gemm_ms = ph["gemm"][0]
+            tf = alg["gemm_flops"] / (gemm_ms * 1e-3) / 1e12
+            entry.update(gemm_ms=round(gemm_ms, 3), gemm_tflops=round(tf, 2),
+                         gemm_frac_fp64_peak=round(tf / FP64_PEAK_TFLOPS, 4))
+        if name == "split":
+            sg = ph.get("split_gemm", (0.0, 0))[0]
+            flops_exec = 2.0 * N / 2 * N / 2 * N * 2 * (7 * 8 / 2)  # both halves, 28 slice pairs
+            entry.update(update_ms=round(sg, 3), bf16_tflops_executed=round(flops_exec / (sg * 1e-3) / 1e12, 1))
+        if name == "hss":
+            entry.update(hss_ms={k: round(ph[k][0], 3) for k in ("hss_sample", "hss_compress", "hss_apply") if k in ph})
+        log(f"[bench]   {name}: {entry}")
+        res[name] = entry
+        del wm, qm
+        torch.cuda.empty_cache()
+    return res
+
+
+def sec_toeplitz(P, W, args):
+    import torch
+    ns = 16383
+    ds, es = W.toeplitz_121(ns, 1.0)
+    res = {"workload": f"toeplitz121_n{ns} (top merge K = n)"}
+    for name, o in (("fp64", P.opts(gemm_mode=P.GEMM_FP64)), ("hss", P.opts(gemm_mode=P.GEMM_HSS)),
+                    ("split", P.opts(gemm_mode=P.GEMM_SPLIT))):
+        if name in args.skip_paths:
+            continue
+        s = Solver(P, ds, es, o)
+        t = timed(s, 2, 1)
+        orth, rr = s.accuracy()
+        tab = merge_table(P, s.work)
+        ph = profile_phases(P, s, reps=1)
+        entry = {"solve_s": round(t, 5), "orth": orth, "residual": rr, "top_K": int(tab[-1, 2]),
+                 "top_path": int(tab[-1, 8]), "hss_rank": int(tab[-1, 9])}
+        if name == "fp64":
+            alg = algorithmic(tab)
+            tf = alg["gemm_flops"] / (ph["gemm"][0] * 1e-3) / 1e12
+            entry.update(gemm_tflops_all_levels=round(tf, 2), gemm_frac_fp64_peak=round(tf / FP64_PEAK_TFLOPS, 4))
+        log(f"[bench] toeplitz {name}: {entry}")
+        res[name] = entry
+        del s
+        torch.cuda.empty_cache()
+    return res
+
+
+def sec_split(P, W, args):
+    import torch
+    n = 32768
+    d, e = W.normal_pos(n, seed=0)
+    res = {"workload": f"normal_pos_n{n}: d~N(0,1), e~U[0.1,1]"}
+    for name, o in (("fp64", P.opts(gemm_mode=P.GEMM_FP64)), ("split", P.opts(gemm_mode=P.GEMM_SPLIT))):
+        s = Solver(P, d, e, o)
+        t = timed(s, 2, 1)
+        orth, rr = s.accuracy()
+        res[name] = {"solve_s": round(t, 5), "orth": orth, "residual": rr, "top_K": int(merge_table(P, s.work)[-1, 2])}
+        log(f"[bench] n=32768 {name}: {res[name]}")
+        del s
+        torch.cuda.empty_cache()
+    return res
+
+
+def sec_batch(P, W, args):
+    import torch
+    sizes = W.batch_sizes(4096, 32, 1024, seed=0).tolist()
+    ds, es = W.normal_batch(sizes, seed=0)
+    bs = P.BatchedSolver(sizes, P.opts())
+    bs.d[: sum(sizes)] = torch.tensor(np.concatenate(ds), device="cuda")
+    ecat = np.concatenate(es)
+    bs.e[: ecat.size] = torch.tensor(ecat, device="cuda")
+    bs.prepare()
+    bs.launch()
+    sync()
+    bs.capture()
+    t_graph = timed(bs.replay, 3, 1)
+    st = P.status(bs.work)
+    if st != 0:
+        raise RuntimeError(f"batched status {st}")
+    log(f"[bench] batch of {len(sizes)}: graph replay {t_graph * 1e3:.1f} ms")
+    # one solve call per matrix (each call plans, uploads and launches its own kernels)
+    lib = P.load()
+    o = P.opts()
+    nmax = max(sizes)
+    nb = ctypes.c_size_t()
+    lib.phdc_stedc_workspace(nmax, ctypes.byref(o), ctypes.byref(nb))
+    work = P.workspace(nb.value, "cuda")
+    lam = torch.empty(nmax, dtype=torch.float64, device="cuda")
+    Q = torch.empty(nmax * nmax, dtype=torch.float64, device="cuda")
+    dd = [torch.tensor(x, device="cuda") for x in ds]
+    ee = [torch.tensor(x if x.size else np.zeros(1), device="cuda") for x in es]
+
+    def per_matrix():
+        for b, n in enumerate(sizes):
+            rc = lib.phdc_stedc(n, P._ptr(dd[b]), P._ptr(ee[b]), P._ptr(lam), P._ptr(Q), n, P._ptr(work),
+                                work.numel(), ctypes.byref(o), P._stream())
+            if rc != 0:
+                raise RuntimeError(rc)
+    t_pm = timed(per_matrix, 1, 1)
+    log(f"[bench] batch: per-matrix calls {t_pm * 1e3:.1f} ms")
+    res = {"workload": "4096 tridiagonals, n_b ~ U{32..1024}, d,e ~ N(0,1)", "graph_s": round(t_graph, 5),
+           "per_matrix_s": round(t_pm, 5), "speedup": round(t_pm / t_graph, 2),
+           "matrices_per_s": round(len(sizes) / t_graph, 1)}
+    del bs, work
+    torch.cuda.empty_cache()
+    return res
+
+
+def sec_adjoint(P, W, args):
+    import torch
+    B, n = 64, 4096
+    g = np.random.default_rng(0)
+    d = 4.0 * np.arange(1, n + 1, dtype=np.float64)[None, :] / n + g.uniform(-0.01, 0.01, (B, n))
+    e = g.uniform(0.1, 0.5, (B, n - 1))
+    w = torch.tensor(g.standard_normal((B, n)), device="cuda")
+    G = torch.randn(B, n, n, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(0))
+    dt = torch.tensor(d, device="cuda", requires_grad=True)
+    et = torch.tensor(e, device="cuda", requires_grad=True)
+
+    def step():
+        dt.grad = None
+        et.grad = None
+        lam, Q = P.eigh_tridiagonal(dt, et)
+        L = (w * lam).sum() + (G * Q).sum()
+        L.backward()
+    t = timed(step, 2, 1)
+    ph = profile_phases(P, step, reps=1)
+    res = {"workload": f"batch {B} x n={n} ramp, loss sum w.lambda + <G,Q>", "fwd_bwd_s": round(t, 4),
+           "backward_flops": 2 * 2 * B * n ** 3}
+    log(f"[bench] adjoint: {res}")
+    del G
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-supp", action="store_true", help="skip the supplementary large-K measurements")
-    ap.add_argument("--only", default="", help="profiling aid: run only 'value', 'gemm' or 'supp'")
+    ap.add_argument("--skip", default="", help="comma list of sections: merge_gemm,toeplitz,split,batch,adjoint,cpu")
+    ap.add_argument("--skip-paths", default="", help="comma list of update paths to leave out: hss,split")
+    ap.add_argument("--only-value", action="store_true", help="time the headline solve only (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU sharding is a design, not an implementation", file=sys.stderr)
         sys.exit(2)
+    args.skip = set(x for x in args.skip.split(",") if x)
+    args.skip_paths = set(x for x in args.skip_paths.split(",") if x)
+    if args.only_value:
+        args.skip |= {"merge_gemm", "toeplitz", "split", "batch", "adjoint", "cpu"}
 
-    import torch
     import paper_1612_07526_amd as P
     import workloads as W
 
-    dev = torch.device("cuda:0")
-    n = 16384
-    d_np, e_np = W.uniform(n, seed=0)
-    d = torch.tensor(d_np, device=dev)
-    e = torch.tensor(e_np, device=dev)
-    lam = torch.empty(n, dtype=torch.float64, device=dev)
-    qbuf = torch.empty((n, n), dtype=torch.float64, device=dev)
-    lib = P.load()
-    o_hss = P.opts(gemm_mode=P.GEMM_HSS)
-    o_plain = P.opts(gemm_mode=P.GEMM_FP64)
-    nb = ctypes.c_size_t()
-    lib.phdc_stedc_workspace(n, ctypes.byref(o_hss), ctypes.byref(nb))
-    work = P.workspace(nb.value, dev)
+    v = {}
+    sec_value(P, W, args, v)
+    sections = {}
+    for name, fn in (("merge_gemm", sec_merge_gemm), ("toeplitz", sec_toeplitz), ("split", sec_split),
+                     ("batch", sec_batch), ("adjoint", sec_adjoint)):
+        if name in args.skip:
+            continue
+        try:
+            sections[name] = fn(P, W, args)
+        except Exception as ex:  # report and continue: one section must not hide the others
+            log(f"[bench] section {name} failed: {ex!r}")
+            sections[name] = {"error": repr(ex)}
 
-    def solve(o):
-        def f():
-            rc = lib.phdc_stedc(n, P._ptr(d), P._ptr(e), P._ptr(lam), P._ptr(qbuf), n, P._ptr(work), work.numel(),
-                                ctypes.byref(o), P._stream())
-            if rc != 0:
-                raise RuntimeError(f"phdc_stedc returned {rc}")
-        return f
-
-    result = {}
-    if args.only in ("", "value"):
-        log(f"[bench] warmup {args.warmup}, timing {args.steps} solves of uniform n={n} (chosen form)")
-        t_hss = timed(solve(o_hss), args.steps, args.warmup)
-        st = P.status(work)
-        if st != 0:
-            raise RuntimeError(f"device status {st}")
-        table = merge_table(P, work)
-        log(f"[bench] chosen form {t_hss * 1e3:.3f} ms/solve; top merge K={table[-1, 2]}")
-        t_plain = timed(solve(o_plain), args.steps, 1)
-        log(f"[bench] plain FP64 {t_plain * 1e3:.3f} ms/solve")
-        # accuracy of the timed solve
-        Qd = qbuf.t()
-        nrm = float(lam.abs().max())
-        orth = float((Qd.T @ Qd - torch.eye(n, dtype=torch.float64, device=dev)).abs().max())
-        R = d[:, None] * Qd - Qd * lam[None, :]
-        R[:-1] += e[:, None] * Qd[1:]
-        R[1:] += e[:, None] * Qd[:-1]
-        res = float(torch.linalg.norm(R) / (n * nrm))
-        del R
-        log(f"[bench] orthogonality {orth:.2e} residual {res:.2e}")
-        phases = profile_phases(P, solve(o_plain))
-        alg = algorithmic(table)
-        log("[bench] phases (ms/solve): " + ", ".join(f"{k}={v[0]:.3f}" for k, v in phases.items()))
-        result.update(t_hss=t_hss, t_plain=t_plain, orth=orth, res=res, phases=phases, alg=alg, table=table)
-
-    merge_gemm = None
-    if args.only in ("", "gemm") and not args.no_supp:
-        N = 16384
-        D, z, rho, Q1, Q2 = W.fig3_merge(N, seed=0, with_q=True)
-        Dt = torch.tensor(D, device=dev)
-        zt = torch.tensor(z, device=dev)
-        Q1c, ld1 = P._colmajor(torch.tensor(Q1, device=dev))
-        Q2c, ld2 = P._colmajor(torch.tensor(Q2, device=dev))
-        del Q1, Q2
-        lamm = torch.empty(N, dtype=torch.float64, device=dev)
-        qm = torch.empty((N, N), dtype=torch.float64, device=dev)
-        lib.phdc_merge_workspace(N // 2, N - N // 2, ctypes.byref(o_plain), ctypes.byref(nb))
-        wm = P.workspace(nb.value, dev)
-
-        def mg():
-            rc = lib.phdc_merge(N // 2, N - N // 2, P._ptr(Dt), P._ptr(zt), rho, P._ptr(Q1c), ld1, P._ptr(Q2c), ld2,
-                                P._ptr(lamm), P._ptr(qm), N, P._ptr(wm), wm.numel(), ctypes.byref(o_plain),
-                                P._stream())
-            if rc != 0:
-                raise RuntimeError(f"phdc_merge returned {rc}")
-        log(f"[bench] merge N={N} (poles i/N): warmup")
-        mg()
-        torch.cuda.synchronize()
-        ph = profile_phases(P, mg, reps=2)
-        tab = merge_table(P, wm)
-        alg = algorithmic(tab)
-        gemm_ms = ph["gemm"][0]
-        tf = alg["gemm_flops"] / (gemm_ms * 1e-3) / 1e12
-        merge_gemm = {"workload": f"rank-one merge, poles i/N, N={N}, K={int(tab[0, 2])}", "tflops": round(tf, 2),
-                      "frac_fp64_mfma_peak": round(tf / FP64_PEAK_TFLOPS, 4), "gemm_ms": round(gemm_ms, 3),
-                      "merge_ms": round(sum(v[0] for v in ph.values()), 3)}
-        log(f"[bench] merge GEMM {tf:.2f} TFLOP/s ({100 * tf / FP64_PEAK_TFLOPS:.1f}% of FP64 MFMA peak)")
-        del wm, qm, Q1c, Q2c
-        torch.cuda.empty_cache()
-
-    supp = None
-    if args.only in ("", "supp") and not args.no_supp:
-        ns = 16383
-        ds, es = W.toeplitz_121(ns, 1.0)
-        dts = torch.tensor(ds, device=dev)
-        ets = torch.tensor(es, device=dev)
-        lib.phdc_stedc_workspace(ns, ctypes.byref(o_hss), ctypes.byref(nb))
-        ws = P.workspace(nb.value, dev)
-        ls = torch.empty(ns, dtype=torch.float64, device=dev)
-        qs = torch.empty((ns, ns), dtype=torch.float64, device=dev)
-
-        def ss(o):
-            def f():
-                rc = lib.phdc_stedc(ns, P._ptr(dts), P._ptr(ets), P._ptr(ls), P._ptr(qs), ns, P._ptr(ws),
-                                    ws.numel(), ctypes.byref(o), P._stream())
-                if rc != 0:
-                    raise RuntimeError(f"phdc_stedc returned {rc}")
-            return f
-        log(f"[bench] Toeplitz-type n={ns}")
-        tp = timed(ss(o_plain), 2, 1)
-        th = timed(ss(o_hss), 2, 1)
-        ph = profile_phases(P, ss(o_plain), reps=1)
-        tab = merge_table(P, ws)
-        alg = algorithmic(tab)
-        tf = alg["gemm_flops"] / (ph["gemm"][0] * 1e-3) / 1e12
-        supp = {"workload": f"toeplitz121_n{ns}", "plain_s": round(tp, 5), "chosen_s": round(th, 5),
-                "top_K": int(tab[-1, 2]), "gemm_tflops_all_levels": round(tf, 2),
-                "gemm_frac_fp64_peak": round(tf / FP64_PEAK_TFLOPS, 4)}
-        log(f"[bench] toeplitz plain {tp * 1e3:.1f} ms, chosen {th * 1e3:.1f} ms, GEMM {tf:.1f} TF/s")
-        del ws, qs
-        torch.cuda.empty_cache()
-
-    if args.only not in ("", "value"):
-        return
-
-    # roofline of the dominant kernel class of the timed workload
-    phases, alg = result["phases"], result["alg"]
+    phases, alg = v["phases"], v["alg"]
     dom = max(phases.items(), key=lambda kv: kv[1][0])[0]
     ms_dom, cnt_dom = phases[dom]
     if dom == "gemm":
         roof = {"bound": "mfma", "achieved": alg["gemm_flops"] / (ms_dom * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s"}
-    else:
-        key = {"copy": "copy_bytes", "uhat_write": "uhat_write_bytes", "rotate": "rotate_bytes"}.get(dom)
-        byts = alg.get(key, 0.0) if key else 0.0
+    elif dom in ("copy", "uhat_write"):
+        byts = alg["copy_bytes" if dom == "copy" else "uhat_write_bytes"]
         roof = {"bound": "hbm", "achieved": byts / (ms_dom * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
-    roof["achieved"] = round(roof["achieved"], 3)
-    roof["frac"] = round(roof["achieved"] / roof["peak"], 5)
-    roof["traffic"] = None
-    roof["kernel"] = dom
-    roof["launches_per_step"] = int(cnt_dom)
-    roof["ms_per_step"] = round(ms_dom, 4)
+    else:
+        # latency-bound kernel classes: report the copy kernel's HBM rate alongside
+        roof = {"bound": "latency", "achieved": None, "peak": None, "unit": None}
+    if roof["achieved"] is not None:
+        roof["achieved"] = round(roof["achieved"], 2)
+        roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
+    else:
+        roof["frac"] = None
+    roof.update(traffic=None, kernel=dom, launches_per_step=int(cnt_dom), ms_per_step=round(ms_dom, 4))
+    if "copy" in phases:
+        roof["copy_kernel_gbs"] = round(alg["copy_bytes"] / (phases["copy"][0] * 1e-3) / 1e9, 1)
 
     cpu = None
-    if not args.no_cpu:
+    if "cpu" not in args.skip:
         import oracle
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         log(f"[bench] CPU oracle: one full solve of the same matrix on {threads} threads")
-        orc = oracle.get()
         t0 = time.perf_counter()
-        lref, _, _ = orc.stedc(d_np, e_np)
+        lref, _, _ = oracle.get().stedc(v["d"], v["e"])
         tc = time.perf_counter() - t0
-        err = float(np.abs(lam.cpu().numpy() - lref).max())
+        err = float(np.abs(v["lam"] - lref).max())
         cpu = {"value": round(tc, 3), "unit": "s", "cores": threads, "kind": "oracle",
-               "sample": f"one full solve, uniform n={n} (whole workload)", "max_abs_dlambda_vs_gpu": err}
+               "sample": "one full solve of the uniform n=16384 matrix (the whole workload)",
+               "max_abs_dlambda_vs_gpu": err}
         log(f"[bench] oracle {tc:.2f} s; max |lambda_gpu - lambda_oracle| = {err:.2e}")
 
-    t_val = result["t_hss"]
     line = {
         "metric": "n=16384 eigensolve time (s) + merge-GEMM % MFMA peak, plain vs chosen form",
-        "value": round(t_val, 6),
+        "value": round(v["t_ch"], 6),
         "unit": "s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(t_val * 1e3, 4),
+        "ms_per_step": round(v["t_ch"] * 1e3, 4),
         "higher_is_better": False,
         "scaling": "strong",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "uniform_n16384", "n": n, "dist": "d,e iid U[-1,1] seed 0", "leaf": 32,
-                   "chosen_form": "hss (K>=4096) else fp64-mfma", "top_merge_K": int(result["table"][-1, 2])},
-        "plain_fp64_s": round(result["t_plain"], 6),
-        "accuracy": {"orth_max": result["orth"], "residual": result["res"]},
-        "phases_ms": {k: round(v[0], 4) for k, v in phases.items()},
+        "config": {"workload": "uniform_n16384", "n": 16384, "dist": "d,e iid U[-1,1] seed 0", "leaf": 32,
+                   "chosen_form": "hss for merges with K>=4096, else fp64-mfma",
+                   "top_merge_K": int(v["table"][-1, 2])},
+        "plain_fp64_s": round(v["t_pl"], 6),
+        "accuracy": {"orth_max": v["orth"], "residual": v["res"]},
+        "phases_ms": {k: round(x[0], 4) for k, x in phases.items()},
         "roofline": roof,
-        "merge_gemm": merge_gemm,
-        "supplementary": supp,
         "cpu_baseline": cpu,
     }
+    line.update(sections)
     print(json.dumps(line), flush=True)
 
 

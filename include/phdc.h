@@ -119,6 +119,20 @@ int phdc_stedc_batched(int64_t B, const int64_t *n_host, const int64_t *off_host
                        const double *d, const double *e, double *lambda, double *Q, void *work,
                        size_t lwork, const phdc_opts *o, void *stream);
 
+/* Two-step form of the batched solve for callers that replay it in a HIP
+ * graph: phdc_stedc_batched_prepare builds the plan (split trees, level
+ * schedule, block maps) and copies it into `work` synchronously (same
+ * arguments as phdc_stedc_batched; PHDC_GEMM_HSS is rejected with -11 because
+ * that path reads sizes back on the host).  phdc_launch_prepared then only
+ * enqueues kernels (no memcpy, memset or host synchronisation), so it may be
+ * captured on `stream` and the graph replayed; every replay recomputes the
+ * solve from the current contents of d and e.  The prepared plan belongs to
+ * `work` until the next prepare or solve call on it. */
+int phdc_stedc_batched_prepare(int64_t B, const int64_t *n_host, const int64_t *off_host, const int64_t *qoff_host,
+                               const double *d, const double *e, double *lambda, double *Q, void *work,
+                               size_t lwork, const phdc_opts *o, void *stream);
+int phdc_launch_prepared(void *work, void *stream);
+
 /* ---------------------------------------------------------------- adjoint
  * Gradients of a loss L(lambda, Q) with respect to d and e, given lbar =
  * dL/dlambda and Qbar = dL/dQ at the eigenpairs (lambda, Q) of T:

@@ -72,6 +72,9 @@ def load():
     lib.phdc_secular.argtypes = [_i64, _vp, _vp, ctypes.c_double, _vp, _vp, _vp, _sz, _vp]
     lib.phdc_status.argtypes = [_vp, _vp]
     lib.phdc_merge_stats.argtypes = [_vp, P(ctypes.c_int32)]
+    lib.phdc_stedc_batched_prepare.argtypes = [_i64, P(_i64), P(_i64), P(_i64), _vp, _vp, _vp, _vp, _vp, _sz,
+                                               P(Opts), _vp]
+    lib.phdc_launch_prepared.argtypes = [_vp, _vp]
     if hasattr(lib, "phdc_stedc_backward"):
         lib.phdc_stedc_backward_workspace.argtypes = [_i64, _i64, P(_sz)]
         lib.phdc_stedc_backward.argtypes = [_i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
@@ -79,7 +82,7 @@ def load():
     return lib
 
 
-EXPORTS = ["phdc_opts_default", "phdc_version", "phdc_stedc_workspace", "phdc_stedc", "phdc_merge_workspace",
+EXPORTS = ["phdc_stedc_batched_prepare", "phdc_launch_prepared", "phdc_opts_default", "phdc_version", "phdc_stedc_workspace", "phdc_stedc", "phdc_merge_workspace",
            "phdc_merge", "phdc_stedc_batched_workspace", "phdc_stedc_batched", "phdc_stedc_backward_workspace",
            "phdc_stedc_backward", "phdc_status", "phdc_merge_stats", "phdc_secular"]
 
@@ -305,3 +308,62 @@ def eigh_tridiagonal(d: torch.Tensor, e: torch.Tensor, leaf_size: int = 32, gemm
     with lambda ascending and Q[..., :, j] the eigenvector of lambda[..., j].
     """
     return _TridiagonalEigh.apply(d, e, leaf_size, gemm_mode)
+
+
+class BatchedSolver:
+    """A batch of tridiagonals of fixed sizes, planned once and launched many times.
+
+    ``prepare`` uploads the plan; ``launch`` enqueues the kernels only, so it can
+    be captured with ``capture()`` into a HIP graph (torch.cuda.CUDAGraph) and
+    replayed: each replay solves for the current contents of ``self.d``/``self.e``.
+    """
+
+    def __init__(self, sizes, o: Opts | None = None, device="cuda"):
+        lib = load()
+        self.o = o or opts()
+        self.sizes = [int(x) for x in sizes]
+        B = len(self.sizes)
+        self.B = B
+        off, qoff, acc, qacc, eacc = [], [], 0, 0, 0
+        for nb_ in self.sizes:
+            off.append(acc)
+            qoff.append(qacc)
+            acc += nb_
+            qacc += nb_ * nb_
+            eacc += max(nb_ - 1, 0)
+        self.off, self.qoff = off, qoff
+        self._n = (ctypes.c_int64 * max(B, 1))(*self.sizes)
+        self._off = (ctypes.c_int64 * max(B, 1))(*off)
+        self._qoff = (ctypes.c_int64 * max(B, 1))(*qoff)
+        self.d = torch.zeros(max(acc, 1), dtype=torch.float64, device=device)
+        self.e = torch.zeros(max(eacc, 1), dtype=torch.float64, device=device)
+        self.lam = torch.empty(max(acc, 1), dtype=torch.float64, device=device)
+        self.Q = torch.empty(max(qacc, 1), dtype=torch.float64, device=device)
+        nb = ctypes.c_size_t()
+        _check(lib.phdc_stedc_batched_workspace(B, self._n, ctypes.byref(self.o), ctypes.byref(nb)),
+               "phdc_stedc_batched_workspace")
+        self.work = workspace(nb.value, device)
+        self.graph = None
+
+    def prepare(self, stream=None):
+        _check(load().phdc_stedc_batched_prepare(self.B, self._n, self._off, self._qoff, _ptr(self.d), _ptr(self.e),
+                                                 _ptr(self.lam), _ptr(self.Q), _ptr(self.work), self.work.numel(),
+                                                 ctypes.byref(self.o), _stream(stream)),
+               "phdc_stedc_batched_prepare")
+
+    def launch(self, stream=None):
+        _check(load().phdc_launch_prepared(_ptr(self.work), _stream(stream)), "phdc_launch_prepared")
+
+    def capture(self):
+        """Capture ``launch`` into a HIP graph (after ``prepare``)."""
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            self.launch()
+        torch.cuda.current_stream().wait_stream(s)
+        self.graph = g
+        return g
+
+    def replay(self):
+        self.graph.replay()

@@ -17,6 +17,7 @@
 #include "phdc_internal.h"
 #include "profile.h"
 #include "hss.h"
+#include "split.h"
 
 namespace phdc {
 
@@ -82,11 +83,13 @@ struct Sizes {
   int H = 0;
   size_t hss_arena = 0;    // HSS working storage (largest HSS-eligible merge)
   size_t hss_desc = 0;     // HSS descriptor staging area
+  int64_t xslots = 0;      // split precision: max over levels of sum m (m + 8) (per slice, bf16)
+  int nsl = 0;             // split precision: slices per operand (0: path off)
 };
 
 struct Layout {
   size_t status, hdr, counters, mparam, descs, leaves, canon, canon_pfx, maps, scratch, uhat, qtwin, ltwin, hss,
-      hss_desc, total;
+      hss_desc, sa, sb, serow, sfcol, total;
 };
 
 constexpr int kScratchD = 12, kScratchI = 22;
@@ -95,6 +98,14 @@ int32_t hss_threshold(const phdc_opts* o) {
   if (!o || o->gemm_mode != PHDC_GEMM_HSS) return 0;
   return (int32_t)std::min<int64_t>(std::max<int64_t>(o->hss_min_K, 1), 1 << 30);
 }
+
+int split_slices(const phdc_opts* o) {
+  if (!o || o->gemm_mode != PHDC_GEMM_SPLIT) return 0;
+  return std::min(7, std::max(1, o->split_slices));
+}
+
+// split-precision slot of one merge (per slice, in bf16 elements), a multiple of 8
+int64_t xslot(int64_t m) { return (m * (m + 8) + 7) / 8 * 8; }
 
 int hss_dmax(const phdc_opts* o) {
   return std::min(512, std::max(16, o->hss_samples) + 2 * std::max(16, o->hss_samples_inc));
@@ -113,7 +124,12 @@ Sizes sizes_of(const Tree& T, const std::vector<int64_t>& n, int64_t q_total, co
     for (int i = T.hstart[h - 1]; i < T.hstart[h]; ++i) u += (int64_t)T.merges[i].m * T.merges[i].m;
     z.uhat = std::max(z.uhat, u);
     z.map_ints += (int64_t)MAP_COUNT * (T.hstart[h] - T.hstart[h - 1] + 1);
+    int64_t x = 0;
+    for (int i = T.hstart[h - 1]; i < T.hstart[h]; ++i) x += xslot(T.merges[i].m);
+    z.xslots = std::max(z.xslots, x);
   }
+  z.nsl = split_slices(o);
+  if (!z.nsl) z.xslots = 0;
   const int32_t thr = hss_threshold(o);
   if (thr > 0) {
     int64_t mh = 0;
@@ -150,6 +166,10 @@ Layout layout_of(const Sizes& z) {
   L.ltwin = take((size_t)z.n_total * 8);
   L.hss = take(z.hss_arena);
   L.hss_desc = take(z.hss_desc);
+  L.sa = take((size_t)z.nsl * z.xslots * 2);
+  L.sb = take((size_t)z.nsl * z.xslots * 2);
+  L.serow = take(z.nsl ? (size_t)z.n_total * 4 : 0);
+  L.sfcol = take(z.nsl ? (size_t)z.n_total * 4 : 0);
   L.total = p;
   return L;
 }
@@ -178,6 +198,17 @@ Scratch scratch_of(char* base, const Layout& L, const Sizes& z) {
   S.counters = (int32_t*)(base + L.counters);
   S.status = (int32_t*)(base + L.status);
   return S;
+}
+
+SplitBufs split_of(char* base, const Layout& L) {
+  SplitBufs B;
+  B.aslice = (__bf16*)(base + L.sa);
+  B.bslice = (__bf16*)(base + L.sb);
+  B.erow = (int32_t*)(base + L.serow);
+  B.fcol = (int32_t*)(base + L.sfcol);
+  B.kgroups = kSplitKGroups;
+  B.rgroups = kSplitRGroups;
+  return B;
 }
 
 // Pinned staging buffer for the plan upload, one per workspace pointer.  The
@@ -274,15 +305,50 @@ int run_hss_level(const MergeDesc* hdescs, int nm, const Scratch& S, char* arena
   return 0;
 }
 
+// Everything the kernel launches of a solve need once its plan is on the device.
+struct Prepared {
+  Scratch S;
+  SplitBufs SB;
+  Layout L;
+  Sizes z;
+  std::vector<int32_t> hstart;
+  std::vector<LevelMaps> lm;
+  int nleaves = 0, nmat = 0, ncols = 0;
+  phdc_opts o;
+};
+std::mutex g_pm_mu;
+std::unordered_map<const void*, Prepared> g_prepared;
+
+// Launch every kernel of a prepared solve: no host synchronisation, no memcpy,
+// no memset -- safe to capture in a HIP graph and replay.
+void launch_prepared_all(char* base, const Prepared& P, hipStream_t s) {
+  launch_clear_status(P.S.status, s);
+  {
+    ProfScope p(PH_LEAF, s);
+    launch_leaf_ql((const LeafArgs*)(base + P.L.leaves), P.nleaves, P.S.status, s);
+  }
+  const MergeDesc* dd = (const MergeDesc*)(base + P.L.descs);
+  for (int h = 1; h <= P.z.H; ++h) {
+    const int a = P.hstart[h - 1], e = P.hstart[h];
+    launch_merge_level(dd + a, e - a, P.lm[h], P.S, P.o.gemm_mode, &P.SB, P.z.nsl, s);
+  }
+  if (P.o.canonical_sign && P.ncols > 0) {
+    ProfScope p(PH_CANON, s);
+    launch_canonical_sign(base + P.L.canon, (const int32_t*)(base + P.L.canon_pfx), P.nmat, P.ncols, s);
+  }
+}
+
 // Build the device plan (descriptors, leaves, block maps), upload it and
-// launch every kernel of the solve.
+// launch every kernel of the solve.  With prepare_only the plan is uploaded
+// synchronously and kept for phdc_launch_prepared instead.
 int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n, void* work, const phdc_opts* o,
-              hipStream_t s) {
+              hipStream_t s, bool prepare_only = false) {
   const Tree& T = SU.T;
   const Sizes& z = SU.z;
   const Layout& L = SU.L;
   char* base = (char*)work;
   Scratch S = scratch_of(base, L, z);
+  SplitBufs SB = split_of(base, L);
 
   std::vector<char> plan;
   const size_t plan0 = L.hdr;  // plan region spans hdr .. maps (contiguous)
@@ -292,12 +358,14 @@ int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n,
   put(plan, 4, &nmerges32, 1);
 
   std::vector<MergeDesc> descs(T.merges.size());
-  std::vector<int64_t> uoff(T.merges.size(), 0);
+  std::vector<int64_t> uoff(T.merges.size(), 0), xoff(T.merges.size(), 0);
   for (int h = 1; h <= z.H; ++h) {
-    int64_t u = 0;
+    int64_t u = 0, x = 0;
     for (int i = T.hstart[h - 1]; i < T.hstart[h]; ++i) {
       uoff[i] = u;
+      xoff[i] = x;
       u += (int64_t)T.merges[i].m * T.merges[i].m;
+      x += xslot(T.merges[i].m);
     }
   }
   for (size_t i = 0; i < T.merges.size(); ++i) {
@@ -322,6 +390,8 @@ int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n,
     D.u_off = uoff[i];
     D.id = (int32_t)i;
     D.hss_min_k = hss_threshold(o);
+    D.x_off = xoff[i];
+    D.split_on = z.nsl > 0 ? 1 : 0;
   }
   put(plan, L.descs - plan0, descs.data(), descs.size());
 
@@ -370,9 +440,32 @@ int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n,
   put(plan, L.maps - plan0, maps.data(), maps.size());
   plan.resize(L.scratch - plan0);
 
+  Prepared P;
+  P.S = S;
+  P.SB = SB;
+  P.L = L;
+  P.z = z;
+  P.hstart = T.hstart;
+  P.lm = lm;
+  P.nleaves = (int)T.leaves.size();
+  P.nmat = (int)n.size();
+  P.ncols = cpfx.back();
+  P.o = *o;
+  if (prepare_only) {
+    if (hipStreamSynchronize(s) != hipSuccess) return -100;
+    if (hipMemcpy(base + plan0, plan.data(), plan.size(), hipMemcpyHostToDevice) != hipSuccess) return -101;
+    std::lock_guard<std::mutex> lk(g_pm_mu);
+    g_prepared[work] = P;
+    return 0;
+  }
+  if (hss_threshold(o) <= 0) {
+    if (upload(work, base + plan0, plan, s) != 0) return -101;
+    launch_prepared_all(base, P, s);
+    return hipGetLastError() == hipSuccess ? 0 : -103;
+  }
+  // HSS: the host reads K back after each level that has eligible merges
   launch_clear_status(S.status, s);
   if (upload(work, base + plan0, plan, s) != 0) return -101;
-
   {
     ProfScope p(PH_LEAF, s);
     launch_leaf_ql((const LeafArgs*)(base + L.leaves), (int)T.leaves.size(), S.status, s);
@@ -380,7 +473,7 @@ int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n,
   const MergeDesc* dd = (const MergeDesc*)(base + L.descs);
   for (int h = 1; h <= z.H; ++h) {
     const int a = T.hstart[h - 1], e = T.hstart[h];
-    launch_merge_level(dd + a, e - a, lm[h], S, o->gemm_mode, s);
+    launch_merge_level(dd + a, e - a, lm[h], S, o->gemm_mode, &SB, z.nsl, s);
     int rc = run_hss_level(descs.data() + a, e - a, S, base + L.hss, L.hss_desc - L.hss, base + L.hss_desc,
                            z.hss_desc, o, s);
     if (rc != 0) return rc;
@@ -487,9 +580,41 @@ int phdc_stedc_batched_workspace(int64_t B, const int64_t* n_host, const phdc_op
   return 0;
 }
 
+static int stedc_batched_impl(int64_t B, const int64_t* n_host, const int64_t* off_host, const int64_t* qoff_host,
+                              const double* d, const double* e, double* lambda, double* Q, void* work, size_t lwork,
+                              const phdc_opts* o, void* stream, bool prepare_only);
+
 int phdc_stedc_batched(int64_t B, const int64_t* n_host, const int64_t* off_host, const int64_t* qoff_host,
                        const double* d, const double* e, double* lambda, double* Q, void* work, size_t lwork,
                        const phdc_opts* o, void* stream) {
+  return stedc_batched_impl(B, n_host, off_host, qoff_host, d, e, lambda, Q, work, lwork, o, stream, false);
+}
+
+int phdc_stedc_batched_prepare(int64_t B, const int64_t* n_host, const int64_t* off_host, const int64_t* qoff_host,
+                               const double* d, const double* e, double* lambda, double* Q, void* work,
+                               size_t lwork, const phdc_opts* o, void* stream) {
+  phdc_opts def;
+  if (!o) { phdc_opts_default(&def); o = &def; }
+  if (o->gemm_mode == PHDC_GEMM_HSS) return -11;  // the HSS path reads sizes back on the host
+  return stedc_batched_impl(B, n_host, off_host, qoff_host, d, e, lambda, Q, work, lwork, o, stream, true);
+}
+
+int phdc_launch_prepared(void* work, void* stream) {
+  if (!work) return -1;
+  Prepared P;
+  {
+    std::lock_guard<std::mutex> lk(g_pm_mu);
+    auto it = g_prepared.find(work);
+    if (it == g_prepared.end()) return -1;
+    P = it->second;
+  }
+  launch_prepared_all((char*)work, P, (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? 0 : -103;
+}
+
+static int stedc_batched_impl(int64_t B, const int64_t* n_host, const int64_t* off_host, const int64_t* qoff_host,
+                              const double* d, const double* e, double* lambda, double* Q, void* work, size_t lwork,
+                              const phdc_opts* o, void* stream, bool prepare_only) {
   phdc_opts def;
   if (!o) { phdc_opts_default(&def); o = &def; }
   if (B < 0) return -1;
@@ -538,7 +663,7 @@ int phdc_stedc_batched(int64_t B, const int64_t* n_host, const int64_t* off_host
   }
   BF.ld[0] = n;
   BF.ld[1] = n;
-  return run_solve(SU, BF, n, work, o, (hipStream_t)stream);
+  return run_solve(SU, BF, n, work, o, (hipStream_t)stream, prepare_only);
 }
 
 int phdc_merge_workspace(int64_t n1, int64_t n2, const phdc_opts* o, size_t* bytes) {
@@ -625,6 +750,8 @@ int phdc_merge(int64_t n1, int64_t n2, const double* D, const double* z, double 
   Dd.u_off = 0;
   Dd.id = 0;
   Dd.hss_min_k = hss_threshold(o);
+  Dd.x_off = 0;
+  Dd.split_on = zs.nsl > 0 ? 1 : 0;
   std::vector<char> plan(L.scratch - L.hdr, 0);
   const int32_t root_and_count[2] = {0, 1};
   std::memcpy(plan.data(), root_and_count, 8);
@@ -644,7 +771,8 @@ int phdc_merge(int64_t n1, int64_t n2, const double* D, const double* z, double 
   std::memcpy(plan.data() + (L.maps - L.hdr), maps.data(), maps.size() * 4);
   launch_clear_status(S.status, s);
   if (upload(work, base + L.hdr, plan, s) != 0) return -101;
-  launch_merge_level((const MergeDesc*)(base + L.descs), 1, lm, S, o->gemm_mode, s);
+  SplitBufs SB = split_of(base, L);
+  launch_merge_level((const MergeDesc*)(base + L.descs), 1, lm, S, o->gemm_mode, &SB, zs.nsl, s);
   {
     int rc = run_hss_level(&Dd, 1, S, base + L.hss, L.hss_desc - L.hss, base + L.hss_desc, zs.hss_desc, o, s);
     if (rc != 0) return rc;

@@ -9,7 +9,20 @@
 
 namespace phdc {
 
-// Z is stored column-major in LDS (column c at Z[c * kMaxLeaf]); lane t owns row t.
+// Z is stored column-major in LDS (column c at Z[c * kMaxLeaf]); lane t owns
+// row t.  The block is a single wavefront: every lane runs the scalar QL
+// recurrence redundantly and stores the same values to LDS, so no barrier is
+// needed (LDS instructions of one wavefront complete in program order); only
+// the eigenvector rotations are lane-parallel.
+// Store of a value every lane computed identically.  The wave barriers only
+// keep the compiler from moving other LDS accesses across the store; on the
+// hardware the lanes of a wavefront are in lockstep anyway.
+__device__ inline void lockstep_store(double* a, double v) {
+  __builtin_amdgcn_wave_barrier();
+  *a = v;
+  __builtin_amdgcn_wave_barrier();
+}
+
 __global__ void __launch_bounds__(64) k_leaf_ql(const LeafArgs* __restrict__ leaves, int32_t* status) {
   __shared__ double sd[kMaxLeaf];
   __shared__ double se[kMaxLeaf];
@@ -19,23 +32,17 @@ __global__ void __launch_bounds__(64) k_leaf_ql(const LeafArgs* __restrict__ lea
   const int t = threadIdx.x;
   if (s <= 0) return;
   for (int c = 0; c < s; ++c) Z[c * kMaxLeaf + t] = (c == t) ? 1.0 : 0.0;
-  if (t < s) {
-    sd[t] = L.d[t];
-    se[t] = (t < s - 1) ? L.e[t] : 0.0;
+  // Corner updates of the split: the first/last row lost |e| of the removed coupling.
+  const double cl = (L.couple & 1) ? fabs(L.e[-1]) : 0.0;
+  const double cr = (L.couple & 2) ? fabs(L.e[s - 1]) : 0.0;
+  for (int i = 0; i < s; ++i) {
+    double di = L.d[i];
+    if (i == 0) di -= cl;
+    if (i == s - 1) di -= cr;
+    lockstep_store(&sd[i], di);
+    lockstep_store(&se[i], (i < s - 1) ? L.e[i] : 0.0);
   }
-  __syncthreads();
-  // Corner updates of the split (the first/last row lost |e| of the removed coupling).
-  double cl = (L.couple & 1) ? fabs(L.e[-1]) : 0.0;
-  double cr = (L.couple & 2) ? fabs(L.e[s - 1]) : 0.0;
-  __syncthreads();
-  if (t == 0) {
-    sd[0] -= cl;
-    sd[s - 1] -= cr;
-  }
-  __syncthreads();
 
-  // Every lane runs the scalar recurrence redundantly (uniform control flow);
-  // only the eigenvector rotations are lane-parallel.
   bool failed = false;
   for (int l = 0; l < s && !failed; ++l) {
     int iter = 0;
@@ -43,7 +50,7 @@ __global__ void __launch_bounds__(64) k_leaf_ql(const LeafArgs* __restrict__ lea
       // First negligible off-diagonal entry at or below row l splits the matrix.
       int mm = l;
       while (mm < s - 1) {
-        double dd = fabs(sd[mm]) + fabs(sd[mm + 1]);
+        const double dd = fabs(sd[mm]) + fabs(sd[mm + 1]);
         if (fabs(se[mm]) <= kUnitRoundoff * dd) break;
         ++mm;
       }
@@ -62,20 +69,15 @@ __global__ void __launch_bounds__(64) k_leaf_ql(const LeafArgs* __restrict__ lea
       // Chase the bulge from the bottom of the unreduced block up to row l,
       // one plane rotation in rows/columns (i, i+1) at a time.
       for (int i = mm - 1; i >= l; --i) {
-        double f = sn * se[i];
-        double b = cs * se[i];
+        const double f = sn * se[i];
+        const double b = cs * se[i];
         r = hypot(f, g);
-        __syncthreads();
-        if (t == 0) se[i + 1] = r;
-        __syncthreads();
+        lockstep_store(&se[i + 1], r);
         if (r == 0.0) {
           // The rotation underflowed: the block has split at i+1; undo the
           // pending shift correction and look for the split again.
-          if (t == 0) {
-            sd[i + 1] -= p;
-            se[mm] = 0.0;
-          }
-          __syncthreads();
+          lockstep_store(&sd[i + 1], sd[i + 1] - p);
+          lockstep_store(&se[mm], 0.0);
           restart = true;
           break;
         }
@@ -84,31 +86,22 @@ __global__ void __launch_bounds__(64) k_leaf_ql(const LeafArgs* __restrict__ lea
         g = sd[i + 1] - p;
         r = (sd[i] - g) * sn + 2.0 * cs * b;
         p = sn * r;
-        __syncthreads();
-        if (t == 0) sd[i + 1] = g + p;
+        lockstep_store(&sd[i + 1], g + p);
         g = cs * r - b;
         if (t < s) {
-          double zi = Z[i * kMaxLeaf + t];
-          double zj = Z[(i + 1) * kMaxLeaf + t];
+          const double zi = Z[i * kMaxLeaf + t];
+          const double zj = Z[(i + 1) * kMaxLeaf + t];
           Z[(i + 1) * kMaxLeaf + t] = sn * zi + cs * zj;
           Z[i * kMaxLeaf + t] = cs * zi - sn * zj;
         }
-        __syncthreads();
       }
       if (restart) continue;
-      __syncthreads();
-      if (t == 0) {
-        sd[l] -= p;
-        se[l] = g;
-        se[mm] = 0.0;
-      }
-      __syncthreads();
+      lockstep_store(&sd[l], sd[l] - p);
+      lockstep_store(&se[l], g);
+      lockstep_store(&se[mm], 0.0);
     }
   }
-  if (failed) {
-    if (t == 0) set_status(status, PHDC_ERR_LEAF);
-  }
-  __syncthreads();
+  if (failed && t == 0) set_status(status, PHDC_ERR_LEAF);
   // Selection sort into ascending order, moving eigenvector columns along.
   for (int i = 0; i < s - 1; ++i) {
     int best = i;
@@ -119,22 +112,16 @@ __global__ void __launch_bounds__(64) k_leaf_ql(const LeafArgs* __restrict__ lea
         best = j;
       }
     if (best != i) {
-      __syncthreads();
-      double a = sd[i];
+      const double a = sd[i];
       if (t < s) {
-        double zi = Z[i * kMaxLeaf + t];
+        const double zi = Z[i * kMaxLeaf + t];
         Z[i * kMaxLeaf + t] = Z[best * kMaxLeaf + t];
         Z[best * kMaxLeaf + t] = zi;
       }
-      __syncthreads();
-      if (t == 0) {
-        sd[i] = bv;
-        sd[best] = a;
-      }
-      __syncthreads();
+      lockstep_store(&sd[i], bv);
+      lockstep_store(&sd[best], a);
     }
   }
-  __syncthreads();
   if (t < s) {
     L.lam[t] = sd[t];
     for (int c = 0; c < s; ++c) L.q[t + (int64_t)c * L.ldq] = Z[c * kMaxLeaf + t];

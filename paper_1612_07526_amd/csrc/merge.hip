@@ -5,6 +5,7 @@
 // counts) from device counters, so no host round trip is needed.
 #include "phdc_internal.h"
 #include "profile.h"
+#include "split.h"
 
 namespace phdc {
 
@@ -355,7 +356,7 @@ __global__ void __launch_bounds__(kDefThreads) k_deflate(const MergeDesc* __rest
     cnt[C_NT2] = nd2;
     cnt[C_ND1] = nd1;
     cnt[C_ND2] = nd2;
-    cnt[C_PATH] = (M.hss_min_k > 0 && K >= M.hss_min_k) ? 2 : 0;
+    cnt[C_PATH] = M.split_on ? 1 : (M.hss_min_k > 0 && K >= M.hss_min_k) ? 2 : 0;
     cnt[C_HSSRANK] = 0;
   }
 }
@@ -401,16 +402,37 @@ __global__ void __launch_bounds__(256) k_rotate(BlockMap bm, Scratch S) {
 }
 
 // ------------------------------------------------------------ secular roots
-// One root per thread.  Root j of f(lambda) = 1 + rho sum_i z_i^2/(d_i - lambda)
-// (Sec. 1, after Eq. (4)) is bracketed in (d_j, d_{j+1}) (last root: (d_K,
-// d_K + rho|z|^2)); its origin is the bracket end nearer to the root (sign of f
-// at the midpoint).  tau is then refined by the two-pole rational model of f
-// (the "middle way" of R.-C. Li, 1993: psi = poles left of the bracket, phi =
-// poles right of it, each matched in value and slope at the current iterate),
-// with the bracket kept up to date and a bisection step whenever the model
-// step leaves it.  All differences are formed as (d_i - d_org) - tau.
+// Root j of f(lambda) = 1 + rho sum_i z_i^2/(d_i - lambda) (Sec. 1, after
+// Eq. (4)) is bracketed in (d_j, d_{j+1}) (last root: (d_K, d_K + rho|z|^2));
+// its origin is the bracket end nearer to the root (sign of f at the midpoint).
+// tau is then refined by the two-pole rational model of f (the "middle way" of
+// R.-C. Li, 1993: psi = poles left of the bracket, phi = poles right of it,
+// each matched in value and slope at the current iterate), with the bracket
+// kept up to date and a bisection step whenever the model step leaves it.  All
+// differences are formed as (d_i - d_org) - tau.
+//
+// Each root is owned by a group of G consecutive lanes that split the sums over
+// the poles and combine them with shuffles, so every lane of the group takes
+// the same decisions.  Reciprocals in the sums use the hardware estimate
+// refined by two Newton-Raphson steps y <- y (2 - x y) (quadratic convergence
+// from the ~2^-26 estimate: full double precision up to an ulp).
+__device__ inline double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(y, fma(-x, y, 1.0), y);
+  y = fma(y, fma(-x, y, 1.0), y);
+  return y;
+}
+
+template <int G>
+__device__ inline double group_sum(double v) {
+#pragma unroll
+  for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <int G>
 __device__ bool secular_root(int K, const double* __restrict__ d, const double* __restrict__ z, double rho, int j,
-                             int* org_out, double* tau_out) {
+                             int sub, int* org_out, double* tau_out) {
   const double inv_rho = 1.0 / rho;
   if (K == 1) {
     *org_out = 0;
@@ -422,8 +444,9 @@ __device__ bool secular_root(int K, const double* __restrict__ d, const double* 
   if (j < K - 1) {
     const double dj = d[j], dj1 = d[j + 1];
     const double half = 0.5 * (dj1 - dj);
-    double w = inv_rho;
-    for (int i = 0; i < K; ++i) w += z[i] * z[i] / ((d[i] - dj) - half);
+    double w = 0.0;
+    for (int i = sub; i < K; i += G) w += z[i] * z[i] / ((d[i] - dj) - half);
+    w = inv_rho + group_sum<G>(w);
     if (w >= 0.0) {
       org = j; lo = 0.0; hi = half;
     } else {
@@ -433,11 +456,12 @@ __device__ bool secular_root(int K, const double* __restrict__ d, const double* 
     org = K - 1;
     lo = 0.0;
     double zz = 0.0;
-    for (int i = 0; i < K; ++i) zz += z[i] * z[i];
-    hi = rho * zz;
+    for (int i = sub; i < K; i += G) zz += z[i] * z[i];
+    hi = rho * group_sum<G>(zz);
     for (int guard = 0; guard < 64; ++guard) {
-      double w = inv_rho;
-      for (int i = 0; i < K; ++i) w += z[i] * z[i] / ((d[i] - d[org]) - hi);
+      double w = 0.0;
+      for (int i = sub; i < K; i += G) w += z[i] * z[i] / ((d[i] - d[org]) - hi);
+      w = inv_rho + group_sum<G>(w);
       if (w >= 0.0) break;
       hi *= 2.0;
     }
@@ -449,14 +473,19 @@ __device__ bool secular_root(int K, const double* __restrict__ d, const double* 
   bool ok = false;
   for (int it = 0; it < 120; ++it) {
     double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0, eabs = 0.0;
-    for (int i = 0; i < K; ++i) {
+    for (int i = sub; i < K; i += G) {
       const double del = (d[i] - dorg) - tau;
-      const double rcp = 1.0 / del;
+      const double rcp = rcp_nr(del);
       const double tt = z[i] * z[i] * rcp;
       const double dt = tt * rcp;
       if (i <= jl) { psi += tt; dpsi += dt; } else { phi += tt; dphi += dt; }
       eabs += fabs(tt);
     }
+    psi = group_sum<G>(psi);
+    dpsi = group_sum<G>(dpsi);
+    phi = group_sum<G>(phi);
+    dphi = group_sum<G>(dphi);
+    eabs = group_sum<G>(eabs);
     const double w = inv_rho + psi + phi;
     if (w > 0.0) hi = tau;
     else if (w < 0.0) lo = tau;
@@ -481,35 +510,47 @@ __device__ bool secular_root(int K, const double* __restrict__ d, const double* 
   return ok;
 }
 
+constexpr int kSecG = 4;  // lanes per root
+
+// 64-lane blocks, 16 roots per block.
 __global__ void __launch_bounds__(64) k_secular(BlockMap bm, Scratch S) {
   const int b = blockIdx.x;
   const int mi = find_merge(bm, b);
   const int lb = b - bm.pfx[mi];
   const MergeDesc M = bm.descs[mi];
   const int K = S.counters[(int64_t)M.id * kCounters + C_K];
-  const int j = lb * 64 + threadIdx.x;
-  if (j >= K) return;
+  const int j = lb * (64 / kSecG) + (int)threadIdx.x / kSecG;
+  const int sub = threadIdx.x % kSecG;
+  if (lb * (64 / kSecG) >= K) return;  // whole block idle (uniform)
+  const bool active = j < K;
   const int64_t so = M.s_off;
   const double rho = S.mparam[(int64_t)M.id * 4 + 0];
-  int org;
-  double tau;
-  bool ok = secular_root(K, S.ds + so, S.zs + so, rho, j, &org, &tau);
-  S.org[so + j] = org;
-  S.tau[so + j] = tau;
-  S.dorg[so + j] = S.ds[so + org];
-  if (!ok) set_status(S.status, PHDC_ERR_SECULAR);
+  int org = 0;
+  double tau = 0.0;
+  // inactive groups of a partly filled block run root K-1 redundantly so that
+  // every lane takes part in the group shuffles; only active groups write
+  bool ok = secular_root<kSecG>(K, S.ds + so, S.zs + so, rho, active ? j : K - 1, sub, &org, &tau);
+  if (active && sub == 0) {
+    S.org[so + j] = org;
+    S.tau[so + j] = tau;
+    S.dorg[so + j] = S.ds[so + org];
+    if (!ok) set_status(S.status, PHDC_ERR_SECULAR);
+  }
 }
 
 __global__ void __launch_bounds__(64) k_secular_raw(int K, const double* d, const double* z, double rho,
                                                     int32_t* org, double* tau, int32_t* status) {
-  const int j = blockIdx.x * 64 + threadIdx.x;
-  if (j >= K) return;
-  int o;
-  double t;
-  bool ok = secular_root(K, d, z, rho, j, &o, &t);
-  org[j] = o;
-  tau[j] = t;
-  if (!ok) set_status(status, PHDC_ERR_SECULAR);
+  const int j = blockIdx.x * (64 / kSecG) + (int)threadIdx.x / kSecG;
+  const int sub = threadIdx.x % kSecG;
+  const bool active = j < K;
+  int o = 0;
+  double t = 0.0;
+  bool ok = secular_root<kSecG>(K, d, z, rho, active ? j : K - 1, sub, &o, &t);
+  if (active && sub == 0) {
+    org[j] = o;
+    tau[j] = t;
+    if (!ok) set_status(status, PHDC_ERR_SECULAR);
+  }
 }
 
 // ------------------------------------------------------------ Loewner z
@@ -680,11 +721,14 @@ int map_blocks(int kind, int m, int n1) {
   auto cdiv = [](int a, int b) { return (a + b - 1) / b; };
   switch (kind) {
     case MAP_ROOTS64: return cdiv(m, 64);
+    case MAP_ROOTS16: return cdiv(m, 64 / kSecG);
     case MAP_ROWS256: return cdiv(m, 256);
     case MAP_ROT: return cdiv(m, 256) * std::max(1, std::min(m / 2, kRotGroups));
     case MAP_UWRITE: return cdiv(m, 256) * std::max(1, std::min(m, kUwRowGroups));
     case MAP_GEMM: return (cdiv(n1, kGemmTile) + cdiv(m - n1, kGemmTile)) * cdiv(m, kGemmTile);
     case MAP_COPY: return cdiv(m, 256) * std::max(1, std::min(m, kCopyGroups));
+    case MAP_SPLITA: return cdiv(m, 256) * kSplitKGroups;
+    case MAP_SPLITB: return cdiv(m + 8, 256) * kSplitRGroups;
   }
   return 0;
 }
@@ -692,16 +736,15 @@ int map_blocks(int kind, int m, int n1) {
 void launch_merge_gemm_f64(const BlockMap& bm, int total, const Scratch& S, hipStream_t s);
 
 void launch_merge_level(const MergeDesc* descs, int nm, const LevelMaps& maps, const Scratch& S, int gemm_mode,
-                        hipStream_t s) {
+                        const SplitBufs* split, int nsl, hipStream_t s) {
   if (nm <= 0) return;
-  (void)gemm_mode;
   auto bmap = [&](int kind) { return BlockMap{descs, maps.pfx[kind], nm}; };
   { ProfScope p(PH_DEFLATE, s);
     hipLaunchKernelGGL(k_deflate, dim3(nm), dim3(kDefThreads), 0, s, descs, S); }
   { ProfScope p(PH_ROTATE, s);
     hipLaunchKernelGGL(k_rotate, dim3(maps.total[MAP_ROT]), dim3(256), 0, s, bmap(MAP_ROT), S); }
   { ProfScope p(PH_SECULAR, s);
-    hipLaunchKernelGGL(k_secular, dim3(maps.total[MAP_ROOTS64]), dim3(64), 0, s, bmap(MAP_ROOTS64), S); }
+    hipLaunchKernelGGL(k_secular, dim3(maps.total[MAP_ROOTS16]), dim3(64), 0, s, bmap(MAP_ROOTS16), S); }
   { ProfScope p(PH_LOWNER, s);
     hipLaunchKernelGGL(k_lowner, dim3(maps.total[MAP_ROOTS64]), dim3(64), 0, s, bmap(MAP_ROOTS64), S); }
   { ProfScope p(PH_UNORM, s);
@@ -712,6 +755,10 @@ void launch_merge_level(const MergeDesc* descs, int nm, const LevelMaps& maps, c
     hipLaunchKernelGGL(k_rank, dim3(maps.total[MAP_ROWS256]), dim3(256), 0, s, bmap(MAP_ROWS256), S); }
   { ProfScope p(PH_GEMM, s);
     launch_merge_gemm_f64(bmap(MAP_GEMM), maps.total[MAP_GEMM], S, s); }
+  if (gemm_mode == PHDC_GEMM_SPLIT && split) {
+    ProfScope p(PH_SPLIT_GEMM, s);
+    launch_split_update(descs, nm, maps, S, *split, nsl, s);
+  }
   { ProfScope p(PH_COPY, s);
     hipLaunchKernelGGL(k_copy_deflated, dim3(maps.total[MAP_COPY]), dim3(256), 0, s, bmap(MAP_COPY), S); }
 }
@@ -719,7 +766,8 @@ void launch_merge_level(const MergeDesc* descs, int nm, const LevelMaps& maps, c
 void launch_secular_standalone(int64_t K, const double* d, const double* z, double rho, int32_t* org, double* tau,
                                int32_t* status, hipStream_t s) {
   if (K <= 0) return;
-  hipLaunchKernelGGL(k_secular_raw, dim3((unsigned)((K + 63) / 64)), dim3(64), 0, s, (int)K, d, z, rho, org, tau,
+  const int per = 64 / kSecG;
+  hipLaunchKernelGGL(k_secular_raw, dim3((unsigned)((K + per - 1) / per)), dim3(64), 0, s, (int)K, d, z, rho, org, tau,
                      status);
 }
 

@@ -34,6 +34,9 @@ struct MergeDesc {
   int64_t u_off;        // offset of this merge's m*m slot in the Uhat arena
   int32_t id;           // row in the counters table
   int32_t hss_min_k;    // HSS update for this merge when K >= hss_min_k (0: never)
+  int64_t x_off;        // offset of this merge's m*(m+8) slot (per slice) in the split-precision arenas
+  int32_t split_on;     // split-precision update for this merge
+  int32_t pad;
 };
 
 // One leaf solve (one wavefront).
@@ -123,15 +126,16 @@ __device__ inline void set_status(int32_t* status, int code) {
 void launch_leaf_ql(const LeafArgs* leaves, int nleaves, int32_t* status, hipStream_t s);
 
 // Block maps of one merge level (device prefix arrays, nm + 1 entries each).
-enum MapKind { MAP_ROOTS64 = 0, MAP_ROWS256, MAP_ROT, MAP_UWRITE, MAP_GEMM, MAP_COPY, MAP_COUNT };
+enum MapKind { MAP_ROOTS64 = 0, MAP_ROOTS16, MAP_ROWS256, MAP_ROT, MAP_UWRITE, MAP_GEMM, MAP_COPY, MAP_SPLITA, MAP_SPLITB, MAP_COUNT };
 struct LevelMaps {
   const int32_t* pfx[MAP_COUNT];
   int32_t total[MAP_COUNT];
 };
 int map_blocks(int kind, int m, int n1);
 
+struct SplitBufs;
 void launch_merge_level(const MergeDesc* descs, int nm, const LevelMaps& maps, const Scratch& S,
-                        int gemm_mode, hipStream_t s);
+                        int gemm_mode, const SplitBufs* split, int nsl, hipStream_t s);
 void launch_secular_standalone(int64_t K, const double* d, const double* z, double rho, int32_t* org,
                                double* tau, int32_t* status, hipStream_t s);
 

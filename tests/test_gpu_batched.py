@@ -1,0 +1,103 @@
+"""Batched solves of uneven sizes: one launch per kernel per tree height across the
+batch, the prepare/launch split, and HIP-graph replays (on the GPU).
+
+Graph replays are checked against the eager result each time, with eager work
+and synchronisation between replays, and with the inputs changed in place
+between replays (a replay must solve the current inputs).
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from checks import orth, residual
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1612_07526_amd as P
+    P.load()
+    return P
+
+
+def _fill(bs, ds, es):
+    bs.d[: sum(bs.sizes)] = torch.tensor(np.concatenate(ds), device=bs.d.device)
+    ecat = np.concatenate([x for x in es if x.size] or [np.zeros(0)])
+    if ecat.size:
+        bs.e[: ecat.size] = torch.tensor(ecat, device=bs.e.device)
+
+
+def _blocks(bs):
+    lam = bs.lam.cpu().numpy()
+    Q = bs.Q.cpu().numpy()
+    out = []
+    for b, n in enumerate(bs.sizes):
+        out.append((lam[bs.off[b]:bs.off[b] + n], Q[bs.qoff[b]:bs.qoff[b] + n * n].reshape(n, n).T))
+    return out
+
+
+def test_batched_uneven_sizes_vs_oracle(P, orc):
+    sizes = W.batch_sizes(60, 32, 400, seed=3).tolist() + [1, 2, 31, 33, 0]
+    ds, es = W.normal_batch(sizes, seed=3)
+    lam, Q, off, qoff = P.stedc_batched(sizes, np.concatenate(ds), np.concatenate(es))
+    lam, Q = lam.cpu().numpy(), Q.cpu().numpy()
+    for b in range(0, len(sizes), 7):
+        n = sizes[b]
+        if n == 0:
+            continue
+        lr, _, _ = orc.stedc(ds[b], es[b])
+        lb = lam[off[b]:off[b] + n]
+        Qb = Q[qoff[b]:qoff[b] + n * n].reshape(n, n).T
+        assert np.abs(lb - lr).max() <= 1e-13 * np.abs(lr).max()
+        assert orth(Qb) <= 1e-12
+        assert residual(ds[b], es[b], lb, Qb) <= 1e-13
+
+
+def test_batched_equals_single_solves(P):
+    sizes = [100, 257, 64, 1000]
+    ds, es = W.normal_batch(sizes, seed=4)
+    lam, Q, off, qoff = P.stedc_batched(sizes, np.concatenate(ds), np.concatenate(es))
+    for b, n in enumerate(sizes):
+        l1, Q1 = P.stedc(ds[b], es[b])
+        assert torch.equal(l1, lam[off[b]:off[b] + n])
+        assert torch.equal(Q1.t().contiguous().reshape(-1), Q[qoff[b]:qoff[b] + n * n])
+
+
+@pytest.mark.parametrize("mode", ["fp64", "split"])
+def test_graph_replay_matches_eager(P, mode):
+    sizes = W.batch_sizes(40, 32, 300, seed=5).tolist()
+    o = P.opts(gemm_mode=P.GEMM_FP64 if mode == "fp64" else P.GEMM_SPLIT)
+    bs = P.BatchedSolver(sizes, o)
+    rounds = []
+    for r in range(3):
+        ds, es = W.normal_batch(sizes, seed=10 + r)
+        rounds.append((ds, es))
+    # eager reference for each input set
+    ref = []
+    for ds, es in rounds:
+        _fill(bs, ds, es)
+        bs.prepare()
+        bs.launch()
+        torch.cuda.synchronize()
+        assert P.status(bs.work) == 0
+        ref.append((bs.lam.clone(), bs.Q.clone()))
+    _fill(bs, *rounds[0])
+    bs.prepare()
+    bs.capture()
+    for r, (ds, es) in enumerate(rounds * 2):
+        _fill(bs, ds, es)
+        torch.cuda.synchronize()
+        bs.replay()
+        # eager work between replays
+        x = torch.randn(1000, 1000, device="cuda", dtype=torch.float64)
+        (x @ x).sum().item()
+        torch.cuda.synchronize()
+        assert P.status(bs.work) == 0
+        assert torch.equal(bs.lam, ref[r % 3][0]) and torch.equal(bs.Q, ref[r % 3][1]), f"replay {r} differs"
+    # and the replays are correct solves
+    for b, (lb, Qb) in enumerate(_blocks(bs)[:5]):
+        ds, es = rounds[(len(rounds) * 2 - 1) % 3]
+        assert orth(Qb) <= (1e-11 if mode == "split" else 1e-12)
+        assert residual(ds[b], es[b], lb, Qb) <= (1e-12 if mode == "split" else 1e-13)
