@@ -35,10 +35,6 @@ sys.path.insert(0, ROOT)
 FP64_PEAK_TFLOPS = 78.6
 BF16_PEAK_TFLOPS = 2500.0
 HBM_PEAK_GBS = 8000.0
-PHASES = ["leaf", "deflate", "rotate", "secular", "loewner", "uhat_norm", "uhat_write", "rank", "gemm", "copy",
-          "sign", "split_slice", "split_gemm", "hss_sample", "hss_compress", "hss_apply", "adj_gemm", "adj_band"]
-
-
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -60,14 +56,7 @@ def timed(fn, steps, warmup):
 
 
 def merge_table(P, work):
-    lib = P.load()
-    lib.phdc_merge_table.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]
-    rows = ctypes.c_int64()
-    lib.phdc_merge_table(ctypes.c_void_p(work.data_ptr()), 0, None, ctypes.byref(rows))
-    n = rows.value
-    buf = (ctypes.c_int32 * max(n * 10, 1))()
-    lib.phdc_merge_table(ctypes.c_void_p(work.data_ptr()), n, buf, ctypes.byref(rows))
-    return np.frombuffer(buf, dtype=np.int32)[: n * 10].reshape(n, 10).copy()
+    return P.merge_table(work)
 
 
 def algorithmic(table):
@@ -75,35 +64,23 @@ def algorithmic(table):
 
     gemm_flops: 2 [n1 (k1+k2) + n2 (k2+k3)] K over merges on the FP64 path (Gu's
                 grouped products, Eq. (6));
-    copy_bytes: every deflated column read and written once, 16 m bytes;
-    uhat_write_bytes: 8 K^2 bytes per merge;
-    secular_flops: K^2 pole terms (1 reciprocal + 8 flops) per iteration, 5 iterations.
+    copy_bytes: each deflated column read once over its nonzero rows (n1, m or n2)
+                and written once over all m rows, 8 bytes per entry;
+    uhat_write_bytes: 8 K^2 bytes per merge.
     """
-    m, n1, K, k1, k2, k3, nt1, nt2, path = (table[:, i].astype(np.float64) for i in range(9))
+    t = table.astype(np.float64)
+    m, n1, K, k1, k2, k3, path, dp1, dp2, dp3 = (t[:, i] for i in (0, 1, 2, 3, 4, 5, 8, 10, 11, 12))
     n2 = m - n1
     plain = path == 0
     return {
         "gemm_flops": float(np.sum((2 * (n1 * (k1 + k2) + n2 * (k2 + k3)) * K)[plain])),
-        "copy_bytes": float(np.sum((nt1 + nt2) * m * 16)),
+        "copy_bytes": float(np.sum(8 * (n1 * dp1 + m * dp2 + n2 * dp3 + m * (dp1 + dp2 + dp3)))),
         "uhat_write_bytes": float(np.sum(K * K * 8)),
     }
 
 
 def profile_phases(P, fn, reps=2):
-    lib = P.load()
-    lib.phdc_profile_enable.argtypes = [ctypes.c_int]
-    lib.phdc_profile_read.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
-    sync()
-    lib.phdc_profile_read((ctypes.c_double * 32)(), (ctypes.c_int64 * 32)(), 32)
-    lib.phdc_profile_enable(1)
-    for _ in range(reps):
-        fn()
-    sync()
-    lib.phdc_profile_enable(0)
-    ms = (ctypes.c_double * 32)()
-    cnt = (ctypes.c_int64 * 32)()
-    lib.phdc_profile_read(ms, cnt, 32)
-    return {PHASES[i]: (ms[i] / reps, cnt[i] // reps) for i in range(len(PHASES)) if cnt[i]}
+    return P.profile_phases(fn, reps)
 
 
 class Solver:
@@ -146,29 +123,82 @@ class Solver:
         return orth, res
 
 
+# Kernel phase -> (counter summary under profiles/, source file the kernel is built from).
+TRAFFIC_SUMMARIES = {
+    "copy": ("profiles/k_copy_deflated_uniform_n16384_traffic.md", "paper_1612_07526_amd/csrc/merge.hip"),
+}
+
+
+def measured_traffic(phase):
+    """HBM bytes per launch of the phase's kernel from its committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy kernel's reading), or None when no
+    summary exists or the kernel's source file has changed since the counters were taken."""
+    import hashlib
+    if phase not in TRAFFIC_SUMMARIES:
+        return None
+    summ, src = (os.path.join(ROOT, x) for x in TRAFFIC_SUMMARIES[phase])
+    if not os.path.exists(summ):
+        return None
+    fields = {}
+    for line in open(summ):
+        if ":" in line and line.strip().startswith("- "):
+            k, v = line.strip()[2:].split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if fields.get("source_sha256") != sha or "traffic_bytes_per_launch" not in fields:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
+def timed_profiled(P, fn, steps, warmup):
+    """Time `steps` calls with the library's per-phase HIP events recorded on the launch
+    stream inside the same timed region: returns (s per call, {phase: (ms, launches) per call})."""
+    import torch
+    lib = P.load()
+    for _ in range(warmup):
+        fn()
+    sync()
+    n = len(P.PHASES)
+    lib.phdc_profile_read((ctypes.c_double * n)(), (ctypes.c_int64 * n)(), n)
+    lib.phdc_profile_enable(1)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    lib.phdc_profile_enable(0)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int64 * n)()
+    lib.phdc_profile_read(ms, cnt, n)
+    return dt, {P.PHASES[i]: (ms[i] / steps, cnt[i] // steps) for i in range(n) if cnt[i]}
+
+
 def sec_value(P, W, args, out):
     n = 16384
     d, e = W.uniform(n, seed=0)
     chosen = P.GEMM_FP64 if "hss" in args.skip_paths else P.GEMM_HSS
     ch = Solver(P, d, e, P.opts(gemm_mode=chosen))
-    log(f"[bench] value: warmup {args.warmup}, timing {args.steps} solves of uniform n={n} (chosen form)")
-    t_ch = timed(ch, args.steps, args.warmup)
+    log(f"[bench] value: warmup {args.warmup}, timing {args.steps} solves of uniform n={n} (chosen form, "
+        "phase events on the launch stream)")
+    t_ch, phases = timed_profiled(P, ch, args.steps, args.warmup)
     st = P.status(ch.work)
     if st != 0:
         raise RuntimeError(f"device status {st}")
     table = merge_table(P, ch.work)
+    alg = algorithmic(table)
+    log("[bench] phases (ms/solve): " + ", ".join(f"{k}={v[0]:.3f}" for k, v in phases.items()))
+    t_clean = timed(ch, args.steps, 0)
     orth, res = ch.accuracy()
-    log(f"[bench] chosen form {t_ch * 1e3:.3f} ms/solve; top merge K={table[-1, 2]}; orth {orth:.2e} res {res:.2e}")
+    log(f"[bench] chosen form {t_ch * 1e3:.3f} ms/solve ({t_clean * 1e3:.3f} without events); "
+        f"top merge K={table[-1, 2]}; orth {orth:.2e} res {res:.2e}")
     lam_gpu = ch.lam.cpu().numpy()
     del ch
     pl = Solver(P, d, e, P.opts(gemm_mode=P.GEMM_FP64))
     t_pl = timed(pl, args.steps, 1)
     log(f"[bench] plain FP64 {t_pl * 1e3:.3f} ms/solve")
-    phases = profile_phases(P, pl)
-    log("[bench] phases (ms/solve): " + ", ".join(f"{k}={v[0]:.3f}" for k, v in phases.items()))
-    alg = algorithmic(merge_table(P, pl.work))
     del pl
-    out.update(t_ch=t_ch, t_pl=t_pl, orth=orth, res=res, phases=phases, alg=alg, table=table, lam=lam_gpu, d=d, e=e)
+    out.update(t_ch=t_ch, t_clean=t_clean, t_pl=t_pl, orth=orth, res=res, phases=phases, alg=alg, table=table,
+               lam=lam_gpu, d=d, e=e)
 
 
 def sec_merge_gemm(P, W, args):
@@ -351,6 +381,8 @@ def main():
     ap.add_argument("--skip", default="", help="comma list of sections: merge_gemm,toeplitz,split,batch,adjoint,cpu")
     ap.add_argument("--skip-paths", default="", help="comma list of update paths to leave out: hss,split")
     ap.add_argument("--only-value", action="store_true", help="time the headline solve only (profiling runs)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run a plain 1 GiB device copy (reference kernel for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -364,6 +396,15 @@ def main():
     import paper_1612_07526_amd as P
     import workloads as W
 
+    if args.calib_copy:
+        import torch
+        x = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        x.fill_(1.0)
+        y.copy_(x)  # reads 1 GiB, writes 1 GiB
+        sync()
+        del x, y
+        torch.cuda.empty_cache()
     v = {}
     sec_value(P, W, args, v)
     sections = {}
@@ -394,7 +435,10 @@ def main():
         roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
     else:
         roof["frac"] = None
-    roof.update(traffic=None, kernel=dom, launches_per_step=int(cnt_dom), ms_per_step=round(ms_dom, 4))
+    roof.update(traffic=measured_traffic(dom), kernel=dom, launches_per_step=int(cnt_dom),
+                ms_per_step=round(ms_dom, 4))
+    if dom == "copy":
+        roof["algorithmic_bytes_per_launch"] = round(alg["copy_bytes"] / max(cnt_dom, 1))
     if "copy" in phases:
         roof["copy_kernel_gbs"] = round(alg["copy_bytes"] / (phases["copy"][0] * 1e-3) / 1e9, 1)
 
@@ -429,6 +473,7 @@ def main():
                    "chosen_form": "hss for merges with K>=4096, else fp64-mfma",
                    "top_merge_K": int(v["table"][-1, 2])},
         "plain_fp64_s": round(v["t_pl"], 6),
+        "value_without_phase_events_s": round(v["t_clean"], 6),
         "accuracy": {"orth_max": v["orth"], "residual": v["res"]},
         "phases_ms": {k: round(x[0], 4) for k, x in phases.items()},
         "roofline": roof,

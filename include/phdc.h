@@ -167,9 +167,13 @@ int phdc_profile_enable(int on);
 int phdc_profile_read(double *ms, int64_t *count, int nphase);
 
 /* Sizes of every merge of the last stedc/merge call on `work` (call after
- * phdc_status): up to max_rows rows of 10 int32 each: {m, n1, K, k1, k2, k3,
- * type-1 deflations, type-2 deflations, path (0 FP64, 1 split, 2 HSS), HSS rank}.
+ * phdc_status): up to max_rows rows of PHDC_MERGE_TABLE_COLS int32 each:
+ * {m, n1, K, k1, k2, k3, type-1 deflations, type-2 deflations,
+ *  path (0 FP64, 1 split, 2 HSS), HSS rank,
+ *  deflated columns nonzero in the Q1 rows only, in both halves, in the Q2 rows only}.
+ * Rows are in the order the merges were planned (leaves upward, the root last).
  * *rows_out receives the number of merges.  Returns 0 or -1. */
+#define PHDC_MERGE_TABLE_COLS 13
 int phdc_merge_table(const void *work, int64_t max_rows, int32_t *table_host, int64_t *rows_out);
 
 /* ---------------------------------------------------------------- secular roots

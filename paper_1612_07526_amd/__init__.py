@@ -75,16 +75,42 @@ def load():
     lib.phdc_stedc_batched_prepare.argtypes = [_i64, P(_i64), P(_i64), P(_i64), _vp, _vp, _vp, _vp, _vp, _sz,
                                                P(Opts), _vp]
     lib.phdc_launch_prepared.argtypes = [_vp, _vp]
-    if hasattr(lib, "phdc_stedc_backward"):
-        lib.phdc_stedc_backward_workspace.argtypes = [_i64, _i64, P(_sz)]
-        lib.phdc_stedc_backward.argtypes = [_i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+    lib.phdc_stedc_backward_workspace.argtypes = [_i64, _i64, P(_sz)]
+    lib.phdc_stedc_backward.argtypes = [_i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+    lib.phdc_merge_table.argtypes = [_vp, _i64, P(ctypes.c_int32), P(_i64)]
+    lib.phdc_profile_enable.argtypes = [ctypes.c_int]
+    lib.phdc_profile_read.argtypes = [P(ctypes.c_double), P(_i64), ctypes.c_int]
     _lib = lib
     return lib
 
 
 EXPORTS = ["phdc_stedc_batched_prepare", "phdc_launch_prepared", "phdc_opts_default", "phdc_version", "phdc_stedc_workspace", "phdc_stedc", "phdc_merge_workspace",
            "phdc_merge", "phdc_stedc_batched_workspace", "phdc_stedc_batched", "phdc_stedc_backward_workspace",
-           "phdc_stedc_backward", "phdc_status", "phdc_merge_stats", "phdc_secular"]
+           "phdc_stedc_backward", "phdc_status", "phdc_merge_stats", "phdc_secular", "phdc_merge_table",
+           "phdc_profile_enable", "phdc_profile_read"]
+
+PHASES = ["leaf", "deflate", "rotate", "secular", "loewner", "uhat_norm", "uhat_write", "rank", "gemm", "copy",
+          "sign", "split_slice", "split_gemm", "hss_sample", "hss_compress", "hss_apply", "adj_gemm", "adj_band"]
+
+
+def profile_phases(fn, reps: int = 1) -> dict:
+    """Run fn() reps times with the library's per-phase HIP-event timing on; returns
+    {phase: (ms per rep, launches per rep)} for the phases that ran."""
+    lib = load()
+    torch.cuda.synchronize()
+    n = len(PHASES)
+    lib.phdc_profile_read((ctypes.c_double * n)(), (_i64 * n)(), n)  # drop anything pending
+    lib.phdc_profile_enable(1)
+    try:
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+    finally:
+        lib.phdc_profile_enable(0)
+    ms = (ctypes.c_double * n)()
+    cnt = (_i64 * n)()
+    _check(lib.phdc_profile_read(ms, cnt, n), "phdc_profile_read")
+    return {PHASES[i]: (ms[i] / reps, cnt[i] // reps) for i in range(n) if cnt[i]}
 
 
 def opts(**kw) -> Opts:
@@ -128,6 +154,24 @@ def merge_stats(work: torch.Tensor) -> list:
     buf = (ctypes.c_int32 * 8)()
     _check(load().phdc_merge_stats(_ptr(work), buf), "phdc_merge_stats")
     return list(buf)
+
+
+MERGE_TABLE_COLS = 13
+
+
+def merge_table(work: torch.Tensor):
+    """Per-merge sizes of the last solve on `work` as an (nmerges, 13) int32 numpy array:
+    m, n1, K, k1, k2, k3, type-1 deflations, type-2 deflations, path (0 FP64, 1 split,
+    2 HSS), HSS rank, deflated columns nonzero in the Q1 rows only / both halves / the
+    Q2 rows only.  Rows follow the planning order (the root merge last)."""
+    import numpy as np
+    lib = load()
+    rows = ctypes.c_int64()
+    _check(lib.phdc_merge_table(_ptr(work), 0, None, ctypes.byref(rows)), "phdc_merge_table")
+    n = rows.value
+    buf = (ctypes.c_int32 * max(n * MERGE_TABLE_COLS, 1))()
+    _check(lib.phdc_merge_table(_ptr(work), n, buf, ctypes.byref(rows)), "phdc_merge_table")
+    return np.frombuffer(buf, dtype=np.int32)[: n * MERGE_TABLE_COLS].reshape(n, MERGE_TABLE_COLS).copy()
 
 
 def _raise_status(work, stream=None):

@@ -848,10 +848,13 @@ int phdc_merge_table(const void* work, int64_t max_rows, int32_t* table_host, in
       hipSuccess)
     return -1;
   for (int64_t i = 0; i < rows; ++i) {
-    int32_t* r = table_host + i * 10;
+    int32_t* r = table_host + i * PHDC_MERGE_TABLE_COLS;
     r[0] = d[i].m;
     r[1] = d[i].n1;
     for (int k = 0; k < 8; ++k) r[2 + k] = c[i * kCounters + k];
+    r[10] = c[i * kCounters + C_DP1];
+    r[11] = c[i * kCounters + C_DP2];
+    r[12] = c[i * kCounters + C_DP3];
   }
   return 0;
 }

@@ -5,27 +5,41 @@
 // tridiagonal eigensolver is a correct leaf.  Before solving, the leaf's first
 // and last diagonal entries lose |e| of the coupling that the Cuppen split
 // (Eq. (2)) removed on that side.
+//
+// Layout on the wavefront: lane t holds d_t and e_t in registers; the scalar
+// recurrence of the bulge chase is computed identically by every lane, reading
+// the entry it needs with a lane read and writing it back with a lane select
+// (no LDS round trip on the critical path).  The eigenvector matrix Z sits in
+// LDS, column-major, and lane t owns row t of it, so the rotations need no
+// communication between lanes and no barrier.
 #include "phdc_internal.h"
 
 namespace phdc {
 
-// Z is stored column-major in LDS (column c at Z[c * kMaxLeaf]); lane t owns
-// row t.  The block is a single wavefront: every lane runs the scalar QL
-// recurrence redundantly and stores the same values to LDS, so no barrier is
-// needed (LDS instructions of one wavefront complete in program order); only
-// the eigenvector rotations are lane-parallel.
-// Store of a value every lane computed identically.  The wave barriers only
-// keep the compiler from moving other LDS accesses across the store; on the
-// hardware the lanes of a wavefront are in lockstep anyway.
-__device__ inline void lockstep_store(double* a, double v) {
-  __builtin_amdgcn_wave_barrier();
-  *a = v;
-  __builtin_amdgcn_wave_barrier();
+namespace {
+
+__device__ inline double lane_get(double v, int lane) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
+__device__ inline double lane_put(double old, double v, int lane) {
+  return (int)threadIdx.x == lane ? v : old;
+}
+
+// sqrt(a^2 + b^2); the plain form is exact to rounding inside [1e-150, 1e150],
+// the scaled library routine covers the rest.
+__device__ inline double hyp(double a, double b) {
+  const double mx = fmax(fabs(a), fabs(b));
+  if (mx > 1e150 || mx < 1e-150) return hypot(a, b);
+  return sqrt(a * a + b * b);
+}
+
+}  // namespace
+
 __global__ void __launch_bounds__(64) k_leaf_ql(const LeafArgs* __restrict__ leaves, int32_t* status) {
-  __shared__ double sd[kMaxLeaf];
-  __shared__ double se[kMaxLeaf];
   __shared__ double Z[kMaxLeaf * kMaxLeaf];
   const LeafArgs L = leaves[blockIdx.x];
   const int s = L.s;
@@ -33,27 +47,23 @@ __global__ void __launch_bounds__(64) k_leaf_ql(const LeafArgs* __restrict__ lea
   if (s <= 0) return;
   for (int c = 0; c < s; ++c) Z[c * kMaxLeaf + t] = (c == t) ? 1.0 : 0.0;
   // Corner updates of the split: the first/last row lost |e| of the removed coupling.
-  const double cl = (L.couple & 1) ? fabs(L.e[-1]) : 0.0;
-  const double cr = (L.couple & 2) ? fabs(L.e[s - 1]) : 0.0;
-  for (int i = 0; i < s; ++i) {
-    double di = L.d[i];
-    if (i == 0) di -= cl;
-    if (i == s - 1) di -= cr;
-    lockstep_store(&sd[i], di);
-    lockstep_store(&se[i], (i < s - 1) ? L.e[i] : 0.0);
+  double d = 0.0, e = 0.0;
+  if (t < s) {
+    d = L.d[t];
+    if (t == 0 && (L.couple & 1)) d -= fabs(L.e[-1]);
+    if (t == s - 1 && (L.couple & 2)) d -= fabs(L.e[s - 1]);
+    e = (t < s - 1) ? L.e[t] : 0.0;
   }
 
   bool failed = false;
   for (int l = 0; l < s && !failed; ++l) {
     int iter = 0;
     for (;;) {
-      // First negligible off-diagonal entry at or below row l splits the matrix.
-      int mm = l;
-      while (mm < s - 1) {
-        const double dd = fabs(sd[mm]) + fabs(sd[mm + 1]);
-        if (fabs(se[mm]) <= kUnitRoundoff * dd) break;
-        ++mm;
-      }
+      // First negligible off-diagonal entry at or below row l splits the matrix
+      // (row s-1 always ends it).
+      const double dn = __shfl(d, (t + 1) & 63);
+      const bool split = t >= l && t < s && (t == s - 1 || fabs(e) <= kUnitRoundoff * (fabs(d) + fabs(dn)));
+      const int mm = __ffsll((unsigned long long)__ballot(split)) - 1;
       if (mm == l) break;
       if (++iter > 64) {
         failed = true;
@@ -61,70 +71,60 @@ __global__ void __launch_bounds__(64) k_leaf_ql(const LeafArgs* __restrict__ lea
       }
       // Shift: the eigenvalue of the leading 2x2 block [d_l e_l; e_l d_{l+1}]
       // nearer d_l, folded into the starting value g of the bulge chase.
-      double g = (sd[l + 1] - sd[l]) / (2.0 * se[l]);
-      double r = hypot(g, 1.0);
-      g = sd[mm] - sd[l] + se[l] / (g + copysign(r, g));
+      const double dl = lane_get(d, l), el = lane_get(e, l);
+      double g = (lane_get(d, l + 1) - dl) / (2.0 * el);
+      double r = hyp(g, 1.0);
+      g = lane_get(d, mm) - dl + el / (g + copysign(r, g));
       double sn = 1.0, cs = 1.0, p = 0.0;
       bool restart = false;
       // Chase the bulge from the bottom of the unreduced block up to row l,
       // one plane rotation in rows/columns (i, i+1) at a time.
       for (int i = mm - 1; i >= l; --i) {
-        const double f = sn * se[i];
-        const double b = cs * se[i];
-        r = hypot(f, g);
-        lockstep_store(&se[i + 1], r);
+        const double ei = lane_get(e, i);
+        const double f = sn * ei;
+        const double b = cs * ei;
+        r = hyp(f, g);
+        e = lane_put(e, r, i + 1);
+        const double di1 = lane_get(d, i + 1);
         if (r == 0.0) {
           // The rotation underflowed: the block has split at i+1; undo the
           // pending shift correction and look for the split again.
-          lockstep_store(&sd[i + 1], sd[i + 1] - p);
-          lockstep_store(&se[mm], 0.0);
+          d = lane_put(d, di1 - p, i + 1);
+          e = lane_put(e, 0.0, mm);
           restart = true;
           break;
         }
-        sn = f / r;
-        cs = g / r;
-        g = sd[i + 1] - p;
-        r = (sd[i] - g) * sn + 2.0 * cs * b;
+        const double rinv = 1.0 / r;
+        sn = f * rinv;
+        cs = g * rinv;
+        g = di1 - p;
+        r = (lane_get(d, i) - g) * sn + 2.0 * cs * b;
         p = sn * r;
-        lockstep_store(&sd[i + 1], g + p);
+        d = lane_put(d, g + p, i + 1);
         g = cs * r - b;
-        if (t < s) {
-          const double zi = Z[i * kMaxLeaf + t];
-          const double zj = Z[(i + 1) * kMaxLeaf + t];
-          Z[(i + 1) * kMaxLeaf + t] = sn * zi + cs * zj;
-          Z[i * kMaxLeaf + t] = cs * zi - sn * zj;
-        }
+        const double zi = Z[i * kMaxLeaf + t];
+        const double zj = Z[(i + 1) * kMaxLeaf + t];
+        Z[(i + 1) * kMaxLeaf + t] = sn * zi + cs * zj;
+        Z[i * kMaxLeaf + t] = cs * zi - sn * zj;
       }
       if (restart) continue;
-      lockstep_store(&sd[l], sd[l] - p);
-      lockstep_store(&se[l], g);
-      lockstep_store(&se[mm], 0.0);
+      d = lane_put(d, lane_get(d, l) - p, l);
+      e = lane_put(e, g, l);
+      e = lane_put(e, 0.0, mm);
     }
   }
   if (failed && t == 0) set_status(status, PHDC_ERR_LEAF);
-  // Selection sort into ascending order, moving eigenvector columns along.
-  for (int i = 0; i < s - 1; ++i) {
-    int best = i;
-    double bv = sd[i];
-    for (int j = i + 1; j < s; ++j)
-      if (sd[j] < bv) {
-        bv = sd[j];
-        best = j;
-      }
-    if (best != i) {
-      const double a = sd[i];
-      if (t < s) {
-        const double zi = Z[i * kMaxLeaf + t];
-        Z[i * kMaxLeaf + t] = Z[best * kMaxLeaf + t];
-        Z[best * kMaxLeaf + t] = zi;
-      }
-      lockstep_store(&sd[i], bv);
-      lockstep_store(&sd[best], a);
-    }
+  // Ascending order: rank of each eigenvalue (ties by index), then column c of
+  // Z goes to output column rank(c).
+  int rank = 0;
+  for (int j = 0; j < s; ++j) {
+    const double dj = lane_get(d, j);
+    rank += (dj < d || (dj == d && j < t)) ? 1 : 0;
   }
-  if (t < s) {
-    L.lam[t] = sd[t];
-    for (int c = 0; c < s; ++c) L.q[t + (int64_t)c * L.ldq] = Z[c * kMaxLeaf + t];
+  if (t < s) L.lam[rank] = d;
+  for (int c = 0; c < s; ++c) {
+    const int rc = __builtin_amdgcn_readlane(rank, c);
+    if (t < s) L.q[t + (int64_t)rc * L.ldq] = Z[c * kMaxLeaf + t];
   }
 }
 

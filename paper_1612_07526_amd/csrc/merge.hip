@@ -285,20 +285,24 @@ __global__ void __launch_bounds__(kDefThreads) k_deflate(const MergeDesc* __rest
   // 5. final survivors in pole order, Gu's grouping by part (Sec. 1): rows of
   // Uhat ordered [part 1 | part 2 | part 3]; the Q1-row product uses columns of
   // parts 1,2 and the Q2-row product those of parts 2,3.  Type-2 deflated list.
-  int c1 = 0, c2 = 0, c3 = 0, c4 = 0;
+  int c1 = 0, c2 = 0, c3 = 0, c4 = 0, g1 = 0, g2 = 0, g3 = 0;
   for (int k = t; k < m; k += kDefThreads) {
     int f = flag[k];
+    int p = part[k];
     if (f == 0) {
-      int p = part[k];
       c1 += (p == 1); c2 += (p == 2); c3 += (p == 3);
-    } else if (f == 2) {
-      ++c4;
+    } else {
+      c4 += (f == 2);
+      g1 += (p == 1); g2 += (p == 2); g3 += (p == 3);  // deflated columns by nonzero half
     }
   }
   const int k1 = (int)block_sum<kDefThreads>((double)c1, shd);
   const int k2 = (int)block_sum<kDefThreads>((double)c2, shd);
   const int k3 = (int)block_sum<kDefThreads>((double)c3, shd);
   const int nd2 = (int)block_sum<kDefThreads>((double)c4, shd);
+  const int dp1 = (int)block_sum<kDefThreads>((double)g1, shd);
+  const int dp2 = (int)block_sum<kDefThreads>((double)g2, shd);
+  const int dp3 = (int)block_sum<kDefThreads>((double)g3, shd);
   const int K = k1 + k2 + k3;
   int64_t b1 = 0, b2 = 0, b3 = 0, b4 = 0;
   for (int c0 = 0; c0 < m; c0 += kDefThreads) {
@@ -356,6 +360,9 @@ __global__ void __launch_bounds__(kDefThreads) k_deflate(const MergeDesc* __rest
     cnt[C_NT2] = nd2;
     cnt[C_ND1] = nd1;
     cnt[C_ND2] = nd2;
+    cnt[C_DP1] = dp1;
+    cnt[C_DP2] = dp2;
+    cnt[C_DP3] = dp3;
     cnt[C_PATH] = M.split_on ? 1 : (M.hss_min_k > 0 && K >= M.hss_min_k) ? 2 : 0;
     cnt[C_HSSRANK] = 0;
   }

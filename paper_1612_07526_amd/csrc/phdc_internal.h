@@ -15,7 +15,8 @@ constexpr int kCounters = 16;  // per-merge int32 counters
 // Counter slots (per merge).
 enum : int {
   C_K = 0, C_K1 = 1, C_K2 = 2, C_K3 = 3, C_NT1 = 4, C_NT2 = 5, C_PATH = 6, C_HSSRANK = 7,
-  C_NROT = 8, C_NCHAIN = 9, C_ND1 = 10, C_ND2 = 11
+  C_NROT = 8, C_NCHAIN = 9, C_ND1 = 10, C_ND2 = 11,
+  C_DP1 = 12, C_DP2 = 13, C_DP3 = 14  // deflated columns nonzero in the Q1 half only / both / the Q2 half only
 };
 
 // One rank-one merge of the divide-and-conquer tree.  All pointers are device pointers.
