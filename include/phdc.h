@@ -59,11 +59,12 @@ typedef struct phdc_opts {
     int32_t leaf_size;      /* largest block solved directly (default 32, range 2..64) */
     int32_t gemm_mode;      /* enum phdc_gemm_mode (default PHDC_GEMM_FP64) */
     int64_t hss_min_K;      /* HSS only for merges with at least this many surviving poles (default 4096) */
-    double hss_rel_tol;     /* relative ID truncation tolerance for HSS compression (default 1e-14) */
-    int32_t hss_leaf;       /* HSS leaf block size (default 256) */
-    int32_t hss_samples;    /* initial number of random sample columns d (default 256) */
-    int32_t hss_samples_inc;/* extra sample columns when a rank reaches d - 8 (default 128) */
-    int32_t split_slices;   /* number of BF16 slices per operand for PHDC_GEMM_SPLIT (default 7) */
+    double hss_rel_tol;     /* ID truncation tolerance for HSS compression (default 1e-14): a node's
+                               rank ends at |R_kk| <= tol * max(|R_00|, sqrt(d)), d samples */
+    int32_t hss_leaf;       /* HSS leaf block size, 8..1024 (default 256) */
+    int32_t hss_samples;    /* initial number of random sample columns d, 16..512 (default 256) */
+    int32_t hss_samples_inc;/* extra sample columns when a rank reaches d - 8, >= 0 (default 128) */
+    int32_t split_slices;   /* number of BF16 slices per operand for PHDC_GEMM_SPLIT, 1..7 (default 7) */
     uint64_t seed;          /* seed of the counter-based Gaussian generator used by HSS sampling */
     int32_t canonical_sign; /* if nonzero: each eigenvector's largest-magnitude entry is made positive */
     int32_t check_finite;   /* if nonzero: scan the inputs for NaN/Inf on the device */

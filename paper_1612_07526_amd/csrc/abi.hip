@@ -101,7 +101,7 @@ int32_t hss_threshold(const phdc_opts* o) {
 
 int split_slices(const phdc_opts* o) {
   if (!o || o->gemm_mode != PHDC_GEMM_SPLIT) return 0;
-  return std::min(7, std::max(1, o->split_slices));
+  return std::min(kSplitMaxSlices, std::max(1, o->split_slices));
 }
 
 // split-precision slot of one merge (per slice, in bf16 elements), a multiple of 8
@@ -254,7 +254,10 @@ void put(std::vector<char>& buf, size_t at, const T* src, size_t count) {
 }
 
 bool opts_ok(const phdc_opts* o) {
-  return o->leaf_size >= 2 && o->leaf_size <= kMaxLeaf && o->gemm_mode >= 0 && o->gemm_mode <= 2;
+  return o->leaf_size >= 2 && o->leaf_size <= kMaxLeaf && o->gemm_mode >= 0 && o->gemm_mode <= 2 &&
+         o->hss_leaf >= 8 && o->hss_leaf <= kHssLeafMax && o->hss_samples >= 16 && o->hss_samples <= 512 &&
+         o->hss_samples_inc >= 0 && o->hss_rel_tol > 0.0 && o->hss_rel_tol < 1.0 && o->split_slices >= 1 &&
+         o->split_slices <= kSplitMaxSlices;
 }
 
 // Everything one solve needs: tree, sizes and layout.

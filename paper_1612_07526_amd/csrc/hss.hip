@@ -23,9 +23,16 @@
 //   couple   Yh_c2 = Xh_c1 B_c1,         Yh_c1 = Xh_c2 B_c2
 //   down     [Yh_c1 Yh_c2] += Yh_p V_p^T
 //   leaves   U(:, t_i) += Yh_i V_i^T
-// The IDs use column-pivoted Householder QR of Phi^T with the relative
-// truncation tolerance hss_rel_tol (|R_kk| <= tol |R_00| ends the rank).
+// The IDs use column-pivoted Householder QR of Phi^T.  The rank ends at the
+// first pivot with |R_kk| <= max(tol |R_00|, tol sqrt(d) ||Uhat||_2), tol =
+// hss_rel_tol: relative to the node's own largest pivot, with a floor at the
+// size a Gaussian sample of a block with singular value tol ||Uhat||_2 has.
+// Uhat is orthogonal (||Uhat||_2 = 1).  Without the floor, the parents'
+// samples, formed by subtracting the sibling coupling from the children's
+// skeleton rows, carry rounding noise far above tol times their own (small)
+// largest pivot, and the ranks grow to the sample count.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <vector>
 
@@ -111,33 +118,51 @@ __global__ void __launch_bounds__(256) k_skel(const SkelDesc* __restrict__ sd) {
 // is the number of pivots with |R_kk| > tol |R_00|; T = R11^{-1} R12 and
 // U(perm[r + c], :) = T(:, c)^T.  One block per decomposition; the work copy
 // keeps Phi's layout, so row c of Phi (a column of Phi^T) is W(c, :).
-constexpr int kIdMax = 1024;
+constexpr int kIdMax = kHssLeafMax;  // rows p of one decomposition; the sample count d <= 512 < kIdMax
+constexpr int kIdThreads = 1024;
+constexpr int kIdWaves = kIdThreads / 64;
+constexpr int kIdLanes = 4;                     // lanes per column in the reflector update
+constexpr int kIdCols = kIdThreads / kIdLanes;  // columns updated at a time
 
-__global__ void __launch_bounds__(256) k_row_id(const IdDesc* __restrict__ ids, double tol) {
+__device__ inline double id_group_sum(double s) {
+  s += __shfl_xor(s, 1, 64);
+  s += __shfl_xor(s, 2, 64);
+  return s;
+}
+
+__global__ void __launch_bounds__(kIdThreads) k_row_id(const IdDesc* __restrict__ ids, double tol, double abs_tol) {
   __shared__ double cn[kIdMax], cn0[kIdMax], v[kIdMax];
   __shared__ int pv[kIdMax];
-  __shared__ double redv[4];
-  __shared__ int redi[4];
+  __shared__ double redv[kIdWaves];
+  __shared__ int redi[kIdWaves];
   __shared__ double sh_norm, sh_r00;
   __shared__ int sh_piv, sh_stop;
   const IdDesc D = ids[blockIdx.x];
   const int p = D.p, d = D.d;
   double* W = D.work;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  for (int e = t; e < p * d; e += 256) {
-    const int c = e % p, k = e / p;
+  const int sub = t % kIdLanes, cg = t / kIdLanes;
+  for (int64_t e = t; e < (int64_t)p * d; e += kIdThreads) {
+    const int c = (int)(e % p), k = (int)(e / p);
     W[c + (int64_t)k * p] = D.phi[c + (int64_t)k * D.ldphi];
   }
   __syncthreads();
-  for (int c = t; c < p; c += 256) {
+  // Squared norms of Phi's rows (columns of Phi^T), four lanes per row; each
+  // lane only touches the entries k = sub (mod 4) of its column.
+  for (int c0 = 0; c0 < p; c0 += kIdCols) {
+    const int c = c0 + cg;
     double s = 0.0;
-    for (int k = 0; k < d; ++k) {
-      const double x = W[c + (int64_t)k * p];
-      s += x * x;
+    if (c < p)
+      for (int k = sub; k < d; k += kIdLanes) {
+        const double x = W[c + (int64_t)k * p];
+        s += x * x;
+      }
+    s = id_group_sum(s);
+    if (c < p && sub == 0) {
+      cn[c] = s;
+      cn0[c] = s;
+      pv[c] = c;
     }
-    cn[c] = s;
-    cn0[c] = s;
-    pv[c] = c;
   }
   if (t == 0) {
     sh_r00 = 0.0;
@@ -149,7 +174,7 @@ __global__ void __launch_bounds__(256) k_row_id(const IdDesc* __restrict__ ids, 
   for (int j = 0; j < kmax; ++j) {
     double bv = -1.0;
     int bi = 0x7fffffff;
-    for (int c = j + t; c < p; c += 256)
+    for (int c = j + t; c < p; c += kIdThreads)
       if (cn[c] > bv) {
         bv = cn[c];
         bi = c;
@@ -170,7 +195,7 @@ __global__ void __launch_bounds__(256) k_row_id(const IdDesc* __restrict__ ids, 
     if (t == 0) {
       double b0 = redv[0];
       int i0 = redi[0];
-      for (int q = 1; q < 4; ++q)
+      for (int q = 1; q < kIdWaves; ++q)
         if (redv[q] > b0 || (redv[q] == b0 && redi[q] < i0)) {
           b0 = redv[q];
           i0 = redi[q];
@@ -178,13 +203,13 @@ __global__ void __launch_bounds__(256) k_row_id(const IdDesc* __restrict__ ids, 
       sh_piv = i0;
       const double nrm = sqrt(fmax(b0, 0.0));
       if (j == 0) sh_r00 = nrm;
-      sh_stop = (i0 >= p || sh_r00 == 0.0 || nrm <= tol * sh_r00) ? 1 : 0;
+      sh_stop = (i0 >= p || sh_r00 == 0.0 || nrm <= fmax(tol * sh_r00, abs_tol)) ? 1 : 0;
     }
     __syncthreads();
     if (sh_stop) break;
     const int piv = sh_piv;
     if (piv != j) {
-      for (int k = t; k < d; k += 256) {
+      for (int k = t; k < d; k += kIdThreads) {
         const double a = W[j + (int64_t)k * p];
         W[j + (int64_t)k * p] = W[piv + (int64_t)k * p];
         W[piv + (int64_t)k * p] = a;
@@ -204,7 +229,7 @@ __global__ void __launch_bounds__(256) k_row_id(const IdDesc* __restrict__ ids, 
     }
     // Householder reflector of x = W(j, j:d): v = x - alpha e_j, alpha = -sign(x_j) |x|
     double s = 0.0;
-    for (int k = j + t; k < d; k += 256) {
+    for (int k = j + t; k < d; k += kIdThreads) {
       const double x = W[j + (int64_t)k * p];
       v[k] = x;
       s += x * x;
@@ -212,7 +237,11 @@ __global__ void __launch_bounds__(256) k_row_id(const IdDesc* __restrict__ ids, 
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
     if (lane == 0) redv[w] = s;
     __syncthreads();
-    if (t == 0) sh_norm = sqrt(redv[0] + redv[1] + redv[2] + redv[3]);
+    if (t == 0) {
+      double tot = 0.0;
+      for (int q = 0; q < kIdWaves; ++q) tot += redv[q];
+      sh_norm = sqrt(tot);
+    }
     __syncthreads();
     const double xn = sh_norm;
     const double x0 = W[j + (int64_t)j * p];
@@ -222,22 +251,43 @@ __global__ void __launch_bounds__(256) k_row_id(const IdDesc* __restrict__ ids, 
     if (t == 0) v[j] = x0 - alpha;
     __syncthreads();
     if (vtv > 0.0) {
-      for (int c = j + 1 + t; c < p; c += 256) {
+      // Apply the reflector to the remaining columns, four lanes per column.
+      for (int c0 = j + 1; c0 < p; c0 += kIdCols) {
+        const int c = c0 + cg;
+        const bool on = c < p;
         double dot = 0.0;
-        for (int k = j; k < d; ++k) dot += v[k] * W[c + (int64_t)k * p];
+        if (on)
+          for (int k = j + sub; k < d; k += kIdLanes) dot += v[k] * W[c + (int64_t)k * p];
+        dot = id_group_sum(dot);
         const double f = 2.0 * dot / vtv;
-        for (int k = j; k < d; ++k) W[c + (int64_t)k * p] -= f * v[k];
-        const double rjc = W[c + (int64_t)j * p];
-        double nc = cn[c] - rjc * rjc;
-        if (nc <= 1e-2 * cn0[c]) {  // cancellation: recompute the remaining norm
-          nc = 0.0;
-          for (int k = j + 1; k < d; ++k) {
-            const double x = W[c + (int64_t)k * p];
-            nc += x * x;
+        double rjc = 0.0;
+        if (on)
+          for (int k = j + sub; k < d; k += kIdLanes) {
+            const double x = W[c + (int64_t)k * p] - f * v[k];
+            W[c + (int64_t)k * p] = x;
+            if (k == j) rjc = x;  // R_jc, held by lane sub == 0
           }
-          cn0[c] = nc;
+        rjc = id_group_sum(rjc);
+        double nc = on ? cn[c] - rjc * rjc : 0.0;
+        const bool redo = on && nc <= 1e-2 * cn0[c];  // same decision in all four lanes
+        if (redo) {  // cancellation: recompute the remaining norm
+          double q = 0.0;
+          for (int k = j + sub; k < d; k += kIdLanes)
+            if (k > j) {
+              const double x = W[c + (int64_t)k * p];
+              q += x * x;
+            }
+          nc = q;
         }
-        cn[c] = nc;
+        const double nred = id_group_sum(redo ? nc : 0.0);
+        if (on && sub == 0) {
+          if (redo) {
+            cn0[c] = nred;
+            cn[c] = nred;
+          } else {
+            cn[c] = nc;
+          }
+        }
       }
     }
     __syncthreads();
@@ -245,19 +295,25 @@ __global__ void __launch_bounds__(256) k_row_id(const IdDesc* __restrict__ ids, 
     __syncthreads();
     r = j + 1;
   }
-  double* U = D.U;
-  for (int e = t; e < p * r; e += 256) U[e % p + (int64_t)(e / p) * p] = 0.0;
-  __syncthreads();
-  for (int a = t; a < r; a += 256) U[pv[a] + (int64_t)a * p] = 1.0;
-  for (int c = r + t; c < p; c += 256) {
-    const int row = pv[c];
-    for (int a = r - 1; a >= 0; --a) {  // back substitution with R_ab = W(b, a)
-      double s = W[c + (int64_t)a * p];
-      for (int b = a + 1; b < r; ++b) s -= W[b + (int64_t)a * p] * U[row + (int64_t)b * p];
-      U[row + (int64_t)a * p] = s / W[a + (int64_t)a * p];
+  // T = R11^{-1} R12 by column-oriented back substitution: the thread of
+  // column c (c >= r) overwrites W(c, 0:r) = R12(:, c) with T(:, c).
+  for (int a = r - 1; a >= 0; --a) {
+    const double raa = W[a + (int64_t)a * p];
+    for (int c = r + t; c < p; c += kIdThreads) {
+      const double x = W[c + (int64_t)a * p] / raa;
+      W[c + (int64_t)a * p] = x;
+      for (int b = 0; b < a; ++b) W[c + (int64_t)b * p] -= W[a + (int64_t)b * p] * x;  // R_ba at W(a, b)
     }
   }
-  for (int c = t; c < p; c += 256) D.perm[c] = pv[c];
+  double* U = D.U;
+  for (int64_t e = t; e < (int64_t)p * r; e += kIdThreads) U[e] = 0.0;
+  __syncthreads();
+  for (int a = t; a < r; a += kIdThreads) U[pv[a] + (int64_t)a * p] = 1.0;
+  for (int c = r + t; c < p; c += kIdThreads) {
+    const int row = pv[c];
+    for (int a = 0; a < r; ++a) U[row + (int64_t)a * p] = W[c + (int64_t)a * p];
+  }
+  for (int c = t; c < p; c += kIdThreads) D.perm[c] = pv[c];
   if (t == 0) *D.rank = r;
 }
 
@@ -513,7 +569,8 @@ int run_hss_merge(const MergeDesc& M, int K, const Scratch& S, char* arena, size
         const IdDesc* did = st.push(idd);
         if (st.flush(key, s)) return -202;
         if (dg2) vgemm_launch(dg2, dp2, (int)g2.g.size(), g2.pf.back(), s);
-        hipLaunchKernelGGL(k_row_id, dim3((unsigned)idd.size()), dim3(256), 0, s, did, o->hss_rel_tol);
+        hipLaunchKernelGGL(k_row_id, dim3((unsigned)idd.size()), dim3(kIdThreads), 0, s, did, o->hss_rel_tol,
+                           o->hss_rel_tol * std::sqrt((double)d));
         if (hipMemcpyAsync(hr.data(), ranks, hr.size() * 4, hipMemcpyDeviceToHost, s) != hipSuccess) return -203;
         if (hipStreamSynchronize(s) != hipSuccess) return -204;
         for (int i : nodes) {

@@ -437,13 +437,15 @@ __device__ inline double group_sum(double v) {
   return v;
 }
 
-template <int G>
-__device__ bool secular_root(int K, const double* __restrict__ d, const double* __restrict__ z, double rho, int j,
-                             int sub, int* org_out, double* tau_out) {
+// SQ: z holds the squares z_i^2 (staged copies) instead of z_i.
+template <int G, bool SQ>
+__device__ __forceinline__ bool secular_root(int K, const double* __restrict__ d, const double* __restrict__ z,
+                                             double rho, int j, int sub, int* org_out, double* tau_out) {
+  auto z2 = [&](int i) { return SQ ? z[i] : z[i] * z[i]; };
   const double inv_rho = 1.0 / rho;
   if (K == 1) {
     *org_out = 0;
-    *tau_out = rho * z[0] * z[0];
+    *tau_out = rho * z2(0);
     return true;
   }
   int org;
@@ -452,7 +454,7 @@ __device__ bool secular_root(int K, const double* __restrict__ d, const double* 
     const double dj = d[j], dj1 = d[j + 1];
     const double half = 0.5 * (dj1 - dj);
     double w = 0.0;
-    for (int i = sub; i < K; i += G) w += z[i] * z[i] / ((d[i] - dj) - half);
+    for (int i = sub; i < K; i += G) w += z2(i) / ((d[i] - dj) - half);
     w = inv_rho + group_sum<G>(w);
     if (w >= 0.0) {
       org = j; lo = 0.0; hi = half;
@@ -463,11 +465,11 @@ __device__ bool secular_root(int K, const double* __restrict__ d, const double* 
     org = K - 1;
     lo = 0.0;
     double zz = 0.0;
-    for (int i = sub; i < K; i += G) zz += z[i] * z[i];
+    for (int i = sub; i < K; i += G) zz += z2(i);
     hi = rho * group_sum<G>(zz);
     for (int guard = 0; guard < 64; ++guard) {
       double w = 0.0;
-      for (int i = sub; i < K; i += G) w += z[i] * z[i] / ((d[i] - d[org]) - hi);
+      for (int i = sub; i < K; i += G) w += z2(i) / ((d[i] - d[org]) - hi);
       w = inv_rho + group_sum<G>(w);
       if (w >= 0.0) break;
       hi *= 2.0;
@@ -483,7 +485,7 @@ __device__ bool secular_root(int K, const double* __restrict__ d, const double* 
     for (int i = sub; i < K; i += G) {
       const double del = (d[i] - dorg) - tau;
       const double rcp = rcp_nr(del);
-      const double tt = z[i] * z[i] * rcp;
+      const double tt = z2(i) * rcp;
       const double dt = tt * rcp;
       if (i <= jl) { psi += tt; dpsi += dt; } else { phi += tt; dphi += dt; }
       eabs += fabs(tt);
@@ -517,18 +519,25 @@ __device__ bool secular_root(int K, const double* __restrict__ d, const double* 
   return ok;
 }
 
-constexpr int kSecG = 4;  // lanes per root
+constexpr int kSecG = 4;                        // lanes per root
+constexpr int kSecThreads = 256;                // threads per block
+constexpr int kSecRoots = kSecThreads / kSecG;  // roots per block
+constexpr int kSecLds = 2048;                   // poles staged in LDS (d_i and z_i^2: 32 KB)
 
-// 64-lane blocks, 16 roots per block.
-__global__ void __launch_bounds__(64) k_secular(BlockMap bm, Scratch S) {
+// 256-lane blocks, 64 roots per block.  Merges with K <= kSecLds stage the
+// poles and squared weights in LDS once; larger ones read them from global
+// memory (L2-resident).
+__global__ void __launch_bounds__(kSecThreads) k_secular(BlockMap bm, Scratch S) {
+  __shared__ double sd[kSecLds];
+  __shared__ double sz[kSecLds];
   const int b = blockIdx.x;
   const int mi = find_merge(bm, b);
   const int lb = b - bm.pfx[mi];
   const MergeDesc M = bm.descs[mi];
   const int K = S.counters[(int64_t)M.id * kCounters + C_K];
-  const int j = lb * (64 / kSecG) + (int)threadIdx.x / kSecG;
+  if (lb * kSecRoots >= K) return;  // whole block idle (uniform)
+  const int j = lb * kSecRoots + (int)threadIdx.x / kSecG;
   const int sub = threadIdx.x % kSecG;
-  if (lb * (64 / kSecG) >= K) return;  // whole block idle (uniform)
   const bool active = j < K;
   const int64_t so = M.s_off;
   const double rho = S.mparam[(int64_t)M.id * 4 + 0];
@@ -536,7 +545,19 @@ __global__ void __launch_bounds__(64) k_secular(BlockMap bm, Scratch S) {
   double tau = 0.0;
   // inactive groups of a partly filled block run root K-1 redundantly so that
   // every lane takes part in the group shuffles; only active groups write
-  bool ok = secular_root<kSecG>(K, S.ds + so, S.zs + so, rho, active ? j : K - 1, sub, &org, &tau);
+  const int jj = active ? j : K - 1;
+  bool ok;
+  if (K <= kSecLds) {
+    for (int i = threadIdx.x; i < K; i += kSecThreads) {
+      sd[i] = S.ds[so + i];
+      const double zi = S.zs[so + i];
+      sz[i] = zi * zi;
+    }
+    __syncthreads();
+    ok = secular_root<kSecG, true>(K, sd, sz, rho, jj, sub, &org, &tau);
+  } else {
+    ok = secular_root<kSecG, false>(K, S.ds + so, S.zs + so, rho, jj, sub, &org, &tau);
+  }
   if (active && sub == 0) {
     S.org[so + j] = org;
     S.tau[so + j] = tau;
@@ -552,7 +573,7 @@ __global__ void __launch_bounds__(64) k_secular_raw(int K, const double* d, cons
   const bool active = j < K;
   int o = 0;
   double t = 0.0;
-  bool ok = secular_root<kSecG>(K, d, z, rho, active ? j : K - 1, sub, &o, &t);
+  bool ok = secular_root<kSecG, false>(K, d, z, rho, active ? j : K - 1, sub, &o, &t);
   if (active && sub == 0) {
     org[j] = o;
     tau[j] = t;
@@ -695,29 +716,47 @@ __global__ void __launch_bounds__(256) k_rank(BlockMap bm, Scratch S) {
 // ------------------------------------------------------------ deflated columns
 // Deflated columns of Q G P (Eq. (6), the identity block) go unchanged to
 // their output position; halves that are structurally zero are written as 0.
-constexpr int kCopyGroups = 64;
+constexpr int kCopyBlocks = 16384;  // cap on column blocks per merge
 
+// Each block streams whole columns: a column group of RPT lanes (RPT = m
+// rounded up to a power of two, at most 256) walks the rows, 256 / RPT columns
+// per block at a time, four rows in flight per lane.  Only the half a column
+// can be nonzero in is read; the other half is written as zeros.
 __global__ void __launch_bounds__(256) k_copy_deflated(BlockMap bm, Scratch S) {
   const int b = blockIdx.x;
   const int mi = find_merge(bm, b);
   const int lb = b - bm.pfx[mi];
+  const int G = bm.pfx[mi + 1] - bm.pfx[mi];
   const MergeDesc M = bm.descs[mi];
-  const int m = M.m;
-  const int RB = cdiv_d(m, 256);
-  const int G = (bm.pfx[mi + 1] - bm.pfx[mi]) / RB;
-  const int rb = lb % RB, g = lb / RB;
-  const int r = rb * 256 + threadIdx.x;
-  if (r >= m) return;
+  const int m = M.m, n1 = M.n1;
   const int32_t* cnt = S.counters + (int64_t)M.id * kCounters;
-  const int nd1 = cnt[C_ND1], nd2 = cnt[C_ND2];
+  const int nd1 = cnt[C_ND1], nd = nd1 + cnt[C_ND2];
   const int64_t so = M.s_off;
-  const bool top = r < M.n1;
-  for (int q = g; q < nd1 + nd2; q += G) {
+  int rpt = 1;
+  while (rpt < m && rpt < 256) rpt <<= 1;
+  const int cpb = 256 / rpt;
+  const int lane = threadIdx.x % rpt, sub = threadIdx.x / rpt;
+  for (int q = lb * cpb + sub; q < nd; q += G * cpb) {
     int c, p, dst;
     if (q < nd1) { c = S.dfc1[so + q]; p = S.dfp1[so + q]; dst = S.destd1[so + q]; }
     else { const int q2 = q - nd1; c = S.dfc2[so + q2]; p = S.dfp2[so + q2]; dst = S.destd2[so + q2]; }
-    const double v = part_valid(p, top) ? M.qin[r + (int64_t)c * M.ldin] : 0.0;
-    M.qout[r + (int64_t)dst * M.ldout] = v;
+    const int lo = (p == 3) ? n1 : 0, hi = (p == 1) ? n1 : m;  // rows that can be nonzero
+    const double* src = M.qin + (int64_t)c * M.ldin;
+    double* out = M.qout + (int64_t)dst * M.ldout;
+    constexpr int U = 4;
+    for (int r0 = lane; r0 < m; r0 += U * rpt) {
+      double v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int r = r0 + u * rpt;
+        v[u] = (r >= lo && r < hi) ? src[r] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int r = r0 + u * rpt;
+        if (r < m) out[r] = v[u];
+      }
+    }
   }
 }
 
@@ -733,7 +772,11 @@ int map_blocks(int kind, int m, int n1) {
     case MAP_ROT: return cdiv(m, 256) * std::max(1, std::min(m / 2, kRotGroups));
     case MAP_UWRITE: return cdiv(m, 256) * std::max(1, std::min(m, kUwRowGroups));
     case MAP_GEMM: return (cdiv(n1, kGemmTile) + cdiv(m - n1, kGemmTile)) * cdiv(m, kGemmTile);
-    case MAP_COPY: return cdiv(m, 256) * std::max(1, std::min(m, kCopyGroups));
+    case MAP_COPY: {  // columns per block = 256 / (m rounded up to a power of two, at most 256)
+      int rpt = 1;
+      while (rpt < m && rpt < 256) rpt <<= 1;
+      return std::max(1, std::min(cdiv(m, 256 / rpt), kCopyBlocks));
+    }
     case MAP_SPLITA: return cdiv(m, 256) * kSplitKGroups;
     case MAP_SPLITB: return cdiv(m + 8, 256) * kSplitRGroups;
   }
@@ -751,7 +794,7 @@ void launch_merge_level(const MergeDesc* descs, int nm, const LevelMaps& maps, c
   { ProfScope p(PH_ROTATE, s);
     hipLaunchKernelGGL(k_rotate, dim3(maps.total[MAP_ROT]), dim3(256), 0, s, bmap(MAP_ROT), S); }
   { ProfScope p(PH_SECULAR, s);
-    hipLaunchKernelGGL(k_secular, dim3(maps.total[MAP_ROOTS16]), dim3(64), 0, s, bmap(MAP_ROOTS16), S); }
+    hipLaunchKernelGGL(k_secular, dim3(maps.total[MAP_ROOTS64]), dim3(kSecThreads), 0, s, bmap(MAP_ROOTS64), S); }
   { ProfScope p(PH_LOWNER, s);
     hipLaunchKernelGGL(k_lowner, dim3(maps.total[MAP_ROOTS64]), dim3(64), 0, s, bmap(MAP_ROOTS64), S); }
   { ProfScope p(PH_UNORM, s);

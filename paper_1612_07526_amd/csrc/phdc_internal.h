@@ -10,6 +10,8 @@ namespace phdc {
 
 constexpr double kUnitRoundoff = 1.1102230246251565e-16;  // 2^-53
 constexpr int kMaxLeaf = 64;
+constexpr int kHssLeafMax = 1024;    // largest HSS leaf (rows of one interpolative decomposition)
+constexpr int kSplitMaxSlices = 7;   // BF16 slices per operand on the split-precision path
 constexpr int kCounters = 16;  // per-merge int32 counters
 
 // Counter slots (per merge).

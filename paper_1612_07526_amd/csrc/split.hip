@@ -127,7 +127,7 @@ __global__ void __launch_bounds__(256) k_split_slice_b(BlockMap bm, Scratch S, S
 constexpr int XT = 128;  // output tile
 constexpr int XK = 32;   // k per step (one BF16 MFMA depth)
 constexpr int XLD = XK + 8;  // LDS row stride in bf16 (16-byte aligned rows)
-constexpr int XMAXS = 7;
+constexpr int XMAXS = kSplitMaxSlices;
 
 __global__ void __launch_bounds__(256) k_split_gemm(BlockMap bm, Scratch S, SplitBufs B, int nsl) {
   __shared__ __attribute__((aligned(16))) __bf16 As[XMAXS][XT][XLD];

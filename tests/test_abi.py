@@ -58,7 +58,10 @@ def test_workspace_queries_are_host_only():
     assert lib.phdc_stedc_batched_workspace(3, n, ctypes.byref(o), ctypes.byref(nb)) == 0
 
 
-@pytest.mark.parametrize("field,value", [("leaf_size", 1), ("leaf_size", 65), ("gemm_mode", 7)])
+@pytest.mark.parametrize("field,value", [("leaf_size", 1), ("leaf_size", 65), ("gemm_mode", 7), ("hss_leaf", 4),
+                                         ("hss_leaf", 2048), ("hss_samples", 8), ("hss_samples", 1024),
+                                         ("hss_samples_inc", -1), ("hss_rel_tol", 0.0), ("hss_rel_tol", 1.5),
+                                         ("split_slices", 0), ("split_slices", 8)])
 def test_bad_options_rejected(field, value):
     P, lib = _lib()
     o = P.opts(**{field: value})
