@@ -12,6 +12,8 @@ Also on the same JSON line (each section can be skipped with --skip):
   merge_gemm   -- the large-K rank-one merge of Sec. 2.2 (poles i/N, N = 16384, K = N):
                   FP64-MFMA update TFLOP/s vs peak; HSS and split-precision update times
   toeplitz     -- diagonal 2 / off-diagonal 1 at n = 16383 (no deflation at the top)
+  examples     -- the paper's Examples 3-4 (Clement, Hermite, Toeplitz-type, SHT) at n = 30000,
+                  plain vs HSS for merges with K >= 20000
   split        -- n = 32768, d ~ N(0,1), e ~ U[0.1,1]: split precision vs FP64 MFMA
   batch        -- 4096 matrices of sizes U{32..1024}: graph-replayed batched launches vs
                   one solve call per matrix
@@ -123,6 +125,25 @@ class Solver:
         return orth, res
 
 
+def reference_copy_gbs():
+    """Bytes moved per second by a plain 1 GiB device-to-device copy (read + write), the
+    practical ceiling of a copy-like kernel on this GPU."""
+    import torch
+    x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        y.copy_(x)
+    e1.record()
+    e1.synchronize()
+    gbs = 5 * 2 * x.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+    return round(gbs, 1)
+
+
 # Kernel phase -> (counter summary under profiles/, source file the kernel is built from).
 TRAFFIC_SUMMARIES = {
     "copy": ("profiles/k_copy_deflated_uniform_n16384_traffic.md", "paper_1612_07526_amd/csrc/merge.hip"),
@@ -150,9 +171,10 @@ def measured_traffic(phase):
     return float(fields["traffic_bytes_per_launch"])
 
 
-def timed_profiled(P, fn, steps, warmup):
-    """Time `steps` calls with the library's per-phase HIP events recorded on the launch
-    stream inside the same timed region: returns (s per call, {phase: (ms, launches) per call})."""
+def timed_profiled(P, fn, steps, warmup, phases):
+    """Time `steps` calls with the library's HIP events recorded on the launch stream around
+    the kernels of `phases` only, inside the same timed region: returns
+    (s per call, {phase: (ms, launches) per call})."""
     import torch
     lib = P.load()
     for _ in range(warmup):
@@ -160,6 +182,7 @@ def timed_profiled(P, fn, steps, warmup):
     sync()
     n = len(P.PHASES)
     lib.phdc_profile_read((ctypes.c_double * n)(), (ctypes.c_int64 * n)(), n)
+    lib.phdc_profile_select(sum(1 << P.PHASES.index(p) for p in phases))
     lib.phdc_profile_enable(1)
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -167,6 +190,7 @@ def timed_profiled(P, fn, steps, warmup):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     lib.phdc_profile_enable(0)
+    lib.phdc_profile_select(0xFFFFFFFF)
     ms = (ctypes.c_double * n)()
     cnt = (ctypes.c_int64 * n)()
     lib.phdc_profile_read(ms, cnt, n)
@@ -178,27 +202,34 @@ def sec_value(P, W, args, out):
     d, e = W.uniform(n, seed=0)
     chosen = P.GEMM_FP64 if "hss" in args.skip_paths else P.GEMM_HSS
     ch = Solver(P, d, e, P.opts(gemm_mode=chosen))
-    log(f"[bench] value: warmup {args.warmup}, timing {args.steps} solves of uniform n={n} (chosen form, "
-        "phase events on the launch stream)")
-    t_ch, phases = timed_profiled(P, ch, args.steps, args.warmup)
+    for _ in range(args.warmup):
+        ch()
+    # every phase, in an untimed pass: the breakdown and the dominant kernel
+    phases = profile_phases(P, ch, reps=2)
+    dom = max(phases.items(), key=lambda kv: kv[1][0])[0]
+    log("[bench] phases (ms/solve, untimed pass with events around every phase): "
+        + ", ".join(f"{k}={v[0]:.3f}" for k, v in phases.items()))
+    log(f"[bench] value: timing {args.steps} solves of uniform n={n} (chosen form; HIP events around the "
+        f"dominant kernel class '{dom}' only)")
+    t_ch, dom_ph = timed_profiled(P, ch, args.steps, 0, [dom])
     st = P.status(ch.work)
     if st != 0:
         raise RuntimeError(f"device status {st}")
     table = merge_table(P, ch.work)
     alg = algorithmic(table)
-    log("[bench] phases (ms/solve): " + ", ".join(f"{k}={v[0]:.3f}" for k, v in phases.items()))
     t_clean = timed(ch, args.steps, 0)
     orth, res = ch.accuracy()
     log(f"[bench] chosen form {t_ch * 1e3:.3f} ms/solve ({t_clean * 1e3:.3f} without events); "
-        f"top merge K={table[-1, 2]}; orth {orth:.2e} res {res:.2e}")
+        f"{dom} {dom_ph[dom][0]:.3f} ms in {dom_ph[dom][1]} launches; top merge K={table[-1, 2]}; "
+        f"orth {orth:.2e} res {res:.2e}")
     lam_gpu = ch.lam.cpu().numpy()
     del ch
     pl = Solver(P, d, e, P.opts(gemm_mode=P.GEMM_FP64))
     t_pl = timed(pl, args.steps, 1)
     log(f"[bench] plain FP64 {t_pl * 1e3:.3f} ms/solve")
     del pl
-    out.update(t_ch=t_ch, t_clean=t_clean, t_pl=t_pl, orth=orth, res=res, phases=phases, alg=alg, table=table,
-               lam=lam_gpu, d=d, e=e)
+    out.update(t_ch=t_ch, t_clean=t_clean, t_pl=t_pl, orth=orth, res=res, phases=phases, dom=dom, dom_ph=dom_ph,
+               alg=alg, table=table, lam=lam_gpu, d=d, e=e)
 
 
 def sec_merge_gemm(P, W, args):
@@ -285,6 +316,32 @@ def sec_toeplitz(P, W, args):
     return res
 
 
+def sec_examples(P, W, args):
+    """The paper's Example 3 matrices (Clement, Hermite, Toeplitz-type) and Example 4 (SHT, m = n)
+    at n = 30000, plain FP64-MFMA vs HSS for merges with K >= 20000 (the paper's rule)."""
+    import torch
+    n = 30000
+    res = {"workload": f"Examples 3-4 of the paper at n={n}; HSS for merges with K >= 20000"}
+    for gen in ("clement", "hermite", "toeplitz_121", "sht"):
+        d, e = W.tridiag(gen, n)
+        entry = {}
+        for name, o in (("fp64", P.opts(gemm_mode=P.GEMM_FP64)),
+                        ("hss", P.opts(gemm_mode=P.GEMM_HSS, hss_min_K=20000))):
+            s = Solver(P, d, e, o)
+            t = timed(s, 1, 1)
+            orth, rr = s.accuracy()
+            tab = merge_table(P, s.work)
+            entry[name] = {"solve_s": round(t, 4), "orth": orth, "residual": rr, "top_K": int(tab[-1, 2]),
+                           "top_path": int(tab[-1, 8]), "hss_rank": int(tab[-1, 9])}
+            del s
+            torch.cuda.empty_cache()
+        if "fp64" in entry and "hss" in entry:
+            entry["hss_speedup"] = round(entry["fp64"]["solve_s"] / entry["hss"]["solve_s"], 3)
+        log(f"[bench] example {gen} n={n}: {entry}")
+        res[gen] = entry
+    return res
+
+
 def sec_split(P, W, args):
     import torch
     n = 32768
@@ -312,6 +369,9 @@ def sec_batch(P, W, args):
     bs.prepare()
     bs.launch()
     sync()
+    t_eager = timed(bs.launch, 3, 1)
+    phases = profile_phases(P, bs.launch, reps=1)
+    log("[bench] batch phases (ms, one eager launch): " + ", ".join(f"{k}={v[0]:.3f}" for k, v in phases.items()))
     bs.capture()
     t_graph = timed(bs.replay, 3, 1)
     st = P.status(bs.work)
@@ -339,6 +399,7 @@ def sec_batch(P, W, args):
     t_pm = timed(per_matrix, 1, 1)
     log(f"[bench] batch: per-matrix calls {t_pm * 1e3:.1f} ms")
     res = {"workload": "4096 tridiagonals, n_b ~ U{32..1024}, d,e ~ N(0,1)", "graph_s": round(t_graph, 5),
+           "eager_launch_s": round(t_eager, 5), "phases_ms": {k: round(v[0], 3) for k, v in phases.items()},
            "per_matrix_s": round(t_pm, 5), "speedup": round(t_pm / t_graph, 2),
            "matrices_per_s": round(len(sizes) / t_graph, 1)}
     del bs, work
@@ -378,7 +439,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--skip", default="", help="comma list of sections: merge_gemm,toeplitz,split,batch,adjoint,cpu")
+    ap.add_argument("--skip", default="", help="comma list of sections: merge_gemm,toeplitz,examples,split,batch,adjoint,cpu")
     ap.add_argument("--skip-paths", default="", help="comma list of update paths to leave out: hss,split")
     ap.add_argument("--only-value", action="store_true", help="time the headline solve only (profiling runs)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -391,7 +452,7 @@ def main():
     args.skip = set(x for x in args.skip.split(",") if x)
     args.skip_paths = set(x for x in args.skip_paths.split(",") if x)
     if args.only_value:
-        args.skip |= {"merge_gemm", "toeplitz", "split", "batch", "adjoint", "cpu"}
+        args.skip |= {"merge_gemm", "toeplitz", "examples", "split", "batch", "adjoint", "cpu"}
 
     import paper_1612_07526_amd as P
     import workloads as W
@@ -408,8 +469,8 @@ def main():
     v = {}
     sec_value(P, W, args, v)
     sections = {}
-    for name, fn in (("merge_gemm", sec_merge_gemm), ("toeplitz", sec_toeplitz), ("split", sec_split),
-                     ("batch", sec_batch), ("adjoint", sec_adjoint)):
+    for name, fn in (("merge_gemm", sec_merge_gemm), ("toeplitz", sec_toeplitz), ("examples", sec_examples),
+                     ("split", sec_split), ("batch", sec_batch), ("adjoint", sec_adjoint)):
         if name in args.skip:
             continue
         try:
@@ -418,9 +479,8 @@ def main():
             log(f"[bench] section {name} failed: {ex!r}")
             sections[name] = {"error": repr(ex)}
 
-    phases, alg = v["phases"], v["alg"]
-    dom = max(phases.items(), key=lambda kv: kv[1][0])[0]
-    ms_dom, cnt_dom = phases[dom]
+    phases, alg, dom = v["phases"], v["alg"], v["dom"]
+    ms_dom, cnt_dom = v["dom_ph"][dom]  # measured inside the timed region
     if dom == "gemm":
         roof = {"bound": "mfma", "achieved": alg["gemm_flops"] / (ms_dom * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s"}
@@ -439,8 +499,8 @@ def main():
                 ms_per_step=round(ms_dom, 4))
     if dom == "copy":
         roof["algorithmic_bytes_per_launch"] = round(alg["copy_bytes"] / max(cnt_dom, 1))
-    if "copy" in phases:
-        roof["copy_kernel_gbs"] = round(alg["copy_bytes"] / (phases["copy"][0] * 1e-3) / 1e9, 1)
+    if roof["bound"] == "hbm":
+        roof["reference_copy_gbs"] = reference_copy_gbs()
 
     cpu = None
     if "cpu" not in args.skip:

@@ -166,6 +166,10 @@ int phdc_merge_stats(const void *work, int32_t *stats_host);
  * and forgets them.  Returns 0. */
 int phdc_profile_enable(int on);
 int phdc_profile_read(double *ms, int64_t *count, int nphase);
+/* Restrict the recorded phases to the set bits of mask (bit i = phase i in the
+ * order above; default: all).  Fewer events perturb the timed work less.
+ * Returns 0. */
+int phdc_profile_select(uint32_t mask);
 
 /* Sizes of every merge of the last stedc/merge call on `work` (call after
  * phdc_status): up to max_rows rows of PHDC_MERGE_TABLE_COLS int32 each:
@@ -185,6 +189,25 @@ int phdc_merge_table(const void *work, int64_t max_rows, int32_t *table_host, in
  * Non-convergence is reported through phdc_status(work). */
 int phdc_secular(int64_t K, const double *d, const double *z, double rho, int32_t *org, double *tau,
                  void *work, size_t lwork, void *stream);
+
+/* ---------------------------------------------------------------- GEMM tile autotuner
+ * The FP64 update GEMM (Eq. (6)) of every tree level uses square output tiles
+ * of edge 64 or 128, looked up per merge-size bucket (2^(b-1) < m <= 2^b) in a
+ * process-wide table when a solve is planned.  phdc_autotune_gemm times both
+ * edges with HIP events on a synthetic merge of each size m = 64, 128, ...,
+ * max_m (no deflation, K = m) and records the faster one; untimed buckets use
+ * 64 up to m = 256 and 128 above.  The tile changes the speed only: both edges
+ * accumulate in the same k order, so results are bitwise identical.
+ *   max_m   largest merge size to time, 2 <= max_m <= 2^20
+ *   work    device scratch of at least phdc_autotune_gemm_workspace(max_m) bytes
+ *           (three max_m x max_m FP64 arrays and index arrays), 256-byte aligned
+ * Synchronises the stream; not for use under graph capture.  Returns 0 or a
+ * negative code (-1 bad size, -2 null work, -3 lwork too small, < -3 HIP error).
+ * phdc_gemm_tile_table copies the table (0 = not timed) into tiles[0:n) and
+ * returns the number of buckets written. */
+int phdc_autotune_gemm_workspace(int64_t max_m, size_t *bytes);
+int phdc_autotune_gemm(int64_t max_m, void *work, size_t lwork, void *stream);
+int phdc_gemm_tile_table(int32_t *tiles, int n);
 
 #ifdef __cplusplus
 }

@@ -80,6 +80,10 @@ def load():
     lib.phdc_merge_table.argtypes = [_vp, _i64, P(ctypes.c_int32), P(_i64)]
     lib.phdc_profile_enable.argtypes = [ctypes.c_int]
     lib.phdc_profile_read.argtypes = [P(ctypes.c_double), P(_i64), ctypes.c_int]
+    lib.phdc_profile_select.argtypes = [ctypes.c_uint32]
+    lib.phdc_autotune_gemm_workspace.argtypes = [_i64, P(_sz)]
+    lib.phdc_autotune_gemm.argtypes = [_i64, _vp, _sz, _vp]
+    lib.phdc_gemm_tile_table.argtypes = [P(ctypes.c_int32), ctypes.c_int]
     _lib = lib
     return lib
 
@@ -87,19 +91,42 @@ def load():
 EXPORTS = ["phdc_stedc_batched_prepare", "phdc_launch_prepared", "phdc_opts_default", "phdc_version", "phdc_stedc_workspace", "phdc_stedc", "phdc_merge_workspace",
            "phdc_merge", "phdc_stedc_batched_workspace", "phdc_stedc_batched", "phdc_stedc_backward_workspace",
            "phdc_stedc_backward", "phdc_status", "phdc_merge_stats", "phdc_secular", "phdc_merge_table",
-           "phdc_profile_enable", "phdc_profile_read"]
+           "phdc_profile_enable", "phdc_profile_read", "phdc_profile_select", "phdc_autotune_gemm_workspace",
+           "phdc_autotune_gemm",
+           "phdc_gemm_tile_table"]
+
+
+def autotune_gemm(max_m: int = 4096, device="cuda", stream=None) -> list:
+    """Time both FP64 update-GEMM tile edges on synthetic merges of size 64..max_m and
+    record the faster per size bucket (used by every solve planned afterwards).
+    Returns the tile table (entry b: bucket 2^(b-1) < m <= 2^b; 0 = not timed)."""
+    lib = load()
+    nb = _sz()
+    _check(lib.phdc_autotune_gemm_workspace(int(max_m), ctypes.byref(nb)), "phdc_autotune_gemm_workspace")
+    work = workspace(nb.value, device)
+    _check(lib.phdc_autotune_gemm(int(max_m), _ptr(work), nb.value, _stream(stream)), "phdc_autotune_gemm")
+    return gemm_tile_table()
+
+
+def gemm_tile_table() -> list:
+    buf = (ctypes.c_int32 * 32)()
+    n = load().phdc_gemm_tile_table(buf, 32)
+    return list(buf)[:max(n, 0)]
 
 PHASES = ["leaf", "deflate", "rotate", "secular", "loewner", "uhat_norm", "uhat_write", "rank", "gemm", "copy",
           "sign", "split_slice", "split_gemm", "hss_sample", "hss_compress", "hss_apply", "adj_gemm", "adj_band"]
 
 
-def profile_phases(fn, reps: int = 1) -> dict:
-    """Run fn() reps times with the library's per-phase HIP-event timing on; returns
-    {phase: (ms per rep, launches per rep)} for the phases that ran."""
+def profile_phases(fn, reps: int = 1, phases=None) -> dict:
+    """Run fn() reps times with the library's per-phase HIP-event timing on (all phases,
+    or only those named in ``phases``); returns {phase: (ms per rep, launches per rep)}
+    for the phases that ran."""
     lib = load()
     torch.cuda.synchronize()
     n = len(PHASES)
     lib.phdc_profile_read((ctypes.c_double * n)(), (_i64 * n)(), n)  # drop anything pending
+    mask = 0xFFFFFFFF if phases is None else sum(1 << PHASES.index(p) for p in phases)
+    lib.phdc_profile_select(mask)
     lib.phdc_profile_enable(1)
     try:
         for _ in range(reps):
@@ -107,6 +134,7 @@ def profile_phases(fn, reps: int = 1) -> dict:
         torch.cuda.synchronize()
     finally:
         lib.phdc_profile_enable(0)
+        lib.phdc_profile_select(0xFFFFFFFF)
     ms = (ctypes.c_double * n)()
     cnt = (_i64 * n)()
     _check(lib.phdc_profile_read(ms, cnt, n), "phdc_profile_read")

@@ -328,7 +328,7 @@ void launch_prepared_all(char* base, const Prepared& P, hipStream_t s) {
   launch_clear_status(P.S.status, s);
   {
     ProfScope p(PH_LEAF, s);
-    launch_leaf_ql((const LeafArgs*)(base + P.L.leaves), P.nleaves, P.S.status, s);
+    launch_leaf_ql((const LeafArgs*)(base + P.L.leaves), P.nleaves, P.S.status, P.o.leaf_size, s);
   }
   const MergeDesc* dd = (const MergeDesc*)(base + P.L.descs);
   for (int h = 1; h <= P.z.H; ++h) {
@@ -428,12 +428,14 @@ int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n,
   std::vector<LevelMaps> lm(z.H + 1);
   for (int h = 1; h <= z.H; ++h) {
     const int a = T.hstart[h - 1], e = T.hstart[h];
+    for (int i = a; i < e; ++i) lm[h].maxm = std::max(lm[h].maxm, T.merges[i].m);
+    lm[h].gemm_tile = (o->gemm_mode == PHDC_GEMM_SPLIT) ? 128 : gemm_tile_for(lm[h].maxm);
     for (int k = 0; k < MAP_COUNT; ++k) {
       const size_t at = maps.size();
       int32_t acc = 0;
       maps.push_back(0);
       for (int i = a; i < e; ++i) {
-        acc += map_blocks(k, T.merges[i].m, T.merges[i].n1);
+        acc += map_blocks(k, T.merges[i].m, T.merges[i].n1, lm[h].gemm_tile);
         maps.push_back(acc);
       }
       lm[h].pfx[k] = (const int32_t*)(base + L.maps) + at;
@@ -471,7 +473,7 @@ int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n,
   if (upload(work, base + plan0, plan, s) != 0) return -101;
   {
     ProfScope p(PH_LEAF, s);
-    launch_leaf_ql((const LeafArgs*)(base + L.leaves), (int)T.leaves.size(), S.status, s);
+    launch_leaf_ql((const LeafArgs*)(base + L.leaves), (int)T.leaves.size(), S.status, o->leaf_size, s);
   }
   const MergeDesc* dd = (const MergeDesc*)(base + L.descs);
   for (int h = 1; h <= z.H; ++h) {
@@ -765,9 +767,11 @@ int phdc_merge(int64_t n1, int64_t n2, const double* D, const double* z, double 
   std::memcpy(plan.data() + (L.canon_pfx - L.hdr), pf, sizeof(pf));
   std::vector<int32_t> maps;
   LevelMaps lm;
+  lm.maxm = (int32_t)m;
+  lm.gemm_tile = (o->gemm_mode == PHDC_GEMM_SPLIT) ? 128 : gemm_tile_for(m);
   for (int k = 0; k < MAP_COUNT; ++k) {
     lm.pfx[k] = (const int32_t*)(base + L.maps) + maps.size();
-    lm.total[k] = map_blocks(k, (int)m, (int)n1);
+    lm.total[k] = map_blocks(k, (int)m, (int)n1, lm.gemm_tile);
     maps.push_back(0);
     maps.push_back(lm.total[k]);
   }

@@ -8,21 +8,32 @@
 // block (no packed copy), Uhat is row-major, and column j of the result is
 // written to its final (sorted) output column dest[j].
 //
-// Tiling for gfx950: 256 threads (4 waves) per 128x128 output tile, each wave a
-// 64x64 quadrant made of 4x4 v_mfma_f64_16x16x4 blocks; k-steps of 16 staged
+// Tiling for gfx950: 256 threads (4 waves) per GT x GT output tile (GT = 64 or
+// 128, chosen per tree level from a table that phdc_autotune_gemm measures),
+// each wave a quadrant of v_mfma_f64_16x16x4 blocks; k-steps of 16 staged
 // through double-buffered LDS.
+#include <algorithm>
+#include <atomic>
+#include <cstdint>
+
 #include "phdc_internal.h"
 
 namespace phdc {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
-constexpr int GT = 128;       // output tile edge
 constexpr int GK = 16;        // k per LDS stage
 constexpr int GPAD = 4;       // LDS row padding (doubles)
-constexpr int GLD = GT + GPAD;
 
+// GT x GT output tile, 256 threads (4 waves in 2 x 2), each wave a GT/2 x GT/2
+// quadrant of 16 x 16 MFMA blocks.  The k loop runs in the same order for
+// every tile size, so the result does not depend on GT.
+template <int GT>
 __global__ void __launch_bounds__(256) k_merge_gemm(BlockMap bm, Scratch S) {
+  constexpr int GLD = GT + GPAD;
+  constexpr int E = GT * GK / 256;  // elements of A (and of B) each thread stages per k-step
+  constexpr int WT = GT / 2;        // wave tile edge
+  constexpr int NB = WT / 16;       // MFMA blocks per wave tile edge
   __shared__ double As[2][GK][GLD];
   __shared__ double Bs[2][GK][GLD];
   const int b = blockIdx.x;
@@ -51,39 +62,39 @@ __global__ void __launch_bounds__(256) k_merge_gemm(BlockMap bm, Scratch S) {
 
   const int t = threadIdx.x;
   const int lkc = t >> 4;          // k index this thread stages (A column / B row)
-  const int l8 = (t & 15) * 8;     // first of 8 consecutive rows (A) / columns (B)
-  double ra[8], rb[8];
+  const int l8 = (t & 15) * E;     // first of E consecutive rows (A) / columns (B)
+  double ra[E], rb[E];
 
   auto gload = [&](int kt) {
     const int kk = kt * GK + lkc;
     if (kk < kd) {
       const double* src = A + (int64_t)colA[kk] * lda + mrow0 + l8;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) ra[e] = (mrow0 + l8 + e < Mrows) ? src[e] : 0.0;
+      for (int e = 0; e < E; ++e) ra[e] = (mrow0 + l8 + e < Mrows) ? src[e] : 0.0;
       const double* bs = Bm + (int64_t)kk * K + ncol0 + l8;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) rb[e] = (ncol0 + l8 + e < K) ? bs[e] : 0.0;
+      for (int e = 0; e < E; ++e) rb[e] = (ncol0 + l8 + e < K) ? bs[e] : 0.0;
     } else {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) { ra[e] = 0.0; rb[e] = 0.0; }
+      for (int e = 0; e < E; ++e) { ra[e] = 0.0; rb[e] = 0.0; }
     }
   };
   auto lstore = [&](int buf) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < E; ++e) {
       As[buf][lkc][l8 + e] = ra[e];
       Bs[buf][lkc][l8 + e] = rb[e];
     }
   };
 
   const int w = t >> 6, lane = t & 63;
-  const int wm = (w & 1) * 64, wn = (w >> 1) * 64;
+  const int wm = (w & 1) * WT, wn = (w >> 1) * WT;
   const int li = lane & 15, lk = lane >> 4;
-  d4_t acc[4][4];
+  d4_t acc[NB][NB];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < NB; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < NB; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
 
   const int nkt = (kd + GK - 1) / GK;
   if (nkt > 0) {
@@ -97,15 +108,15 @@ __global__ void __launch_bounds__(256) k_merge_gemm(BlockMap bm, Scratch S) {
 #pragma unroll
     for (int ks = 0; ks < GK / 4; ++ks) {
       const int kr = ks * 4 + lk;
-      double av[4], bv[4];
+      double av[NB], bv[NB];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = As[buf][kr][wm + i * 16 + li];
+      for (int i = 0; i < NB; ++i) av[i] = As[buf][kr][wm + i * 16 + li];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = Bs[buf][kr][wn + j * 16 + li];
+      for (int j = 0; j < NB; ++j) bv[j] = Bs[buf][kr][wn + j * 16 + li];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < NB; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < NB; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
     }
     if (kt + 1 < nkt) lstore(buf ^ 1);
     __syncthreads();
@@ -117,12 +128,12 @@ __global__ void __launch_bounds__(256) k_merge_gemm(BlockMap bm, Scratch S) {
   double* out = M.qout + rowoff;
   const int64_t ldo = M.ldout;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < NB; ++j) {
     const int cj = ncol0 + wn + j * 16 + li;
     if (cj >= K) continue;
     double* oc = out + (int64_t)dest[cj] * ldo;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < NB; ++i) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = mrow0 + wm + i * 16 + lk + 4 * r;
@@ -132,9 +143,149 @@ __global__ void __launch_bounds__(256) k_merge_gemm(BlockMap bm, Scratch S) {
   }
 }
 
-void launch_merge_gemm_f64(const BlockMap& bm, int total, const Scratch& S, hipStream_t s) {
+void launch_merge_gemm_f64(const BlockMap& bm, int total, const Scratch& S, int tile, hipStream_t s) {
   if (total <= 0) return;
-  hipLaunchKernelGGL(k_merge_gemm, dim3(total), dim3(256), 0, s, bm, S);
+  if (tile == 64) hipLaunchKernelGGL(k_merge_gemm<64>, dim3(total), dim3(256), 0, s, bm, S);
+  else hipLaunchKernelGGL(k_merge_gemm<128>, dim3(total), dim3(256), 0, s, bm, S);
+}
+
+// ------------------------------------------------------------ tile choice
+// Tile edge per merge-size bucket (bucket b holds 2^(b-1) < m <= 2^b); 0 means
+// not measured, in which case 64 is used up to m = 256 and 128 above.
+namespace {
+std::atomic<int> g_tile[kTileBuckets];
+
+int bucket_of(int64_t m) {
+  int b = 0;
+  while (b + 1 < kTileBuckets && ((int64_t)1 << b) < m) ++b;
+  return b;
+}
+
+__global__ void k_autotune_fill(double* q, double* u, int64_t count, int32_t* cnt, int32_t* coltop, int32_t* colbot,
+                                int32_t* dest, int m, int n1) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = i; e < count; e += stride) {  // bounded values, no structure the GEMM could exploit
+    q[e] = (double)((e * 2654435761LL) % 1000003) * 1e-6 - 0.5;
+    u[e] = (double)((e * 40503LL + 17) % 999983) * 1e-6 - 0.5;
+  }
+  for (int64_t c = i; c < m; c += stride) {
+    dest[c] = (int32_t)c;
+    if (c < n1) coltop[c] = (int32_t)c;
+    if (c < m - n1) colbot[c] = (int32_t)(n1 + c);
+  }
+  if (i == 0) {
+    for (int k = 0; k < kCounters; ++k) cnt[k] = 0;
+    cnt[C_K] = m;
+    cnt[C_K1] = n1;
+    cnt[C_K2] = 0;
+    cnt[C_K3] = m - n1;
+    cnt[C_PATH] = 0;
+  }
+}
+
+size_t autotune_bytes(int64_t max_m) {
+  const size_t mm = (size_t)max_m * max_m;
+  return 3 * mm * 8 + (size_t)(3 * max_m + kCounters + 64) * 4 + 2 * 256 + sizeof(MergeDesc);
+}
+}  // namespace
+
+int gemm_tile_for(int64_t maxm) {
+  const int v = g_tile[bucket_of(maxm)].load();
+  if (v == 64 || v == 128) return v;
+  return maxm <= 256 ? 64 : 128;
 }
 
 }  // namespace phdc
+
+using namespace phdc;
+
+extern "C" {
+
+int phdc_autotune_gemm_workspace(int64_t max_m, size_t* bytes) {
+  if (max_m < 2 || max_m > ((int64_t)1 << (kTileBuckets - 1))) return -1;
+  if (!bytes) return -2;
+  *bytes = autotune_bytes(max_m);
+  return 0;
+}
+
+int phdc_autotune_gemm(int64_t max_m, void* work, size_t lwork, void* stream) {
+  if (max_m < 2 || max_m > ((int64_t)1 << (kTileBuckets - 1))) return -1;
+  if (!work) return -2;
+  if (lwork < autotune_bytes(max_m)) return -3;
+  hipStream_t s = (hipStream_t)stream;
+  char* base = (char*)work;
+  const size_t mm = (size_t)max_m * max_m;
+  double* q = (double*)base;
+  double* qo = q + mm;
+  double* u = qo + mm;
+  int32_t* cnt = (int32_t*)(u + mm);
+  int32_t* coltop = cnt + kCounters;
+  int32_t* colbot = coltop + max_m;
+  int32_t* dest = colbot + max_m;
+  char* tail = (char*)(dest + max_m);
+  tail = (char*)(((uintptr_t)tail + 255) / 256 * 256);
+  MergeDesc* desc = (MergeDesc*)tail;
+  int32_t* pfx = (int32_t*)(tail + 256);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -4;
+  int rc = 0;
+  for (int64_t m = 64; m <= max_m && rc == 0; m *= 2) {
+    const int n1 = (int)(m / 2);
+    hipLaunchKernelGGL(k_autotune_fill, dim3(1024), dim3(256), 0, s, q, u, (int64_t)(m * m), cnt, coltop, colbot, dest,
+                       (int)m, n1);
+    MergeDesc D{};
+    D.qin = q;
+    D.qout = qo;
+    D.ldin = m;
+    D.ldout = m;
+    D.m = (int32_t)m;
+    D.n1 = n1;
+    D.id = 0;
+    Scratch S{};
+    S.counters = cnt;
+    S.coltop = coltop;
+    S.colbot = colbot;
+    S.dest = dest;
+    S.uhat = u;
+    float best[2] = {1e30f, 1e30f};
+    const int tiles[2] = {64, 128};
+    for (int v = 0; v < 2 && rc == 0; ++v) {
+      const int gt = tiles[v];
+      const int total = (int)(((n1 + gt - 1) / gt + (m - n1 + gt - 1) / gt) * ((m + gt - 1) / gt));
+      const int32_t hp[2] = {0, total};
+      if (hipMemcpyAsync(desc, &D, sizeof(D), hipMemcpyHostToDevice, s) != hipSuccess ||
+          hipMemcpyAsync(pfx, hp, sizeof(hp), hipMemcpyHostToDevice, s) != hipSuccess) {
+        rc = -5;
+        break;
+      }
+      BlockMap bm{desc, pfx, 1};
+      launch_merge_gemm_f64(bm, total, S, gt, s);  // warm-up
+      for (int r = 0; r < 3; ++r) {
+        hipEventRecord(e0, s);
+        launch_merge_gemm_f64(bm, total, S, gt, s);
+        hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) {
+          rc = -6;
+          break;
+        }
+        float ms = 0.0f;
+        hipEventElapsedTime(&ms, e0, e1);
+        best[v] = std::min(best[v], ms);
+      }
+    }
+    if (rc == 0) g_tile[bucket_of(m)].store(best[0] < best[1] ? 64 : 128);
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc == 0 && hipGetLastError() != hipSuccess) rc = -7;
+  return rc;
+}
+
+int phdc_gemm_tile_table(int32_t* tiles, int n) {
+  if (!tiles || n <= 0) return -1;
+  for (int b = 0; b < n && b < kTileBuckets; ++b) tiles[b] = g_tile[b].load();
+  return std::min(n, kTileBuckets);
+}
+
+}  // extern "C"

@@ -12,6 +12,8 @@
 // (no LDS round trip on the critical path).  The eigenvector matrix Z sits in
 // LDS, column-major, and lane t owns row t of it, so the rotations need no
 // communication between lanes and no barrier.
+#include <algorithm>
+
 #include "phdc_internal.h"
 
 namespace phdc {
@@ -37,15 +39,45 @@ __device__ inline double hyp(double a, double b) {
   return sqrt(a * a + b * b);
 }
 
+// Plane rotation with r = sqrt(f^2 + g^2), c = g / r, s = f / r (c, s unused
+// when r == 0).  Inside [1e-150, 1e150] the reciprocal square root of
+// f^2 + g^2 comes from the hardware estimate and two Newton steps
+// y <- y (3/2 - (x/2) y^2), which leaves a few ulps; outside, the scaled
+// library hypot and a division.
+__device__ inline double rotation(double f, double g, double* c, double* s) {
+  const double mx = fmax(fabs(f), fabs(g));
+  if (mx > 1e150 || mx < 1e-150) {
+    const double r = hypot(f, g);
+    if (r != 0.0) {
+      const double ri = 1.0 / r;
+      *c = g * ri;
+      *s = f * ri;
+    }
+    return r;
+  }
+  const double x = fma(f, f, g * g);
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  *c = g * y;
+  *s = f * y;
+  return x * y;
+}
+
 }  // namespace
 
-__global__ void __launch_bounds__(64) k_leaf_ql(const LeafArgs* __restrict__ leaves, int32_t* status) {
-  __shared__ double Z[kMaxLeaf * kMaxLeaf];
+// Z is ls x ls in dynamic LDS (ls = the largest leaf of the launch), so small
+// leaves leave room for more blocks per CU.
+__global__ void __launch_bounds__(64) k_leaf_ql(const LeafArgs* __restrict__ leaves, int32_t* status, int ls) {
+  HIP_DYNAMIC_SHARED(double, Z)
   const LeafArgs L = leaves[blockIdx.x];
   const int s = L.s;
   const int t = threadIdx.x;
-  if (s <= 0) return;
-  for (int c = 0; c < s; ++c) Z[c * kMaxLeaf + t] = (c == t) ? 1.0 : 0.0;
+  if (s <= 0 || s > ls) return;
+  const bool row = t < s;  // lane t owns row t of Z
+  if (row)
+    for (int c = 0; c < s; ++c) Z[c * ls + t] = (c == t) ? 1.0 : 0.0;
   // Corner updates of the split: the first/last row lost |e| of the removed coupling.
   double d = 0.0, e = 0.0;
   if (t < s) {
@@ -78,12 +110,17 @@ __global__ void __launch_bounds__(64) k_leaf_ql(const LeafArgs* __restrict__ lea
       double sn = 1.0, cs = 1.0, p = 0.0;
       bool restart = false;
       // Chase the bulge from the bottom of the unreduced block up to row l,
-      // one plane rotation in rows/columns (i, i+1) at a time.
+      // one plane rotation in rows/columns (i, i+1) at a time.  Column i+1 of
+      // Z is final after step i; column i is carried to the next step in a
+      // register (zj), so each step reads one untouched column from LDS.
+      double zj = row ? Z[mm * ls + t] : 0.0;
       for (int i = mm - 1; i >= l; --i) {
+        const double zi = row ? Z[i * ls + t] : 0.0;
         const double ei = lane_get(e, i);
         const double f = sn * ei;
         const double b = cs * ei;
-        r = hyp(f, g);
+        double c2 = 1.0, s2 = 0.0;
+        r = rotation(f, g, &c2, &s2);
         e = lane_put(e, r, i + 1);
         const double di1 = lane_get(d, i + 1);
         if (r == 0.0) {
@@ -91,23 +128,22 @@ __global__ void __launch_bounds__(64) k_leaf_ql(const LeafArgs* __restrict__ lea
           // pending shift correction and look for the split again.
           d = lane_put(d, di1 - p, i + 1);
           e = lane_put(e, 0.0, mm);
+          if (row) Z[(i + 1) * ls + t] = zj;
           restart = true;
           break;
         }
-        const double rinv = 1.0 / r;
-        sn = f * rinv;
-        cs = g * rinv;
+        sn = s2;
+        cs = c2;
         g = di1 - p;
         r = (lane_get(d, i) - g) * sn + 2.0 * cs * b;
         p = sn * r;
         d = lane_put(d, g + p, i + 1);
         g = cs * r - b;
-        const double zi = Z[i * kMaxLeaf + t];
-        const double zj = Z[(i + 1) * kMaxLeaf + t];
-        Z[(i + 1) * kMaxLeaf + t] = sn * zi + cs * zj;
-        Z[i * kMaxLeaf + t] = cs * zi - sn * zj;
+        if (row) Z[(i + 1) * ls + t] = sn * zi + cs * zj;
+        zj = cs * zi - sn * zj;
       }
       if (restart) continue;
+      if (row) Z[l * ls + t] = zj;
       d = lane_put(d, lane_get(d, l) - p, l);
       e = lane_put(e, g, l);
       e = lane_put(e, 0.0, mm);
@@ -121,16 +157,17 @@ __global__ void __launch_bounds__(64) k_leaf_ql(const LeafArgs* __restrict__ lea
     const double dj = lane_get(d, j);
     rank += (dj < d || (dj == d && j < t)) ? 1 : 0;
   }
-  if (t < s) L.lam[rank] = d;
+  if (row) L.lam[rank] = d;
   for (int c = 0; c < s; ++c) {
     const int rc = __builtin_amdgcn_readlane(rank, c);
-    if (t < s) L.q[t + (int64_t)rc * L.ldq] = Z[c * kMaxLeaf + t];
+    if (row) L.q[t + (int64_t)rc * L.ldq] = Z[c * ls + t];
   }
 }
 
-void launch_leaf_ql(const LeafArgs* leaves, int nleaves, int32_t* status, hipStream_t s) {
+void launch_leaf_ql(const LeafArgs* leaves, int nleaves, int32_t* status, int max_leaf, hipStream_t s) {
   if (nleaves <= 0) return;
-  hipLaunchKernelGGL(k_leaf_ql, dim3(nleaves), dim3(64), 0, s, leaves, status);
+  const int ls = std::max(1, std::min(max_leaf, kMaxLeaf));
+  hipLaunchKernelGGL(k_leaf_ql, dim3(nleaves), dim3(64), (size_t)ls * ls * sizeof(double), s, leaves, status, ls);
 }
 
 }  // namespace phdc

@@ -93,13 +93,52 @@ __device__ inline bool pair_deflates(double dp, double zp, double dj, double zj,
 }
 
 // ------------------------------------------------------------ deflation
-// One 1024-thread workgroup per merge.
+// One 1024-thread workgroup per merge.  The compactions in pole order give
+// each wave a contiguous index segment and place elements with ballots, so a
+// pass over m costs two block barriers however large m is.  The merge-path
+// searches of step 2 read D from LDS when the level's merges fit
+// (kDefLdsMax poles, dynamic LDS sized per launch).
 constexpr int kDefThreads = 1024;
+constexpr int kDefWaves = kDefThreads / 64;
+constexpr int kDefLdsMax = 16384;
 
-__global__ void __launch_bounds__(kDefThreads) k_deflate(const MergeDesc* __restrict__ descs, Scratch S) {
-  __shared__ double shd[kDefThreads / 64];
-  __shared__ int64_t shl[kDefThreads / 64];
+__device__ inline int lanes_below(uint64_t mask) {
+  return __popcll(mask & ((1ULL << (threadIdx.x & 63)) - 1ULL));
+}
+
+// Sum over lanes 0..15 (lanes 16..63 hold 0), broadcast to the whole wave.
+__device__ inline int sum16_bcast(int v) {
+  v += __shfl_xor(v, 1, 64);
+  v += __shfl_xor(v, 2, 64);
+  v += __shfl_xor(v, 4, 64);
+  v += __shfl_xor(v, 8, 64);
+  return __shfl(v, 0, 64);
+}
+
+// Exclusive prefix over the waves of the block of NC per-wave counts, and the
+// block totals; lane i of every wave reads wave i's count.  Uses sh[NC][kDefWaves].
+template <int NC>
+__device__ inline void wave_prefix(const int (&c)[NC], int (&pre)[NC], int (&tot)[NC], int (*sh)[kDefWaves]) {
+  static_assert(kDefWaves == 16, "sum16_bcast covers 16 waves");
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < NC; ++q) sh[q][w] = c[q];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    const int v = (lane < kDefWaves) ? sh[q][lane] : 0;
+    tot[q] = sum16_bcast(v);
+    pre[q] = sum16_bcast(lane < w ? v : 0);
+  }
+}
+
+__global__ void __launch_bounds__(kDefThreads) k_deflate(const MergeDesc* __restrict__ descs, Scratch S, int lds_cap) {
+  __shared__ double shd[kDefWaves];
+  __shared__ int shc[7][kDefWaves];
   __shared__ int shi[4];
+  HIP_DYNAMIC_SHARED(double, sdl)  // D staged for the merge-path searches (m <= lds_cap)
   const MergeDesc M = descs[blockIdx.x];
   const int m = M.m, n1 = M.n1, t = threadIdx.x;
   const int64_t so = M.s_off;
@@ -123,17 +162,32 @@ __global__ void __launch_bounds__(kDefThreads) k_deflate(const MergeDesc* __rest
   // 1. z (Eq. (3): last row of Q1, first row of Q2), |z|^2, max |D|, sortedness.
   double zz = 0.0, dmx = 0.0;
   int uns = 0;
-  for (int i = t; i < m; i += kDefThreads) {
-    double zi;
-    if (M.zgiven) zi = M.zgiven[i];
-    else zi = (i < n1) ? M.qin[(n1 - 1) + (int64_t)i * M.ldin] : zsign * M.qin[n1 + (int64_t)i * M.ldin];
-    S.zs[so + i] = zi;
-    double di = M.lin[i];
-    zz += zi * zi;
-    dmx = fmax(dmx, fabs(di));
-    // NaN or a descending step inside either run makes the merge of the two
-    // runs ill-defined; such input is reported and merged without sorting.
-    if (!(di == di) || (i > 0 && i != n1 && !(di >= M.lin[i - 1]))) uns = 1;
+  constexpr int U1 = 4;  // loads of four indices issued before their uses
+  for (int i0 = t; i0 < m; i0 += U1 * kDefThreads) {
+    double zi[U1], di[U1], dprev[U1];
+#pragma unroll
+    for (int u = 0; u < U1; ++u) {
+      const int i = i0 + u * kDefThreads;
+      zi[u] = di[u] = dprev[u] = 0.0;
+      if (i < m) {
+        if (M.zgiven) zi[u] = M.zgiven[i];
+        else zi[u] = (i < n1) ? M.qin[(n1 - 1) + (int64_t)i * M.ldin] : zsign * M.qin[n1 + (int64_t)i * M.ldin];
+        di[u] = M.lin[i];
+        if (i > 0) dprev[u] = M.lin[i - 1];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U1; ++u) {
+      const int i = i0 + u * kDefThreads;
+      if (i < m) {
+        S.zs[so + i] = zi[u];
+        zz += zi[u] * zi[u];
+        dmx = fmax(dmx, fabs(di[u]));
+        // NaN or a descending step inside either run makes the merge of the two
+        // runs ill-defined; such input is reported and merged without sorting.
+        if (!(di[u] == di[u]) || (i > 0 && i != n1 && !(di[u] >= dprev[u]))) uns = 1;
+      }
+    }
   }
   zz = block_sum<kDefThreads>(zz, shd);
   dmx = block_max<kDefThreads>(dmx, shd);
@@ -155,42 +209,62 @@ __global__ void __launch_bounds__(kDefThreads) k_deflate(const MergeDesc* __rest
   // 2. merge the two ascending runs (ties: D1 first) and normalise z.  For
   // valid input the positions form a permutation of [0, m); otherwise keep the
   // input order so every slot is still written exactly once.
-  for (int i = t; i < m; i += kDefThreads) {
-    double di = M.lin[i];
-    int pos = uns ? i
-                  : (i < n1) ? i + count_lt(M.lin + n1, m - n1, di) : (i - n1) + count_le(M.lin, n1, di);
-    dv[pos] = di;
-    zv[pos] = (zn > 0.0) ? S.zs[so + i] / zn : 0.0;
-    col[pos] = i;
-    part[pos] = (i < n1) ? 1 : 3;
+  auto place = [&](const double* D) {
+    for (int i = t; i < m; i += kDefThreads) {
+      const double di = D[i];
+      const int pos = uns ? i : (i < n1) ? i + count_lt(D + n1, m - n1, di) : (i - n1) + count_le(D, n1, di);
+      dv[pos] = di;
+      zv[pos] = (zn > 0.0) ? S.zs[so + i] / zn : 0.0;
+      col[pos] = i;
+      part[pos] = (i < n1) ? 1 : 3;
+    }
+  };
+  if (m <= lds_cap) {
+    for (int i = t; i < m; i += kDefThreads) sdl[i] = M.lin[i];
+    __syncthreads();
+    place(sdl);
+  } else {
+    place(M.lin);
   }
   __syncthreads();
 
   // 3. type-1 deflation (rho |z_i| <= tol) and compaction of both lists in pole order.
-  int base_s = 0, base_d = 0;
-  for (int c0 = 0; c0 < m; c0 += kDefThreads) {
-    int k = c0 + t;
-    int isS = 0, isD = 0;
-    if (k < m) {
-      bool dfl = rho * fabs(zv[k]) <= tol;
-      isD = dfl;
-      isS = !dfl;
-      flag[k] = dfl ? 1 : 0;
+  const int lane = t & 63, wv = t >> 6;
+  const int seg = ((m + kDefWaves - 1) / kDefWaves + 63) / 64 * 64;
+  const int seg0 = min(m, wv * seg), seg1 = min(m, seg0 + seg);
+  int ns, nd1;
+  {
+    int c[2] = {0, 0}, pre[2], tot[2];
+    for (int b0 = seg0; b0 < seg1; b0 += 64) {
+      const int k = b0 + lane;
+      const bool valid = k < seg1;
+      const bool dfl = valid && rho * fabs(zv[k]) <= tol;
+      if (valid) flag[k] = dfl ? 1 : 0;
+      const uint64_t md = __ballot(dfl), mv = __ballot(valid);
+      c[0] += __popcll(mv & ~md);
+      c[1] += __popcll(md);
     }
-    int64_t tot;
-    int64_t ex = block_excl_scan<kDefThreads>((int64_t)isS | ((int64_t)isD << 32), &tot, shl);
-    if (isS) surv[base_s + (int)(ex & 0xffffffffLL)] = k;
-    if (isD) {
-      int q = base_d + (int)(ex >> 32);
-      S.dfv1[so + q] = dv[k];
-      S.dfc1[so + q] = col[k];
-      S.dfp1[so + q] = part[k];
+    wave_prefix<2>(c, pre, tot, shc);
+    int ps = pre[0], pd = pre[1];
+    for (int b0 = seg0; b0 < seg1; b0 += 64) {
+      const int k = b0 + lane;
+      const bool valid = k < seg1;
+      const bool dfl = valid && rho * fabs(zv[k]) <= tol;
+      const uint64_t md = __ballot(dfl), ms = __ballot(valid && !dfl);
+      if (valid && !dfl) surv[ps + lanes_below(ms)] = k;
+      if (dfl) {
+        const int q = pd + lanes_below(md);
+        S.dfv1[so + q] = dv[k];
+        S.dfc1[so + q] = col[k];
+        S.dfp1[so + q] = part[k];
+      }
+      ps += __popcll(ms);
+      pd += __popcll(md);
     }
-    base_s += (int)(tot & 0xffffffffLL);
-    base_d += (int)(tot >> 32);
+    ns = tot[0];
+    nd1 = tot[1];
   }
   __syncthreads();
-  const int ns = base_s, nd1 = base_d;
 
   // 4. type-2 deflation: scan consecutive survivors in pole order.  Wave 0 tests
   // 64 survivors at a time speculatively (each against its unmodified
@@ -285,71 +359,65 @@ __global__ void __launch_bounds__(kDefThreads) k_deflate(const MergeDesc* __rest
   // 5. final survivors in pole order, Gu's grouping by part (Sec. 1): rows of
   // Uhat ordered [part 1 | part 2 | part 3]; the Q1-row product uses columns of
   // parts 1,2 and the Q2-row product those of parts 2,3.  Type-2 deflated list.
-  int c1 = 0, c2 = 0, c3 = 0, c4 = 0, g1 = 0, g2 = 0, g3 = 0;
-  for (int k = t; k < m; k += kDefThreads) {
-    int f = flag[k];
-    int p = part[k];
-    if (f == 0) {
-      c1 += (p == 1); c2 += (p == 2); c3 += (p == 3);
-    } else {
-      c4 += (f == 2);
-      g1 += (p == 1); g2 += (p == 2); g3 += (p == 3);  // deflated columns by nonzero half
-    }
+  int c[7] = {0, 0, 0, 0, 0, 0, 0}, pre[7], tot[7];
+  for (int b0 = seg0; b0 < seg1; b0 += 64) {
+    const int k = b0 + lane;
+    const bool valid = k < seg1;
+    const int f = valid ? flag[k] : -1;
+    const int p = valid ? part[k] : 0;
+    c[0] += __popcll(__ballot(f == 0 && p == 1));
+    c[1] += __popcll(__ballot(f == 0 && p == 2));
+    c[2] += __popcll(__ballot(f == 0 && p == 3));
+    c[3] += __popcll(__ballot(f == 2));
+    c[4] += __popcll(__ballot(f > 0 && p == 1));  // deflated columns by nonzero half
+    c[5] += __popcll(__ballot(f > 0 && p == 2));
+    c[6] += __popcll(__ballot(f > 0 && p == 3));
   }
-  const int k1 = (int)block_sum<kDefThreads>((double)c1, shd);
-  const int k2 = (int)block_sum<kDefThreads>((double)c2, shd);
-  const int k3 = (int)block_sum<kDefThreads>((double)c3, shd);
-  const int nd2 = (int)block_sum<kDefThreads>((double)c4, shd);
-  const int dp1 = (int)block_sum<kDefThreads>((double)g1, shd);
-  const int dp2 = (int)block_sum<kDefThreads>((double)g2, shd);
-  const int dp3 = (int)block_sum<kDefThreads>((double)g3, shd);
+  wave_prefix<7>(c, pre, tot, shc);
+  const int k1 = tot[0], k2 = tot[1], k3 = tot[2], nd2 = tot[3];
+  const int dp1 = tot[4], dp2 = tot[5], dp3 = tot[6];
   const int K = k1 + k2 + k3;
-  int64_t b1 = 0, b2 = 0, b3 = 0, b4 = 0;
-  for (int c0 = 0; c0 < m; c0 += kDefThreads) {
-    int k = c0 + t;
-    int f = -1, p = 0;
-    if (k < m) {
-      f = flag[k];
-      p = part[k];
-    }
-    int64_t x = 0;
-    if (f == 0) x = (p == 1) ? 1LL : (p == 2) ? (1LL << 21) : (1LL << 42);
-    int64_t tot;
-    int64_t ex = block_excl_scan<kDefThreads>(x, &tot, shl);
-    int64_t tot4;
-    int64_t ex4 = block_excl_scan<kDefThreads>((int64_t)(f == 2), &tot4, shl);
-    const int64_t msk = (1LL << 21) - 1;
-    if (f == 0) {
-      int e1 = (int)(b1 + (ex & msk)), e2 = (int)(b2 + ((ex >> 21) & msk)), e3 = (int)(b3 + ((ex >> 42) & msk));
-      int ks = e1 + e2 + e3;
-      S.ds[so + ks] = dv[k];
-      S.zs[so + ks] = zv[k];
-      S.csort[so + ks] = col[k];
-      S.psort[so + ks] = p;
-      int g;
-      if (p == 1) {
-        g = e1;
-        S.coltop[so + e1] = col[k];
-      } else if (p == 2) {
-        g = k1 + e2;
-        S.coltop[so + k1 + e2] = col[k];
-        S.colbot[so + e2] = col[k];
-      } else {
-        g = k1 + k2 + e3;
-        S.colbot[so + k2 + e3] = col[k];
+  {
+    int b1 = pre[0], b2 = pre[1], b3 = pre[2], b4 = pre[3];
+    for (int b0 = seg0; b0 < seg1; b0 += 64) {
+      const int k = b0 + lane;
+      const bool valid = k < seg1;
+      const int f = valid ? flag[k] : -1;
+      const int p = valid ? part[k] : 0;
+      const uint64_t m1 = __ballot(f == 0 && p == 1), m2 = __ballot(f == 0 && p == 2);
+      const uint64_t m3 = __ballot(f == 0 && p == 3), m4 = __ballot(f == 2);
+      if (f == 0) {
+        const int e1 = b1 + lanes_below(m1), e2 = b2 + lanes_below(m2), e3 = b3 + lanes_below(m3);
+        const int ks = e1 + e2 + e3;
+        S.ds[so + ks] = dv[k];
+        S.zs[so + ks] = zv[k];
+        S.csort[so + ks] = col[k];
+        S.psort[so + ks] = p;
+        int g;
+        if (p == 1) {
+          g = e1;
+          S.coltop[so + e1] = col[k];
+        } else if (p == 2) {
+          g = k1 + e2;
+          S.coltop[so + k1 + e2] = col[k];
+          S.colbot[so + e2] = col[k];
+        } else {
+          g = k1 + k2 + e3;
+          S.colbot[so + k2 + e3] = col[k];
+        }
+        S.grp[so + ks] = g;
+        S.grpsrc[so + g] = ks;
+      } else if (f == 2) {
+        const int q = b4 + lanes_below(m4);
+        S.dfv2[so + q] = dv[k];
+        S.dfc2[so + q] = col[k];
+        S.dfp2[so + q] = p;
       }
-      S.grp[so + ks] = g;
-      S.grpsrc[so + g] = ks;
-    } else if (f == 2) {
-      int q = (int)(b4 + ex4);
-      S.dfv2[so + q] = dv[k];
-      S.dfc2[so + q] = col[k];
-      S.dfp2[so + q] = p;
+      b1 += __popcll(m1);
+      b2 += __popcll(m2);
+      b3 += __popcll(m3);
+      b4 += __popcll(m4);
     }
-    b1 += tot & msk;
-    b2 += (tot >> 21) & msk;
-    b3 += (tot >> 42) & msk;
-    b4 += tot4;
   }
   if (t == 0) {
     cnt[C_K] = K;
@@ -481,8 +549,23 @@ __device__ __forceinline__ bool secular_root(int K, const double* __restrict__ d
   double tau = 0.5 * (lo + hi);
   bool ok = false;
   for (int it = 0; it < 120; ++it) {
+    // Two independent sets of partial sums (poles i and i + G) keep two
+    // reciprocal chains in flight per lane.
     double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0, eabs = 0.0;
-    for (int i = sub; i < K; i += G) {
+    double psi2 = 0.0, dpsi2 = 0.0, phi2 = 0.0, dphi2 = 0.0, eabs2 = 0.0;
+    int i = sub;
+    for (; i + G < K; i += 2 * G) {
+      const int i2 = i + G;
+      const double del = (d[i] - dorg) - tau, del2 = (d[i2] - dorg) - tau;
+      const double rcp = rcp_nr(del), rcp2 = rcp_nr(del2);
+      const double tt = z2(i) * rcp, tt2 = z2(i2) * rcp2;
+      const double dt = tt * rcp, dt2 = tt2 * rcp2;
+      if (i <= jl) { psi += tt; dpsi += dt; } else { phi += tt; dphi += dt; }
+      if (i2 <= jl) { psi2 += tt2; dpsi2 += dt2; } else { phi2 += tt2; dphi2 += dt2; }
+      eabs += fabs(tt);
+      eabs2 += fabs(tt2);
+    }
+    if (i < K) {
       const double del = (d[i] - dorg) - tau;
       const double rcp = rcp_nr(del);
       const double tt = z2(i) * rcp;
@@ -490,6 +573,11 @@ __device__ __forceinline__ bool secular_root(int K, const double* __restrict__ d
       if (i <= jl) { psi += tt; dpsi += dt; } else { phi += tt; dphi += dt; }
       eabs += fabs(tt);
     }
+    psi += psi2;
+    dpsi += dpsi2;
+    phi += phi2;
+    dphi += dphi2;
+    eabs += eabs2;
     psi = group_sum<G>(psi);
     dpsi = group_sum<G>(dpsi);
     phi = group_sum<G>(phi);
@@ -519,12 +607,12 @@ __device__ __forceinline__ bool secular_root(int K, const double* __restrict__ d
   return ok;
 }
 
-constexpr int kSecG = 4;                        // lanes per root
+constexpr int kSecG = 16;                       // lanes per root
 constexpr int kSecThreads = 256;                // threads per block
 constexpr int kSecRoots = kSecThreads / kSecG;  // roots per block
 constexpr int kSecLds = 2048;                   // poles staged in LDS (d_i and z_i^2: 32 KB)
 
-// 256-lane blocks, 64 roots per block.  Merges with K <= kSecLds stage the
+// 256-lane blocks, 16 roots per block.  Merges with K <= kSecLds stage the
 // poles and squared weights in LDS once; larger ones read them from global
 // memory (L2-resident).
 __global__ void __launch_bounds__(kSecThreads) k_secular(BlockMap bm, Scratch S) {
@@ -585,51 +673,90 @@ __global__ void __launch_bounds__(64) k_secular_raw(int K, const double* d, cons
 // rho zhat_i^2 = prod_j (lambda_j - d_i) / prod_{k != i} (d_k - d_i) (Remark 1),
 // paired so every factor is in (0, 1]: for j < i (d_i - lambda_j)/(d_i - d_j),
 // for i <= j < K-1 (d_i - lambda_j)/(d_i - d_{j+1}), times lambda_{K-1} - d_i.
-__global__ void __launch_bounds__(64) k_lowner(BlockMap bm, Scratch S) {
+template <int G>
+__device__ inline double group_prod(double v) {
+#pragma unroll
+  for (int o = 1; o < G; o <<= 1) v *= __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Both kernels: 256-lane blocks, 16 items per block, 16 lanes per item each
+// taking every 16th term, two terms in flight per lane.
+constexpr int kItemG = 16;
+constexpr int kItemsPerBlock = kSecThreads / kItemG;
+
+// A lane's partial product is a product of factors in (0, 1], so none
+// underflows before the full product does.
+__global__ void __launch_bounds__(kSecThreads) k_lowner(BlockMap bm, Scratch S) {
   const int b = blockIdx.x;
   const int mi = find_merge(bm, b);
   const int lb = b - bm.pfx[mi];
   const MergeDesc M = bm.descs[mi];
   const int K = S.counters[(int64_t)M.id * kCounters + C_K];
-  const int i = lb * 64 + threadIdx.x;
-  if (i >= K) return;
+  if (lb * kItemsPerBlock >= K) return;
+  const int sub = threadIdx.x % kItemG;
+  const int i0 = lb * kItemsPerBlock + (int)threadIdx.x / kItemG;
+  const bool active = i0 < K;
+  const int i = active ? i0 : K - 1;  // idle groups repeat the last item (group shuffles)
   const int64_t so = M.s_off;
   const double* ds = S.ds + so;
   const double* dorg = S.dorg + so;
   const double* tau = S.tau + so;
   const double rho = S.mparam[(int64_t)M.id * 4 + 0];
   const double di = ds[i];
-  double w = -((di - dorg[K - 1]) - tau[K - 1]);
-  for (int j = 0; j < K - 1; ++j) {
+  double w1 = 1.0, w2 = 1.0;
+  int j = sub;
+  for (; j + kItemG < K - 1; j += 2 * kItemG) {
+    const int j2 = j + kItemG;
+    const double num = (di - dorg[j]) - tau[j], num2 = (di - dorg[j2]) - tau[j2];
+    const double den = (j < i) ? (di - ds[j]) : (di - ds[j + 1]);
+    const double den2 = (j2 < i) ? (di - ds[j2]) : (di - ds[j2 + 1]);
+    w1 *= num / den;
+    w2 *= num2 / den2;
+  }
+  if (j < K - 1) {
     const double num = (di - dorg[j]) - tau[j];
     const double den = (j < i) ? (di - ds[j]) : (di - ds[j + 1]);
-    w *= num / den;
+    w1 *= num / den;
   }
-  const double mag = sqrt(fabs(w) / rho);
-  S.zhat[so + i] = (S.zs[so + i] < 0.0) ? -mag : mag;
+  double w = group_prod<kItemG>(w1 * w2);
+  w *= -((di - dorg[K - 1]) - tau[K - 1]);
+  if (active && sub == 0) {
+    const double mag = sqrt(fabs(w) / rho);
+    S.zhat[so + i] = (S.zs[so + i] < 0.0) ? -mag : mag;
+  }
 }
 
-// ------------------------------------------------------------ Uhat
-// Column j of Uhat is (D - lambda_j)^{-1} zhat (Sec. 1, after Eq. (4)), scaled
-// to unit norm.  First the column norms (one thread per column) ...
-__global__ void __launch_bounds__(64) k_unorm(BlockMap bm, Scratch S) {
+// Reciprocal 2-norms of the columns zhat_i / (d_i - lambda_j) of Uhat (Eq. (4)).
+__global__ void __launch_bounds__(kSecThreads) k_unorm(BlockMap bm, Scratch S) {
   const int b = blockIdx.x;
   const int mi = find_merge(bm, b);
   const int lb = b - bm.pfx[mi];
   const MergeDesc M = bm.descs[mi];
   const int K = S.counters[(int64_t)M.id * kCounters + C_K];
-  const int j = lb * 64 + threadIdx.x;
-  if (j >= K) return;
+  if (lb * kItemsPerBlock >= K) return;
+  const int sub = threadIdx.x % kItemG;
+  const int j0 = lb * kItemsPerBlock + (int)threadIdx.x / kItemG;
+  const bool active = j0 < K;
+  const int j = active ? j0 : K - 1;
   const int64_t so = M.s_off;
   const double* ds = S.ds + so;
   const double* zh = S.zhat + so;
   const double lj = S.dorg[so + j], tj = S.tau[so + j];
-  double s = 0.0;
-  for (int i = 0; i < K; ++i) {
-    const double v = zh[i] / ((ds[i] - lj) - tj);
-    s += v * v;
+  double s1 = 0.0, s2 = 0.0;
+  int i = sub;
+  for (; i + kItemG < K; i += 2 * kItemG) {
+    const int i2 = i + kItemG;
+    const double v = zh[i] / ((ds[i] - lj) - tj), v2 = zh[i2] / ((ds[i2] - lj) - tj);
+    s1 += v * v;
+    s2 += v2 * v2;
   }
-  S.cnorm[so + j] = 1.0 / sqrt(s);
+  if (i < K) {
+    const double v = zh[i] / ((ds[i] - lj) - tj);
+    s1 += v * v;
+  }
+  const double s = group_sum<kItemG>(s1 + s2);
+  if (active && sub == 0) S.cnorm[so + j] = 1.0 / sqrt(s);
 }
 
 // ... then the entries, written row-major (row g = grouped row, ld = K) so that
@@ -761,17 +888,16 @@ __global__ void __launch_bounds__(256) k_copy_deflated(BlockMap bm, Scratch S) {
 }
 
 // ------------------------------------------------------------ block maps
-constexpr int kGemmTile = 128;
 
-int map_blocks(int kind, int m, int n1) {
+int map_blocks(int kind, int m, int n1, int gt) {
   auto cdiv = [](int a, int b) { return (a + b - 1) / b; };
   switch (kind) {
     case MAP_ROOTS64: return cdiv(m, 64);
-    case MAP_ROOTS16: return cdiv(m, 64 / kSecG);
+    case MAP_ROOTS16: return cdiv(m, kSecRoots);
     case MAP_ROWS256: return cdiv(m, 256);
     case MAP_ROT: return cdiv(m, 256) * std::max(1, std::min(m / 2, kRotGroups));
     case MAP_UWRITE: return cdiv(m, 256) * std::max(1, std::min(m, kUwRowGroups));
-    case MAP_GEMM: return (cdiv(n1, kGemmTile) + cdiv(m - n1, kGemmTile)) * cdiv(m, kGemmTile);
+    case MAP_GEMM: return (cdiv(n1, gt) + cdiv(m - n1, gt)) * cdiv(m, gt);
     case MAP_COPY: {  // columns per block = 256 / (m rounded up to a power of two, at most 256)
       int rpt = 1;
       while (rpt < m && rpt < 256) rpt <<= 1;
@@ -783,28 +909,28 @@ int map_blocks(int kind, int m, int n1) {
   return 0;
 }
 
-void launch_merge_gemm_f64(const BlockMap& bm, int total, const Scratch& S, hipStream_t s);
 
 void launch_merge_level(const MergeDesc* descs, int nm, const LevelMaps& maps, const Scratch& S, int gemm_mode,
                         const SplitBufs* split, int nsl, hipStream_t s) {
   if (nm <= 0) return;
   auto bmap = [&](int kind) { return BlockMap{descs, maps.pfx[kind], nm}; };
   { ProfScope p(PH_DEFLATE, s);
-    hipLaunchKernelGGL(k_deflate, dim3(nm), dim3(kDefThreads), 0, s, descs, S); }
+    const int cap = maps.maxm <= kDefLdsMax ? maps.maxm : 0;
+    hipLaunchKernelGGL(k_deflate, dim3(nm), dim3(kDefThreads), (size_t)cap * sizeof(double), s, descs, S, cap); }
   { ProfScope p(PH_ROTATE, s);
     hipLaunchKernelGGL(k_rotate, dim3(maps.total[MAP_ROT]), dim3(256), 0, s, bmap(MAP_ROT), S); }
   { ProfScope p(PH_SECULAR, s);
-    hipLaunchKernelGGL(k_secular, dim3(maps.total[MAP_ROOTS64]), dim3(kSecThreads), 0, s, bmap(MAP_ROOTS64), S); }
+    hipLaunchKernelGGL(k_secular, dim3(maps.total[MAP_ROOTS16]), dim3(kSecThreads), 0, s, bmap(MAP_ROOTS16), S); }
   { ProfScope p(PH_LOWNER, s);
-    hipLaunchKernelGGL(k_lowner, dim3(maps.total[MAP_ROOTS64]), dim3(64), 0, s, bmap(MAP_ROOTS64), S); }
+    hipLaunchKernelGGL(k_lowner, dim3(maps.total[MAP_ROOTS16]), dim3(kSecThreads), 0, s, bmap(MAP_ROOTS16), S); }
   { ProfScope p(PH_UNORM, s);
-    hipLaunchKernelGGL(k_unorm, dim3(maps.total[MAP_ROOTS64]), dim3(64), 0, s, bmap(MAP_ROOTS64), S); }
+    hipLaunchKernelGGL(k_unorm, dim3(maps.total[MAP_ROOTS16]), dim3(kSecThreads), 0, s, bmap(MAP_ROOTS16), S); }
   { ProfScope p(PH_UWRITE, s);
     hipLaunchKernelGGL(k_uwrite, dim3(maps.total[MAP_UWRITE]), dim3(256), 0, s, bmap(MAP_UWRITE), S); }
   { ProfScope p(PH_RANK, s);
     hipLaunchKernelGGL(k_rank, dim3(maps.total[MAP_ROWS256]), dim3(256), 0, s, bmap(MAP_ROWS256), S); }
   { ProfScope p(PH_GEMM, s);
-    launch_merge_gemm_f64(bmap(MAP_GEMM), maps.total[MAP_GEMM], S, s); }
+    launch_merge_gemm_f64(bmap(MAP_GEMM), maps.total[MAP_GEMM], S, maps.gemm_tile, s); }
   if (gemm_mode == PHDC_GEMM_SPLIT && split) {
     ProfScope p(PH_SPLIT_GEMM, s);
     launch_split_update(descs, nm, maps, S, *split, nsl, s);

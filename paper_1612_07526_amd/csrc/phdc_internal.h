@@ -126,15 +126,21 @@ __device__ inline void set_status(int32_t* status, int code) {
 }
 
 // Kernel launchers (defined in the .hip files).
-void launch_leaf_ql(const LeafArgs* leaves, int nleaves, int32_t* status, hipStream_t s);
+void launch_leaf_ql(const LeafArgs* leaves, int nleaves, int32_t* status, int max_leaf, hipStream_t s);
 
 // Block maps of one merge level (device prefix arrays, nm + 1 entries each).
 enum MapKind { MAP_ROOTS64 = 0, MAP_ROOTS16, MAP_ROWS256, MAP_ROT, MAP_UWRITE, MAP_GEMM, MAP_COPY, MAP_SPLITA, MAP_SPLITB, MAP_COUNT };
 struct LevelMaps {
   const int32_t* pfx[MAP_COUNT];
   int32_t total[MAP_COUNT];
+  int32_t maxm = 0;         // largest merge of the level
+  int32_t gemm_tile = 128;  // output tile edge of the FP64 update GEMM (64 or 128)
 };
-int map_blocks(int kind, int m, int n1);
+// Blocks of one merge for a kernel class; gt is the FP64 GEMM tile edge (MAP_GEMM).
+int map_blocks(int kind, int m, int n1, int gt);
+constexpr int kTileBuckets = 21;        // merge-size buckets of the GEMM tile table (m <= 2^20)
+int gemm_tile_for(int64_t maxm);        // tile edge for a level whose largest merge is maxm
+void launch_merge_gemm_f64(const BlockMap& bm, int total, const Scratch& S, int tile, hipStream_t s);
 
 struct SplitBufs;
 void launch_merge_level(const MergeDesc* descs, int nm, const LevelMaps& maps, const Scratch& S,

@@ -16,6 +16,7 @@ struct Rec {
 };
 std::mutex g_pm;
 bool g_on = false;
+uint32_t g_mask = 0xffffffffu;  // phases recorded while enabled
 std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_pool;
 
@@ -33,7 +34,7 @@ hipEvent_t take_event() {
 
 ProfScope::ProfScope(int phase, hipStream_t s) : phase_(phase), s_(s), a_(nullptr) {
   std::lock_guard<std::mutex> lk(g_pm);
-  if (!g_on) return;
+  if (!g_on || phase < 0 || phase >= 32 || !((g_mask >> phase) & 1u)) return;
   a_ = take_event();
   hipEventRecord((hipEvent_t)a_, s_);
 }
@@ -55,6 +56,12 @@ extern "C" {
 int phdc_profile_enable(int on) {
   std::lock_guard<std::mutex> lk(g_pm);
   g_on = on != 0;
+  return 0;
+}
+
+int phdc_profile_select(uint32_t mask) {
+  std::lock_guard<std::mutex> lk(g_pm);
+  g_mask = mask;
   return 0;
 }
 

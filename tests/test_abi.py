@@ -101,3 +101,15 @@ def test_argument_validation_codes():
     qoff = (ctypes.c_int64 * 2)(0, 9)
     assert lib.phdc_stedc_batched(2, n, off, qoff, fake, fake, fake, fake, fake, 1 << 30, ctypes.byref(o),
                                   v(0)) == -3
+
+
+def test_autotune_workspace_checks():
+    P, lib = _lib()
+    nb = ctypes.c_size_t()
+    assert lib.phdc_autotune_gemm_workspace(4096, ctypes.byref(nb)) == 0
+    assert nb.value >= 3 * 4096 * 4096 * 8
+    assert lib.phdc_autotune_gemm_workspace(1, ctypes.byref(nb)) == -1
+    assert lib.phdc_autotune_gemm_workspace((1 << 20) + 1, ctypes.byref(nb)) == -1
+    assert lib.phdc_autotune_gemm(4096, None, 0, None) == -2
+    tiles = (ctypes.c_int32 * 32)()
+    assert lib.phdc_gemm_tile_table(tiles, 32) == 21
