@@ -11,6 +11,7 @@
 #include <algorithm>
 
 #include "gemm_generic.h"
+#include "profile.h"
 
 namespace phdc {
 
@@ -86,6 +87,7 @@ int phdc_stedc_backward(int64_t n, int64_t batch, const double* lambda, const do
     const double* lb = lambda_bar ? lambda_bar + b0 * n : nullptr;
     double* W = nullptr;
     if (Q_bar) {
+      ProfScope ps(PH_ADJ_GEMM, s);
       double* W_ = Mp + (int64_t)cb * nn;
       GemmArgs g1{Qb, Q_bar + b0 * nn, n, n, nn, nn, (int32_t)n, (int32_t)n, (int32_t)n, 0};
       gemm_f64_adjoint_f(g1, cb, Mp, n, nn, lambda + b0 * n, lb, n, s);
@@ -93,6 +95,7 @@ int phdc_stedc_backward(int64_t n, int64_t batch, const double* lambda, const do
       gemm_f64(false, false, g2, cb, W_, n, nn, s);
       W = W_;
     }
+    ProfScope pb(PH_ADJ_BAND, s);
     dim3 grid((unsigned)((n + 255) / 256), cb);
     hipLaunchKernelGGL(k_band, grid, dim3(256), 0, s, (int)n, Qb, nn, W, nn, lb, n, d_bar + b0 * n,
                        n > 1 ? e_bar + b0 * (n - 1) : e_bar);

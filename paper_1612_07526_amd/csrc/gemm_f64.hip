@@ -46,8 +46,21 @@ __global__ void __launch_bounds__(256) k_merge_gemm(BlockMap bm, Scratch S) {
   const int n1 = M.n1, n2 = M.m - M.n1;
   const int tmt = (n1 + GT - 1) / GT, tmb = (n2 + GT - 1) / GT;
   const int TM = tmt + tmb;
-  const int mt = lb % TM, nt = lb / TM;
-  if (nt * GT >= K) return;
+  const int TN = (K + GT - 1) / GT;  // column tiles with work (the grid covers m columns)
+  const int nact = TM * TN;
+  if (lb >= nact) return;
+  // Tile order.  Workgroups are dispatched round-robin over the 8 XCDs, each
+  // with its own L2: hand XCD (lb mod 8) a contiguous range of tiles, and walk
+  // each range in groups of 8 row tiles so that the blocks in flight on one XCD
+  // share A panels across columns and B panels across rows.
+  const int n8 = nact - nact % 8;
+  const int lid = (lb < n8) ? (lb % 8) * (n8 / 8) + lb / 8 : lb;
+  constexpr int GM = 8;
+  const int width = GM * TN;
+  const int first = (lid / width) * GM;
+  const int gsz = min(TM - first, GM);
+  const int in = lid % width;
+  const int mt = first + in % gsz, nt = in / gsz;
   const bool top = mt < tmt;
   const int mrow0 = top ? mt * GT : (mt - tmt) * GT;  // first row of the tile within its half
   const int Mrows = top ? n1 : n2;

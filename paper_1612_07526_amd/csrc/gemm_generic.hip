@@ -10,11 +10,23 @@ namespace phdc {
 typedef double d4g_t __attribute__((ext_vector_type(4)));
 
 constexpr int QT = 128, QK = 16, QLD = QT + 4;
+// An operand whose k index is contiguous in memory is staged k-contiguous in LDS
+// ([row][k], row stride QK + 1) so each thread's eight consecutive k values
+// land in consecutive LDS words; the other layout is staged [k][row].
+constexpr int QKP = QK + 1;
+constexpr int QBUF = (QT * QKP > QK * QLD) ? QT * QKP : QK * QLD;
+
+template <bool KC>
+__device__ inline int lds_at(int k, int r) {
+  return KC ? r * QKP + k : k * QLD + r;
+}
 
 template <bool TA, bool TB, class Epi>
 __global__ void __launch_bounds__(256) k_gemm_f64(GemmArgs g, Epi epi) {
-  __shared__ double As[2][QK][QLD];
-  __shared__ double Bs[2][QK][QLD];
+  __shared__ double As[2][QBUF];
+  __shared__ double Bs[2][QBUF];
+  constexpr bool AKC = TA;   // op(A)(i, k) = A[k + i lda]: k contiguous
+  constexpr bool BKC = !TB;  // op(B)(k, j) = B[k + j ldb]: k contiguous
   const int bz = blockIdx.y;
   const double* A = g.A + (int64_t)bz * g.strideA;
   const double* B = g.B + (int64_t)bz * g.strideB;
@@ -52,17 +64,17 @@ __global__ void __launch_bounds__(256) k_gemm_f64(GemmArgs g, Epi epi) {
   auto lstore = [&](int buf) {
     if (!TA) {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) As[buf][t >> 4][(t & 15) * 8 + e] = ra[e];
+      for (int e = 0; e < 8; ++e) As[buf][lds_at<AKC>(t >> 4, (t & 15) * 8 + e)] = ra[e];
     } else {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) As[buf][(t & 1) * 8 + e][t >> 1] = ra[e];
+      for (int e = 0; e < 8; ++e) As[buf][lds_at<AKC>((t & 1) * 8 + e, t >> 1)] = ra[e];
     }
     if (!TB) {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) Bs[buf][(t & 1) * 8 + e][t >> 1] = rb[e];
+      for (int e = 0; e < 8; ++e) Bs[buf][lds_at<BKC>((t & 1) * 8 + e, t >> 1)] = rb[e];
     } else {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) Bs[buf][t >> 4][(t & 15) * 8 + e] = rb[e];
+      for (int e = 0; e < 8; ++e) Bs[buf][lds_at<BKC>(t >> 4, (t & 15) * 8 + e)] = rb[e];
     }
   };
 
@@ -89,9 +101,9 @@ __global__ void __launch_bounds__(256) k_gemm_f64(GemmArgs g, Epi epi) {
       const int kr = ks * 4 + lk;
       double av[4], bv[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = As[buf][kr][wm + i * 16 + li];
+      for (int i = 0; i < 4; ++i) av[i] = As[buf][lds_at<AKC>(kr, wm + i * 16 + li)];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = Bs[buf][kr][wn + j * 16 + li];
+      for (int j = 0; j < 4; ++j) bv[j] = Bs[buf][lds_at<BKC>(kr, wn + j * 16 + li)];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -151,8 +163,8 @@ int vgemm_tiles(int m, int n) {
 // tile prefix and computes one 128 x 128 tile of it.
 __global__ void __launch_bounds__(256) k_vgemm(const VGemm* __restrict__ descs, const int32_t* __restrict__ pfx,
                                                int nd) {
-  __shared__ double As[2][QK][QLD];
-  __shared__ double Bs[2][QK][QLD];
+  __shared__ double As[2][QBUF];
+  __shared__ double Bs[2][QBUF];
   const int bid = blockIdx.x;
   int lo = 0, hi = nd - 1;
   while (lo < hi) {
@@ -164,6 +176,8 @@ __global__ void __launch_bounds__(256) k_vgemm(const VGemm* __restrict__ descs, 
   const int tmn = (g.m + QT - 1) / QT;
   const int i0 = (tile % tmn) * QT, j0 = (tile / tmn) * QT;
   const int t = threadIdx.x;
+  const bool akc = g.ta, bkc = !g.tb;  // operands with k contiguous in memory are staged [row][k]
+  auto at = [](bool kc, int k, int r) { return kc ? r * QKP + k : k * QLD + r; };
   double ra[8], rb[8];
   auto gload = [&](int kt) {
     const int kb = kt * QK;
@@ -188,14 +202,14 @@ __global__ void __launch_bounds__(256) k_vgemm(const VGemm* __restrict__ descs, 
   };
   auto lstore = [&](int buf) {
     if (!g.ta) {
-      for (int e = 0; e < 8; ++e) As[buf][t >> 4][(t & 15) * 8 + e] = ra[e];
+      for (int e = 0; e < 8; ++e) As[buf][at(akc, t >> 4, (t & 15) * 8 + e)] = ra[e];
     } else {
-      for (int e = 0; e < 8; ++e) As[buf][(t & 1) * 8 + e][t >> 1] = ra[e];
+      for (int e = 0; e < 8; ++e) As[buf][at(akc, (t & 1) * 8 + e, t >> 1)] = ra[e];
     }
     if (!g.tb) {
-      for (int e = 0; e < 8; ++e) Bs[buf][(t & 1) * 8 + e][t >> 1] = rb[e];
+      for (int e = 0; e < 8; ++e) Bs[buf][at(bkc, (t & 1) * 8 + e, t >> 1)] = rb[e];
     } else {
-      for (int e = 0; e < 8; ++e) Bs[buf][t >> 4][(t & 15) * 8 + e] = rb[e];
+      for (int e = 0; e < 8; ++e) Bs[buf][at(bkc, t >> 4, (t & 15) * 8 + e)] = rb[e];
     }
   };
   const int w = t >> 6, lane = t & 63;
@@ -220,9 +234,9 @@ __global__ void __launch_bounds__(256) k_vgemm(const VGemm* __restrict__ descs, 
       const int kr = ks * 4 + lk;
       double av[4], bv[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = As[buf][kr][wm + i * 16 + li];
+      for (int i = 0; i < 4; ++i) av[i] = As[buf][at(akc, kr, wm + i * 16 + li)];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = Bs[buf][kr][wn + j * 16 + li];
+      for (int j = 0; j < 4; ++j) bv[j] = Bs[buf][at(bkc, kr, wn + j * 16 + li)];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll

@@ -143,8 +143,17 @@ __global__ void __launch_bounds__(256) k_split_gemm(BlockMap bm, Scratch S, Spli
   const int n1 = M.n1, n2 = M.m - M.n1;
   const int tmt = (n1 + XT - 1) / XT, tmb = (n2 + XT - 1) / XT;
   const int TM = tmt + tmb;
-  const int mt = lb % TM, nt = lb / TM;
-  if (nt * XT >= K) return;
+  const int TN = (K + XT - 1) / XT;
+  const int nact = TM * TN;
+  if (lb >= nact) return;
+  // XCD-aware grouped tile order, as in the FP64 update GEMM
+  const int n8 = nact - nact % 8;
+  const int lid = (lb < n8) ? (lb % 8) * (n8 / 8) + lb / 8 : lb;
+  const int width = 8 * TN;
+  const int first = (lid / width) * 8;
+  const int gsz = min(TM - first, 8);
+  const int in = lid % width;
+  const int mt = first + in % gsz, nt = in / gsz;
   const bool top = mt < tmt;
   const int mrow0 = top ? mt * XT : (mt - tmt) * XT;
   const int rows = top ? n1 : n2;
