@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Benchmark: n = 16384 tridiagonal eigensolve on one MI355X, plain vs chosen form.
 
-value: d, e iid Uniform[-1, 1] (seed 0), n = 16384, leaf 32.  One step = one
+value: d, e iid Uniform[-1, 1] (seed 0), n = 16384, leaf 16 (--leaf; the library default is 32).  One step = one
 complete divide-and-conquer solve (leaves, every merge level, eigenvalues and
 the full n x n eigenvector matrix), inputs resident in HBM.  The chosen form
 (HSS-compressed Uhat for merges with K >= 4096, FP64 MFMA otherwise) is timed
@@ -150,10 +150,11 @@ TRAFFIC_SUMMARIES = {
 }
 
 
-def measured_traffic(phase):
+def measured_traffic(phase, leaf):
     """HBM bytes per launch of the phase's kernel from its committed counter summary
     (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy kernel's reading), or None when no
-    summary exists or the kernel's source file has changed since the counters were taken."""
+    summary exists, it was taken at another leaf size (another tree), or the kernel's
+    source file has changed since the counters were taken."""
     import hashlib
     if phase not in TRAFFIC_SUMMARIES:
         return None
@@ -167,6 +168,8 @@ def measured_traffic(phase):
             fields[k.strip()] = v.strip().strip("`")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     if fields.get("source_sha256") != sha or "traffic_bytes_per_launch" not in fields:
+        return None
+    if fields.get("leaf") != str(leaf):
         return None
     return float(fields["traffic_bytes_per_launch"])
 
@@ -201,7 +204,7 @@ def sec_value(P, W, args, out):
     n = 16384
     d, e = W.uniform(n, seed=0)
     chosen = P.GEMM_FP64 if "hss" in args.skip_paths else P.GEMM_HSS
-    ch = Solver(P, d, e, P.opts(gemm_mode=chosen))
+    ch = Solver(P, d, e, P.opts(gemm_mode=chosen, leaf_size=args.leaf))
     for _ in range(args.warmup):
         ch()
     # every phase, in an untimed pass: the breakdown and the dominant kernel
@@ -224,14 +227,22 @@ def sec_value(P, W, args, out):
         f"orth {orth:.2e} res {res:.2e}")
     lam_gpu = ch.lam.cpu().numpy()
     del ch
-    pl = Solver(P, d, e, P.opts(gemm_mode=P.GEMM_FP64))
+    if args.chosen_only:  # counter runs: nothing but the chosen-form solves
+        out.update(t_ch=t_ch, t_clean=t_clean, t_pl=None, t_graph=None, t_l32=None, orth=orth, res=res, phases=phases,
+                   dom=dom, dom_ph=dom_ph, alg=alg, table=table, lam=lam_gpu, d=d, e=e)
+        return
+    pl = Solver(P, d, e, P.opts(gemm_mode=P.GEMM_FP64, leaf_size=args.leaf))
     t_pl = timed(pl, args.steps, 1)
     log(f"[bench] plain FP64 {t_pl * 1e3:.3f} ms/solve")
     del pl
+    l32 = Solver(P, d, e, P.opts(gemm_mode=P.GEMM_FP64, leaf_size=32))
+    t_l32 = timed(l32, args.steps, 1)
+    log(f"[bench] plain FP64 with the library's default leaf size 32: {t_l32 * 1e3:.3f} ms/solve")
+    del l32
     # the same solve planned once (prepare) and replayed from a HIP graph: GPU time without
     # the per-call host planning and plan upload
     import torch
-    bs = P.BatchedSolver([n], P.opts(gemm_mode=P.GEMM_FP64))
+    bs = P.BatchedSolver([n], P.opts(gemm_mode=P.GEMM_FP64, leaf_size=args.leaf))
     bs.d[:n] = torch.tensor(d, device="cuda")
     bs.e[: n - 1] = torch.tensor(e, device="cuda")
     bs.prepare()
@@ -244,7 +255,7 @@ def sec_value(P, W, args, out):
     log(f"[bench] same solve, planned once and graph-replayed: {t_graph * 1e3:.3f} ms/solve")
     del bs
     torch.cuda.empty_cache()
-    out.update(t_graph=t_graph, t_ch=t_ch, t_clean=t_clean, t_pl=t_pl, orth=orth, res=res, phases=phases, dom=dom, dom_ph=dom_ph,
+    out.update(t_graph=t_graph, t_l32=t_l32, t_ch=t_ch, t_clean=t_clean, t_pl=t_pl, orth=orth, res=res, phases=phases, dom=dom, dom_ph=dom_ph,
                alg=alg, table=table, lam=lam_gpu, d=d, e=e)
 
 
@@ -460,6 +471,10 @@ def main():
     ap.add_argument("--skip", default="", help="comma list of sections: merge_gemm,toeplitz,examples,split,batch,adjoint,cpu")
     ap.add_argument("--skip-paths", default="", help="comma list of update paths to leave out: hss,split")
     ap.add_argument("--only-value", action="store_true", help="time the headline solve only (profiling runs)")
+    ap.add_argument("--leaf", type=int, default=16,
+                    help="leaf size of the headline solve (16: fastest in a sweep over 8..64 on this GPU)")
+    ap.add_argument("--chosen-only", action="store_true",
+                    help="time the chosen-form headline solve only (no plain, leaf-32 or graph timings): counter runs")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (reference kernel for the HBM byte counters)")
     args = ap.parse_args()
@@ -513,7 +528,7 @@ def main():
         roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
     else:
         roof["frac"] = None
-    roof.update(traffic=measured_traffic(dom), kernel=dom, launches_per_step=int(cnt_dom),
+    roof.update(traffic=measured_traffic(dom, args.leaf), kernel=dom, launches_per_step=int(cnt_dom),
                 ms_per_step=round(ms_dom, 4))
     if dom == "copy":
         roof["algorithmic_bytes_per_launch"] = round(alg["copy_bytes"] / max(cnt_dom, 1))
@@ -547,12 +562,13 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "uniform_n16384", "n": 16384, "dist": "d,e iid U[-1,1] seed 0", "leaf": 32,
+        "config": {"workload": "uniform_n16384", "n": 16384, "dist": "d,e iid U[-1,1] seed 0", "leaf": args.leaf,
                    "chosen_form": "hss for merges with K>=4096, else fp64-mfma",
                    "top_merge_K": int(v["table"][-1, 2])},
-        "plain_fp64_s": round(v["t_pl"], 6),
+        "plain_fp64_s": v["t_pl"] and round(v["t_pl"], 6),
         "value_without_phase_events_s": round(v["t_clean"], 6),
-        "graph_replay_prepared_s": round(v["t_graph"], 6),
+        "graph_replay_prepared_s": v["t_graph"] and round(v["t_graph"], 6),
+        "plain_fp64_leaf32_s": v["t_l32"] and round(v["t_l32"], 6),
         "accuracy": {"orth_max": v["orth"], "residual": v["res"]},
         "phases_ms": {k: round(x[0], 4) for k, x in phases.items()},
         "roofline": roof,

@@ -49,110 +49,116 @@ __global__ void __launch_bounds__(256) k_merge_gemm(BlockMap bm, Scratch S) {
   const int TN = (K + GT - 1) / GT;  // column tiles with work (the grid covers m columns)
   const int nact = TM * TN;
   if (lb >= nact) return;
-  // Tile order.  Workgroups are dispatched round-robin over the 8 XCDs, each
-  // with its own L2: hand XCD (lb mod 8) a contiguous range of tiles, and walk
-  // each range in groups of 8 row tiles so that the blocks in flight on one XCD
-  // share A panels across columns and B panels across rows.
-  const int n8 = nact - nact % 8;
-  const int lid = (lb < n8) ? (lb % 8) * (n8 / 8) + lb / 8 : lb;
-  constexpr int GM = 8;
-  const int width = GM * TN;
-  const int first = (lid / width) * GM;
-  const int gsz = min(TM - first, GM);
-  const int in = lid % width;
-  const int mt = first + in % gsz, nt = in / gsz;
-  const bool top = mt < tmt;
-  const int mrow0 = top ? mt * GT : (mt - tmt) * GT;  // first row of the tile within its half
-  const int Mrows = top ? n1 : n2;
-  const int rowoff = top ? 0 : n1;                    // half's first row within the merge block
-  const int kd = top ? k1 + k2 : k2 + k3;
-  const int64_t so = M.s_off;
-  const int32_t* colA = top ? S.coltop + so : S.colbot + so;
-  const double* Bm = S.uhat + M.u_off + (int64_t)(top ? 0 : k1) * K;  // row-major, ld = K
-  const double* A = M.qin + rowoff;
-  const int64_t lda = M.ldin;
-  const int ncol0 = nt * GT;
+  // A block computes tiles lb, lb + G, ... (G = the merge's blocks, at most
+  // kGemmBlockCap), so merges whose K is far below m launch few idle blocks.
+  const int G = bm.pfx[mi + 1] - bm.pfx[mi];
+  for (int tile = lb; tile < nact; tile += G) {
+    // Tile order.  Workgroups are dispatched round-robin over the 8 XCDs, each
+    // with its own L2: hand XCD (tile mod 8) a contiguous range of tiles, and walk
+    // each range in groups of 8 row tiles so that the blocks in flight on one XCD
+    // share A panels across columns and B panels across rows.
+    const int n8 = nact - nact % 8;
+    const int lid = (tile < n8) ? (tile % 8) * (n8 / 8) + tile / 8 : tile;
+    constexpr int GM = 8;
+    const int width = GM * TN;
+    const int first = (lid / width) * GM;
+    const int gsz = min(TM - first, GM);
+    const int in = lid % width;
+    const int mt = first + in % gsz, nt = in / gsz;
+    const bool top = mt < tmt;
+    const int mrow0 = top ? mt * GT : (mt - tmt) * GT;  // first row of the tile within its half
+    const int Mrows = top ? n1 : n2;
+    const int rowoff = top ? 0 : n1;                    // half's first row within the merge block
+    const int kd = top ? k1 + k2 : k2 + k3;
+    const int64_t so = M.s_off;
+    const int32_t* colA = top ? S.coltop + so : S.colbot + so;
+    const double* Bm = S.uhat + M.u_off + (int64_t)(top ? 0 : k1) * K;  // row-major, ld = K
+    const double* A = M.qin + rowoff;
+    const int64_t lda = M.ldin;
+    const int ncol0 = nt * GT;
 
-  const int t = threadIdx.x;
-  const int lkc = t >> 4;          // k index this thread stages (A column / B row)
-  const int l8 = (t & 15) * E;     // first of E consecutive rows (A) / columns (B)
-  double ra[E], rb[E];
+    const int t = threadIdx.x;
+    const int lkc = t >> 4;          // k index this thread stages (A column / B row)
+    const int l8 = (t & 15) * E;     // first of E consecutive rows (A) / columns (B)
+    double ra[E], rb[E];
 
-  auto gload = [&](int kt) {
-    const int kk = kt * GK + lkc;
-    if (kk < kd) {
-      const double* src = A + (int64_t)colA[kk] * lda + mrow0 + l8;
-#pragma unroll
-      for (int e = 0; e < E; ++e) ra[e] = (mrow0 + l8 + e < Mrows) ? src[e] : 0.0;
-      const double* bs = Bm + (int64_t)kk * K + ncol0 + l8;
-#pragma unroll
-      for (int e = 0; e < E; ++e) rb[e] = (ncol0 + l8 + e < K) ? bs[e] : 0.0;
-    } else {
-#pragma unroll
-      for (int e = 0; e < E; ++e) { ra[e] = 0.0; rb[e] = 0.0; }
+    auto gload = [&](int kt) {
+      const int kk = kt * GK + lkc;
+      if (kk < kd) {
+        const double* src = A + (int64_t)colA[kk] * lda + mrow0 + l8;
+  #pragma unroll
+        for (int e = 0; e < E; ++e) ra[e] = (mrow0 + l8 + e < Mrows) ? src[e] : 0.0;
+        const double* bs = Bm + (int64_t)kk * K + ncol0 + l8;
+  #pragma unroll
+        for (int e = 0; e < E; ++e) rb[e] = (ncol0 + l8 + e < K) ? bs[e] : 0.0;
+      } else {
+  #pragma unroll
+        for (int e = 0; e < E; ++e) { ra[e] = 0.0; rb[e] = 0.0; }
+      }
+    };
+    auto lstore = [&](int buf) {
+  #pragma unroll
+      for (int e = 0; e < E; ++e) {
+        As[buf][lkc][l8 + e] = ra[e];
+        Bs[buf][lkc][l8 + e] = rb[e];
+      }
+    };
+
+    const int w = t >> 6, lane = t & 63;
+    const int wm = (w & 1) * WT, wn = (w >> 1) * WT;
+    const int li = lane & 15, lk = lane >> 4;
+    d4_t acc[NB][NB];
+  #pragma unroll
+    for (int i = 0; i < NB; ++i)
+  #pragma unroll
+      for (int j = 0; j < NB; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+
+    const int nkt = (kd + GK - 1) / GK;
+    if (nkt > 0) {
+      gload(0);
+      lstore(0);
     }
-  };
-  auto lstore = [&](int buf) {
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      As[buf][lkc][l8 + e] = ra[e];
-      Bs[buf][lkc][l8 + e] = rb[e];
-    }
-  };
-
-  const int w = t >> 6, lane = t & 63;
-  const int wm = (w & 1) * WT, wn = (w >> 1) * WT;
-  const int li = lane & 15, lk = lane >> 4;
-  d4_t acc[NB][NB];
-#pragma unroll
-  for (int i = 0; i < NB; ++i)
-#pragma unroll
-    for (int j = 0; j < NB; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
-
-  const int nkt = (kd + GK - 1) / GK;
-  if (nkt > 0) {
-    gload(0);
-    lstore(0);
-  }
-  __syncthreads();
-  for (int kt = 0; kt < nkt; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < nkt) gload(kt + 1);
-#pragma unroll
-    for (int ks = 0; ks < GK / 4; ++ks) {
-      const int kr = ks * 4 + lk;
-      double av[NB], bv[NB];
-#pragma unroll
-      for (int i = 0; i < NB; ++i) av[i] = As[buf][kr][wm + i * 16 + li];
-#pragma unroll
-      for (int j = 0; j < NB; ++j) bv[j] = Bs[buf][kr][wn + j * 16 + li];
-#pragma unroll
-      for (int i = 0; i < NB; ++i)
-#pragma unroll
-        for (int j = 0; j < NB; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
-    }
-    if (kt + 1 < nkt) lstore(buf ^ 1);
     __syncthreads();
-  }
+    for (int kt = 0; kt < nkt; ++kt) {
+      const int buf = kt & 1;
+      if (kt + 1 < nkt) gload(kt + 1);
+  #pragma unroll
+      for (int ks = 0; ks < GK / 4; ++ks) {
+        const int kr = ks * 4 + lk;
+        double av[NB], bv[NB];
+  #pragma unroll
+        for (int i = 0; i < NB; ++i) av[i] = As[buf][kr][wm + i * 16 + li];
+  #pragma unroll
+        for (int j = 0; j < NB; ++j) bv[j] = Bs[buf][kr][wn + j * 16 + li];
+  #pragma unroll
+        for (int i = 0; i < NB; ++i)
+  #pragma unroll
+          for (int j = 0; j < NB; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+      }
+      if (kt + 1 < nkt) lstore(buf ^ 1);
+      __syncthreads();
+    }
 
-  // Epilogue: v_mfma_f64_16x16x4 leaves element r of lane (li, lk) of block
-  // (i, j) at row lk + 4 r, column li (rows interleaved across lane groups).
-  const int32_t* dest = S.dest + so;
-  double* out = M.qout + rowoff;
-  const int64_t ldo = M.ldout;
-#pragma unroll
-  for (int j = 0; j < NB; ++j) {
-    const int cj = ncol0 + wn + j * 16 + li;
-    if (cj >= K) continue;
-    double* oc = out + (int64_t)dest[cj] * ldo;
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = mrow0 + wm + i * 16 + lk + 4 * r;
-        if (row < Mrows) oc[row] = acc[i][j][r];
+    // Epilogue: v_mfma_f64_16x16x4 leaves element r of lane (li, lk) of block
+    // (i, j) at row lk + 4 r, column li (rows interleaved across lane groups).
+    const int32_t* dest = S.dest + so;
+    double* out = M.qout + rowoff;
+    const int64_t ldo = M.ldout;
+  #pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int cj = ncol0 + wn + j * 16 + li;
+      if (cj >= K) continue;
+      double* oc = out + (int64_t)dest[cj] * ldo;
+  #pragma unroll
+      for (int i = 0; i < NB; ++i) {
+  #pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = mrow0 + wm + i * 16 + lk + 4 * r;
+          if (row < Mrows) oc[row] = acc[i][j][r];
+        }
       }
     }
+    __syncthreads();  // LDS reused by the next tile
   }
 }
 

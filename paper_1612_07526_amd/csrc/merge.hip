@@ -897,7 +897,7 @@ int map_blocks(int kind, int m, int n1, int gt) {
     case MAP_ROWS256: return cdiv(m, 256);
     case MAP_ROT: return cdiv(m, 256) * std::max(1, std::min(m / 2, kRotGroups));
     case MAP_UWRITE: return cdiv(m, 256) * std::max(1, std::min(m, kUwRowGroups));
-    case MAP_GEMM: return (cdiv(n1, gt) + cdiv(m - n1, gt)) * cdiv(m, gt);
+    case MAP_GEMM: return std::min((cdiv(n1, gt) + cdiv(m - n1, gt)) * cdiv(m, gt), kGemmBlockCap);
     case MAP_COPY: {  // columns per block = 256 / (m rounded up to a power of two, at most 256)
       int rpt = 1;
       while (rpt < m && rpt < 256) rpt <<= 1;

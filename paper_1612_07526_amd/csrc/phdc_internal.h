@@ -138,6 +138,7 @@ struct LevelMaps {
 };
 // Blocks of one merge for a kernel class; gt is the FP64 GEMM tile edge (MAP_GEMM).
 int map_blocks(int kind, int m, int n1, int gt);
+constexpr int kGemmBlockCap = 1024;      // blocks per merge of the update GEMMs (they loop over tiles)
 constexpr int kTileBuckets = 21;        // merge-size buckets of the GEMM tile table (m <= 2^20)
 int gemm_tile_for(int64_t maxm);        // tile edge for a level whose largest merge is maxm
 void launch_merge_gemm_f64(const BlockMap& bm, int total, const Scratch& S, int tile, hipStream_t s);

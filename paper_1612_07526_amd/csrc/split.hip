@@ -146,106 +146,111 @@ __global__ void __launch_bounds__(256) k_split_gemm(BlockMap bm, Scratch S, Spli
   const int TN = (K + XT - 1) / XT;
   const int nact = TM * TN;
   if (lb >= nact) return;
-  // XCD-aware grouped tile order, as in the FP64 update GEMM
-  const int n8 = nact - nact % 8;
-  const int lid = (lb < n8) ? (lb % 8) * (n8 / 8) + lb / 8 : lb;
-  const int width = 8 * TN;
-  const int first = (lid / width) * 8;
-  const int gsz = min(TM - first, 8);
-  const int in = lid % width;
-  const int mt = first + in % gsz, nt = in / gsz;
-  const bool top = mt < tmt;
-  const int mrow0 = top ? mt * XT : (mt - tmt) * XT;
-  const int rows = top ? n1 : n2;
-  const int rowoff = top ? 0 : n1;
-  const int kd = top ? k1 + k2 : k2 + k3;
-  const int kdp = (kd + 7) & ~7;
-  const int64_t so = M.s_off;
-  const __bf16* Abase = B.aslice + (int64_t)nsl * M.x_off + (top ? 0 : (int64_t)nsl * n1 * (((k1 + k2) + 7) & ~7));
-  const int64_t astride = (int64_t)rows * kdp;
-  const __bf16* Bbase = B.bslice + (int64_t)nsl * M.x_off + (int64_t)(top ? 0 : k1) * Kp;
-  const int64_t bstride = (int64_t)K * Kp;
-  const int ncol0 = nt * XT;
-  const int t = threadIdx.x;
-  const int w = t >> 6, lane = t & 63;
-  const int wm = (w & 1) * 64, wn = (w >> 1) * 64;
-  const int li = lane & 15, lg = lane >> 4;
+  // A block computes tiles lb, lb + G, ... (G = the merge's blocks).
+  const int G = bm.pfx[mi + 1] - bm.pfx[mi];
+  for (int tile = lb; tile < nact; tile += G) {
+    // XCD-aware grouped tile order, as in the FP64 update GEMM
+    const int n8 = nact - nact % 8;
+    const int lid = (tile < n8) ? (tile % 8) * (n8 / 8) + tile / 8 : tile;
+    const int width = 8 * TN;
+    const int first = (lid / width) * 8;
+    const int gsz = min(TM - first, 8);
+    const int in = lid % width;
+    const int mt = first + in % gsz, nt = in / gsz;
+    const bool top = mt < tmt;
+    const int mrow0 = top ? mt * XT : (mt - tmt) * XT;
+    const int rows = top ? n1 : n2;
+    const int rowoff = top ? 0 : n1;
+    const int kd = top ? k1 + k2 : k2 + k3;
+    const int kdp = (kd + 7) & ~7;
+    const int64_t so = M.s_off;
+    const __bf16* Abase = B.aslice + (int64_t)nsl * M.x_off + (top ? 0 : (int64_t)nsl * n1 * (((k1 + k2) + 7) & ~7));
+    const int64_t astride = (int64_t)rows * kdp;
+    const __bf16* Bbase = B.bslice + (int64_t)nsl * M.x_off + (int64_t)(top ? 0 : k1) * Kp;
+    const int64_t bstride = (int64_t)K * Kp;
+    const int ncol0 = nt * XT;
+    const int t = threadIdx.x;
+    const int w = t >> 6, lane = t & 63;
+    const int wm = (w & 1) * 64, wn = (w >> 1) * 64;
+    const int li = lane & 15, lg = lane >> 4;
 
-  double acc[4][4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.0;
-
-  const int nks = (kd + XK - 1) / XK;
-  for (int ks = 0; ks < nks; ++ks) {
-    const int kb = ks * XK;
-    __syncthreads();
-    // stage: A slices (rows x 32 k, k contiguous in global), B slices (32 k x 128 j) transposed to [j][k]
-    for (int e = t; e < nsl * XT * 4; e += 256) {
-      const int p = e / (XT * 4), rem = e % (XT * 4), i = rem >> 2, kq = (rem & 3) * 8;
-      const int row = mrow0 + i, k = kb + kq;
-      bf8_t v;
-      if (row < rows && k < kdp) v = *(const bf8_t*)(Abase + (int64_t)p * astride + (int64_t)row * kdp + k);
-      else
-        for (int q = 0; q < 8; ++q) v[q] = (__bf16)0.0f;
-      *(bf8_t*)&As[p][i][kq] = v;
-    }
-    for (int e = t; e < nsl * XK * (XT / 8); e += 256) {
-      const int p = e / (XK * (XT / 8)), rem = e % (XK * (XT / 8)), kk = rem / (XT / 8), j8 = (rem % (XT / 8)) * 8;
-      const int k = kb + kk, col = ncol0 + j8;
-      bf8_t v;
-      if (k < kd && col < Kp) v = *(const bf8_t*)(Bbase + (int64_t)p * bstride + (int64_t)k * Kp + col);
-      else
-        for (int q = 0; q < 8; ++q) v[q] = (__bf16)0.0f;
-      for (int q = 0; q < 8; ++q) Bs[p][j8 + q][kk] = v[q];
-    }
-    __syncthreads();
-    for (int tw = 0; tw < nsl; ++tw) {  // weight group t = p + q
-      f4s_t c[4][4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) c[i][j] = f4s_t{0.f, 0.f, 0.f, 0.f};
-      for (int p = 0; p <= tw; ++p) {
-        const int q = tw - p;
-        bf8_t av[4], bv[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) av[i] = *(const bf8_t*)&As[p][wm + i * 16 + li][lg * 8];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) bv[j] = *(const bf8_t*)&Bs[q][wn + j * 16 + li][lg * 8];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) c[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], c[i][j], 0, 0, 0);
-      }
-      const double wt = ldexp(1.0, -8 * (tw + 2));
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) acc[i][j][r] += (double)c[i][j][r] * wt;
-    }
-  }
-  // epilogue: undo the scales, write to the sorted output columns
-  const int32_t* dest = S.dest + so;
-  double* out = M.qout + rowoff;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int cj = ncol0 + wn + j * 16 + li;
-    if (cj >= K) continue;
-    double* oc = out + (int64_t)dest[cj] * M.ldout;
-    const int fe = B.fcol[so + cj];
-#pragma unroll
+    double acc[4][4][4];
+  #pragma unroll
     for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = mrow0 + wm + i * 16 + kSplitRow(lg, r);
-        if (row < rows) oc[row] = ldexp(acc[i][j][r], B.erow[so + rowoff + row] + fe);
+  #pragma unroll
+      for (int j = 0; j < 4; ++j)
+  #pragma unroll
+        for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.0;
+
+    const int nks = (kd + XK - 1) / XK;
+    for (int ks = 0; ks < nks; ++ks) {
+      const int kb = ks * XK;
+      __syncthreads();
+      // stage: A slices (rows x 32 k, k contiguous in global), B slices (32 k x 128 j) transposed to [j][k]
+      for (int e = t; e < nsl * XT * 4; e += 256) {
+        const int p = e / (XT * 4), rem = e % (XT * 4), i = rem >> 2, kq = (rem & 3) * 8;
+        const int row = mrow0 + i, k = kb + kq;
+        bf8_t v;
+        if (row < rows && k < kdp) v = *(const bf8_t*)(Abase + (int64_t)p * astride + (int64_t)row * kdp + k);
+        else
+          for (int q = 0; q < 8; ++q) v[q] = (__bf16)0.0f;
+        *(bf8_t*)&As[p][i][kq] = v;
       }
+      for (int e = t; e < nsl * XK * (XT / 8); e += 256) {
+        const int p = e / (XK * (XT / 8)), rem = e % (XK * (XT / 8)), kk = rem / (XT / 8), j8 = (rem % (XT / 8)) * 8;
+        const int k = kb + kk, col = ncol0 + j8;
+        bf8_t v;
+        if (k < kd && col < Kp) v = *(const bf8_t*)(Bbase + (int64_t)p * bstride + (int64_t)k * Kp + col);
+        else
+          for (int q = 0; q < 8; ++q) v[q] = (__bf16)0.0f;
+        for (int q = 0; q < 8; ++q) Bs[p][j8 + q][kk] = v[q];
+      }
+      __syncthreads();
+      for (int tw = 0; tw < nsl; ++tw) {  // weight group t = p + q
+        f4s_t c[4][4];
+  #pragma unroll
+        for (int i = 0; i < 4; ++i)
+  #pragma unroll
+          for (int j = 0; j < 4; ++j) c[i][j] = f4s_t{0.f, 0.f, 0.f, 0.f};
+        for (int p = 0; p <= tw; ++p) {
+          const int q = tw - p;
+          bf8_t av[4], bv[4];
+  #pragma unroll
+          for (int i = 0; i < 4; ++i) av[i] = *(const bf8_t*)&As[p][wm + i * 16 + li][lg * 8];
+  #pragma unroll
+          for (int j = 0; j < 4; ++j) bv[j] = *(const bf8_t*)&Bs[q][wn + j * 16 + li][lg * 8];
+  #pragma unroll
+          for (int i = 0; i < 4; ++i)
+  #pragma unroll
+            for (int j = 0; j < 4; ++j) c[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], c[i][j], 0, 0, 0);
+        }
+        const double wt = ldexp(1.0, -8 * (tw + 2));
+  #pragma unroll
+        for (int i = 0; i < 4; ++i)
+  #pragma unroll
+          for (int j = 0; j < 4; ++j)
+  #pragma unroll
+            for (int r = 0; r < 4; ++r) acc[i][j][r] += (double)c[i][j][r] * wt;
+      }
+    }
+    // epilogue: undo the scales, write to the sorted output columns
+    const int32_t* dest = S.dest + so;
+    double* out = M.qout + rowoff;
+  #pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int cj = ncol0 + wn + j * 16 + li;
+      if (cj >= K) continue;
+      double* oc = out + (int64_t)dest[cj] * M.ldout;
+      const int fe = B.fcol[so + cj];
+  #pragma unroll
+      for (int i = 0; i < 4; ++i)
+  #pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = mrow0 + wm + i * 16 + kSplitRow(lg, r);
+          if (row < rows) oc[row] = ldexp(acc[i][j][r], B.erow[so + rowoff + row] + fe);
+        }
+    }
+    __syncthreads();  // LDS reused by the next tile
   }
 }
 
