@@ -66,17 +66,20 @@ def algorithmic(table):
 
     gemm_flops: 2 [n1 (k1+k2) + n2 (k2+k3)] K over merges on the FP64 path (Gu's
                 grouped products, Eq. (6));
-    copy_bytes: each deflated column read once over its nonzero rows (n1, m or n2)
-                and written once over all m rows, 8 bytes per entry;
+    copy_bytes: each deflated column read once over the rows it can be nonzero in and
+                written once over the same rows, or over all m rows at the last merge
+                of the matrix (whose output is the caller's Q), 8 bytes per entry;
     uhat_write_bytes: 8 K^2 bytes per merge.
     """
     t = table.astype(np.float64)
-    m, n1, K, k1, k2, k3, path, dp1, dp2, dp3 = (t[:, i] for i in (0, 1, 2, 3, 4, 5, 8, 10, 11, 12))
+    m, n1, K, k1, k2, k3, nt1, nt2, path, root = (t[:, i] for i in (0, 1, 2, 3, 4, 5, 6, 7, 8, 15))
+    rows = ((table[:, 13].astype(np.int64) & 0xFFFFFFFF) + (table[:, 14].astype(np.int64) << 32)).astype(np.float64)
     n2 = m - n1
     plain = path == 0
+    written = np.where(root > 0, m * (nt1 + nt2), rows)
     return {
         "gemm_flops": float(np.sum((2 * (n1 * (k1 + k2) + n2 * (k2 + k3)) * K)[plain])),
-        "copy_bytes": float(np.sum(8 * (n1 * dp1 + m * dp2 + n2 * dp3 + m * (dp1 + dp2 + dp3)))),
+        "copy_bytes": float(np.sum(8 * (rows + written))),
         "uhat_write_bytes": float(np.sum(K * K * 8)),
     }
 

@@ -175,10 +175,12 @@ int phdc_profile_select(uint32_t mask);
  * phdc_status): up to max_rows rows of PHDC_MERGE_TABLE_COLS int32 each:
  * {m, n1, K, k1, k2, k3, type-1 deflations, type-2 deflations,
  *  path (0 FP64, 1 split, 2 HSS), HSS rank,
- *  deflated columns nonzero in the Q1 rows only, in both halves, in the Q2 rows only}.
+ *  deflated columns nonzero in the Q1 rows only, in both halves, in the Q2 rows only,
+ *  rows the deflated columns can be nonzero in, summed: low 32 bits (as unsigned), high bits,
+ *  1 for the last merge of its matrix (which writes every row of its output) else 0}.
  * Rows are in the order the merges were planned (leaves upward, the root last).
  * *rows_out receives the number of merges.  Returns 0 or -1. */
-#define PHDC_MERGE_TABLE_COLS 13
+#define PHDC_MERGE_TABLE_COLS 16
 int phdc_merge_table(const void *work, int64_t max_rows, int32_t *table_host, int64_t *rows_out);
 
 /* ---------------------------------------------------------------- secular roots

@@ -184,14 +184,16 @@ def merge_stats(work: torch.Tensor) -> list:
     return list(buf)
 
 
-MERGE_TABLE_COLS = 13
+MERGE_TABLE_COLS = 16
 
 
 def merge_table(work: torch.Tensor):
-    """Per-merge sizes of the last solve on `work` as an (nmerges, 13) int32 numpy array:
+    """Per-merge sizes of the last solve on `work` as an (nmerges, 16) int32 numpy array:
     m, n1, K, k1, k2, k3, type-1 deflations, type-2 deflations, path (0 FP64, 1 split,
     2 HSS), HSS rank, deflated columns nonzero in the Q1 rows only / both halves / the
-    Q2 rows only.  Rows follow the planning order (the root merge last)."""
+    Q2 rows only, rows the deflated columns can be nonzero in (summed; low 32 bits as
+    unsigned, then the high bits: see deflated_rows), 1 for the last merge of its matrix.
+    Rows follow the planning order (the root merge last)."""
     import numpy as np
     lib = load()
     rows = ctypes.c_int64()
@@ -200,6 +202,14 @@ def merge_table(work: torch.Tensor):
     buf = (ctypes.c_int32 * max(n * MERGE_TABLE_COLS, 1))()
     _check(lib.phdc_merge_table(_ptr(work), n, buf, ctypes.byref(rows)), "phdc_merge_table")
     return np.frombuffer(buf, dtype=np.int32)[: n * MERGE_TABLE_COLS].reshape(n, MERGE_TABLE_COLS).copy()
+
+
+def deflated_rows(table):
+    """Rows the deflated columns of each merge can be nonzero in, summed (int64 numpy
+    array), from the two 32-bit columns of merge_table."""
+    import numpy as np
+    lo = table[:, 13].astype(np.int64) & 0xFFFFFFFF
+    return lo + (table[:, 14].astype(np.int64) << 32)
 
 
 def _raise_status(work, stream=None):

@@ -88,11 +88,11 @@ struct Sizes {
 };
 
 struct Layout {
-  size_t status, hdr, counters, mparam, descs, leaves, canon, canon_pfx, maps, scratch, uhat, qtwin, ltwin, hss,
-      hss_desc, sa, sb, serow, sfcol, total;
+  size_t status, hdr, counters, mparam, descs, leaves, canon, canon_pfx, maps, scratch, uhat, qtwin, ltwin, ranges,
+      hss, hss_desc, sa, sb, serow, sfcol, total;
 };
 
-constexpr int kScratchD = 12, kScratchI = 22;
+constexpr int kScratchD = 17, kScratchI = 18;  // 8-byte arrays (doubles, row ranges), int32 arrays
 
 int32_t hss_threshold(const phdc_opts* o) {
   if (!o || o->gemm_mode != PHDC_GEMM_HSS) return 0;
@@ -164,6 +164,7 @@ Layout layout_of(const Sizes& z) {
   L.uhat = take((size_t)z.uhat * 8);
   L.qtwin = take((size_t)z.q_total * 8);
   L.ltwin = take((size_t)z.n_total * 8);
+  L.ranges = take((size_t)z.n_total * 2 * sizeof(RowRange));  // column ranges, one set per eigenvector buffer
   L.hss = take(z.hss_arena);
   L.hss_desc = take(z.hss_desc);
   L.sa = take((size_t)z.nsl * z.xslots * 2);
@@ -187,12 +188,14 @@ Scratch scratch_of(char* base, const Layout& L, const Sizes& z) {
     p += align_up((size_t)z.n_total * 4);
     return r;
   };
+  auto rtake = [&]() { return (RowRange*)dtake(); };  // 8 bytes per entry, like a double
   S.dv = dtake(); S.zv = dtake(); S.ds = dtake(); S.zs = dtake(); S.rc = dtake(); S.rs = dtake();
   S.dfv1 = dtake(); S.dfv2 = dtake(); S.tau = dtake(); S.dorg = dtake(); S.zhat = dtake(); S.cnorm = dtake();
+  S.rgtop = rtake(); S.rgbot = rtake(); S.crng = rtake(); S.rrp = rtake(); S.rrj = rtake();
   S.col = itake(); S.part = itake(); S.flag = itake(); S.surv = itake(); S.grp = itake(); S.coltop = itake();
-  S.colbot = itake(); S.rcolp = itake(); S.rcolj = itake(); S.rpart = itake(); S.chain = itake();
-  S.dfc1 = itake(); S.dfp1 = itake(); S.dfc2 = itake(); S.dfp2 = itake(); S.org = itake(); S.dest = itake();
-  S.destd1 = itake(); S.destd2 = itake(); S.grpsrc = itake(); S.csort = itake(); S.psort = itake();
+  S.colbot = itake(); S.rcolp = itake(); S.rcolj = itake(); S.chain = itake();
+  S.dfc1 = itake(); S.dfc2 = itake(); S.org = itake(); S.dest = itake();
+  S.destd1 = itake(); S.destd2 = itake(); S.grpsrc = itake(); S.csort = itake();
   S.mparam = (double*)(base + L.mparam);
   S.uhat = (double*)(base + L.uhat);
   S.counters = (int32_t*)(base + L.counters);
@@ -280,6 +283,7 @@ struct Buffers {
   const double* e;
   double* lam[2];
   double* q[2];
+  RowRange* rng[2];                      // column ranges of q[0], q[1] (indexed like lam)
   std::vector<int64_t> off, eoff, qoff;  // per matrix
   std::vector<int64_t> ld[2];            // per matrix
 };
@@ -295,13 +299,21 @@ int run_hss_level(const MergeDesc* hdescs, int nm, const Scratch& S, char* arena
   for (int i = 0; i < nm; ++i)
     if (hdescs[i].m >= thr) cand.push_back(i);
   if (cand.empty()) return 0;
-  if (hipStreamSynchronize(s) != hipSuccess) return -110;
+  // one read of the counters of the level's merges (their ids are consecutive)
+  int32_t lo = hdescs[cand.front()].id, hi = lo;
   for (int i : cand) {
-    int32_t c[kCounters];
-    if (hipMemcpy(c, S.counters + (int64_t)hdescs[i].id * kCounters, sizeof(c), hipMemcpyDeviceToHost) != hipSuccess)
-      return -111;
-    if (c[C_PATH] != 2) continue;
-    int rc = run_hss_merge(hdescs[i], c[C_K], S, arena, arena_bytes, descarea, desc_bytes, o,
+    lo = std::min(lo, hdescs[i].id);
+    hi = std::max(hi, hdescs[i].id);
+  }
+  std::vector<int32_t> c((size_t)(hi - lo + 1) * kCounters);
+  if (hipMemcpyAsync(c.data(), S.counters + (int64_t)lo * kCounters, c.size() * 4, hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return -111;
+  for (int i : cand) {
+    const int32_t* ci = c.data() + (size_t)(hdescs[i].id - lo) * kCounters;
+    if (ci[C_PATH] != 2) continue;
+    int rc = run_hss_merge(hdescs[i], ci[C_K], S, arena, arena_bytes, descarea, desc_bytes, o,
                            S.counters + (int64_t)hdescs[i].id * kCounters, s);
     if (rc != 0) return rc;
   }
@@ -395,6 +407,10 @@ int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n,
     D.hss_min_k = hss_threshold(o);
     D.x_off = xoff[i];
     D.split_on = z.nsl > 0 ? 1 : 0;
+    D.rin = BF.rng[pin] + BF.off[b] + nd.r0;
+    D.rout = BF.rng[pout] + BF.off[b] + nd.r0;
+    D.r0 = (int32_t)nd.r0;
+    D.root = nd.depth == 0 ? 1 : 0;
   }
   put(plan, L.descs - plan0, descs.data(), descs.size());
 
@@ -412,6 +428,8 @@ int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n,
     A.lam = BF.lam[p] + BF.off[b] + nd.r0;
     A.s = nd.m;
     A.couple = (nd.r0 > 0 ? 1 : 0) | (nd.r0 + nd.m < n[b] ? 2 : 0);
+    A.rng = BF.rng[p] + BF.off[b] + nd.r0;
+    A.r0 = (int32_t)nd.r0;
   }
   put(plan, L.leaves - plan0, leaves.data(), leaves.size());
 
@@ -559,6 +577,8 @@ int phdc_stedc(int64_t n, const double* d, const double* e, double* lambda, doub
   BF.lam[1] = (double*)(base + SU.L.ltwin);
   BF.q[0] = Q;
   BF.q[1] = (double*)(base + SU.L.qtwin);
+  BF.rng[0] = (RowRange*)(base + SU.L.ranges);
+  BF.rng[1] = BF.rng[0] + n;
   BF.off = {0};
   BF.eoff = {0};
   BF.qoff = {0};
@@ -658,6 +678,8 @@ static int stedc_batched_impl(int64_t B, const int64_t* n_host, const int64_t* o
   BF.lam[1] = (double*)(base + SU.L.ltwin);
   BF.q[0] = Q;
   BF.q[1] = (double*)(base + SU.L.qtwin);
+  BF.rng[0] = (RowRange*)(base + SU.L.ranges);
+  BF.rng[1] = BF.rng[0] + acc;
   BF.off.assign(off_host, off_host + B);
   BF.qoff.assign(qoff_host, qoff_host + B);
   BF.eoff.resize(B);
@@ -757,6 +779,10 @@ int phdc_merge(int64_t n1, int64_t n2, const double* D, const double* z, double 
   Dd.hss_min_k = hss_threshold(o);
   Dd.x_off = 0;
   Dd.split_on = zs.nsl > 0 ? 1 : 0;
+  Dd.rin = nullptr;  // Q1 and Q2 fill their halves
+  Dd.rout = nullptr;
+  Dd.r0 = 0;
+  Dd.root = 1;
   std::vector<char> plan(L.scratch - L.hdr, 0);
   const int32_t root_and_count[2] = {0, 1};
   std::memcpy(plan.data(), root_and_count, 8);
@@ -862,6 +888,9 @@ int phdc_merge_table(const void* work, int64_t max_rows, int32_t* table_host, in
     r[10] = c[i * kCounters + C_DP1];
     r[11] = c[i * kCounters + C_DP2];
     r[12] = c[i * kCounters + C_DP3];
+    r[13] = c[i * kCounters + C_DROWS_LO];
+    r[14] = c[i * kCounters + C_DROWS_HI];
+    r[15] = d[i].root;
   }
   return 0;
 }

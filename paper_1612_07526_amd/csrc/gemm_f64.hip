@@ -21,6 +21,7 @@
 namespace phdc {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) double gdouble_t;  // a double in global memory
 
 constexpr int GK = 16;        // k per LDS stage
 constexpr int GPAD = 4;       // LDS row padding (doubles)
@@ -72,6 +73,7 @@ __global__ void __launch_bounds__(256) k_merge_gemm(BlockMap bm, Scratch S) {
     const int kd = top ? k1 + k2 : k2 + k3;
     const int64_t so = M.s_off;
     const int32_t* colA = top ? S.coltop + so : S.colbot + so;
+    const RowRange* rgA = top ? S.rgtop + so : S.rgbot + so;  // rows of each column that can be nonzero
     const double* Bm = S.uhat + M.u_off + (int64_t)(top ? 0 : k1) * K;  // row-major, ld = K
     const double* A = M.qin + rowoff;
     const int64_t lda = M.ldin;
@@ -82,10 +84,17 @@ __global__ void __launch_bounds__(256) k_merge_gemm(BlockMap bm, Scratch S) {
     const int l8 = (t & 15) * E;     // first of E consecutive rows (A) / columns (B)
     double ra[E], rb[E];
 
+    // The range of the staged A column is applied when the values go to LDS
+    // (after the MFMAs of the current stage), so the loads need not wait for it.
+    RowRange ag{0, 0};  // merge rows of the staged A column that can be nonzero
+    const int arow = rowoff + mrow0 + l8;  // merge row of this thread's first staged element
     auto gload = [&](int kt) {
       const int kk = kt * GK + lkc;
       if (kk < kd) {
-        const double* src = A + (int64_t)colA[kk] * lda + mrow0 + l8;
+        // The input block is global memory: say so, so that the loads are
+        // global (not flat) ones and the waits can count them separately.
+        const gdouble_t* src = (const gdouble_t*)(A + (int64_t)colA[kk] * lda + mrow0 + l8);
+        ag = rgA[kk];
   #pragma unroll
         for (int e = 0; e < E; ++e) ra[e] = (mrow0 + l8 + e < Mrows) ? src[e] : 0.0;
         const double* bs = Bm + (int64_t)kk * K + ncol0 + l8;
@@ -94,12 +103,13 @@ __global__ void __launch_bounds__(256) k_merge_gemm(BlockMap bm, Scratch S) {
       } else {
   #pragma unroll
         for (int e = 0; e < E; ++e) { ra[e] = 0.0; rb[e] = 0.0; }
+        ag = RowRange{0, 0};
       }
     };
     auto lstore = [&](int buf) {
   #pragma unroll
       for (int e = 0; e < E; ++e) {
-        As[buf][lkc][l8 + e] = ra[e];
+        As[buf][lkc][l8 + e] = (arow + e >= ag.lo && arow + e < ag.hi) ? ra[e] : 0.0;
         Bs[buf][lkc][l8 + e] = rb[e];
       }
     };
@@ -181,7 +191,7 @@ int bucket_of(int64_t m) {
 }
 
 __global__ void k_autotune_fill(double* q, double* u, int64_t count, int32_t* cnt, int32_t* coltop, int32_t* colbot,
-                                int32_t* dest, int m, int n1) {
+                                int32_t* dest, RowRange* rgtop, RowRange* rgbot, int m, int n1) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t e = i; e < count; e += stride) {  // bounded values, no structure the GEMM could exploit
@@ -190,8 +200,14 @@ __global__ void k_autotune_fill(double* q, double* u, int64_t count, int32_t* cn
   }
   for (int64_t c = i; c < m; c += stride) {
     dest[c] = (int32_t)c;
-    if (c < n1) coltop[c] = (int32_t)c;
-    if (c < m - n1) colbot[c] = (int32_t)(n1 + c);
+    if (c < n1) {
+      coltop[c] = (int32_t)c;
+      rgtop[c] = RowRange{0, n1};
+    }
+    if (c < m - n1) {
+      colbot[c] = (int32_t)(n1 + c);
+      rgbot[c] = RowRange{n1, m};
+    }
   }
   if (i == 0) {
     for (int k = 0; k < kCounters; ++k) cnt[k] = 0;
@@ -205,7 +221,8 @@ __global__ void k_autotune_fill(double* q, double* u, int64_t count, int32_t* cn
 
 size_t autotune_bytes(int64_t max_m) {
   const size_t mm = (size_t)max_m * max_m;
-  return 3 * mm * 8 + (size_t)(3 * max_m + kCounters + 64) * 4 + 2 * 256 + sizeof(MergeDesc);
+  return 3 * mm * 8 + (size_t)(3 * max_m + kCounters + 64) * 4 + (size_t)2 * max_m * sizeof(RowRange) + 3 * 256 +
+         sizeof(MergeDesc);
 }
 }  // namespace
 
@@ -242,7 +259,9 @@ int phdc_autotune_gemm(int64_t max_m, void* work, size_t lwork, void* stream) {
   int32_t* coltop = cnt + kCounters;
   int32_t* colbot = coltop + max_m;
   int32_t* dest = colbot + max_m;
-  char* tail = (char*)(dest + max_m);
+  RowRange* rgtop = (RowRange*)(((uintptr_t)(dest + max_m) + 255) / 256 * 256);
+  RowRange* rgbot = rgtop + max_m;
+  char* tail = (char*)(rgbot + max_m);
   tail = (char*)(((uintptr_t)tail + 255) / 256 * 256);
   MergeDesc* desc = (MergeDesc*)tail;
   int32_t* pfx = (int32_t*)(tail + 256);
@@ -252,7 +271,7 @@ int phdc_autotune_gemm(int64_t max_m, void* work, size_t lwork, void* stream) {
   for (int64_t m = 64; m <= max_m && rc == 0; m *= 2) {
     const int n1 = (int)(m / 2);
     hipLaunchKernelGGL(k_autotune_fill, dim3(1024), dim3(256), 0, s, q, u, (int64_t)(m * m), cnt, coltop, colbot, dest,
-                       (int)m, n1);
+                       rgtop, rgbot, (int)m, n1);
     MergeDesc D{};
     D.qin = q;
     D.qout = qo;
@@ -265,6 +284,8 @@ int phdc_autotune_gemm(int64_t max_m, void* work, size_t lwork, void* stream) {
     S.counters = cnt;
     S.coltop = coltop;
     S.colbot = colbot;
+    S.rgtop = rgtop;
+    S.rgbot = rgbot;
     S.dest = dest;
     S.uhat = u;
     float best[2] = {1e30f, 1e30f};

@@ -62,17 +62,16 @@ __global__ void __launch_bounds__(256) k_gauss(int64_t count, uint64_t seed, dou
 }
 
 // ------------------------------------------------------------ gathers
-// X(:, k) = input column of survivor k (pole order), structurally zero half as 0.
-__global__ void __launch_bounds__(256) k_gather_x(const double* __restrict__ qin, int64_t ldin, int m, int n1, int K,
+// X(:, k) = input column of survivor k (pole order), rows outside its range as 0.
+__global__ void __launch_bounds__(256) k_gather_x(const double* __restrict__ qin, int64_t ldin, int m, int K,
                                                   const int32_t* __restrict__ csort,
-                                                  const int32_t* __restrict__ psort, double* X) {
+                                                  const RowRange* __restrict__ crng, double* X) {
   const int k = blockIdx.y;
   const int r = blockIdx.x * 256 + threadIdx.x;
   if (k >= K || r >= m) return;
-  const int p = psort[k];
-  const bool top = r < n1;
-  const bool valid = p == 2 || (top ? p == 1 : p == 3);
-  X[r + (int64_t)k * m] = valid ? qin[r + (int64_t)csort[k] * ldin] : 0.0;
+  const int c = csort[k];
+  const RowRange g = crng[c];
+  X[r + (int64_t)k * m] = (r >= g.lo && r < g.hi) ? qin[r + (int64_t)c * ldin] : 0.0;
 }
 
 // Entries of Uhat evaluated from the secular solution with the same arithmetic
@@ -482,8 +481,8 @@ int run_hss_merge(const MergeDesc& M, int K, const Scratch& S, char* arena, size
 
     {
       ProfScope ps(PH_HSS_SAMPLE, s);
-      hipLaunchKernelGGL(k_gather_x, dim3((m + 255) / 256, K), dim3(256), 0, s, M.qin, M.ldin, m, M.n1, K,
-                         S.csort + so, S.psort + so, X);
+      hipLaunchKernelGGL(k_gather_x, dim3((m + 255) / 256, K), dim3(256), 0, s, M.qin, M.ldin, m, K,
+                         S.csort + so, S.crng + so, X);
       const int64_t cnt = (int64_t)K * d;
       const uint64_t sd = o->seed + 0x9e3779b97f4a7c15ULL * (uint64_t)(attempt + 1);
       hipLaunchKernelGGL(k_gauss, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, cnt, sd, Om1);

@@ -162,6 +162,7 @@ __global__ void __launch_bounds__(64) k_leaf_ql(const LeafArgs* __restrict__ lea
     const int rc = __builtin_amdgcn_readlane(rank, c);
     if (row) L.q[t + (int64_t)rc * L.ldq] = Z[c * ls + t];
   }
+  if (row && L.rng) L.rng[t] = RowRange{L.r0, L.r0 + s};  // every column spans the leaf's rows
 }
 
 void launch_leaf_ql(const LeafArgs* leaves, int nleaves, int32_t* status, int max_leaf, hipStream_t s) {

@@ -76,11 +76,6 @@ __device__ inline int count_le(const double* a, int n, double x) {
   return lo;
 }
 
-// Part codes: which halves of a merge column can be nonzero.
-__device__ inline bool part_valid(int part, bool top) {
-  return part == 2 || (top ? part == 1 : part == 3);
-}
-
 // Type-2 deflation test for consecutive survivors p < j (Sec. 1, after Remark 1):
 // the rotation that zeroes z_p leaves the off-diagonal residue (d_j - d_p) c s.
 __device__ inline bool pair_deflates(double dp, double zp, double dj, double zj, double tol, double* c,
@@ -159,7 +154,8 @@ __global__ void __launch_bounds__(kDefThreads) k_deflate(const MergeDesc* __rest
     zsign = (bk < 0.0) ? -1.0 : 1.0;
   }
 
-  // 1. z (Eq. (3): last row of Q1, first row of Q2), |z|^2, max |D|, sortedness.
+  // 1. z (Eq. (3): last row of Q1, first row of Q2), |z|^2, max |D|, sortedness;
+  // the row range of every input column, in rows of the merge block.
   double zz = 0.0, dmx = 0.0;
   int uns = 0;
   constexpr int U1 = 4;  // loads of four indices issued before their uses
@@ -170,8 +166,12 @@ __global__ void __launch_bounds__(kDefThreads) k_deflate(const MergeDesc* __rest
       const int i = i0 + u * kDefThreads;
       zi[u] = di[u] = dprev[u] = 0.0;
       if (i < m) {
+        RowRange g = (i < n1) ? RowRange{0, n1} : RowRange{n1, m};
+        if (M.rin) g = RowRange{M.rin[i].lo - M.r0, M.rin[i].hi - M.r0};
+        S.crng[so + i] = g;
+        const int zr = (i < n1) ? n1 - 1 : n1;  // the row of the column that enters z
         if (M.zgiven) zi[u] = M.zgiven[i];
-        else zi[u] = (i < n1) ? M.qin[(n1 - 1) + (int64_t)i * M.ldin] : zsign * M.qin[n1 + (int64_t)i * M.ldin];
+        else if (zr >= g.lo && zr < g.hi) zi[u] = ((i < n1) ? 1.0 : zsign) * M.qin[zr + (int64_t)i * M.ldin];
         di[u] = M.lin[i];
         if (i > 0) dprev[u] = M.lin[i - 1];
       }
@@ -256,7 +256,6 @@ __global__ void __launch_bounds__(kDefThreads) k_deflate(const MergeDesc* __rest
         const int q = pd + lanes_below(md);
         S.dfv1[so + q] = dv[k];
         S.dfc1[so + q] = col[k];
-        S.dfp1[so + q] = part[k];
       }
       ps += __popcll(ms);
       pd += __popcll(md);
@@ -306,11 +305,17 @@ __global__ void __launch_bounds__(kDefThreads) k_deflate(const MergeDesc* __rest
             const int np = (pp == partL) ? pp : 2;
             if (lane == 0) {
               if (!pmod) S.chain[so + nchain] = nrot;
-              S.rcolp[so + nrot] = col[pk];
-              S.rcolj[so + nrot] = col[kL];
+              const int cp = col[pk], cj = col[kL];
+              const RowRange gp = S.crng[so + cp], gj = S.crng[so + cj];
+              const RowRange gh{min(gp.lo, gj.lo), max(gp.hi, gj.hi)};  // both results span the hull
+              S.rcolp[so + nrot] = cp;
+              S.rcolj[so + nrot] = cj;
               S.rc[so + nrot] = c;
               S.rs[so + nrot] = s;
-              S.rpart[so + nrot] = pp | (partL << 8);
+              S.rrp[so + nrot] = gp;
+              S.rrj[so + nrot] = gj;
+              S.crng[so + cp] = gh;
+              S.crng[so + cj] = gh;
               dv[pk] = dpn;
               zv[pk] = 0.0;
               flag[pk] = 2;
@@ -377,6 +382,7 @@ __global__ void __launch_bounds__(kDefThreads) k_deflate(const MergeDesc* __rest
   const int k1 = tot[0], k2 = tot[1], k3 = tot[2], nd2 = tot[3];
   const int dp1 = tot[4], dp2 = tot[5], dp3 = tot[6];
   const int K = k1 + k2 + k3;
+  double drows = 0.0;  // rows in range over the deflated columns (exact: integers below 2^53)
   {
     int b1 = pre[0], b2 = pre[1], b3 = pre[2], b4 = pre[3];
     for (int b0 = seg0; b0 < seg1; b0 += 64) {
@@ -391,19 +397,24 @@ __global__ void __launch_bounds__(kDefThreads) k_deflate(const MergeDesc* __rest
         const int ks = e1 + e2 + e3;
         S.ds[so + ks] = dv[k];
         S.zs[so + ks] = zv[k];
-        S.csort[so + ks] = col[k];
-        S.psort[so + ks] = p;
+        const int ck = col[k];
+        const RowRange gk = S.crng[so + ck];
+        S.csort[so + ks] = ck;
         int g;
         if (p == 1) {
           g = e1;
-          S.coltop[so + e1] = col[k];
+          S.coltop[so + e1] = ck;
+          S.rgtop[so + e1] = gk;
         } else if (p == 2) {
           g = k1 + e2;
-          S.coltop[so + k1 + e2] = col[k];
-          S.colbot[so + e2] = col[k];
+          S.coltop[so + k1 + e2] = ck;
+          S.rgtop[so + k1 + e2] = gk;
+          S.colbot[so + e2] = ck;
+          S.rgbot[so + e2] = gk;
         } else {
           g = k1 + k2 + e3;
-          S.colbot[so + k2 + e3] = col[k];
+          S.colbot[so + k2 + e3] = ck;
+          S.rgbot[so + k2 + e3] = gk;
         }
         S.grp[so + ks] = g;
         S.grpsrc[so + g] = ks;
@@ -411,7 +422,10 @@ __global__ void __launch_bounds__(kDefThreads) k_deflate(const MergeDesc* __rest
         const int q = b4 + lanes_below(m4);
         S.dfv2[so + q] = dv[k];
         S.dfc2[so + q] = col[k];
-        S.dfp2[so + q] = p;
+      }
+      if (f > 0) {
+        const RowRange gk = S.crng[so + col[k]];
+        drows += (double)(gk.hi - gk.lo);
       }
       b1 += __popcll(m1);
       b2 += __popcll(m2);
@@ -419,7 +433,11 @@ __global__ void __launch_bounds__(kDefThreads) k_deflate(const MergeDesc* __rest
       b4 += __popcll(m4);
     }
   }
+  drows = block_sum<kDefThreads>(drows, shd);
   if (t == 0) {
+    const int64_t dr = (int64_t)drows;
+    cnt[C_DROWS_LO] = (int32_t)(uint32_t)(dr & 0xffffffffLL);
+    cnt[C_DROWS_HI] = (int32_t)(dr >> 32);
     cnt[C_K] = K;
     cnt[C_K1] = k1;
     cnt[C_K2] = k2;
@@ -439,7 +457,10 @@ __global__ void __launch_bounds__(kDefThreads) k_deflate(const MergeDesc* __rest
 // ------------------------------------------------------------ rotations
 // Applies the recorded rotation chains to the columns of the merge's input
 // block, in place.  A chain's records share a column and run in order per row;
-// distinct chains touch disjoint columns and run in parallel.
+// distinct chains touch disjoint columns and run in parallel.  A rotation reads
+// each column inside its recorded range only and writes both over the hull of
+// the two ranges (zeros where neither column has rows), which is the range the
+// rotated columns carry on.
 constexpr int kRotGroups = 16;
 
 __global__ void __launch_bounds__(256) k_rotate(BlockMap bm, Scratch S) {
@@ -447,7 +468,7 @@ __global__ void __launch_bounds__(256) k_rotate(BlockMap bm, Scratch S) {
   const int mi = find_merge(bm, b);
   const int lb = b - bm.pfx[mi];
   const MergeDesc M = bm.descs[mi];
-  const int m = M.m, n1 = M.n1;
+  const int m = M.m;
   const int RB = cdiv_d(m, 256);
   const int G = (bm.pfx[mi + 1] - bm.pfx[mi]) / RB;
   const int rb = lb % RB, g = lb / RB;
@@ -456,7 +477,6 @@ __global__ void __launch_bounds__(256) k_rotate(BlockMap bm, Scratch S) {
   const int r = rb * 256 + threadIdx.x;
   if (r >= m) return;
   const int64_t so = M.s_off;
-  const bool top = r < n1;
   double* q = M.qin;
   const int64_t ld = M.ldin;
   for (int ci = g; ci < nchain; ci += G) {
@@ -464,9 +484,9 @@ __global__ void __launch_bounds__(256) k_rotate(BlockMap bm, Scratch S) {
     const int e = (ci + 1 < nchain) ? S.chain[so + ci + 1] : nrot;
     for (int x = a; x < e; ++x) {
       const int cp = S.rcolp[so + x], cj = S.rcolj[so + x];
-      const int pr = S.rpart[so + x];
-      const bool vp = part_valid(pr & 255, top), vj = part_valid(pr >> 8, top);
-      if (!vp && !vj) continue;
+      const RowRange gp = S.rrp[so + x], gj = S.rrj[so + x];
+      if (r < min(gp.lo, gj.lo) || r >= max(gp.hi, gj.hi)) continue;
+      const bool vp = r >= gp.lo && r < gp.hi, vj = r >= gj.lo && r < gj.hi;
       const double c = S.rc[so + x], s = S.rs[so + x];
       const double xp = vp ? q[r + (int64_t)cp * ld] : 0.0;
       const double xj = vj ? q[r + (int64_t)cj * ld] : 0.0;
@@ -838,50 +858,63 @@ __global__ void __launch_bounds__(256) k_rank(BlockMap bm, Scratch S) {
   if (cls == 0) S.dest[so + idx] = r;
   else if (cls == 1) S.destd1[so + idx] = r;
   else S.destd2[so + idx] = r;
+  if (M.rout) {  // roots fill every row of the block; deflated columns keep their range
+    RowRange g{0, M.m};
+    if (cls > 0) g = S.crng[so + (cls == 1 ? S.dfc1[so + idx] : S.dfc2[so + idx])];
+    M.rout[r] = RowRange{g.lo + M.r0, g.hi + M.r0};
+  }
 }
 
 // ------------------------------------------------------------ deflated columns
 // Deflated columns of Q G P (Eq. (6), the identity block) go unchanged to
-// their output position; halves that are structurally zero are written as 0.
+// their output position.  Only the rows of a column's range are read and, below
+// the root of the tree, written: the next merge reads no other row.  The root
+// merge writes every row (zeros outside the range), since its output is the
+// caller's eigenvector matrix.
 constexpr int kCopyBlocks = 16384;  // cap on column blocks per merge
 
 // Each block streams whole columns: a column group of RPT lanes (RPT = m
-// rounded up to a power of two, at most 256) walks the rows, 256 / RPT columns
-// per block at a time, four rows in flight per lane.  Only the half a column
-// can be nonzero in is read; the other half is written as zeros.
+// rounded up to a power of two, at most 64) walks the rows, 256 / RPT columns
+// per block at a time, four rows in flight per lane.
+__device__ inline int copy_rpt(int m) {
+  int rpt = 1;
+  while (rpt < m && rpt < 64) rpt <<= 1;
+  return rpt;
+}
+
 __global__ void __launch_bounds__(256) k_copy_deflated(BlockMap bm, Scratch S) {
   const int b = blockIdx.x;
   const int mi = find_merge(bm, b);
   const int lb = b - bm.pfx[mi];
   const int G = bm.pfx[mi + 1] - bm.pfx[mi];
   const MergeDesc M = bm.descs[mi];
-  const int m = M.m, n1 = M.n1;
+  const int m = M.m;
   const int32_t* cnt = S.counters + (int64_t)M.id * kCounters;
   const int nd1 = cnt[C_ND1], nd = nd1 + cnt[C_ND2];
   const int64_t so = M.s_off;
-  int rpt = 1;
-  while (rpt < m && rpt < 256) rpt <<= 1;
+  const int rpt = copy_rpt(m);
   const int cpb = 256 / rpt;
   const int lane = threadIdx.x % rpt, sub = threadIdx.x / rpt;
   for (int q = lb * cpb + sub; q < nd; q += G * cpb) {
-    int c, p, dst;
-    if (q < nd1) { c = S.dfc1[so + q]; p = S.dfp1[so + q]; dst = S.destd1[so + q]; }
-    else { const int q2 = q - nd1; c = S.dfc2[so + q2]; p = S.dfp2[so + q2]; dst = S.destd2[so + q2]; }
-    const int lo = (p == 3) ? n1 : 0, hi = (p == 1) ? n1 : m;  // rows that can be nonzero
+    int c, dst;
+    if (q < nd1) { c = S.dfc1[so + q]; dst = S.destd1[so + q]; }
+    else { const int q2 = q - nd1; c = S.dfc2[so + q2]; dst = S.destd2[so + q2]; }
+    const RowRange g = S.crng[so + c];
     const double* src = M.qin + (int64_t)c * M.ldin;
     double* out = M.qout + (int64_t)dst * M.ldout;
+    const int w0 = M.root ? 0 : g.lo, w1 = M.root ? m : g.hi;  // rows written
     constexpr int U = 4;
-    for (int r0 = lane; r0 < m; r0 += U * rpt) {
+    for (int r0 = w0 + lane; r0 < w1; r0 += U * rpt) {
       double v[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int r = r0 + u * rpt;
-        v[u] = (r >= lo && r < hi) ? src[r] : 0.0;
+        v[u] = (r >= g.lo && r < g.hi) ? src[r] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int r = r0 + u * rpt;
-        if (r < m) out[r] = v[u];
+        if (r < w1) out[r] = v[u];
       }
     }
   }
@@ -898,9 +931,9 @@ int map_blocks(int kind, int m, int n1, int gt) {
     case MAP_ROT: return cdiv(m, 256) * std::max(1, std::min(m / 2, kRotGroups));
     case MAP_UWRITE: return cdiv(m, 256) * std::max(1, std::min(m, kUwRowGroups));
     case MAP_GEMM: return std::min((cdiv(n1, gt) + cdiv(m - n1, gt)) * cdiv(m, gt), kGemmBlockCap);
-    case MAP_COPY: {  // columns per block = 256 / (m rounded up to a power of two, at most 256)
+    case MAP_COPY: {  // columns per block = 256 / (m rounded up to a power of two, at most 64)
       int rpt = 1;
-      while (rpt < m && rpt < 256) rpt <<= 1;
+      while (rpt < m && rpt < 64) rpt <<= 1;
       return std::max(1, std::min(cdiv(m, 256 / rpt), kCopyBlocks));
     }
     case MAP_SPLITA: return cdiv(m, 256) * kSplitKGroups;

@@ -12,13 +12,23 @@ constexpr double kUnitRoundoff = 1.1102230246251565e-16;  // 2^-53
 constexpr int kMaxLeaf = 64;
 constexpr int kHssLeafMax = 1024;    // largest HSS leaf (rows of one interpolative decomposition)
 constexpr int kSplitMaxSlices = 7;   // BF16 slices per operand on the split-precision path
-constexpr int kCounters = 16;  // per-merge int32 counters
+constexpr int kCounters = 18;  // per-merge int32 counters
 
 // Counter slots (per merge).
 enum : int {
   C_K = 0, C_K1 = 1, C_K2 = 2, C_K3 = 3, C_NT1 = 4, C_NT2 = 5, C_PATH = 6, C_HSSRANK = 7,
   C_NROT = 8, C_NCHAIN = 9, C_ND1 = 10, C_ND2 = 11,
-  C_DP1 = 12, C_DP2 = 13, C_DP3 = 14  // deflated columns nonzero in the Q1 half only / both / the Q2 half only
+  C_DP1 = 12, C_DP2 = 13, C_DP3 = 14,  // deflated columns nonzero in the Q1 half only / both / the Q2 half only
+  C_DROWS_LO = 15, C_DROWS_HI = 16     // sum over deflated columns of the rows in their range (64 bits)
+};
+
+// Rows [lo, hi) of an eigenvector column that can be nonzero; rows outside
+// are structurally zero and their storage is not read.  Columns leave a leaf
+// with the leaf's rows, a root of a merge with all its rows, and a deflated
+// column with the range it entered the merge with (after the type-2 rotations,
+// which join the hulls of the two columns they combine).
+struct alignas(8) RowRange {
+  int32_t lo, hi;
 };
 
 // One rank-one merge of the divide-and-conquer tree.  All pointers are device pointers.
@@ -40,6 +50,10 @@ struct MergeDesc {
   int64_t x_off;        // offset of this merge's m*(m+8) slot (per slice) in the split-precision arenas
   int32_t split_on;     // split-precision update for this merge
   int32_t pad;
+  const RowRange* rin;  // input column ranges in rows of the whole matrix (nullptr: [0, n1) / [n1, m) by half)
+  RowRange* rout;       // output column ranges (nullptr: not recorded)
+  int32_t r0;           // first row (= first column) of the merge block within the matrix
+  int32_t root;         // 1: last merge of its matrix (every output entry is written, zeros included)
 };
 
 // One leaf solve (one wavefront).
@@ -51,6 +65,9 @@ struct LeafArgs {
   double* lam;         // eigenvalue output
   int32_t s;           // rows
   int32_t couple;      // bit 0: coupled to the left, bit 1: coupled to the right
+  RowRange* rng;       // column ranges of the leaf's eigenvectors (nullptr: not recorded)
+  int32_t r0;          // first row of the leaf within the matrix
+  int32_t pad;
 };
 
 // One matrix for the eigenvector sign pass.
@@ -75,18 +92,20 @@ struct Scratch {
   int32_t* grp;    //                  row of Uhat in Gu's grouped order
   int32_t* coltop; // GEMM column list for the Q1 rows (types 1, 2)
   int32_t* colbot; // GEMM column list for the Q2 rows (types 2, 3)
+  RowRange* rgtop; // row range (merge rows) of each column of coltop
+  RowRange* rgbot; //                                     of colbot
+  RowRange* crng;  // row range (merge rows) of every merge column, after the rotations
   int32_t* rcolp;  // rotation records: column p
   int32_t* rcolj;  //                   column j
   double* rc;      //                   cosine
   double* rs;      //                   sine
-  int32_t* rpart;  //                   part of p (low byte) and j (next byte) before the rotation
+  RowRange* rrp;   //                   row range of column p before the rotation (merge rows)
+  RowRange* rrj;   //                   row range of column j before the rotation
   int32_t* chain;  // first record of each rotation chain
   double* dfv1;    // type-1 deflated: value (ascending)
   int32_t* dfc1;   //                  column
-  int32_t* dfp1;   //                  part
   double* dfv2;    // type-2 deflated: value
   int32_t* dfc2;   //                  column
-  int32_t* dfp2;   //                  part
   int32_t* org;    // secular root: origin pole
   double* tau;     //                offset
   double* dorg;    //                origin pole value d[org]
@@ -97,7 +116,6 @@ struct Scratch {
   int32_t* destd2; // output column of type-2 deflated item
   int32_t* grpsrc; // survivor that fills grouped row g of Uhat
   int32_t* csort;  // input column of survivor k (pole order)
-  int32_t* psort;  // part of survivor k
   double* mparam;  // per merge (4 doubles): normalised rho, deflation tolerance
   double* uhat;    // Uhat arena
   int32_t* counters;

@@ -43,8 +43,10 @@ __global__ void __launch_bounds__(256) k_split_scales(BlockMap bm, Scratch S, Sp
     const bool top = x < M.n1;
     const int kd = top ? k1 + k2 : k2 + k3;
     const int32_t* cols = top ? S.coltop + so : S.colbot + so;
+    const RowRange* rg = top ? S.rgtop + so : S.rgbot + so;
     double mx = 0.0;
-    for (int k = 0; k < kd; ++k) mx = fmax(mx, fabs(M.qin[x + (int64_t)cols[k] * M.ldin]));
+    for (int k = 0; k < kd; ++k)
+      if (x >= rg[k].lo && x < rg[k].hi) mx = fmax(mx, fabs(M.qin[x + (int64_t)cols[k] * M.ldin]));
     B.erow[so + x] = exp_above(mx);
   }
   if (x < K) {  // column x of Uhat
@@ -86,13 +88,14 @@ __global__ void __launch_bounds__(256) k_split_slice_a(BlockMap bm, Scratch S, S
   const int rows = top ? M.n1 : M.m - M.n1;
   const int row = top ? x : x - M.n1;
   const int32_t* cols = top ? S.coltop + so : S.colbot + so;
+  const RowRange* rg = top ? S.rgtop + so : S.rgbot + so;
   __bf16* base = B.aslice + (int64_t)nsl * M.x_off + (top ? 0 : (int64_t)nsl * M.n1 * (((k1 + k2) + 7) & ~7));
   const int64_t stride = (int64_t)rows * kdp;
   const double sc = ldexp(1.0, -B.erow[so + x]);
   for (int k0 = kg * 8; k0 < kdp; k0 += 8 * B.kgroups) {
     for (int e = 0; e < 8; ++e) {
       const int k = k0 + e;
-      const double v = (k < kd) ? M.qin[x + (int64_t)cols[k] * M.ldin] * sc : 0.0;
+      const double v = (k < kd && x >= rg[k].lo && x < rg[k].hi) ? M.qin[x + (int64_t)cols[k] * M.ldin] * sc : 0.0;
       cut(v, nsl, base + (int64_t)row * kdp + k, stride);
     }
   }

@@ -34,7 +34,7 @@ def _np(t):
     return t.detach().cpu().numpy()
 
 
-def _check_eig(d, e, lam, Q, lref=None, Qref=None, vec_tol=1e-9):
+def _check_eig(d, e, lam, Q, lref=None, Qref=None, vec_tol=1e-9, orth_tol=ORTH_TOL, res_tol=RES_TOL):
     d = np.asarray(d, dtype=np.float64)
     e = np.asarray(e, dtype=np.float64)
     nrm = max(np.abs(lam).max(), 1e-300) if lam.size else 1.0
@@ -42,8 +42,8 @@ def _check_eig(d, e, lam, Q, lref=None, Qref=None, vec_tol=1e-9):
     if lref is not None:
         err = np.abs(lam - lref).max() if lam.size else 0.0
         assert err <= LAM_TOL * nrm, f"eigenvalue error {err:.3e} > {LAM_TOL * nrm:.3e}"
-    assert orth(Q) <= ORTH_TOL
-    assert residual(d, e, lam, Q) <= RES_TOL
+    assert orth(Q) <= orth_tol
+    assert residual(d, e, lam, Q) <= res_tol
     if Qref is not None and lam.size:
         iso = isolated_columns(lref, 1e-3 * nrm)
         if iso.any():
@@ -134,6 +134,16 @@ def test_merge_all_deflated(P):
     assert P.merge_stats(work)[0] == 0
     assert np.array_equal(_np(lam), np.sort(D))
     assert orth(_np(Q)) <= 1e-15
+    # every column is copied over the rows of its own half; the merge is a root
+    tab = P.merge_table(work)
+    assert tab.shape == (1, P.MERGE_TABLE_COLS)
+    assert int(P.deflated_rows(tab)[0]) == 40 * 40 + 30 * 30
+    assert tab[0, 15] == 1
+    # the copy wrote the structural zeros of the other half
+    Qh = _np(Q)
+    for j in range(70):
+        top = np.abs(Qh[:40, j]).max() > 0
+        assert np.all(Qh[40:, j] == 0.0) if top else np.all(Qh[:40, j] == 0.0)
 
 
 def test_merge_unsorted_reports_status(P):
@@ -175,6 +185,21 @@ def test_stedc_vs_oracle(P, orc, gen, n, seed):
     lref, Qref, _ = orc.stedc(d, e)
     lam, Q = P.stedc(d, e)
     _check_eig(d, e, _np(lam), _np(Q), lref, Qref)
+
+
+@pytest.mark.parametrize("mode", ["fp64", "hss", "split"])
+@pytest.mark.parametrize("gen,n,leaf", [("weak_coupling", 3000, 16), ("glued", 2401, 16), ("glued", 1000, 8)])
+def test_stedc_deflation_stress(P, orc, gen, n, leaf, mode):
+    # heavy type-1 deflation at every level, or type-2 rotations joining columns of
+    # Q1 and Q2: deflated columns are nonzero on part of the rows only
+    d, e = W.tridiag(gen, n, 7)
+    o = {"fp64": P.opts(leaf_size=leaf), "hss": P.opts(leaf_size=leaf, gemm_mode=P.GEMM_HSS, hss_min_K=64),
+         "split": P.opts(leaf_size=leaf, gemm_mode=P.GEMM_SPLIT)}[mode]
+    lref, Qref, _ = orc.stedc(d, e, leaf=leaf)
+    lam, Q = P.stedc(d, e, o=o)
+    loose = mode == "split"  # the split-precision update is held to 10x the FP64 bounds
+    _check_eig(d, e, _np(lam), _np(Q), lref, Qref, vec_tol=1e-8 if loose else 1e-9,
+               orth_tol=10 * ORTH_TOL if loose else ORTH_TOL, res_tol=10 * RES_TOL if loose else RES_TOL)
 
 
 @pytest.mark.parametrize("leaf", [2, 7, 16, 64])

@@ -182,6 +182,26 @@ CONFIGS = {
 }
 
 
+def weak_coupling(n: int, seed: int = 0, every: int = 5):
+    """d ~ N(0, 1); one off-diagonal entry in `every` ~ N(0, 1), the rest ~ 1e-18 N(0, 1):
+    most z entries fall below the deflation tolerance at every merge (type-1 deflation)."""
+    g = rng(seed)
+    d = g.standard_normal(n)
+    e = 1e-18 * g.standard_normal(max(n - 1, 0))
+    e[::every] = g.standard_normal(len(e[::every]))
+    return d, e
+
+
+def glued_blocks(n: int, block: int = 7, glue: float = 1e-9):
+    """Copies of the block tridiag(1, |c - i|, 1) (c = block // 2) joined by off-diagonal
+    entries `glue`: nearly equal eigenvalues in both halves of a merge, which deflate by
+    rotations between columns of Q1 and Q2 (type 2)."""
+    i = np.arange(n)
+    d = np.abs((block // 2) - (i % block)).astype(np.float64)
+    e = np.where((np.arange(1, n) % block) == 0, glue, 1.0).astype(np.float64)
+    return d, e
+
+
 def tridiag(kind: str, n: int, seed: int = 0, **kw):
     if kind == "toeplitz_121":
         return toeplitz_121(n, kw.get("off", 1.0))
@@ -199,4 +219,8 @@ def tridiag(kind: str, n: int, seed: int = 0, **kw):
         return normal(n, seed)
     if kind == "ramp":
         return ramp(n, seed)
+    if kind == "weak_coupling":
+        return weak_coupling(n, seed)
+    if kind == "glued":
+        return glued_blocks(n)
     raise ValueError(kind)
