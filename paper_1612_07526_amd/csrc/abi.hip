@@ -288,29 +288,70 @@ struct Buffers {
   std::vector<int64_t> ld[2];            // per matrix
 };
 
-// HSS update of the merges of one level that kept K >= hss_min_K poles.  The
-// path was chosen on the device; reading K back is the one host
-// synchronisation of this path (per level that has eligible merges).
-int run_hss_level(const MergeDesc* hdescs, int nm, const Scratch& S, char* arena, size_t arena_bytes, char* descarea,
-                  size_t desc_bytes, const phdc_opts* o, hipStream_t s) {
+// Pinned, device-mapped host memory per workspace for the counters the HSS
+// path reads back (LevelProbe), and the event that marks their arrival.
+struct Probe {
+  int32_t* host = nullptr;
+  int32_t* dev = nullptr;
+  size_t cap = 0;  // int32 values
+  hipEvent_t done = nullptr;
+};
+std::unordered_map<const void*, Probe> g_probe;
+
+// The level's merges that may take the HSS path (m >= hss_min_K), as the id
+// range [lo, hi] (ids of one level are consecutive).  False if there are none.
+bool hss_candidates(const MergeDesc* hdescs, int nm, const phdc_opts* o, int32_t* lo, int32_t* hi) {
   const int32_t thr = hss_threshold(o);
-  if (thr <= 0) return 0;
-  std::vector<int> cand;
-  for (int i = 0; i < nm; ++i)
-    if (hdescs[i].m >= thr) cand.push_back(i);
-  if (cand.empty()) return 0;
-  // one read of the counters of the level's merges (their ids are consecutive)
-  int32_t lo = hdescs[cand.front()].id, hi = lo;
-  for (int i : cand) {
-    lo = std::min(lo, hdescs[i].id);
-    hi = std::max(hi, hdescs[i].id);
+  if (thr <= 0) return false;
+  bool any = false;
+  for (int i = 0; i < nm; ++i) {
+    if (hdescs[i].m < thr) continue;
+    *lo = any ? std::min(*lo, hdescs[i].id) : hdescs[i].id;
+    *hi = any ? std::max(*hi, hdescs[i].id) : hdescs[i].id;
+    any = true;
   }
+  return any;
+}
+
+// A probe for the counters of merges lo..hi on the workspace's mapped buffer.
+int make_probe(const void* work, const Scratch& S, int32_t lo, int32_t hi, LevelProbe* lp) {
+  const size_t n = (size_t)(hi - lo + 1) * kCounters;
+  std::lock_guard<std::mutex> lk(g_mu);
+  Probe& p = g_probe[work];
+  if (p.cap < n) {
+    if (p.host) hipHostFree(p.host);
+    p.host = p.dev = nullptr;
+    p.cap = 0;
+    if (hipHostMalloc((void**)&p.host, n * 4, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) return -1;
+    if (hipHostGetDevicePointer((void**)&p.dev, p.host, 0) != hipSuccess) return -1;
+    p.cap = n;
+  }
+  if (!p.done && hipEventCreateWithFlags(&p.done, hipEventDisableTiming) != hipSuccess) return -1;
+  *lp = LevelProbe{S.counters + (int64_t)lo * kCounters, p.dev, (int32_t)n, p.done};
+  return 0;
+}
+
+// HSS update of the merges of one level that kept K >= hss_min_K poles.  The
+// path was chosen on the device.  The host needs K: with a probe it waits for
+// the counter copy made right after deflation (the rest of the level keeps the
+// GPU busy meanwhile); without one it copies the counters and synchronises.
+int run_hss_level(const MergeDesc* hdescs, int nm, const Scratch& S, char* arena, size_t arena_bytes, char* descarea,
+                  size_t desc_bytes, const phdc_opts* o, hipStream_t s, const void* work = nullptr,
+                  const LevelProbe* probe = nullptr) {
+  int32_t lo = 0, hi = 0;
+  if (!hss_candidates(hdescs, nm, o, &lo, &hi)) return 0;
   std::vector<int32_t> c((size_t)(hi - lo + 1) * kCounters);
-  if (hipMemcpyAsync(c.data(), S.counters + (int64_t)lo * kCounters, c.size() * 4, hipMemcpyDeviceToHost, s) !=
-          hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
+  if (probe) {
+    if (hipEventSynchronize(probe->done) != hipSuccess) return -111;
+    std::lock_guard<std::mutex> lk(g_mu);
+    std::memcpy(c.data(), g_probe[work].host, c.size() * 4);
+  } else if (hipMemcpyAsync(c.data(), S.counters + (int64_t)lo * kCounters, c.size() * 4, hipMemcpyDeviceToHost,
+                            s) != hipSuccess ||
+             hipStreamSynchronize(s) != hipSuccess) {
     return -111;
-  for (int i : cand) {
+  }
+  for (int i = 0; i < nm; ++i) {
+    if (hdescs[i].m < hss_threshold(o)) continue;
     const int32_t* ci = c.data() + (size_t)(hdescs[i].id - lo) * kCounters;
     if (ci[C_PATH] != 2) continue;
     int rc = run_hss_merge(hdescs[i], ci[C_K], S, arena, arena_bytes, descarea, desc_bytes, o,
@@ -496,9 +537,14 @@ int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n,
   const MergeDesc* dd = (const MergeDesc*)(base + L.descs);
   for (int h = 1; h <= z.H; ++h) {
     const int a = T.hstart[h - 1], e = T.hstart[h];
-    launch_merge_level(dd + a, e - a, lm[h], S, o->gemm_mode, &SB, z.nsl, s);
+    int32_t lo = 0, hi = 0;
+    LevelProbe lp{};
+    const bool cand = hss_candidates(descs.data() + a, e - a, o, &lo, &hi);
+    if (cand && make_probe(work, S, lo, hi, &lp) != 0) return -112;
+    launch_merge_level(dd + a, e - a, lm[h], S, o->gemm_mode, &SB, z.nsl, s, cand ? &lp : nullptr);
+    if (!cand) continue;
     int rc = run_hss_level(descs.data() + a, e - a, S, base + L.hss, L.hss_desc - L.hss, base + L.hss_desc,
-                           z.hss_desc, o, s);
+                           z.hss_desc, o, s, work, &lp);
     if (rc != 0) return rc;
   }
   if (o->canonical_sign && cpfx.back() > 0) {

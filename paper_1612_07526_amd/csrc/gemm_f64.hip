@@ -84,32 +84,29 @@ __global__ void __launch_bounds__(256) k_merge_gemm(BlockMap bm, Scratch S) {
     const int l8 = (t & 15) * E;     // first of E consecutive rows (A) / columns (B)
     double ra[E], rb[E];
 
-    // The range of the staged A column is applied when the values go to LDS
-    // (after the MFMAs of the current stage), so the loads need not wait for it.
-    RowRange ag{0, 0};  // merge rows of the staged A column that can be nonzero
-    const int arow = rowoff + mrow0 + l8;  // merge row of this thread's first staged element
+    // Rows outside the staged A column's range are not loaded (they read as 0).
     auto gload = [&](int kt) {
       const int kk = kt * GK + lkc;
       if (kk < kd) {
         // The input block is global memory: say so, so that the loads are
         // global (not flat) ones and the waits can count them separately.
         const gdouble_t* src = (const gdouble_t*)(A + (int64_t)colA[kk] * lda + mrow0 + l8);
-        ag = rgA[kk];
+        const RowRange g = rgA[kk];
+        const int lo = g.lo - (rowoff + mrow0 + l8), hi = min(g.hi - rowoff, Mrows) - (mrow0 + l8);
   #pragma unroll
-        for (int e = 0; e < E; ++e) ra[e] = (mrow0 + l8 + e < Mrows) ? src[e] : 0.0;
+        for (int e = 0; e < E; ++e) ra[e] = (e >= lo && e < hi) ? src[e] : 0.0;
         const double* bs = Bm + (int64_t)kk * K + ncol0 + l8;
   #pragma unroll
         for (int e = 0; e < E; ++e) rb[e] = (ncol0 + l8 + e < K) ? bs[e] : 0.0;
       } else {
   #pragma unroll
         for (int e = 0; e < E; ++e) { ra[e] = 0.0; rb[e] = 0.0; }
-        ag = RowRange{0, 0};
       }
     };
     auto lstore = [&](int buf) {
   #pragma unroll
       for (int e = 0; e < E; ++e) {
-        As[buf][lkc][l8 + e] = (arow + e >= ag.lo && arow + e < ag.hi) ? ra[e] : 0.0;
+        As[buf][lkc][l8 + e] = ra[e];
         Bs[buf][lkc][l8 + e] = rb[e];
       }
     };

@@ -518,10 +518,37 @@ __device__ inline double rcp_nr(double x) {
   return y;
 }
 
+// A double moved between lanes of a 16-lane row by a DPP lane pattern (a VALU
+// operand modifier: no LDS round trip, unlike a general shuffle).
+template <int CTRL>
+__device__ inline double dpp_row(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+constexpr int kDppQuadXor1 = 0xB1;       // quad_perm [1, 0, 3, 2]
+constexpr int kDppQuadXor2 = 0x4E;       // quad_perm [2, 3, 0, 1]
+constexpr int kDppRowHalfMirror = 0x141; // lane i <-> 7 - i within each 8 lanes
+constexpr int kDppRowMirror = 0x140;     // lane i <-> 15 - i within each 16 lanes
+
+// Sum (product) over the G consecutive lanes of a group, every lane receiving
+// the same value.  For G = 16 the partners are the lane's quad neighbours, then
+// the mirrored quad and the mirrored half-row: the same pairing tree as xor 1,
+// 2, 4, 8 (quads hold equal values by then), so the result does not depend on
+// which form runs, and IEEE addition being commutative every lane holds the
+// identical total.
 template <int G>
 __device__ inline double group_sum(double v) {
+  if constexpr (G == 16) {
+    v += dpp_row<kDppQuadXor1>(v);
+    v += dpp_row<kDppQuadXor2>(v);
+    v += dpp_row<kDppRowHalfMirror>(v);
+    v += dpp_row<kDppRowMirror>(v);
+  } else {
 #pragma unroll
-  for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o, 64);
+    for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o, 64);
+  }
   return v;
 }
 
@@ -695,8 +722,15 @@ __global__ void __launch_bounds__(64) k_secular_raw(int K, const double* d, cons
 // for i <= j < K-1 (d_i - lambda_j)/(d_i - d_{j+1}), times lambda_{K-1} - d_i.
 template <int G>
 __device__ inline double group_prod(double v) {
+  if constexpr (G == 16) {
+    v *= dpp_row<kDppQuadXor1>(v);
+    v *= dpp_row<kDppQuadXor2>(v);
+    v *= dpp_row<kDppRowHalfMirror>(v);
+    v *= dpp_row<kDppRowMirror>(v);
+  } else {
 #pragma unroll
-  for (int o = 1; o < G; o <<= 1) v *= __shfl_xor(v, o, 64);
+    for (int o = 1; o < G; o <<= 1) v *= __shfl_xor(v, o, 64);
+  }
   return v;
 }
 
@@ -943,13 +977,23 @@ int map_blocks(int kind, int m, int n1, int gt) {
 }
 
 
+__global__ void __launch_bounds__(256) k_copy_ints(const int32_t* __restrict__ src, int32_t* dst, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
 void launch_merge_level(const MergeDesc* descs, int nm, const LevelMaps& maps, const Scratch& S, int gemm_mode,
-                        const SplitBufs* split, int nsl, hipStream_t s) {
+                        const SplitBufs* split, int nsl, hipStream_t s, const LevelProbe* probe) {
   if (nm <= 0) return;
   auto bmap = [&](int kind) { return BlockMap{descs, maps.pfx[kind], nm}; };
   { ProfScope p(PH_DEFLATE, s);
     const int cap = maps.maxm <= kDefLdsMax ? maps.maxm : 0;
     hipLaunchKernelGGL(k_deflate, dim3(nm), dim3(kDefThreads), (size_t)cap * sizeof(double), s, descs, S, cap); }
+  if (probe && probe->count > 0) {
+    hipLaunchKernelGGL(k_copy_ints, dim3((probe->count + 255) / 256), dim3(256), 0, s, probe->src, probe->dst,
+                       probe->count);
+    hipEventRecord(probe->done, s);
+  }
   { ProfScope p(PH_ROTATE, s);
     hipLaunchKernelGGL(k_rotate, dim3(maps.total[MAP_ROT]), dim3(256), 0, s, bmap(MAP_ROT), S); }
   { ProfScope p(PH_SECULAR, s);

@@ -161,9 +161,19 @@ constexpr int kTileBuckets = 21;        // merge-size buckets of the GEMM tile t
 int gemm_tile_for(int64_t maxm);        // tile edge for a level whose largest merge is maxm
 void launch_merge_gemm_f64(const BlockMap& bm, int total, const Scratch& S, int tile, hipStream_t s);
 
+// Copy of a level's counters to host-visible memory, made right after the
+// deflation kernel has fixed the sizes and the update path of every merge.
+struct LevelProbe {
+  const int32_t* src;  // device counters of the first merge of interest
+  int32_t* dst;        // device address of pinned, mapped host memory
+  int32_t count;       // int32 values to copy
+  hipEvent_t done;     // recorded after the copy
+};
+
 struct SplitBufs;
 void launch_merge_level(const MergeDesc* descs, int nm, const LevelMaps& maps, const Scratch& S,
-                        int gemm_mode, const SplitBufs* split, int nsl, hipStream_t s);
+                        int gemm_mode, const SplitBufs* split, int nsl, hipStream_t s,
+                        const LevelProbe* probe = nullptr);
 void launch_secular_standalone(int64_t K, const double* d, const double* z, double rho, int32_t* org,
                                double* tau, int32_t* status, hipStream_t s);
 
