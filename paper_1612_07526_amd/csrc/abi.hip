@@ -494,7 +494,7 @@ int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n,
       int32_t acc = 0;
       maps.push_back(0);
       for (int i = a; i < e; ++i) {
-        acc += map_blocks(k, T.merges[i].m, T.merges[i].n1, lm[h].gemm_tile);
+        acc += map_blocks(k, T.merges[i].m, T.merges[i].n1, lm[h].gemm_tile, T.merges[i].depth == 0);
         maps.push_back(acc);
       }
       lm[h].pfx[k] = (const int32_t*)(base + L.maps) + at;
@@ -843,7 +843,7 @@ int phdc_merge(int64_t n1, int64_t n2, const double* D, const double* z, double 
   lm.gemm_tile = (o->gemm_mode == PHDC_GEMM_SPLIT) ? 128 : gemm_tile_for(m);
   for (int k = 0; k < MAP_COUNT; ++k) {
     lm.pfx[k] = (const int32_t*)(base + L.maps) + maps.size();
-    lm.total[k] = map_blocks(k, (int)m, (int)n1, lm.gemm_tile);
+    lm.total[k] = map_blocks(k, (int)m, (int)n1, lm.gemm_tile, true);
     maps.push_back(0);
     maps.push_back(lm.total[k]);
   }

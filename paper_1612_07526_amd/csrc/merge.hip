@@ -907,9 +907,9 @@ __global__ void __launch_bounds__(256) k_rank(BlockMap bm, Scratch S) {
 // caller's eigenvector matrix.
 constexpr int kCopyBlocks = 16384;  // cap on column blocks per merge
 
-// Each block streams whole columns: a column group of RPT lanes (RPT = m
-// rounded up to a power of two, at most 64) walks the rows, 256 / RPT columns
-// per block at a time, four rows in flight per lane.
+// Below the root, each block streams whole columns: a column group of RPT
+// lanes (RPT = m rounded up to a power of two, at most 64) walks the range, 256
+// / RPT columns per block at a time, four rows in flight per lane.
 __device__ inline int copy_rpt(int m) {
   int rpt = 1;
   while (rpt < m && rpt < 64) rpt <<= 1;
@@ -926,6 +926,34 @@ __global__ void __launch_bounds__(256) k_copy_deflated(BlockMap bm, Scratch S) {
   const int32_t* cnt = S.counters + (int64_t)M.id * kCounters;
   const int nd1 = cnt[C_ND1], nd = nd1 + cnt[C_ND2];
   const int64_t so = M.s_off;
+  if (M.root) {
+    // The caller's Q: every row is written.  A whole block per column, rows
+    // in pairs with 16-byte stores (a scalar first row when the column starts
+    // at an odd 8-byte offset, a scalar last row when the rest is odd).
+    typedef double d2_t __attribute__((ext_vector_type(2)));
+    for (int q = lb; q < nd; q += G) {
+      int c, dst;
+      if (q < nd1) { c = S.dfc1[so + q]; dst = S.destd1[so + q]; }
+      else { const int q2 = q - nd1; c = S.dfc2[so + q2]; dst = S.destd2[so + q2]; }
+      const RowRange g = S.crng[so + c];
+      const double* src = M.qin + (int64_t)c * M.ldin;
+      double* out = M.qout + (int64_t)dst * M.ldout;
+      const int a = (int)(((uintptr_t)out >> 3) & 1);
+      const int np = (m - a) >> 1;
+      auto val = [&](int r) { return (r >= g.lo && r < g.hi) ? src[r] : 0.0; };
+      if (threadIdx.x == 0) {
+        if (a) out[0] = val(0);
+        if ((m - a) & 1) out[m - 1] = val(m - 1);
+      }
+      d2_t* o2 = (d2_t*)(out + a);
+#pragma unroll 4
+      for (int p = threadIdx.x; p < np; p += 256) {
+        const int r = a + 2 * p;
+        o2[p] = d2_t{val(r), val(r + 1)};
+      }
+    }
+    return;
+  }
   const int rpt = copy_rpt(m);
   const int cpb = 256 / rpt;
   const int lane = threadIdx.x % rpt, sub = threadIdx.x / rpt;
@@ -956,7 +984,7 @@ __global__ void __launch_bounds__(256) k_copy_deflated(BlockMap bm, Scratch S) {
 
 // ------------------------------------------------------------ block maps
 
-int map_blocks(int kind, int m, int n1, int gt) {
+int map_blocks(int kind, int m, int n1, int gt, bool root) {
   auto cdiv = [](int a, int b) { return (a + b - 1) / b; };
   switch (kind) {
     case MAP_ROOTS64: return cdiv(m, 64);
@@ -965,7 +993,8 @@ int map_blocks(int kind, int m, int n1, int gt) {
     case MAP_ROT: return cdiv(m, 256) * std::max(1, std::min(m / 2, kRotGroups));
     case MAP_UWRITE: return cdiv(m, 256) * std::max(1, std::min(m, kUwRowGroups));
     case MAP_GEMM: return std::min((cdiv(n1, gt) + cdiv(m - n1, gt)) * cdiv(m, gt), kGemmBlockCap);
-    case MAP_COPY: {  // columns per block = 256 / (m rounded up to a power of two, at most 64)
+    case MAP_COPY: {  // root: one column per block; else 256 / (m rounded up to a power of two, at most 64)
+      if (root) return std::max(1, std::min(m, kCopyBlocks));
       int rpt = 1;
       while (rpt < m && rpt < 64) rpt <<= 1;
       return std::max(1, std::min(cdiv(m, 256 / rpt), kCopyBlocks));

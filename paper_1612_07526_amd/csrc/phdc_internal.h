@@ -154,8 +154,9 @@ struct LevelMaps {
   int32_t maxm = 0;         // largest merge of the level
   int32_t gemm_tile = 128;  // output tile edge of the FP64 update GEMM (64 or 128)
 };
-// Blocks of one merge for a kernel class; gt is the FP64 GEMM tile edge (MAP_GEMM).
-int map_blocks(int kind, int m, int n1, int gt);
+// Blocks of one merge for a kernel class; gt is the FP64 GEMM tile edge (MAP_GEMM);
+// root: the merge is the last one of its matrix (MAP_COPY: one column per block).
+int map_blocks(int kind, int m, int n1, int gt, bool root);
 constexpr int kGemmBlockCap = 1024;      // blocks per merge of the update GEMMs (they loop over tiles)
 constexpr int kTileBuckets = 21;        // merge-size buckets of the GEMM tile table (m <= 2^20)
 int gemm_tile_for(int64_t maxm);        // tile edge for a level whose largest merge is maxm
