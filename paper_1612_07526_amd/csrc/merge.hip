@@ -88,7 +88,8 @@ __device__ inline bool pair_deflates(double dp, double zp, double dj, double zj,
 }
 
 // ------------------------------------------------------------ deflation
-// One 1024-thread workgroup per merge.  The compactions in pole order give
+// One workgroup per merge (1024 threads; 256 on levels whose merges have at
+// most kDefSmall rows).  The compactions in pole order give
 // each wave a contiguous index segment and place elements with ballots, so a
 // pass over m costs two block barriers however large m is.  The merge-path
 // searches of step 2 read D from LDS when the level's merges fit
@@ -96,6 +97,7 @@ __device__ inline bool pair_deflates(double dp, double zp, double dj, double zj,
 constexpr int kDefThreads = 1024;
 constexpr int kDefWaves = kDefThreads / 64;
 constexpr int kDefLdsMax = 16384;
+constexpr int kDefSmall = 256;
 
 __device__ inline int lanes_below(uint64_t mask) {
   return __popcll(mask & ((1ULL << (threadIdx.x & 63)) - 1ULL));
@@ -110,11 +112,11 @@ __device__ inline int sum16_bcast(int v) {
   return __shfl(v, 0, 64);
 }
 
-// Exclusive prefix over the waves of the block of NC per-wave counts, and the
-// block totals; lane i of every wave reads wave i's count.  Uses sh[NC][kDefWaves].
-template <int NC>
+// Exclusive prefix over the NW waves of the block of NC per-wave counts, and
+// the block totals; lane i of every wave reads wave i's count.  Uses sh[NC][kDefWaves].
+template <int NC, int NW>
 __device__ inline void wave_prefix(const int (&c)[NC], int (&pre)[NC], int (&tot)[NC], int (*sh)[kDefWaves]) {
-  static_assert(kDefWaves == 16, "sum16_bcast covers 16 waves");
+  static_assert(NW <= 16, "sum16_bcast covers 16 waves");
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   __syncthreads();
   if (lane == 0)
@@ -123,13 +125,16 @@ __device__ inline void wave_prefix(const int (&c)[NC], int (&pre)[NC], int (&tot
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < NC; ++q) {
-    const int v = (lane < kDefWaves) ? sh[q][lane] : 0;
+    const int v = (lane < NW) ? sh[q][lane] : 0;
     tot[q] = sum16_bcast(v);
     pre[q] = sum16_bcast(lane < w ? v : 0);
   }
 }
 
-__global__ void __launch_bounds__(kDefThreads) k_deflate(const MergeDesc* __restrict__ descs, Scratch S, int lds_cap) {
+template <int NT>
+__global__ void __launch_bounds__(NT) k_deflate(const MergeDesc* __restrict__ descs, Scratch S, int lds_cap) {
+  constexpr int NW = NT / 64;
+  static_assert(NW <= kDefWaves, "wave_prefix covers at most kDefWaves waves");
   __shared__ double shd[kDefWaves];
   __shared__ int shc[7][kDefWaves];
   __shared__ int shi[4];
@@ -159,11 +164,11 @@ __global__ void __launch_bounds__(kDefThreads) k_deflate(const MergeDesc* __rest
   double zz = 0.0, dmx = 0.0;
   int uns = 0;
   constexpr int U1 = 4;  // loads of four indices issued before their uses
-  for (int i0 = t; i0 < m; i0 += U1 * kDefThreads) {
+  for (int i0 = t; i0 < m; i0 += U1 * NT) {
     double zi[U1], di[U1], dprev[U1];
 #pragma unroll
     for (int u = 0; u < U1; ++u) {
-      const int i = i0 + u * kDefThreads;
+      const int i = i0 + u * NT;
       zi[u] = di[u] = dprev[u] = 0.0;
       if (i < m) {
         RowRange g = (i < n1) ? RowRange{0, n1} : RowRange{n1, m};
@@ -178,7 +183,7 @@ __global__ void __launch_bounds__(kDefThreads) k_deflate(const MergeDesc* __rest
     }
 #pragma unroll
     for (int u = 0; u < U1; ++u) {
-      const int i = i0 + u * kDefThreads;
+      const int i = i0 + u * NT;
       if (i < m) {
         S.zs[so + i] = zi[u];
         zz += zi[u] * zi[u];
@@ -189,8 +194,8 @@ __global__ void __launch_bounds__(kDefThreads) k_deflate(const MergeDesc* __rest
       }
     }
   }
-  zz = block_sum<kDefThreads>(zz, shd);
-  dmx = block_max<kDefThreads>(dmx, shd);
+  zz = block_sum<NT>(zz, shd);
+  dmx = block_max<NT>(dmx, shd);
   __syncthreads();
   if (t == 0) shi[0] = 0;
   __syncthreads();
@@ -210,7 +215,7 @@ __global__ void __launch_bounds__(kDefThreads) k_deflate(const MergeDesc* __rest
   // valid input the positions form a permutation of [0, m); otherwise keep the
   // input order so every slot is still written exactly once.
   auto place = [&](const double* D) {
-    for (int i = t; i < m; i += kDefThreads) {
+    for (int i = t; i < m; i += NT) {
       const double di = D[i];
       const int pos = uns ? i : (i < n1) ? i + count_lt(D + n1, m - n1, di) : (i - n1) + count_le(D, n1, di);
       dv[pos] = di;
@@ -220,7 +225,7 @@ __global__ void __launch_bounds__(kDefThreads) k_deflate(const MergeDesc* __rest
     }
   };
   if (m <= lds_cap) {
-    for (int i = t; i < m; i += kDefThreads) sdl[i] = M.lin[i];
+    for (int i = t; i < m; i += NT) sdl[i] = M.lin[i];
     __syncthreads();
     place(sdl);
   } else {
@@ -230,7 +235,7 @@ __global__ void __launch_bounds__(kDefThreads) k_deflate(const MergeDesc* __rest
 
   // 3. type-1 deflation (rho |z_i| <= tol) and compaction of both lists in pole order.
   const int lane = t & 63, wv = t >> 6;
-  const int seg = ((m + kDefWaves - 1) / kDefWaves + 63) / 64 * 64;
+  const int seg = ((m + NW - 1) / NW + 63) / 64 * 64;
   const int seg0 = min(m, wv * seg), seg1 = min(m, seg0 + seg);
   int ns, nd1;
   {
@@ -244,7 +249,7 @@ __global__ void __launch_bounds__(kDefThreads) k_deflate(const MergeDesc* __rest
       c[0] += __popcll(mv & ~md);
       c[1] += __popcll(md);
     }
-    wave_prefix<2>(c, pre, tot, shc);
+    wave_prefix<2, NW>(c, pre, tot, shc);
     int ps = pre[0], pd = pre[1];
     for (int b0 = seg0; b0 < seg1; b0 += 64) {
       const int k = b0 + lane;
@@ -378,7 +383,7 @@ __global__ void __launch_bounds__(kDefThreads) k_deflate(const MergeDesc* __rest
     c[5] += __popcll(__ballot(f > 0 && p == 2));
     c[6] += __popcll(__ballot(f > 0 && p == 3));
   }
-  wave_prefix<7>(c, pre, tot, shc);
+  wave_prefix<7, NW>(c, pre, tot, shc);
   const int k1 = tot[0], k2 = tot[1], k3 = tot[2], nd2 = tot[3];
   const int dp1 = tot[4], dp2 = tot[5], dp3 = tot[6];
   const int K = k1 + k2 + k3;
@@ -433,7 +438,7 @@ __global__ void __launch_bounds__(kDefThreads) k_deflate(const MergeDesc* __rest
       b4 += __popcll(m4);
     }
   }
-  drows = block_sum<kDefThreads>(drows, shd);
+  drows = block_sum<NT>(drows, shd);
   if (t == 0) {
     const int64_t dr = (int64_t)drows;
     cnt[C_DROWS_LO] = (int32_t)(uint32_t)(dr & 0xffffffffLL);
@@ -740,16 +745,9 @@ constexpr int kItemG = 16;
 constexpr int kItemsPerBlock = kSecThreads / kItemG;
 
 // A lane's partial product is a product of factors in (0, 1], so none
-// underflows before the full product does.
-__global__ void __launch_bounds__(kSecThreads) k_lowner(BlockMap bm, Scratch S) {
-  const int b = blockIdx.x;
-  const int mi = find_merge(bm, b);
-  const int lb = b - bm.pfx[mi];
-  const MergeDesc M = bm.descs[mi];
-  const int K = S.counters[(int64_t)M.id * kCounters + C_K];
-  if (lb * kItemsPerBlock >= K) return;
-  const int sub = threadIdx.x % kItemG;
-  const int i0 = lb * kItemsPerBlock + (int)threadIdx.x / kItemG;
+// underflows before the full product does.  Item i0 of a merge with K poles,
+// computed by the 16 lanes of a group (sub = lane within the group).
+__device__ inline void lowner_item(const MergeDesc& M, const Scratch& S, int K, int i0, int sub) {
   const bool active = i0 < K;
   const int i = active ? i0 : K - 1;  // idle groups repeat the last item (group shuffles)
   const int64_t so = M.s_off;
@@ -781,16 +779,18 @@ __global__ void __launch_bounds__(kSecThreads) k_lowner(BlockMap bm, Scratch S) 
   }
 }
 
-// Reciprocal 2-norms of the columns zhat_i / (d_i - lambda_j) of Uhat (Eq. (4)).
-__global__ void __launch_bounds__(kSecThreads) k_unorm(BlockMap bm, Scratch S) {
+__global__ void __launch_bounds__(kSecThreads) k_lowner(BlockMap bm, Scratch S) {
   const int b = blockIdx.x;
   const int mi = find_merge(bm, b);
   const int lb = b - bm.pfx[mi];
   const MergeDesc M = bm.descs[mi];
   const int K = S.counters[(int64_t)M.id * kCounters + C_K];
   if (lb * kItemsPerBlock >= K) return;
-  const int sub = threadIdx.x % kItemG;
-  const int j0 = lb * kItemsPerBlock + (int)threadIdx.x / kItemG;
+  lowner_item(M, S, K, lb * kItemsPerBlock + (int)threadIdx.x / kItemG, threadIdx.x % kItemG);
+}
+
+// Reciprocal 2-norms of the columns zhat_i / (d_i - lambda_j) of Uhat (Eq. (4)).
+__device__ inline void unorm_item(const MergeDesc& M, const Scratch& S, int K, int j0, int sub) {
   const bool active = j0 < K;
   const int j = active ? j0 : K - 1;
   const int64_t so = M.s_off;
@@ -813,9 +813,28 @@ __global__ void __launch_bounds__(kSecThreads) k_unorm(BlockMap bm, Scratch S) {
   if (active && sub == 0) S.cnorm[so + j] = 1.0 / sqrt(s);
 }
 
+__global__ void __launch_bounds__(kSecThreads) k_unorm(BlockMap bm, Scratch S) {
+  const int b = blockIdx.x;
+  const int mi = find_merge(bm, b);
+  const int lb = b - bm.pfx[mi];
+  const MergeDesc M = bm.descs[mi];
+  const int K = S.counters[(int64_t)M.id * kCounters + C_K];
+  if (lb * kItemsPerBlock >= K) return;
+  unorm_item(M, S, K, lb * kItemsPerBlock + (int)threadIdx.x / kItemG, threadIdx.x % kItemG);
+}
+
 // ... then the entries, written row-major (row g = grouped row, ld = K) so that
-// the product's operand tiles are contiguous.  A block covers 256 columns and
-// strides over rows.
+// the product's operand tiles are contiguous.  HSS merges keep the pole order
+// (Gu's grouping would break the low-rank structure of the off-diagonal
+// blocks, Sec. 2.2); plain merges use it.
+__device__ inline double uhat_entry(const MergeDesc& M, const Scratch& S, bool pole_order, int g, double lj,
+                                    double tj, double sc) {
+  const int64_t so = M.s_off;
+  const int i = pole_order ? g : S.grpsrc[so + g];
+  return S.zhat[so + i] / ((S.ds[so + i] - lj) - tj) * sc;
+}
+
+// A block covers 256 columns and strides over rows.
 constexpr int kUwRowGroups = 64;
 
 __global__ void __launch_bounds__(256) k_uwrite(BlockMap bm, Scratch S) {
@@ -830,17 +849,36 @@ __global__ void __launch_bounds__(256) k_uwrite(BlockMap bm, Scratch S) {
   const int j = cb * 256 + threadIdx.x;
   if (j >= K) return;
   const int64_t so = M.s_off;
-  const double* ds = S.ds + so;
-  const double* zh = S.zhat + so;
-  // HSS merges keep the pole order (Gu's grouping would break the low-rank
-  // structure of the off-diagonal blocks, Sec. 2.2); plain merges use it.
   const bool pole_order = S.counters[(int64_t)M.id * kCounters + C_PATH] == 2;
-  const int32_t* src = S.grpsrc + so;
   const double lj = S.dorg[so + j], tj = S.tau[so + j], sc = S.cnorm[so + j];
   double* U = S.uhat + M.u_off;
-  for (int g = rg; g < K; g += RG) {
-    const int i = pole_order ? g : src[g];
-    U[(int64_t)g * K + j] = zh[i] / ((ds[i] - lj) - tj) * sc;
+  for (int g = rg; g < K; g += RG) U[(int64_t)g * K + j] = uhat_entry(M, S, pole_order, g, lj, tj, sc);
+}
+
+// Levels whose merges have at most kSmallUhat rows: one workgroup per merge
+// forms zhat, the column norms and Uhat in turn (three launches fewer, and no
+// grid sized for K = m at small m).  Same per-item arithmetic as above.
+constexpr int kSmallUhat = 64;
+
+__global__ void __launch_bounds__(kSecThreads) k_small_uhat(const MergeDesc* __restrict__ descs, Scratch S) {
+  const MergeDesc M = descs[blockIdx.x];
+  const int K = S.counters[(int64_t)M.id * kCounters + C_K];
+  if (K <= 0) return;
+  const int grp = (int)threadIdx.x / kItemG, sub = threadIdx.x % kItemG;
+  for (int i0 = 0; i0 < K; i0 += kItemsPerBlock) lowner_item(M, S, K, i0 + grp, sub);
+  __syncthreads();
+  for (int j0 = 0; j0 < K; j0 += kItemsPerBlock) unorm_item(M, S, K, j0 + grp, sub);
+  __syncthreads();
+  const int64_t so = M.s_off;
+  const bool pole_order = S.counters[(int64_t)M.id * kCounters + C_PATH] == 2;
+  double* U = S.uhat + M.u_off;
+  const int nj = min(K, kSecThreads), rg = kSecThreads / nj;  // column j = t % nj, row group t / nj
+  const int t = threadIdx.x;
+  if (t < nj * rg) {
+    for (int j = t % nj; j < K; j += nj) {
+      const double lj = S.dorg[so + j], tj = S.tau[so + j], sc = S.cnorm[so + j];
+      for (int g = t / nj; g < K; g += rg) U[(int64_t)g * K + j] = uhat_entry(M, S, pole_order, g, lj, tj, sc);
+    }
   }
 }
 
@@ -1017,7 +1055,11 @@ void launch_merge_level(const MergeDesc* descs, int nm, const LevelMaps& maps, c
   auto bmap = [&](int kind) { return BlockMap{descs, maps.pfx[kind], nm}; };
   { ProfScope p(PH_DEFLATE, s);
     const int cap = maps.maxm <= kDefLdsMax ? maps.maxm : 0;
-    hipLaunchKernelGGL(k_deflate, dim3(nm), dim3(kDefThreads), (size_t)cap * sizeof(double), s, descs, S, cap); }
+    if (maps.maxm <= kDefSmall)
+      hipLaunchKernelGGL(k_deflate<256>, dim3(nm), dim3(256), (size_t)cap * sizeof(double), s, descs, S, cap);
+    else
+      hipLaunchKernelGGL(k_deflate<kDefThreads>, dim3(nm), dim3(kDefThreads), (size_t)cap * sizeof(double), s, descs,
+                         S, cap); }
   if (probe && probe->count > 0) {
     hipLaunchKernelGGL(k_copy_ints, dim3((probe->count + 255) / 256), dim3(256), 0, s, probe->src, probe->dst,
                        probe->count);
@@ -1027,12 +1069,17 @@ void launch_merge_level(const MergeDesc* descs, int nm, const LevelMaps& maps, c
     hipLaunchKernelGGL(k_rotate, dim3(maps.total[MAP_ROT]), dim3(256), 0, s, bmap(MAP_ROT), S); }
   { ProfScope p(PH_SECULAR, s);
     hipLaunchKernelGGL(k_secular, dim3(maps.total[MAP_ROOTS16]), dim3(kSecThreads), 0, s, bmap(MAP_ROOTS16), S); }
-  { ProfScope p(PH_LOWNER, s);
-    hipLaunchKernelGGL(k_lowner, dim3(maps.total[MAP_ROOTS16]), dim3(kSecThreads), 0, s, bmap(MAP_ROOTS16), S); }
-  { ProfScope p(PH_UNORM, s);
-    hipLaunchKernelGGL(k_unorm, dim3(maps.total[MAP_ROOTS16]), dim3(kSecThreads), 0, s, bmap(MAP_ROOTS16), S); }
-  { ProfScope p(PH_UWRITE, s);
-    hipLaunchKernelGGL(k_uwrite, dim3(maps.total[MAP_UWRITE]), dim3(256), 0, s, bmap(MAP_UWRITE), S); }
+  if (maps.maxm <= kSmallUhat) {
+    ProfScope p(PH_UWRITE, s);
+    hipLaunchKernelGGL(k_small_uhat, dim3(nm), dim3(kSecThreads), 0, s, descs, S);
+  } else {
+    { ProfScope p(PH_LOWNER, s);
+      hipLaunchKernelGGL(k_lowner, dim3(maps.total[MAP_ROOTS16]), dim3(kSecThreads), 0, s, bmap(MAP_ROOTS16), S); }
+    { ProfScope p(PH_UNORM, s);
+      hipLaunchKernelGGL(k_unorm, dim3(maps.total[MAP_ROOTS16]), dim3(kSecThreads), 0, s, bmap(MAP_ROOTS16), S); }
+    { ProfScope p(PH_UWRITE, s);
+      hipLaunchKernelGGL(k_uwrite, dim3(maps.total[MAP_UWRITE]), dim3(256), 0, s, bmap(MAP_UWRITE), S); }
+  }
   { ProfScope p(PH_RANK, s);
     hipLaunchKernelGGL(k_rank, dim3(maps.total[MAP_ROWS256]), dim3(256), 0, s, bmap(MAP_ROWS256), S); }
   { ProfScope p(PH_GEMM, s);
