@@ -238,32 +238,57 @@ __global__ void __launch_bounds__(NT) k_deflate(const MergeDesc* __restrict__ de
   const int seg = ((m + NW - 1) / NW + 63) / 64 * 64;
   const int seg0 = min(m, wv * seg), seg1 = min(m, seg0 + seg);
   int ns, nd1;
+  // The passes below load UC chunks of 64 before using any of them (the chunks
+  // are then consumed in order), so a wave waits on memory once per UC chunks.
+  constexpr int UC = 4;
   {
     int c[2] = {0, 0}, pre[2], tot[2];
-    for (int b0 = seg0; b0 < seg1; b0 += 64) {
-      const int k = b0 + lane;
-      const bool valid = k < seg1;
-      const bool dfl = valid && rho * fabs(zv[k]) <= tol;
-      if (valid) flag[k] = dfl ? 1 : 0;
-      const uint64_t md = __ballot(dfl), mv = __ballot(valid);
-      c[0] += __popcll(mv & ~md);
-      c[1] += __popcll(md);
+    for (int b0 = seg0; b0 < seg1; b0 += 64 * UC) {
+      double zk[UC];
+#pragma unroll
+      for (int u = 0; u < UC; ++u) {
+        const int k = b0 + u * 64 + lane;
+        zk[u] = (k < seg1) ? zv[k] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < UC; ++u) {
+        const int k = b0 + u * 64 + lane;
+        const bool valid = k < seg1;
+        const bool dfl = valid && rho * fabs(zk[u]) <= tol;
+        if (valid) flag[k] = dfl ? 1 : 0;
+        const uint64_t md = __ballot(dfl), mv = __ballot(valid);
+        c[0] += __popcll(mv & ~md);
+        c[1] += __popcll(md);
+      }
     }
     wave_prefix<2, NW>(c, pre, tot, shc);
     int ps = pre[0], pd = pre[1];
-    for (int b0 = seg0; b0 < seg1; b0 += 64) {
-      const int k = b0 + lane;
-      const bool valid = k < seg1;
-      const bool dfl = valid && rho * fabs(zv[k]) <= tol;
-      const uint64_t md = __ballot(dfl), ms = __ballot(valid && !dfl);
-      if (valid && !dfl) surv[ps + lanes_below(ms)] = k;
-      if (dfl) {
-        const int q = pd + lanes_below(md);
-        S.dfv1[so + q] = dv[k];
-        S.dfc1[so + q] = col[k];
+    for (int b0 = seg0; b0 < seg1; b0 += 64 * UC) {
+      double zk[UC], dk[UC];
+      int ck[UC];
+#pragma unroll
+      for (int u = 0; u < UC; ++u) {
+        const int k = b0 + u * 64 + lane;
+        const bool valid = k < seg1;
+        zk[u] = valid ? zv[k] : 0.0;
+        dk[u] = valid ? dv[k] : 0.0;
+        ck[u] = valid ? col[k] : 0;
       }
-      ps += __popcll(ms);
-      pd += __popcll(md);
+#pragma unroll
+      for (int u = 0; u < UC; ++u) {
+        const int k = b0 + u * 64 + lane;
+        const bool valid = k < seg1;
+        const bool dfl = valid && rho * fabs(zk[u]) <= tol;
+        const uint64_t md = __ballot(dfl), ms = __ballot(valid && !dfl);
+        if (valid && !dfl) surv[ps + lanes_below(ms)] = k;
+        if (dfl) {
+          const int q = pd + lanes_below(md);
+          S.dfv1[so + q] = dk[u];
+          S.dfc1[so + q] = ck[u];
+        }
+        ps += __popcll(ms);
+        pd += __popcll(md);
+      }
     }
     ns = tot[0];
     nd1 = tot[1];
@@ -370,18 +395,26 @@ __global__ void __launch_bounds__(NT) k_deflate(const MergeDesc* __restrict__ de
   // Uhat ordered [part 1 | part 2 | part 3]; the Q1-row product uses columns of
   // parts 1,2 and the Q2-row product those of parts 2,3.  Type-2 deflated list.
   int c[7] = {0, 0, 0, 0, 0, 0, 0}, pre[7], tot[7];
-  for (int b0 = seg0; b0 < seg1; b0 += 64) {
-    const int k = b0 + lane;
-    const bool valid = k < seg1;
-    const int f = valid ? flag[k] : -1;
-    const int p = valid ? part[k] : 0;
-    c[0] += __popcll(__ballot(f == 0 && p == 1));
-    c[1] += __popcll(__ballot(f == 0 && p == 2));
-    c[2] += __popcll(__ballot(f == 0 && p == 3));
-    c[3] += __popcll(__ballot(f == 2));
-    c[4] += __popcll(__ballot(f > 0 && p == 1));  // deflated columns by nonzero half
-    c[5] += __popcll(__ballot(f > 0 && p == 2));
-    c[6] += __popcll(__ballot(f > 0 && p == 3));
+  for (int b0 = seg0; b0 < seg1; b0 += 64 * UC) {
+    int fu[UC], pu[UC];
+#pragma unroll
+    for (int u = 0; u < UC; ++u) {
+      const int k = b0 + u * 64 + lane;
+      const bool valid = k < seg1;
+      fu[u] = valid ? flag[k] : -1;
+      pu[u] = valid ? part[k] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < UC; ++u) {
+      const int f = fu[u], p = pu[u];
+      c[0] += __popcll(__ballot(f == 0 && p == 1));
+      c[1] += __popcll(__ballot(f == 0 && p == 2));
+      c[2] += __popcll(__ballot(f == 0 && p == 3));
+      c[3] += __popcll(__ballot(f == 2));
+      c[4] += __popcll(__ballot(f > 0 && p == 1));  // deflated columns by nonzero half
+      c[5] += __popcll(__ballot(f > 0 && p == 2));
+      c[6] += __popcll(__ballot(f > 0 && p == 3));
+    }
   }
   wave_prefix<7, NW>(c, pre, tot, shc);
   const int k1 = tot[0], k2 = tot[1], k3 = tot[2], nd2 = tot[3];
@@ -390,52 +423,64 @@ __global__ void __launch_bounds__(NT) k_deflate(const MergeDesc* __restrict__ de
   double drows = 0.0;  // rows in range over the deflated columns (exact: integers below 2^53)
   {
     int b1 = pre[0], b2 = pre[1], b3 = pre[2], b4 = pre[3];
-    for (int b0 = seg0; b0 < seg1; b0 += 64) {
-      const int k = b0 + lane;
-      const bool valid = k < seg1;
-      const int f = valid ? flag[k] : -1;
-      const int p = valid ? part[k] : 0;
-      const uint64_t m1 = __ballot(f == 0 && p == 1), m2 = __ballot(f == 0 && p == 2);
-      const uint64_t m3 = __ballot(f == 0 && p == 3), m4 = __ballot(f == 2);
-      if (f == 0) {
-        const int e1 = b1 + lanes_below(m1), e2 = b2 + lanes_below(m2), e3 = b3 + lanes_below(m3);
-        const int ks = e1 + e2 + e3;
-        S.ds[so + ks] = dv[k];
-        S.zs[so + ks] = zv[k];
-        const int ck = col[k];
-        const RowRange gk = S.crng[so + ck];
-        S.csort[so + ks] = ck;
-        int g;
-        if (p == 1) {
-          g = e1;
-          S.coltop[so + e1] = ck;
-          S.rgtop[so + e1] = gk;
-        } else if (p == 2) {
-          g = k1 + e2;
-          S.coltop[so + k1 + e2] = ck;
-          S.rgtop[so + k1 + e2] = gk;
-          S.colbot[so + e2] = ck;
-          S.rgbot[so + e2] = gk;
-        } else {
-          g = k1 + k2 + e3;
-          S.colbot[so + k2 + e3] = ck;
-          S.rgbot[so + k2 + e3] = gk;
+    for (int b0 = seg0; b0 < seg1; b0 += 64 * UC) {
+      int fu[UC], pu[UC], cu[UC];
+      double du[UC], zu[UC];
+      RowRange gu[UC];
+#pragma unroll
+      for (int u = 0; u < UC; ++u) {
+        const int k = b0 + u * 64 + lane;
+        const bool valid = k < seg1;
+        fu[u] = valid ? flag[k] : -1;
+        pu[u] = valid ? part[k] : 0;
+        cu[u] = valid ? col[k] : 0;
+        du[u] = valid ? dv[k] : 0.0;
+        zu[u] = valid ? zv[k] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < UC; ++u) gu[u] = (fu[u] >= 0) ? S.crng[so + cu[u]] : RowRange{0, 0};
+#pragma unroll
+      for (int u = 0; u < UC; ++u) {
+        const int f = fu[u], p = pu[u];
+        const uint64_t m1 = __ballot(f == 0 && p == 1), m2 = __ballot(f == 0 && p == 2);
+        const uint64_t m3 = __ballot(f == 0 && p == 3), m4 = __ballot(f == 2);
+        if (f == 0) {
+          const int e1 = b1 + lanes_below(m1), e2 = b2 + lanes_below(m2), e3 = b3 + lanes_below(m3);
+          const int ks = e1 + e2 + e3;
+          S.ds[so + ks] = du[u];
+          S.zs[so + ks] = zu[u];
+          const int ck = cu[u];
+          const RowRange gk = gu[u];
+          S.csort[so + ks] = ck;
+          int g;
+          if (p == 1) {
+            g = e1;
+            S.coltop[so + e1] = ck;
+            S.rgtop[so + e1] = gk;
+          } else if (p == 2) {
+            g = k1 + e2;
+            S.coltop[so + k1 + e2] = ck;
+            S.rgtop[so + k1 + e2] = gk;
+            S.colbot[so + e2] = ck;
+            S.rgbot[so + e2] = gk;
+          } else {
+            g = k1 + k2 + e3;
+            S.colbot[so + k2 + e3] = ck;
+            S.rgbot[so + k2 + e3] = gk;
+          }
+          S.grp[so + ks] = g;
+          S.grpsrc[so + g] = ks;
+        } else if (f == 2) {
+          const int q = b4 + lanes_below(m4);
+          S.dfv2[so + q] = du[u];
+          S.dfc2[so + q] = cu[u];
         }
-        S.grp[so + ks] = g;
-        S.grpsrc[so + g] = ks;
-      } else if (f == 2) {
-        const int q = b4 + lanes_below(m4);
-        S.dfv2[so + q] = dv[k];
-        S.dfc2[so + q] = col[k];
+        if (f > 0) drows += (double)(gu[u].hi - gu[u].lo);
+        b1 += __popcll(m1);
+        b2 += __popcll(m2);
+        b3 += __popcll(m3);
+        b4 += __popcll(m4);
       }
-      if (f > 0) {
-        const RowRange gk = S.crng[so + col[k]];
-        drows += (double)(gk.hi - gk.lo);
-      }
-      b1 += __popcll(m1);
-      b2 += __popcll(m2);
-      b3 += __popcll(m3);
-      b4 += __popcll(m4);
     }
   }
   drows = block_sum<NT>(drows, shd);
