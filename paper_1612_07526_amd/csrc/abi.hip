@@ -491,14 +491,19 @@ int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n,
     lm[h].gemm_tile = (o->gemm_mode == PHDC_GEMM_SPLIT) ? 128 : gemm_tile_for(lm[h].maxm);
     for (int k = 0; k < MAP_COUNT; ++k) {
       const size_t at = maps.size();
-      int32_t acc = 0;
+      int32_t acc = 0, first = -1;
+      bool equal = true;
       maps.push_back(0);
       for (int i = a; i < e; ++i) {
-        acc += map_blocks(k, T.merges[i].m, T.merges[i].n1, lm[h].gemm_tile, T.merges[i].depth == 0);
+        const int32_t bl = map_blocks(k, T.merges[i].m, T.merges[i].n1, lm[h].gemm_tile, T.merges[i].depth == 0);
+        if (first < 0) first = bl;
+        else if (bl != first) equal = false;
+        acc += bl;
         maps.push_back(acc);
       }
       lm[h].pfx[k] = (const int32_t*)(base + L.maps) + at;
       lm[h].total[k] = acc;
+      lm[h].per[k] = (equal && first > 0) ? first : 0;
     }
   }
   put(plan, L.maps - plan0, maps.data(), maps.size());
@@ -844,6 +849,7 @@ int phdc_merge(int64_t n1, int64_t n2, const double* D, const double* z, double 
   for (int k = 0; k < MAP_COUNT; ++k) {
     lm.pfx[k] = (const int32_t*)(base + L.maps) + maps.size();
     lm.total[k] = map_blocks(k, (int)m, (int)n1, lm.gemm_tile, true);
+    lm.per[k] = lm.total[k] > 0 ? lm.total[k] : 0;
     maps.push_back(0);
     maps.push_back(lm.total[k]);
   }

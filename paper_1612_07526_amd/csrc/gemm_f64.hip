@@ -39,7 +39,7 @@ __global__ void __launch_bounds__(256) k_merge_gemm(BlockMap bm, Scratch S) {
   __shared__ double Bs[2][GK][GLD];
   const int b = blockIdx.x;
   const int mi = find_merge(bm, b);
-  const int lb = b - bm.pfx[mi];
+  const int lb = b - merge_first_block(bm, mi);
   const MergeDesc M = bm.descs[mi];
   const int32_t* cnt = S.counters + (int64_t)M.id * kCounters;
   if (cnt[C_PATH] != 0) return;  // formed by another update path
@@ -52,7 +52,7 @@ __global__ void __launch_bounds__(256) k_merge_gemm(BlockMap bm, Scratch S) {
   if (lb >= nact) return;
   // A block computes tiles lb, lb + G, ... (G = the merge's blocks, at most
   // kGemmBlockCap), so merges whose K is far below m launch few idle blocks.
-  const int G = bm.pfx[mi + 1] - bm.pfx[mi];
+  const int G = merge_blocks(bm, mi);
   for (int tile = lb; tile < nact; tile += G) {
     // Tile order.  Workgroups are dispatched round-robin over the 8 XCDs, each
     // with its own L2: hand XCD (tile mod 8) a contiguous range of tiles, and walk
@@ -296,7 +296,7 @@ int phdc_autotune_gemm(int64_t max_m, void* work, size_t lwork, void* stream) {
         rc = -5;
         break;
       }
-      BlockMap bm{desc, pfx, 1};
+      BlockMap bm{desc, pfx, 1, 0};
       launch_merge_gemm_f64(bm, total, S, gt, s);  // warm-up
       for (int r = 0; r < 3; ++r) {
         hipEventRecord(e0, s);

@@ -516,11 +516,11 @@ constexpr int kRotGroups = 16;
 __global__ void __launch_bounds__(256) k_rotate(BlockMap bm, Scratch S) {
   const int b = blockIdx.x;
   const int mi = find_merge(bm, b);
-  const int lb = b - bm.pfx[mi];
+  const int lb = b - merge_first_block(bm, mi);
   const MergeDesc M = bm.descs[mi];
   const int m = M.m;
   const int RB = cdiv_d(m, 256);
-  const int G = (bm.pfx[mi + 1] - bm.pfx[mi]) / RB;
+  const int G = (merge_blocks(bm, mi)) / RB;
   const int rb = lb % RB, g = lb / RB;
   const int32_t* cnt = S.counters + (int64_t)M.id * kCounters;
   const int nrot = cnt[C_NROT], nchain = cnt[C_NCHAIN];
@@ -717,7 +717,7 @@ __global__ void __launch_bounds__(kSecThreads) k_secular(BlockMap bm, Scratch S)
   __shared__ double sz[kSecLds];
   const int b = blockIdx.x;
   const int mi = find_merge(bm, b);
-  const int lb = b - bm.pfx[mi];
+  const int lb = b - merge_first_block(bm, mi);
   const MergeDesc M = bm.descs[mi];
   const int K = S.counters[(int64_t)M.id * kCounters + C_K];
   if (lb * kSecRoots >= K) return;  // whole block idle (uniform)
@@ -827,7 +827,7 @@ __device__ inline void lowner_item(const MergeDesc& M, const Scratch& S, int K, 
 __global__ void __launch_bounds__(kSecThreads) k_lowner(BlockMap bm, Scratch S) {
   const int b = blockIdx.x;
   const int mi = find_merge(bm, b);
-  const int lb = b - bm.pfx[mi];
+  const int lb = b - merge_first_block(bm, mi);
   const MergeDesc M = bm.descs[mi];
   const int K = S.counters[(int64_t)M.id * kCounters + C_K];
   if (lb * kItemsPerBlock >= K) return;
@@ -861,7 +861,7 @@ __device__ inline void unorm_item(const MergeDesc& M, const Scratch& S, int K, i
 __global__ void __launch_bounds__(kSecThreads) k_unorm(BlockMap bm, Scratch S) {
   const int b = blockIdx.x;
   const int mi = find_merge(bm, b);
-  const int lb = b - bm.pfx[mi];
+  const int lb = b - merge_first_block(bm, mi);
   const MergeDesc M = bm.descs[mi];
   const int K = S.counters[(int64_t)M.id * kCounters + C_K];
   if (lb * kItemsPerBlock >= K) return;
@@ -885,11 +885,11 @@ constexpr int kUwRowGroups = 64;
 __global__ void __launch_bounds__(256) k_uwrite(BlockMap bm, Scratch S) {
   const int b = blockIdx.x;
   const int mi = find_merge(bm, b);
-  const int lb = b - bm.pfx[mi];
+  const int lb = b - merge_first_block(bm, mi);
   const MergeDesc M = bm.descs[mi];
   const int K = S.counters[(int64_t)M.id * kCounters + C_K];
   const int CB = cdiv_d(M.m, 256);
-  const int RG = (bm.pfx[mi + 1] - bm.pfx[mi]) / CB;
+  const int RG = (merge_blocks(bm, mi)) / CB;
   const int cb = lb % CB, rg = lb / CB;
   const int j = cb * 256 + threadIdx.x;
   if (j >= K) return;
@@ -935,7 +935,7 @@ __global__ void __launch_bounds__(kSecThreads) k_small_uhat(const MergeDesc* __r
 __global__ void __launch_bounds__(256) k_rank(BlockMap bm, Scratch S) {
   const int b = blockIdx.x;
   const int mi = find_merge(bm, b);
-  const int lb = b - bm.pfx[mi];
+  const int lb = b - merge_first_block(bm, mi);
   const MergeDesc M = bm.descs[mi];
   const int x = lb * 256 + threadIdx.x;
   if (x >= M.m) return;
@@ -1002,8 +1002,8 @@ __device__ inline int copy_rpt(int m) {
 __global__ void __launch_bounds__(256) k_copy_deflated(BlockMap bm, Scratch S) {
   const int b = blockIdx.x;
   const int mi = find_merge(bm, b);
-  const int lb = b - bm.pfx[mi];
-  const int G = bm.pfx[mi + 1] - bm.pfx[mi];
+  const int lb = b - merge_first_block(bm, mi);
+  const int G = merge_blocks(bm, mi);
   const MergeDesc M = bm.descs[mi];
   const int m = M.m;
   const int32_t* cnt = S.counters + (int64_t)M.id * kCounters;
@@ -1097,7 +1097,7 @@ __global__ void __launch_bounds__(256) k_copy_ints(const int32_t* __restrict__ s
 void launch_merge_level(const MergeDesc* descs, int nm, const LevelMaps& maps, const Scratch& S, int gemm_mode,
                         const SplitBufs* split, int nsl, hipStream_t s, const LevelProbe* probe) {
   if (nm <= 0) return;
-  auto bmap = [&](int kind) { return BlockMap{descs, maps.pfx[kind], nm}; };
+  auto bmap = [&](int kind) { return BlockMap{descs, maps.pfx[kind], nm, maps.per[kind]}; };
   { ProfScope p(PH_DEFLATE, s);
     const int cap = maps.maxm <= kDefLdsMax ? maps.maxm : 0;
     if (maps.maxm <= kDefSmall)

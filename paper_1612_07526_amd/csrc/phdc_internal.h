@@ -123,19 +123,28 @@ struct Scratch {
 };
 
 // Block map: launch of `total` blocks split over merges by prefix pfx[0..nm].
+// When every merge of the launch has the same number of blocks (per > 0) the
+// merge of a block is b / per, with no search through pfx.
 struct BlockMap {
   const MergeDesc* descs;
   const int32_t* pfx;
   int32_t nm;
+  int32_t per;
 };
 
 __device__ inline int find_merge(const BlockMap& bm, int b) {
+  if (bm.per > 0) return b / bm.per;
   int lo = 0, hi = bm.nm - 1;
   while (lo < hi) {
     int mid = (lo + hi + 1) >> 1;
     if (bm.pfx[mid] <= b) lo = mid; else hi = mid - 1;
   }
   return lo;
+}
+// First block of merge mi, and its number of blocks.
+__device__ inline int merge_first_block(const BlockMap& bm, int mi) { return bm.per > 0 ? mi * bm.per : bm.pfx[mi]; }
+__device__ inline int merge_blocks(const BlockMap& bm, int mi) {
+  return bm.per > 0 ? bm.per : bm.pfx[mi + 1] - bm.pfx[mi];
 }
 
 __device__ inline void set_status(int32_t* status, int code) {
@@ -151,6 +160,7 @@ enum MapKind { MAP_ROOTS64 = 0, MAP_ROOTS16, MAP_ROWS256, MAP_ROT, MAP_UWRITE, M
 struct LevelMaps {
   const int32_t* pfx[MAP_COUNT];
   int32_t total[MAP_COUNT];
+  int32_t per[MAP_COUNT] = {};  // blocks per merge when equal for all merges of the level, else 0
   int32_t maxm = 0;         // largest merge of the level
   int32_t gemm_tile = 128;  // output tile edge of the FP64 update GEMM (64 or 128)
 };

@@ -33,7 +33,7 @@ __device__ inline int exp_above(double v) {
 __global__ void __launch_bounds__(256) k_split_scales(BlockMap bm, Scratch S, SplitBufs B) {
   const int b = blockIdx.x;
   const int mi = find_merge(bm, b);
-  const int lb = b - bm.pfx[mi];
+  const int lb = b - merge_first_block(bm, mi);
   const MergeDesc M = bm.descs[mi];
   const int32_t* cnt = S.counters + (int64_t)M.id * kCounters;
   const int K = cnt[C_K], k1 = cnt[C_K1], k2 = cnt[C_K2], k3 = cnt[C_K3];
@@ -72,7 +72,7 @@ __device__ inline void cut(double v, int nsl, __bf16* out, int64_t stride) {
 __global__ void __launch_bounds__(256) k_split_slice_a(BlockMap bm, Scratch S, SplitBufs B, int nsl) {
   const int b = blockIdx.x;
   const int mi = find_merge(bm, b);
-  const int lb = b - bm.pfx[mi];
+  const int lb = b - merge_first_block(bm, mi);
   const MergeDesc M = bm.descs[mi];
   const int32_t* cnt = S.counters + (int64_t)M.id * kCounters;
   if (cnt[C_PATH] != 1) return;
@@ -105,7 +105,7 @@ __global__ void __launch_bounds__(256) k_split_slice_a(BlockMap bm, Scratch S, S
 __global__ void __launch_bounds__(256) k_split_slice_b(BlockMap bm, Scratch S, SplitBufs B, int nsl) {
   const int b = blockIdx.x;
   const int mi = find_merge(bm, b);
-  const int lb = b - bm.pfx[mi];
+  const int lb = b - merge_first_block(bm, mi);
   const MergeDesc M = bm.descs[mi];
   const int32_t* cnt = S.counters + (int64_t)M.id * kCounters;
   if (cnt[C_PATH] != 1) return;
@@ -137,7 +137,7 @@ __global__ void __launch_bounds__(256) k_split_gemm(BlockMap bm, Scratch S, Spli
   __shared__ __attribute__((aligned(16))) __bf16 Bs[XMAXS][XT][XLD];
   const int b = blockIdx.x;
   const int mi = find_merge(bm, b);
-  const int lb = b - bm.pfx[mi];
+  const int lb = b - merge_first_block(bm, mi);
   const MergeDesc M = bm.descs[mi];
   const int32_t* cnt = S.counters + (int64_t)M.id * kCounters;
   if (cnt[C_PATH] != 1) return;
@@ -150,7 +150,7 @@ __global__ void __launch_bounds__(256) k_split_gemm(BlockMap bm, Scratch S, Spli
   const int nact = TM * TN;
   if (lb >= nact) return;
   // A block computes tiles lb, lb + G, ... (G = the merge's blocks).
-  const int G = bm.pfx[mi + 1] - bm.pfx[mi];
+  const int G = merge_blocks(bm, mi);
   for (int tile = lb; tile < nact; tile += G) {
     // XCD-aware grouped tile order, as in the FP64 update GEMM
     const int n8 = nact - nact % 8;
@@ -259,7 +259,7 @@ __global__ void __launch_bounds__(256) k_split_gemm(BlockMap bm, Scratch S, Spli
 
 void launch_split_update(const MergeDesc* descs, int nm, const LevelMaps& maps, const Scratch& S,
                          const SplitBufs& B, int nsl, hipStream_t s) {
-  auto bmap = [&](int kind) { return BlockMap{descs, maps.pfx[kind], nm}; };
+  auto bmap = [&](int kind) { return BlockMap{descs, maps.pfx[kind], nm, maps.per[kind]}; };
   hipLaunchKernelGGL(k_split_scales, dim3(maps.total[MAP_ROWS256]), dim3(256), 0, s, bmap(MAP_ROWS256), S, B);
   hipLaunchKernelGGL(k_split_slice_a, dim3(maps.total[MAP_SPLITA]), dim3(256), 0, s, bmap(MAP_SPLITA), S, B, nsl);
   hipLaunchKernelGGL(k_split_slice_b, dim3(maps.total[MAP_SPLITB]), dim3(256), 0, s, bmap(MAP_SPLITB), S, B, nsl);
