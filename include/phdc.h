@@ -20,11 +20,17 @@
  *    frees device memory.
  *  - `stream` is a hipStream_t (may be NULL for the default stream).  Work is
  *    only enqueued; nothing waits for the GPU except phdc_status().
- *  - Return value: 0 on success, -i if argument i (1-based) is invalid.  The
- *    argument checks are done on the host before anything is enqueued.
+ *  - Return value: 0 on success; -i (1 <= i <= 99) if argument i (1-based) is
+ *    invalid, found by host-side checks before anything is enqueued (with
+ *    opts.check_finite set, also a NaN or Inf in an input array, found by a
+ *    device scan the call waits for); PHDC_E_HIP (-100) if a HIP runtime call
+ *    made by the library failed (launch, copy, synchronisation, event or
+ *    pinned host allocation).  No other value is returned.
  *    Failures that can only be seen on the device (a leaf QL or secular
  *    iteration that does not converge, unsorted merge input, non-finite
- *    input) are reported through phdc_status().
+ *    input) are reported through phdc_status() (enum phdc_info); the solve
+ *    still runs to completion and every access stays inside the caller's
+ *    buffers, but its results are then meaningless.
  *  - Every call needs a workspace of at least the size returned by the
  *    matching *_workspace query; the same workspace must not be used by two
  *    calls that may run at the same time.
@@ -46,13 +52,28 @@ enum phdc_gemm_mode {
     PHDC_GEMM_HSS = 2    /* HSS-compressed Uhat (Sec. 2.2, Algorithm 1) when K >= hss_min_K, else FP64 */
 };
 
-/* Device-side status codes returned by phdc_status(). */
+/* Device-side status codes returned by phdc_status().  The first failure of a
+ * call is kept. */
 enum phdc_info {
     PHDC_OK = 0,
-    PHDC_ERR_LEAF = 1,     /* a leaf QL iteration did not converge */
-    PHDC_ERR_SECULAR = 2,  /* a secular root did not converge */
+    PHDC_ERR_LEAF = 1,     /* a leaf QL iteration did not converge (or opts.force_fail bit 0) */
+    PHDC_ERR_SECULAR = 2,  /* a secular root did not converge, or the secular function was NaN
+                              (or opts.force_fail bit 1) */
     PHDC_ERR_UNSORTED = 3, /* merge(): D1 or D2 not ascending */
-    PHDC_ERR_NONFINITE = 4 /* non-finite input */
+    PHDC_ERR_NONFINITE = 4 /* a NaN or Inf among the merge's poles, z or coupling, or found by the
+                              check_finite scan */
+};
+
+/* Host-side return code: a HIP runtime call made by the library failed. */
+#define PHDC_E_HIP (-100)
+
+/* Bits of phdc_opts.force_fail: test hooks that make a bounded device loop give
+ * up at once, so that the failure path runs without any fault or hang. */
+enum phdc_force_fail {
+    PHDC_FAIL_LEAF = 1,    /* leaf QL gets no iterations: PHDC_ERR_LEAF for any leaf that needs one */
+    PHDC_FAIL_SECULAR = 2, /* secular roots get no iterations: PHDC_ERR_SECULAR when a merge keeps K >= 2 */
+    PHDC_FAIL_HSS = 4      /* every HSS compression reports rank overflow, so each HSS merge takes
+                              the FP64 fall-back product (HSS rank -1 in the merge table) */
 };
 
 typedef struct phdc_opts {
@@ -67,7 +88,11 @@ typedef struct phdc_opts {
     int32_t split_slices;   /* number of BF16 slices per operand for PHDC_GEMM_SPLIT, 1..7 (default 7) */
     uint64_t seed;          /* seed of the counter-based Gaussian generator used by HSS sampling */
     int32_t canonical_sign; /* if nonzero: each eigenvector's largest-magnitude entry is made positive */
-    int32_t check_finite;   /* if nonzero: scan the inputs for NaN/Inf on the device */
+    int32_t check_finite;   /* if nonzero: scan the input arrays for NaN/Inf on the device first; the
+                               call waits for the scan and, on a hit, sets PHDC_ERR_NONFINITE, enqueues
+                               nothing else and returns -(index of the first such array argument).
+                               phdc_launch_prepared (graph capture: no waiting) only sets the status. */
+    int32_t force_fail;     /* test hook, bits of enum phdc_force_fail (default 0) */
 } phdc_opts;
 
 /* Fill *o with the defaults listed above. */
@@ -85,7 +110,7 @@ int phdc_version(void);
  *   Q       device, ldq*n doubles, output eigenvectors (column j for lambda[j])
  *   ldq     leading dimension of Q, ldq >= max(1, n)
  *   work    device workspace of lwork bytes (phdc_stedc_workspace), 256-byte aligned
- * Returns 0 or -(argument index). */
+ * Returns 0, -(argument index) or PHDC_E_HIP. */
 int phdc_stedc_workspace(int64_t n, const phdc_opts *o, size_t *bytes);
 int phdc_stedc(int64_t n, const double *d, const double *e, double *lambda, double *Q, int64_t ldq,
                void *work, size_t lwork, const phdc_opts *o, void *stream);
@@ -132,6 +157,8 @@ int phdc_stedc_batched(int64_t B, const int64_t *n_host, const int64_t *off_host
 int phdc_stedc_batched_prepare(int64_t B, const int64_t *n_host, const int64_t *off_host, const int64_t *qoff_host,
                                const double *d, const double *e, double *lambda, double *Q, void *work,
                                size_t lwork, const phdc_opts *o, void *stream);
+/* Returns 0, -1 if `work` holds no prepared plan (never prepared, or another
+ * solve, merge or phdc_release on `work` came after the prepare), or PHDC_E_HIP. */
 int phdc_launch_prepared(void *work, void *stream);
 
 /* ---------------------------------------------------------------- adjoint
@@ -149,21 +176,34 @@ int phdc_stedc_backward(int64_t n, int64_t batch, const double *lambda, const do
 
 /* ---------------------------------------------------------------- status
  * Waits for `stream`, then returns the device status word (enum phdc_info)
- * written by the last call that used `work`. */
+ * written by the last call that used `work`, or PHDC_E_HIP. */
 int phdc_status(const void *work, void *stream);
+
+/* Forget the host-side state the library keeps for `work` (the prepared plan
+ * of phdc_stedc_batched_prepare, and the pinned staging buffers and events of
+ * the plan upload and of the HSS path), freeing its pinned memory and events.
+ * Call it before freeing a workspace; a later call on the same address starts
+ * afresh.  Waits for uploads still in flight.  Returns 0, or -1 if work is NULL. */
+int phdc_release(void *work);
 
 /* After phdc_status(): statistics of the top-level merge of the last
  * stedc/merge call on `work` (8 int32, see phdc_merge). Returns 0 or -1. */
 int phdc_merge_stats(const void *work, int32_t *stats_host);
 
 /* ---------------------------------------------------------------- measurement
- * Opt-in timing: while enabled, every kernel class of a solve is bracketed by
- * HIP events on the launch stream (small overhead).  phdc_profile_read waits
- * for the recorded events, returns per-phase milliseconds and launch counts in
+ * Opt-in timing: while enabled, every launch of a solve is bracketed by HIP
+ * events on the launch stream (small overhead).  phdc_profile_read waits for
+ * the recorded events, returns per-phase milliseconds and launch counts in
  * ms[0:nphase], count[0:nphase] (phase order: leaf, deflate, rotate, secular,
  * loewner, uhat-norm, uhat-write, rank, gemm, copy, sign, split-slice,
  * split-gemm, hss-sample, hss-compress, hss-apply, adjoint-gemm, adjoint-band)
- * and forgets them.  Returns 0. */
+ * and forgets them.  A merge level runs some steps in one launch, timed under
+ * one phase: "secular" = rotations + secular roots (merges of at most 64 rows:
+ * also Loewner z, column norms, Uhat and output ranks); "loewner" = Loewner z +
+ * output ranks; "uhat-write" = column norms + Uhat + the deflated-column copy
+ * ("uhat-norm" when the norms run first, for normalized Uhat); "copy" = the
+ * deflated-column copy of a lone root merge (the caller's whole Q); "rotate"
+ * and "rank" are no longer recorded separately.  Returns 0. */
 int phdc_profile_enable(int on);
 int phdc_profile_read(double *ms, int64_t *count, int nphase);
 /* Restrict the recorded phases to the set bits of mask (bit i = phase i in the
@@ -174,7 +214,9 @@ int phdc_profile_select(uint32_t mask);
 /* Sizes of every merge of the last stedc/merge call on `work` (call after
  * phdc_status): up to max_rows rows of PHDC_MERGE_TABLE_COLS int32 each:
  * {m, n1, K, k1, k2, k3, type-1 deflations, type-2 deflations,
- *  path (0 FP64, 1 split, 2 HSS), HSS rank,
+ *  path (0 FP64, 1 split, 2 HSS), HSS rank (largest interpolative-decomposition
+ *  rank; -1 when the HSS compression gave up -- ranks beyond the largest
+ *  sample count, or opts.force_fail -- and the merge took the FP64 product),
  *  deflated columns nonzero in the Q1 rows only, in both halves, in the Q2 rows only,
  *  rows the deflated columns can be nonzero in, summed: low 32 bits (as unsigned), high bits,
  *  1 for the last merge of its matrix (which writes every row of its output) else 0}.
@@ -183,12 +225,38 @@ int phdc_profile_select(uint32_t mask);
 #define PHDC_MERGE_TABLE_COLS 16
 int phdc_merge_table(const void *work, int64_t max_rows, int32_t *table_host, int64_t *rows_out);
 
+/* ---------------------------------------------------------------- HSS product of a dense matrix
+ * The compression of the merge update (Sec. 2.2, Algorithm 1) applied to a
+ * general dense K x K matrix, as in the paper's Example 1 (Table 1): A is
+ * compressed into HSS form by randomized sampling and interpolative
+ * decompositions (tolerance opts.hss_rel_tol relative to each node's largest
+ * pivot, with an absolute floor of hss_rel_tol sqrt(d) ||A||_F / sqrt(K);
+ * leaves of opts.hss_leaf rows; opts.hss_samples samples, growing by
+ * opts.hss_samples_inc), then C = X A is formed in that form.
+ *   K      order of A, 1 <= K <= 2^30
+ *   A      device, K x K column-major, lda >= K, read only
+ *   m      rows of X and C, 1 <= m <= 2^30
+ *   X      device, m x K column-major, ldx >= m, read only
+ *   C      device, m x K column-major output, ldc >= m; must not overlap A or X
+ *   rank_host  host, may be NULL: the largest ID rank, or -1 when the compression
+ *          gave up (ranks beyond the largest sample count, or opts.force_fail
+ *          PHDC_FAIL_HSS) and C was formed by the dense FP64 MFMA product instead
+ *   work   device workspace of phdc_hss_gemm_workspace(K, m) bytes, 256-byte aligned
+ * Waits for the stream (the ID ranks of each tree level are read on the host).
+ * Returns 0, -(argument index) or PHDC_E_HIP.  Timing phases: hss-sample,
+ * hss-compress, hss-apply (also the dense product when the compression gave up). */
+int phdc_hss_gemm_workspace(int64_t K, int64_t m, const phdc_opts *o, size_t *bytes);
+int phdc_hss_gemm(int64_t K, const double *A, int64_t lda, int64_t m, const double *X, int64_t ldx, double *C,
+                  int64_t ldc, int32_t *rank_host, void *work, size_t lwork, const phdc_opts *o, void *stream);
+
 /* ---------------------------------------------------------------- secular roots
  * The K roots of f(lambda) = 1 + rho sum_i z_i^2/(d_i - lambda) (Sec. 1, after
  * Eq. (4)) for strictly ascending d, rho > 0 and nonzero z, one root per GPU
  * thread.  Root j is returned as origin pole org[j] (int32) and offset tau[j]
  * with lambda_j = d[org[j]] + tau[j].  All pointers are device pointers.
- * Non-convergence is reported through phdc_status(work). */
+ * Non-convergence is reported through phdc_status(work); the int32 after the
+ * status word in work receives the largest number of evaluations of the
+ * secular function spent on one root. */
 int phdc_secular(int64_t K, const double *d, const double *z, double rho, int32_t *org, double *tau,
                  void *work, size_t lwork, void *stream);
 
@@ -204,7 +272,7 @@ int phdc_secular(int64_t K, const double *d, const double *z, double rho, int32_
  *   work    device scratch of at least phdc_autotune_gemm_workspace(max_m) bytes
  *           (three max_m x max_m FP64 arrays and index arrays), 256-byte aligned
  * Synchronises the stream; not for use under graph capture.  Returns 0 or a
- * negative code (-1 bad size, -2 null work, -3 lwork too small, < -3 HIP error).
+ * negative code (-1 bad size, -2 null work, -3 lwork too small, PHDC_E_HIP).
  * phdc_gemm_tile_table copies the table (0 = not timed) into tiles[0:n) and
  * returns the number of buckets written. */
 int phdc_autotune_gemm_workspace(int64_t max_m, size_t *bytes);

@@ -19,8 +19,12 @@ GEMM_FP64 = 0
 GEMM_SPLIT = 1
 GEMM_HSS = 2
 
+STATUS_OK, STATUS_LEAF, STATUS_SECULAR, STATUS_UNSORTED, STATUS_NONFINITE = 0, 1, 2, 3, 4
 STATUS_TEXT = {0: "ok", 1: "leaf QL did not converge", 2: "secular root did not converge",
                3: "merge input D1/D2 not ascending", 4: "non-finite input"}
+E_HIP = -100  # host-side return code: a HIP runtime call failed
+# bits of Opts.force_fail (test hooks)
+FAIL_LEAF, FAIL_SECULAR, FAIL_HSS = 1, 2, 4
 
 
 class Opts(ctypes.Structure):
@@ -36,6 +40,7 @@ class Opts(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("canonical_sign", ctypes.c_int32),
         ("check_finite", ctypes.c_int32),
+        ("force_fail", ctypes.c_int32),
     ]
 
 
@@ -71,6 +76,7 @@ def load():
                                        _vp]
     lib.phdc_secular.argtypes = [_i64, _vp, _vp, ctypes.c_double, _vp, _vp, _vp, _sz, _vp]
     lib.phdc_status.argtypes = [_vp, _vp]
+    lib.phdc_release.argtypes = [_vp]
     lib.phdc_merge_stats.argtypes = [_vp, P(ctypes.c_int32)]
     lib.phdc_stedc_batched_prepare.argtypes = [_i64, P(_i64), P(_i64), P(_i64), _vp, _vp, _vp, _vp, _vp, _sz,
                                                P(Opts), _vp]
@@ -84,16 +90,19 @@ def load():
     lib.phdc_autotune_gemm_workspace.argtypes = [_i64, P(_sz)]
     lib.phdc_autotune_gemm.argtypes = [_i64, _vp, _sz, _vp]
     lib.phdc_gemm_tile_table.argtypes = [P(ctypes.c_int32), ctypes.c_int]
+    lib.phdc_hss_gemm_workspace.argtypes = [_i64, _i64, P(Opts), P(_sz)]
+    lib.phdc_hss_gemm.argtypes = [_i64, _vp, _i64, _i64, _vp, _i64, _vp, _i64, P(ctypes.c_int32), _vp, _sz, P(Opts),
+                                  _vp]
     _lib = lib
     return lib
 
 
 EXPORTS = ["phdc_stedc_batched_prepare", "phdc_launch_prepared", "phdc_opts_default", "phdc_version", "phdc_stedc_workspace", "phdc_stedc", "phdc_merge_workspace",
            "phdc_merge", "phdc_stedc_batched_workspace", "phdc_stedc_batched", "phdc_stedc_backward_workspace",
-           "phdc_stedc_backward", "phdc_status", "phdc_merge_stats", "phdc_secular", "phdc_merge_table",
+           "phdc_stedc_backward", "phdc_status", "phdc_release", "phdc_merge_stats", "phdc_secular", "phdc_merge_table",
            "phdc_profile_enable", "phdc_profile_read", "phdc_profile_select", "phdc_autotune_gemm_workspace",
            "phdc_autotune_gemm",
-           "phdc_gemm_tile_table"]
+           "phdc_gemm_tile_table", "phdc_hss_gemm_workspace", "phdc_hss_gemm"]
 
 
 def autotune_gemm(max_m: int = 4096, device="cuda", stream=None) -> list:
@@ -176,6 +185,11 @@ def workspace(nbytes: int, device) -> torch.Tensor:
 
 def status(work: torch.Tensor, stream=None) -> int:
     return load().phdc_status(_ptr(work), _stream(stream))
+
+
+def release(work: torch.Tensor) -> None:
+    """Drop the library's host-side state for this workspace (call before freeing it)."""
+    _check(load().phdc_release(_ptr(work)), "phdc_release")
 
 
 def merge_stats(work: torch.Tensor) -> list:
@@ -313,8 +327,30 @@ def stedc_batched(sizes, d, e, o: Opts | None = None, device="cuda", stream=None
     return out + (work,) if return_work else out
 
 
-def secular(d, z, rho, device="cuda", stream=None, check=True):
-    """Roots of 1 + rho sum z_i^2/(d_i - lambda) as (origin index int32, offset) device tensors."""
+def hss_gemm(A: torch.Tensor, X: torch.Tensor, o: Opts | None = None, stream=None, work=None):
+    """C = X A with the K x K matrix A compressed to HSS form (Algorithm 1), as in the
+    paper's Example 1.  A (K x K) and X (m x K) are float64 CUDA tensors in column-major
+    storage: pass them as transposed views of contiguous tensors (``A = At.t()``), or any
+    tensor with stride (1, ld).  Returns (C as an (m, K) column-major view, largest ID
+    rank or -1 if the dense product was used)."""
+    lib = load()
+    o = o or opts()
+    K, m = A.shape[0], X.shape[0]
+    assert A.shape == (K, K) and X.shape[1] == K and A.stride(0) == 1 and X.stride(0) == 1
+    Cs = torch.empty((K, m), dtype=torch.float64, device=A.device)
+    nb = ctypes.c_size_t()
+    _check(lib.phdc_hss_gemm_workspace(K, m, ctypes.byref(o), ctypes.byref(nb)), "phdc_hss_gemm_workspace")
+    if work is None or work.numel() < nb.value:
+        work = workspace(nb.value, A.device)
+    rank = ctypes.c_int32(0)
+    _check(lib.phdc_hss_gemm(K, _ptr(A), A.stride(1), m, _ptr(X), X.stride(1), _ptr(Cs), m, ctypes.byref(rank),
+                             _ptr(work), work.numel(), ctypes.byref(o), _stream(stream)), "phdc_hss_gemm")
+    return Cs.t(), rank.value
+
+
+def secular(d, z, rho, device="cuda", stream=None, check=True, return_iters=False):
+    """Roots of 1 + rho sum z_i^2/(d_i - lambda) as (origin index int32, offset) device tensors
+    (and, with return_iters, the largest number of secular-function evaluations of one root)."""
     lib = load()
     d = _dev_f64(d, device)
     z = _dev_f64(z, d.device)
@@ -326,6 +362,8 @@ def secular(d, z, rho, device="cuda", stream=None, check=True):
                             _stream(stream)), "phdc_secular")
     if check:
         _raise_status(work, stream)
+    if return_iters:
+        return org[:K], tau[:K], int(work[4:8].view(torch.int32).item())
     return org[:K], tau[:K]
 
 

@@ -136,7 +136,7 @@ Sizes sizes_of(const Tree& T, const std::vector<int64_t>& n, int64_t q_total, co
     for (auto& nd : T.merges)
       if (nd.m >= thr) mh = std::max<int64_t>(mh, nd.m);
     if (mh > 0) {
-      z.hss_arena = hss_arena_bytes(mh, mh, o->hss_leaf, hss_dmax(o));
+      z.hss_arena = hss_arena_bytes(mh, mh, o->hss_leaf, hss_dmax(o), true);
       z.hss_desc = (size_t)16 << 20;
     }
   }
@@ -214,22 +214,42 @@ SplitBufs split_of(char* base, const Layout& L) {
   return B;
 }
 
-// Pinned staging buffer for the plan upload, one per workspace pointer.  The
-// next call on the same workspace waits for the previous upload to finish
-// before reusing the buffer.
+// Pinned staging buffer for an upload.  The next upload through the same
+// buffer waits for the previous one to finish before reusing it.
 struct Staging {
   void* host = nullptr;
   size_t cap = 0;
   hipEvent_t done = nullptr;
   bool pending = false;
 };
-std::mutex g_mu;
-std::unordered_map<const void*, Staging> g_staging;
 
-int upload(const void* work, void* dst, const std::vector<char>& bytes, hipStream_t s) {
-  if (bytes.empty()) return 0;
-  std::lock_guard<std::mutex> lk(g_mu);
-  Staging& st = g_staging[work];
+// Pinned, device-mapped host memory for the counters the HSS path reads back
+// (LevelProbe), and the event that marks their arrival.
+struct Probe {
+  int32_t* host = nullptr;
+  int32_t* dev = nullptr;
+  size_t cap = 0;  // int32 values
+  hipEvent_t done = nullptr;
+};
+
+// Host-side state kept per workspace address: staging for the plan upload and
+// for the HSS descriptors, the HSS counter probe, and the prepared plan of
+// phdc_stedc_batched_prepare.  phdc_release frees it.
+struct WorkState {
+  Staging plan, hss;
+  Probe probe;
+};
+std::mutex g_mu;
+std::unordered_map<const void*, WorkState> g_state;
+
+void free_staging(Staging& st) {
+  if (st.pending) hipEventSynchronize(st.done);
+  if (st.host) hipHostFree(st.host);
+  if (st.done) hipEventDestroy(st.done);
+  st = Staging{};
+}
+
+int upload_through(Staging& st, void* dst, const std::vector<char>& bytes, hipStream_t s) {
   if (st.pending) {
     hipEventSynchronize(st.done);
     st.pending = false;
@@ -238,15 +258,22 @@ int upload(const void* work, void* dst, const std::vector<char>& bytes, hipStrea
     if (st.host) hipHostFree(st.host);
     st.host = nullptr;
     st.cap = 0;
-    if (hipHostMalloc(&st.host, bytes.size(), hipHostMallocDefault) != hipSuccess) return -1;
+    if (hipHostMalloc(&st.host, bytes.size(), hipHostMallocDefault) != hipSuccess) return PHDC_E_HIP;
     st.cap = bytes.size();
   }
-  if (!st.done && hipEventCreateWithFlags(&st.done, hipEventDisableTiming) != hipSuccess) return -1;
+  if (!st.done && hipEventCreateWithFlags(&st.done, hipEventDisableTiming) != hipSuccess) return PHDC_E_HIP;
   std::memcpy(st.host, bytes.data(), bytes.size());
-  if (hipMemcpyAsync(dst, st.host, bytes.size(), hipMemcpyHostToDevice, s) != hipSuccess) return -1;
-  hipEventRecord(st.done, s);
+  if (hipMemcpyAsync(dst, st.host, bytes.size(), hipMemcpyHostToDevice, s) != hipSuccess) return PHDC_E_HIP;
+  if (hipEventRecord(st.done, s) != hipSuccess) return PHDC_E_HIP;
   st.pending = true;
   return 0;
+}
+
+// Upload of a solve's plan through the workspace's staging buffer.
+int upload(const void* work, void* dst, const std::vector<char>& bytes, hipStream_t s) {
+  if (bytes.empty()) return 0;
+  std::lock_guard<std::mutex> lk(g_mu);
+  return upload_through(g_state[work].plan, dst, bytes, s);
 }
 
 template <class T>
@@ -281,6 +308,7 @@ Setup setup_for(const std::vector<int64_t>& n, int64_t q_total, const phdc_opts*
 struct Buffers {
   const double* d;
   const double* e;
+  int64_t nd = 0, ne = 0;  // entries of d and e over all matrices
   double* lam[2];
   double* q[2];
   RowRange* rng[2];                      // column ranges of q[0], q[1] (indexed like lam)
@@ -288,15 +316,6 @@ struct Buffers {
   std::vector<int64_t> ld[2];            // per matrix
 };
 
-// Pinned, device-mapped host memory per workspace for the counters the HSS
-// path reads back (LevelProbe), and the event that marks their arrival.
-struct Probe {
-  int32_t* host = nullptr;
-  int32_t* dev = nullptr;
-  size_t cap = 0;  // int32 values
-  hipEvent_t done = nullptr;
-};
-std::unordered_map<const void*, Probe> g_probe;
 
 // The level's merges that may take the HSS path (m >= hss_min_K), as the id
 // range [lo, hi] (ids of one level are consecutive).  False if there are none.
@@ -317,16 +336,17 @@ bool hss_candidates(const MergeDesc* hdescs, int nm, const phdc_opts* o, int32_t
 int make_probe(const void* work, const Scratch& S, int32_t lo, int32_t hi, LevelProbe* lp) {
   const size_t n = (size_t)(hi - lo + 1) * kCounters;
   std::lock_guard<std::mutex> lk(g_mu);
-  Probe& p = g_probe[work];
+  Probe& p = g_state[work].probe;
   if (p.cap < n) {
     if (p.host) hipHostFree(p.host);
     p.host = p.dev = nullptr;
     p.cap = 0;
-    if (hipHostMalloc((void**)&p.host, n * 4, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) return -1;
-    if (hipHostGetDevicePointer((void**)&p.dev, p.host, 0) != hipSuccess) return -1;
+    if (hipHostMalloc((void**)&p.host, n * 4, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
+      return PHDC_E_HIP;
+    if (hipHostGetDevicePointer((void**)&p.dev, p.host, 0) != hipSuccess) return PHDC_E_HIP;
     p.cap = n;
   }
-  if (!p.done && hipEventCreateWithFlags(&p.done, hipEventDisableTiming) != hipSuccess) return -1;
+  if (!p.done && hipEventCreateWithFlags(&p.done, hipEventDisableTiming) != hipSuccess) return PHDC_E_HIP;
   *lp = LevelProbe{S.counters + (int64_t)lo * kCounters, p.dev, (int32_t)n, p.done};
   return 0;
 }
@@ -335,28 +355,36 @@ int make_probe(const void* work, const Scratch& S, int32_t lo, int32_t hi, Level
 // path was chosen on the device.  The host needs K: with a probe it waits for
 // the counter copy made right after deflation (the rest of the level keeps the
 // GPU busy meanwhile); without one it copies the counters and synchronises.
-int run_hss_level(const MergeDesc* hdescs, int nm, const Scratch& S, char* arena, size_t arena_bytes, char* descarea,
-                  size_t desc_bytes, const phdc_opts* o, hipStream_t s, const void* work = nullptr,
-                  const LevelProbe* probe = nullptr) {
+// A merge whose compression gives up (ranks beyond the largest sample count,
+// an arena or descriptor area too small, or the PHDC_FAIL_HSS test hook) is
+// finished with the FP64 product instead (Sec. 2.2: Gu's GEMMs whenever HSS
+// does not apply).  ddev: the level's device descriptors (same order as hdescs).
+int run_hss_level(const MergeDesc* hdescs, const MergeDesc* ddev, int nm, const Scratch& S, char* arena,
+                  size_t arena_bytes, char* descarea, size_t desc_bytes, const phdc_opts* o, hipStream_t s,
+                  const void* work, const LevelProbe* probe = nullptr) {
   int32_t lo = 0, hi = 0;
   if (!hss_candidates(hdescs, nm, o, &lo, &hi)) return 0;
   std::vector<int32_t> c((size_t)(hi - lo + 1) * kCounters);
   if (probe) {
-    if (hipEventSynchronize(probe->done) != hipSuccess) return -111;
+    if (hipEventSynchronize(probe->done) != hipSuccess) return PHDC_E_HIP;
     std::lock_guard<std::mutex> lk(g_mu);
-    std::memcpy(c.data(), g_probe[work].host, c.size() * 4);
+    std::memcpy(c.data(), g_state[work].probe.host, c.size() * 4);
   } else if (hipMemcpyAsync(c.data(), S.counters + (int64_t)lo * kCounters, c.size() * 4, hipMemcpyDeviceToHost,
                             s) != hipSuccess ||
              hipStreamSynchronize(s) != hipSuccess) {
-    return -111;
+    return PHDC_E_HIP;
   }
   for (int i = 0; i < nm; ++i) {
     if (hdescs[i].m < hss_threshold(o)) continue;
     const int32_t* ci = c.data() + (size_t)(hdescs[i].id - lo) * kCounters;
     if (ci[C_PATH] != 2) continue;
     int rc = run_hss_merge(hdescs[i], ci[C_K], S, arena, arena_bytes, descarea, desc_bytes, o,
-                           S.counters + (int64_t)hdescs[i].id * kCounters, s);
-    if (rc != 0) return rc;
+                           S.counters + (int64_t)hdescs[i].id * kCounters, work, s);
+    if (rc == PHDC_E_HIP) return rc;
+    if (rc != 0) {
+      launch_fp64_fallback(ddev + i, hdescs[i], S, s);
+      if (hipGetLastError() != hipSuccess) return PHDC_E_HIP;
+    }
   }
   return 0;
 }
@@ -371,17 +399,31 @@ struct Prepared {
   std::vector<LevelMaps> lm;
   int nleaves = 0, nmat = 0, ncols = 0;
   phdc_opts o;
+  const double* d = nullptr;  // inputs, for the optional non-finite scan
+  const double* e = nullptr;
+  int64_t nd = 0, ne = 0;
 };
 std::mutex g_pm_mu;
 std::unordered_map<const void*, Prepared> g_prepared;
+
+void forget_prepared(const void* work) {
+  std::lock_guard<std::mutex> lk(g_pm_mu);
+  g_prepared.erase(work);
+}
+
+int leaf_iters(const phdc_opts* o) { return (o->force_fail & PHDC_FAIL_LEAF) ? 0 : kLeafMaxIters; }
 
 // Launch every kernel of a prepared solve: no host synchronisation, no memcpy,
 // no memset -- safe to capture in a HIP graph and replay.
 void launch_prepared_all(char* base, const Prepared& P, hipStream_t s) {
   launch_clear_status(P.S.status, s);
+  if (P.o.check_finite) {  // graph-safe: the scan only sets the status word
+    launch_scan_finite(P.d, P.nd, P.S.status + 1, P.S.status, s);
+    launch_scan_finite(P.e, P.ne, P.S.status + 2, P.S.status, s);
+  }
   {
     ProfScope p(PH_LEAF, s);
-    launch_leaf_ql((const LeafArgs*)(base + P.L.leaves), P.nleaves, P.S.status, P.o.leaf_size, s);
+    launch_leaf_ql((const LeafArgs*)(base + P.L.leaves), P.nleaves, P.S.status, P.o.leaf_size, leaf_iters(&P.o), s);
   }
   const MergeDesc* dd = (const MergeDesc*)(base + P.L.descs);
   for (int h = 1; h <= P.z.H; ++h) {
@@ -448,6 +490,7 @@ int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n,
     D.hss_min_k = hss_threshold(o);
     D.x_off = xoff[i];
     D.split_on = z.nsl > 0 ? 1 : 0;
+    D.flags = (o->force_fail & PHDC_FAIL_SECULAR) ? kFlagNoSecularIters : 0;
     D.rin = BF.rng[pin] + BF.off[b] + nd.r0;
     D.rout = BF.rng[pout] + BF.off[b] + nd.r0;
     D.r0 = (int32_t)nd.r0;
@@ -489,6 +532,10 @@ int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n,
     const int a = T.hstart[h - 1], e = T.hstart[h];
     for (int i = a; i < e; ++i) lm[h].maxm = std::max(lm[h].maxm, T.merges[i].m);
     lm[h].gemm_tile = (o->gemm_mode == PHDC_GEMM_SPLIT) ? 128 : gemm_tile_for(lm[h].maxm);
+    // Uhat keeps unit columns where something other than the FP64 GEMM reads it:
+    // the split-precision slicer, or the HSS sampling of a level with candidates
+    lm[h].uhat_normalized = o->gemm_mode == PHDC_GEMM_SPLIT || (hss_threshold(o) > 0 && lm[h].maxm >= hss_threshold(o));
+    lm[h].copy_alone = (e - a == 1) && T.merges[a].depth == 0;
     for (int k = 0; k < MAP_COUNT; ++k) {
       const size_t at = maps.size();
       int32_t acc = 0, first = -1;
@@ -520,24 +567,31 @@ int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n,
   P.nmat = (int)n.size();
   P.ncols = cpfx.back();
   P.o = *o;
+  P.d = BF.d;
+  P.e = BF.e;
+  P.nd = BF.nd;
+  P.ne = BF.ne;
   if (prepare_only) {
-    if (hipStreamSynchronize(s) != hipSuccess) return -100;
-    if (hipMemcpy(base + plan0, plan.data(), plan.size(), hipMemcpyHostToDevice) != hipSuccess) return -101;
+    if (hipStreamSynchronize(s) != hipSuccess) return PHDC_E_HIP;
+    if (hipMemcpy(base + plan0, plan.data(), plan.size(), hipMemcpyHostToDevice) != hipSuccess) return PHDC_E_HIP;
     std::lock_guard<std::mutex> lk(g_pm_mu);
     g_prepared[work] = P;
     return 0;
   }
+  forget_prepared(work);  // the plan on the device is about to change
+  P.o.check_finite = 0;   // the entry point has scanned the inputs already
   if (hss_threshold(o) <= 0) {
-    if (upload(work, base + plan0, plan, s) != 0) return -101;
+    if (upload(work, base + plan0, plan, s) != 0) return PHDC_E_HIP;
     launch_prepared_all(base, P, s);
-    return hipGetLastError() == hipSuccess ? 0 : -103;
+    return hipGetLastError() == hipSuccess ? 0 : PHDC_E_HIP;
   }
   // HSS: the host reads K back after each level that has eligible merges
   launch_clear_status(S.status, s);
-  if (upload(work, base + plan0, plan, s) != 0) return -101;
+  if (upload(work, base + plan0, plan, s) != 0) return PHDC_E_HIP;
   {
     ProfScope p(PH_LEAF, s);
-    launch_leaf_ql((const LeafArgs*)(base + L.leaves), (int)T.leaves.size(), S.status, o->leaf_size, s);
+    launch_leaf_ql((const LeafArgs*)(base + L.leaves), (int)T.leaves.size(), S.status, o->leaf_size, leaf_iters(o),
+                   s);
   }
   const MergeDesc* dd = (const MergeDesc*)(base + L.descs);
   for (int h = 1; h <= z.H; ++h) {
@@ -545,10 +599,10 @@ int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n,
     int32_t lo = 0, hi = 0;
     LevelProbe lp{};
     const bool cand = hss_candidates(descs.data() + a, e - a, o, &lo, &hi);
-    if (cand && make_probe(work, S, lo, hi, &lp) != 0) return -112;
+    if (cand && make_probe(work, S, lo, hi, &lp) != 0) return PHDC_E_HIP;
     launch_merge_level(dd + a, e - a, lm[h], S, o->gemm_mode, &SB, z.nsl, s, cand ? &lp : nullptr);
     if (!cand) continue;
-    int rc = run_hss_level(descs.data() + a, e - a, S, base + L.hss, L.hss_desc - L.hss, base + L.hss_desc,
+    int rc = run_hss_level(descs.data() + a, dd + a, e - a, S, base + L.hss, L.hss_desc - L.hss, base + L.hss_desc,
                            z.hss_desc, o, s, work, &lp);
     if (rc != 0) return rc;
   }
@@ -556,13 +610,30 @@ int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n,
     ProfScope p(PH_CANON, s);
     launch_canonical_sign(base + L.canon, (const int32_t*)(base + L.canon_pfx), (int)n.size(), cpfx.back(), s);
   }
-  return hipGetLastError() == hipSuccess ? 0 : -103;
+  return hipGetLastError() == hipSuccess ? 0 : PHDC_E_HIP;
+}
+
+// The optional input scan of an entry point: waits for it and returns the
+// 1-based index of the first array argument holding a NaN or Inf (0: none, or
+// PHDC_E_HIP).  On a hit the status word is PHDC_ERR_NONFINITE.
+int scan_inputs(int32_t* status, const double* a0, int64_t n0, int arg0, const double* a1, int64_t n1, int arg1,
+                hipStream_t s) {
+  launch_clear_status(status, s);
+  launch_scan_finite(a0, n0, status + 1, status, s);
+  launch_scan_finite(a1, n1, status + 2, status, s);
+  int32_t f[3] = {0, 0, 0};
+  if (hipMemcpyAsync(f, status, sizeof(f), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return PHDC_E_HIP;
+  return f[1] ? arg0 : f[2] ? arg1 : 0;
 }
 
 }  // namespace
 
-int hss_upload(const void* key, void* dst, const std::vector<char>& bytes, hipStream_t s) {
-  return upload(key, dst, bytes, s);
+int hss_upload(const void* work, void* dst, const std::vector<char>& bytes, hipStream_t s) {
+  if (bytes.empty()) return 0;
+  std::lock_guard<std::mutex> lk(g_mu);
+  return upload_through(g_state[work].hss, dst, bytes, s);
 }
 
 }  // namespace phdc
@@ -585,6 +656,7 @@ void phdc_opts_default(phdc_opts* o) {
   o->seed = 0x9e3779b97f4a7c15ULL;
   o->canonical_sign = 0;
   o->check_finite = 0;
+  o->force_fail = 0;
 }
 
 int phdc_version(void) { return 1; }
@@ -617,13 +689,20 @@ int phdc_stedc(int64_t n, const double* d, const double* e, double* lambda, doub
   if (lwork < SU.L.total) return -8;
   if (((uintptr_t)work & (kAlign - 1)) != 0) return -7;
   if (n == 0) {
+    forget_prepared(work);
     launch_clear_status((int32_t*)work, (hipStream_t)stream);
-    return 0;
+    return hipGetLastError() == hipSuccess ? 0 : PHDC_E_HIP;
+  }
+  if (o->check_finite) {
+    const int bad = scan_inputs((int32_t*)work, d, n, 2, e, n - 1, 3, (hipStream_t)stream);
+    if (bad != 0) return bad == PHDC_E_HIP ? bad : -bad;
   }
   char* base = (char*)work;
   Buffers BF;
   BF.d = d;
   BF.e = e;
+  BF.nd = n;
+  BF.ne = n - 1;
   BF.lam[0] = lambda;
   BF.lam[1] = (double*)(base + SU.L.ltwin);
   BF.q[0] = Q;
@@ -685,7 +764,25 @@ int phdc_launch_prepared(void* work, void* stream) {
     P = it->second;
   }
   launch_prepared_all((char*)work, P, (hipStream_t)stream);
-  return hipGetLastError() == hipSuccess ? 0 : -103;
+  return hipGetLastError() == hipSuccess ? 0 : PHDC_E_HIP;
+}
+
+int phdc_release(void* work) {
+  if (!work) return -1;
+  forget_prepared(work);
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_state.find(work);
+  if (it == g_state.end()) return 0;
+  WorkState& w = it->second;
+  free_staging(w.plan);
+  free_staging(w.hss);
+  if (w.probe.host) hipHostFree(w.probe.host);
+  if (w.probe.done) {
+    hipEventSynchronize(w.probe.done);
+    hipEventDestroy(w.probe.done);
+  }
+  g_state.erase(it);
+  return 0;
 }
 
 static int stedc_batched_impl(int64_t B, const int64_t* n_host, const int64_t* off_host, const int64_t* qoff_host,
@@ -718,13 +815,20 @@ static int stedc_batched_impl(int64_t B, const int64_t* n_host, const int64_t* o
   if (lwork < SU.L.total) return -10;
   if (((uintptr_t)work & (kAlign - 1)) != 0) return -9;
   if (acc == 0) {
+    forget_prepared(work);
     launch_clear_status((int32_t*)work, (hipStream_t)stream);
-    return 0;
+    return hipGetLastError() == hipSuccess ? 0 : PHDC_E_HIP;
+  }
+  if (o->check_finite && !prepare_only) {
+    const int bad = scan_inputs((int32_t*)work, d, acc, 5, e, etot, 6, (hipStream_t)stream);
+    if (bad != 0) return bad == PHDC_E_HIP ? bad : -bad;
   }
   char* base = (char*)work;
   Buffers BF;
   BF.d = d;
   BF.e = e;
+  BF.nd = acc;
+  BF.ne = etot;
   BF.lam[0] = lambda;
   BF.lam[1] = (double*)(base + SU.L.ltwin);
   BF.q[0] = Q;
@@ -799,17 +903,22 @@ int phdc_merge(int64_t n1, int64_t n2, const double* D, const double* z, double 
   if (((uintptr_t)work & (kAlign - 1)) != 0) return -13;
   hipStream_t s = (hipStream_t)stream;
   char* base = (char*)work;
+  forget_prepared(work);
   if (m == 0) {
     launch_clear_status((int32_t*)(base + L.status), s);
-    return 0;
+    return hipGetLastError() == hipSuccess ? 0 : PHDC_E_HIP;
+  }
+  if (o->check_finite) {
+    const int bad = scan_inputs((int32_t*)(base + L.status), D, m, 3, z, m, 4, s);
+    if (bad != 0) return bad == PHDC_E_HIP ? bad : -bad;
   }
   Scratch S = scratch_of(base, L, zs);
   double* qin = (double*)(base + L.qtwin);
   if (n1 > 0 && hipMemcpy2DAsync(qin, m * 8, Q1, ldq1 * 8, n1 * 8, n1, hipMemcpyDeviceToDevice, s) != hipSuccess)
-    return -100;
+    return PHDC_E_HIP;
   if (n2 > 0 && hipMemcpy2DAsync(qin + n1 + n1 * m, m * 8, Q2, ldq2 * 8, n2 * 8, n2, hipMemcpyDeviceToDevice, s) !=
                     hipSuccess)
-    return -100;
+    return PHDC_E_HIP;
   MergeDesc Dd;
   std::memset(&Dd, 0, sizeof(Dd));
   Dd.qin = qin;
@@ -830,6 +939,7 @@ int phdc_merge(int64_t n1, int64_t n2, const double* D, const double* z, double 
   Dd.hss_min_k = hss_threshold(o);
   Dd.x_off = 0;
   Dd.split_on = zs.nsl > 0 ? 1 : 0;
+  Dd.flags = (o->force_fail & PHDC_FAIL_SECULAR) ? kFlagNoSecularIters : 0;
   Dd.rin = nullptr;  // Q1 and Q2 fill their halves
   Dd.rout = nullptr;
   Dd.r0 = 0;
@@ -846,6 +956,8 @@ int phdc_merge(int64_t n1, int64_t n2, const double* D, const double* z, double 
   LevelMaps lm;
   lm.maxm = (int32_t)m;
   lm.gemm_tile = (o->gemm_mode == PHDC_GEMM_SPLIT) ? 128 : gemm_tile_for(m);
+  lm.uhat_normalized = o->gemm_mode == PHDC_GEMM_SPLIT || (hss_threshold(o) > 0 && m >= hss_threshold(o));
+  lm.copy_alone = true;
   for (int k = 0; k < MAP_COUNT; ++k) {
     lm.pfx[k] = (const int32_t*)(base + L.maps) + maps.size();
     lm.total[k] = map_blocks(k, (int)m, (int)n1, lm.gemm_tile, true);
@@ -855,15 +967,17 @@ int phdc_merge(int64_t n1, int64_t n2, const double* D, const double* z, double 
   }
   std::memcpy(plan.data() + (L.maps - L.hdr), maps.data(), maps.size() * 4);
   launch_clear_status(S.status, s);
-  if (upload(work, base + L.hdr, plan, s) != 0) return -101;
+  if (upload(work, base + L.hdr, plan, s) != 0) return PHDC_E_HIP;
   SplitBufs SB = split_of(base, L);
-  launch_merge_level((const MergeDesc*)(base + L.descs), 1, lm, S, o->gemm_mode, &SB, zs.nsl, s);
+  const MergeDesc* ddev = (const MergeDesc*)(base + L.descs);
+  launch_merge_level(ddev, 1, lm, S, o->gemm_mode, &SB, zs.nsl, s);
   {
-    int rc = run_hss_level(&Dd, 1, S, base + L.hss, L.hss_desc - L.hss, base + L.hss_desc, zs.hss_desc, o, s);
+    int rc = run_hss_level(&Dd, ddev, 1, S, base + L.hss, L.hss_desc - L.hss, base + L.hss_desc, zs.hss_desc, o, s,
+                           work);
     if (rc != 0) return rc;
   }
   if (o->canonical_sign) launch_canonical_sign(base + L.canon, (const int32_t*)(base + L.canon_pfx), 1, (int)m, s);
-  return hipGetLastError() == hipSuccess ? 0 : -103;
+  return hipGetLastError() == hipSuccess ? 0 : PHDC_E_HIP;
 }
 
 int phdc_secular(int64_t K, const double* d, const double* z, double rho, int32_t* org, double* tau, void* work,
@@ -879,14 +993,14 @@ int phdc_secular(int64_t K, const double* d, const double* z, double rho, int32_
   hipStream_t s = (hipStream_t)stream;
   launch_clear_status((int32_t*)work, s);
   launch_secular_standalone(K, d, z, rho, org, tau, (int32_t*)work, s);
-  return hipGetLastError() == hipSuccess ? 0 : -103;
+  return hipGetLastError() == hipSuccess ? 0 : PHDC_E_HIP;
 }
 
 int phdc_status(const void* work, void* stream) {
   if (!work) return -1;
-  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return -100;
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return PHDC_E_HIP;
   int32_t v = 0;
-  if (hipMemcpy(&v, work, 4, hipMemcpyDeviceToHost) != hipSuccess) return -101;
+  if (hipMemcpy(&v, work, 4, hipMemcpyDeviceToHost) != hipSuccess) return PHDC_E_HIP;
   return v;
 }
 

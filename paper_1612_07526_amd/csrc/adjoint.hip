@@ -100,7 +100,7 @@ int phdc_stedc_backward(int64_t n, int64_t batch, const double* lambda, const do
     hipLaunchKernelGGL(k_band, grid, dim3(256), 0, s, (int)n, Qb, nn, W, nn, lb, n, d_bar + b0 * n,
                        n > 1 ? e_bar + b0 * (n - 1) : e_bar);
   }
-  return hipGetLastError() == hipSuccess ? 0 : -103;
+  return hipGetLastError() == hipSuccess ? 0 : PHDC_E_HIP;
 }
 
 }  // extern "C"

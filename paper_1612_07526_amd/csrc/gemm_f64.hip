@@ -30,7 +30,7 @@ constexpr int GPAD = 4;       // LDS row padding (doubles)
 // quadrant of 16 x 16 MFMA blocks.  The k loop runs in the same order for
 // every tile size, so the result does not depend on GT.
 template <int GT>
-__global__ void __launch_bounds__(256) k_merge_gemm(BlockMap bm, Scratch S) {
+__global__ void __launch_bounds__(256) k_merge_gemm(BlockMap bm, Scratch S, int scale_cols) {
   constexpr int GLD = GT + GPAD;
   constexpr int E = GT * GK / 256;  // elements of A (and of B) each thread stages per k-step
   constexpr int WT = GT / 2;        // wave tile edge
@@ -83,21 +83,41 @@ __global__ void __launch_bounds__(256) k_merge_gemm(BlockMap bm, Scratch S) {
     const int lkc = t >> 4;          // k index this thread stages (A column / B row)
     const int l8 = (t & 15) * E;     // first of E consecutive rows (A) / columns (B)
     double ra[E], rb[E];
+    // Uhat written with unscaled columns: the B entries take their column's
+    // scale (the reciprocal norm of Uhat's column) as they are staged, which
+    // gives the bits of the normalized entries.  A thread stages the same E
+    // columns at every k-step.
+    double csc[E];
+  #pragma unroll
+    for (int e = 0; e < E; ++e)
+      csc[e] = (scale_cols && ncol0 + l8 + e < K) ? S.cnorm[M.s_off + ncol0 + l8 + e] : 1.0;
 
+    // The column index and row range of the A column a thread stages are read
+    // two k-steps ahead of its data (gidx), so the data load of a step waits on
+    // one memory latency, not on two dependent ones.
+    int nxc = 0;
+    RowRange nxg{0, 0};
+    auto gidx = [&](int kt) {
+      const int kk = kt * GK + lkc;
+      if (kk < kd) {
+        nxc = colA[kk];
+        nxg = rgA[kk];
+      }
+    };
     // Rows outside the staged A column's range are not loaded (they read as 0).
     auto gload = [&](int kt) {
       const int kk = kt * GK + lkc;
       if (kk < kd) {
         // The input block is global memory: say so, so that the loads are
         // global (not flat) ones and the waits can count them separately.
-        const gdouble_t* src = (const gdouble_t*)(A + (int64_t)colA[kk] * lda + mrow0 + l8);
-        const RowRange g = rgA[kk];
+        const gdouble_t* src = (const gdouble_t*)(A + (int64_t)nxc * lda + mrow0 + l8);
+        const RowRange g = nxg;
         const int lo = g.lo - (rowoff + mrow0 + l8), hi = min(g.hi - rowoff, Mrows) - (mrow0 + l8);
   #pragma unroll
         for (int e = 0; e < E; ++e) ra[e] = (e >= lo && e < hi) ? src[e] : 0.0;
         const double* bs = Bm + (int64_t)kk * K + ncol0 + l8;
   #pragma unroll
-        for (int e = 0; e < E; ++e) rb[e] = (ncol0 + l8 + e < K) ? bs[e] : 0.0;
+        for (int e = 0; e < E; ++e) rb[e] = (ncol0 + l8 + e < K) ? bs[e] * csc[e] : 0.0;
       } else {
   #pragma unroll
         for (int e = 0; e < E; ++e) { ra[e] = 0.0; rb[e] = 0.0; }
@@ -122,13 +142,16 @@ __global__ void __launch_bounds__(256) k_merge_gemm(BlockMap bm, Scratch S) {
 
     const int nkt = (kd + GK - 1) / GK;
     if (nkt > 0) {
+      gidx(0);
       gload(0);
+      if (nkt > 1) gidx(1);
       lstore(0);
     }
     __syncthreads();
     for (int kt = 0; kt < nkt; ++kt) {
       const int buf = kt & 1;
       if (kt + 1 < nkt) gload(kt + 1);
+      if (kt + 2 < nkt) gidx(kt + 2);
   #pragma unroll
       for (int ks = 0; ks < GK / 4; ++ks) {
         const int kr = ks * 4 + lk;
@@ -169,10 +192,11 @@ __global__ void __launch_bounds__(256) k_merge_gemm(BlockMap bm, Scratch S) {
   }
 }
 
-void launch_merge_gemm_f64(const BlockMap& bm, int total, const Scratch& S, int tile, hipStream_t s) {
+void launch_merge_gemm_f64(const BlockMap& bm, int total, const Scratch& S, int tile, bool scale_cols,
+                           hipStream_t s) {
   if (total <= 0) return;
-  if (tile == 64) hipLaunchKernelGGL(k_merge_gemm<64>, dim3(total), dim3(256), 0, s, bm, S);
-  else hipLaunchKernelGGL(k_merge_gemm<128>, dim3(total), dim3(256), 0, s, bm, S);
+  if (tile == 64) hipLaunchKernelGGL(k_merge_gemm<64>, dim3(total), dim3(256), 0, s, bm, S, scale_cols ? 1 : 0);
+  else hipLaunchKernelGGL(k_merge_gemm<128>, dim3(total), dim3(256), 0, s, bm, S, scale_cols ? 1 : 0);
 }
 
 // ------------------------------------------------------------ tile choice
@@ -263,7 +287,7 @@ int phdc_autotune_gemm(int64_t max_m, void* work, size_t lwork, void* stream) {
   MergeDesc* desc = (MergeDesc*)tail;
   int32_t* pfx = (int32_t*)(tail + 256);
   hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -4;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return PHDC_E_HIP;
   int rc = 0;
   for (int64_t m = 64; m <= max_m && rc == 0; m *= 2) {
     const int n1 = (int)(m / 2);
@@ -293,17 +317,17 @@ int phdc_autotune_gemm(int64_t max_m, void* work, size_t lwork, void* stream) {
       const int32_t hp[2] = {0, total};
       if (hipMemcpyAsync(desc, &D, sizeof(D), hipMemcpyHostToDevice, s) != hipSuccess ||
           hipMemcpyAsync(pfx, hp, sizeof(hp), hipMemcpyHostToDevice, s) != hipSuccess) {
-        rc = -5;
+        rc = PHDC_E_HIP;
         break;
       }
       BlockMap bm{desc, pfx, 1, 0};
-      launch_merge_gemm_f64(bm, total, S, gt, s);  // warm-up
+      launch_merge_gemm_f64(bm, total, S, gt, false, s);  // warm-up
       for (int r = 0; r < 3; ++r) {
         hipEventRecord(e0, s);
-        launch_merge_gemm_f64(bm, total, S, gt, s);
+        launch_merge_gemm_f64(bm, total, S, gt, false, s);
         hipEventRecord(e1, s);
         if (hipEventSynchronize(e1) != hipSuccess) {
-          rc = -6;
+          rc = PHDC_E_HIP;
           break;
         }
         float ms = 0.0f;
@@ -315,7 +339,7 @@ int phdc_autotune_gemm(int64_t max_m, void* work, size_t lwork, void* stream) {
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
-  if (rc == 0 && hipGetLastError() != hipSuccess) rc = -7;
+  if (rc == 0 && hipGetLastError() != hipSuccess) rc = PHDC_E_HIP;
   return rc;
 }
 

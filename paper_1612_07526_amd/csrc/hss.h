@@ -51,9 +51,32 @@ struct IdDesc {
   int32_t p, d;
 };
 
-size_t hss_arena_bytes(int64_t m, int64_t K, int leaf, int dmax);
+// Arena of one compression of a K x K matrix applied to m rows (with_x: plus
+// the m x K gathered operand of a merge).
+size_t hss_arena_bytes(int64_t m, int64_t K, int leaf, int dmax, bool with_x);
+
+// Where the entries of the matrix A being compressed come from: the Cauchy form
+// of a merge's Uhat (A == nullptr: A(i, j) = zh_i / ((ds_i - dorg_j) - tau_j) cn_j)
+// or a dense column-major matrix; `sample` is a dense copy of A for the
+// sampling products (row-major: it holds A^T column-major, ld lds).
+struct HssSource {
+  const double *ds, *zh, *dorg, *tau, *cn;
+  const double* A;
+  int64_t lda;
+  const double* sample;
+  int64_t lds;
+  bool sample_row_major;
+};
+int hss_core(const HssSource& src, int K, int m, const double* X, int64_t ldx, double* out, int64_t ldo,
+             const int32_t* cmap, char* arena, size_t arena_bytes, char* descarea, size_t desc_bytes,
+             const phdc_opts* o, double anorm, int32_t* rank_dev, const void* work, hipStream_t s);
+// One HSS merge, with K known on the host.  Returns 0, kHssGaveUp when the
+// compression cannot be completed (the caller then forms the FP64 product; no
+// part of the merge's output has been written), or PHDC_E_HIP.
+constexpr int kHssGaveUp = 1;
 int run_hss_merge(const MergeDesc& M, int K, const Scratch& S, char* arena, size_t arena_bytes, char* descarea,
-                  size_t desc_bytes, const phdc_opts* o, int32_t* counters_dev, hipStream_t s);
-int hss_upload(const void* key, void* dst, const std::vector<char>& bytes, hipStream_t s);
+                  size_t desc_bytes, const phdc_opts* o, int32_t* counters_dev, const void* work, hipStream_t s);
+// Upload of HSS descriptors through the workspace's own pinned staging buffer.
+int hss_upload(const void* work, void* dst, const std::vector<char>& bytes, hipStream_t s);
 
 }  // namespace phdc

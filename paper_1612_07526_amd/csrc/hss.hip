@@ -74,17 +74,19 @@ __global__ void __launch_bounds__(256) k_gather_x(const double* __restrict__ qin
   X[r + (int64_t)k * m] = (r >= g.lo && r < g.hi) ? qin[r + (int64_t)c * ldin] : 0.0;
 }
 
-// Entries of Uhat evaluated from the secular solution with the same arithmetic
-// as the dense writer: zhat_i / ((d_i - dorg_j) - tau_j) * cnorm_j.
+// Entries of the compressed matrix: either Uhat evaluated from the secular
+// solution with the same arithmetic as the dense writer, zhat_i / ((d_i -
+// dorg_j) - tau_j) * cnorm_j, or (A != nullptr) a dense column-major matrix.
 __global__ void __launch_bounds__(256) k_ugather(const UGather* __restrict__ g, const double* __restrict__ ds,
                                                  const double* __restrict__ zh, const double* __restrict__ dorg,
-                                                 const double* __restrict__ tau, const double* __restrict__ cn) {
+                                                 const double* __restrict__ tau, const double* __restrict__ cn,
+                                                 const double* __restrict__ A, int64_t lda) {
   const UGather G = g[blockIdx.x];
   for (int e = threadIdx.x; e < G.nr * G.nc; e += 256) {
     const int a = e % G.nr, b = e / G.nr;
     const int i = G.ri ? G.ri[a] : G.r0 + a;
     const int j = G.cj ? G.cj[b] : G.c0 + b;
-    G.out[a + (int64_t)b * G.ld] = zh[i] / ((ds[i] - dorg[j]) - tau[j]) * cn[j];
+    G.out[a + (int64_t)b * G.ld] = A ? A[i + (int64_t)j * lda] : zh[i] / ((ds[i] - dorg[j]) - tau[j]) * cn[j];
   }
 }
 
@@ -352,9 +354,10 @@ struct Stage {
     std::memcpy(host.data() + at, v.data(), v.size() * sizeof(T));
     return (const T*)(dev + at);
   }
+  // 0, kHssGaveUp (descriptor area too small) or PHDC_E_HIP
   int flush(const void* key, hipStream_t s) {
     if (host.empty()) return 0;
-    if (host.size() > cap) return -1;
+    if (host.size() > cap) return kHssGaveUp;
     int rc = hss_upload(key, dev, host, s);
     host.clear();
     return rc;
@@ -384,14 +387,14 @@ VGemm mk(const double* A, int64_t lda, int ta, const double* B, int64_t ldb, int
 
 }  // namespace
 
-size_t hss_arena_bytes(int64_t m, int64_t K, int leaf, int dmax) {
+size_t hss_arena_bytes(int64_t m, int64_t K, int leaf, int dmax, bool with_x) {
   if (K <= 0 || m <= 0) return 0;
   std::vector<HNode> T;
   build_hss_tree(T, 0, (int)K, std::max(8, leaf), 0);
   const int64_t pmax = std::max<int64_t>(std::max(8, leaf), 2 * (int64_t)dmax);
   size_t b = 0;
   auto take = [&](int64_t bytes) { b += ((size_t)bytes + 255) / 256 * 256; };
-  take(m * K * 8);
+  if (with_x) take(m * K * 8);
   for (int q = 0; q < 4; ++q) take(K * dmax * 8);
   take((int64_t)(2 * T.size() + 2) * 4);
   for (auto& h : T) {
@@ -407,26 +410,30 @@ size_t hss_arena_bytes(int64_t m, int64_t K, int leaf, int dmax) {
   return b + 4096;
 }
 
-// One HSS merge; called with K known on the host.  Returns 0 or a negative code.
-int run_hss_merge(const MergeDesc& M, int K, const Scratch& S, char* arena, size_t arena_bytes, char* descarea,
-                  size_t desc_bytes, const phdc_opts* o, int32_t* counters_dev, hipStream_t s) {
-  const int m = M.m;
+__global__ void k_set_int(int32_t* dst, int32_t v) { *dst = v; }
+
+// Compression of the K x K matrix of `src` (Algorithm 1) and the product
+// out(:, cmap[j]) = (X A)(:, j) in HSS form (X: m x K, ld ldx; cmap == nullptr:
+// column j at out + j ldo).  anorm scales the absolute floor of the ID
+// truncation (||A||_2, or an estimate of it).  The largest ID rank goes to
+// *rank_dev (device, may be null).  Returns 0, kHssGaveUp or PHDC_E_HIP.
+int hss_core(const HssSource& src, int K, int m, const double* X, int64_t ldx, double* out, int64_t ldo,
+             const int32_t* cmap, char* arena, size_t arena_bytes, char* descarea, size_t desc_bytes,
+             const phdc_opts* o, double anorm, int32_t* rank_dev, const void* work, hipStream_t s) {
   const int leaf = std::max(8, o->hss_leaf);
   const int dmax = std::min(512, std::max(16, o->hss_samples) + 2 * std::max(16, o->hss_samples_inc));
   int d = std::min(std::max(16, o->hss_samples), 512);
-  const int64_t so = M.s_off;
-  const double* ds = S.ds + so;
-  const double* zh = S.zhat + so;
-  const double* dorg = S.dorg + so;
-  const double* tau = S.tau + so;
-  const double* cn = S.cnorm + so;
-  const double* Shat = S.uhat + M.u_off;  // row-major K x K: Uhat(i, j) at i K + j
+  const double* ds = src.ds;
+  const double* zh = src.zh;
+  const double* dorg = src.dorg;
+  const double* tau = src.tau;
+  const double* cn = src.cn;
   std::vector<HNode> T;
   build_hss_tree(T, 0, K, leaf, 0);
   const int nn = (int)T.size();
   int maxlevel = 0;
   for (auto& h : T) maxlevel = std::max(maxlevel, h.level);
-  const void* key = arena;
+  const void* key = work;
 
   for (int attempt = 0; attempt < 3; ++attempt) {
     const int pmax = std::max(leaf, 2 * dmax);
@@ -441,7 +448,6 @@ int run_hss_merge(const MergeDesc& M, int K, const Scratch& S, char* arena, size
       off += ((size_t)count * 4 + 255) / 256 * 256;
       return p;
     };
-    double* X = dtake((int64_t)m * K);
     double* Om1 = dtake((int64_t)K * dmax);
     double* Om2 = dtake((int64_t)K * dmax);
     double* Y = dtake((int64_t)K * dmax);
@@ -476,23 +482,22 @@ int run_hss_merge(const MergeDesc& M, int K, const Scratch& S, char* arena, size
       stI[i] = itake(2 * dmax);
       stJ[i] = itake(2 * dmax);
     }
-    if (off > arena_bytes) return -200;
+    if (off > arena_bytes) return kHssGaveUp;
     Stage st{descarea, desc_bytes, {}};
 
     {
       ProfScope ps(PH_HSS_SAMPLE, s);
-      hipLaunchKernelGGL(k_gather_x, dim3((m + 255) / 256, K), dim3(256), 0, s, M.qin, M.ldin, m, K,
-                         S.csort + so, S.crng + so, X);
       const int64_t cnt = (int64_t)K * d;
       const uint64_t sd = o->seed + 0x9e3779b97f4a7c15ULL * (uint64_t)(attempt + 1);
       hipLaunchKernelGGL(k_gauss, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, cnt, sd, Om1);
       hipLaunchKernelGGL(k_gauss, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, cnt, sd ^ 0x5bd1e9955bd1e995ULL,
                          Om2);
-      // Shat read column-major (ld K) is Uhat^T: Y = Uhat Omega1, Z = Uhat^T Omega2
-      GemmArgs gy{Shat, Om1, K, K, 0, 0, K, d, K, 0};
-      gemm_f64(true, false, gy, 1, Y, K, 0, s);
-      GemmArgs gz{Shat, Om2, K, K, 0, 0, K, d, K, 0};
-      gemm_f64(false, false, gz, 1, Z, K, 0, s);
+      // Y = A Omega1, Z = A^T Omega2; a row-major A read column-major is A^T
+      const bool rm = src.sample_row_major;
+      GemmArgs gy{src.sample, Om1, src.lds, K, 0, 0, K, d, K, 0};
+      gemm_f64(rm, false, gy, 1, Y, K, 0, s);
+      GemmArgs gz{src.sample, Om2, src.lds, K, 0, 0, K, d, K, 0};
+      gemm_f64(!rm, false, gz, 1, Z, K, 0, s);
     }
 
     std::vector<int32_t> hr(2 * nn + 2, 0), hp(2 * nn + 2, 0);
@@ -540,8 +545,10 @@ int run_hss_merge(const MergeDesc& M, int K, const Scratch& S, char* arena, size
         const RowCopy* drc = st.push(rc);
         const VGemm* dg1 = st.push(g1.g);
         const int32_t* dp1 = st.push(g1.pf);
-        if (st.flush(key, s)) return -201;
-        if (dug) hipLaunchKernelGGL(k_ugather, dim3((unsigned)ug.size()), dim3(256), 0, s, dug, ds, zh, dorg, tau, cn);
+        if (int rc = st.flush(key, s)) return rc;
+        if (dug)
+          hipLaunchKernelGGL(k_ugather, dim3((unsigned)ug.size()), dim3(256), 0, s, dug, ds, zh, dorg, tau, cn, src.A,
+                             src.lda);
         if (root_only) break;
         if (drc) hipLaunchKernelGGL(k_rows, dim3((unsigned)rc.size()), dim3(256), 0, s, drc);
         if (dg1) vgemm_launch(dg1, dp1, (int)g1.g.size(), g1.pf.back(), s);
@@ -566,12 +573,12 @@ int run_hss_merge(const MergeDesc& M, int K, const Scratch& S, char* arena, size
         const VGemm* dg2 = st.push(g2.g);
         const int32_t* dp2 = st.push(g2.pf);
         const IdDesc* did = st.push(idd);
-        if (st.flush(key, s)) return -202;
+        if (int rc = st.flush(key, s)) return rc;
         if (dg2) vgemm_launch(dg2, dp2, (int)g2.g.size(), g2.pf.back(), s);
         hipLaunchKernelGGL(k_row_id, dim3((unsigned)idd.size()), dim3(kIdThreads), 0, s, did, o->hss_rel_tol,
-                           o->hss_rel_tol * std::sqrt((double)d));
-        if (hipMemcpyAsync(hr.data(), ranks, hr.size() * 4, hipMemcpyDeviceToHost, s) != hipSuccess) return -203;
-        if (hipStreamSynchronize(s) != hipSuccess) return -204;
+                           o->hss_rel_tol * std::sqrt((double)d) * anorm);
+        if (hipMemcpyAsync(hr.data(), ranks, hr.size() * 4, hipMemcpyDeviceToHost, s) != hipSuccess) return PHDC_E_HIP;
+        if (hipStreamSynchronize(s) != hipSuccess) return PHDC_E_HIP;
         for (int i : nodes) {
           maxrank = std::max(maxrank, std::max(hr[2 * i], hr[2 * i + 1]));
           if ((hr[2 * i] >= d - 8 && hr[2 * i] < hp[2 * i]) || (hr[2 * i + 1] >= d - 8 && hr[2 * i + 1] < hp[2 * i + 1]))
@@ -615,7 +622,7 @@ int run_hss_merge(const MergeDesc& M, int K, const Scratch& S, char* arena, size
         const int32_t* dp3 = st.push(g3.pf);
         const VGemm* dg4 = st.push(g4.g);
         const int32_t* dp4 = st.push(g4.pf);
-        if (st.flush(key, s)) return -205;
+        if (int rc = st.flush(key, s)) return rc;
         hipLaunchKernelGGL(k_rows, dim3((unsigned)rs.size()), dim3(256), 0, s, drs);
         if (dic) hipLaunchKernelGGL(k_ints, dim3((unsigned)ic.size()), dim3(256), 0, s, dic);
         hipLaunchKernelGGL(k_skel, dim3((unsigned)sk.size()), dim3(256), 0, s, dsk);
@@ -624,22 +631,17 @@ int run_hss_merge(const MergeDesc& M, int K, const Scratch& S, char* arena, size
       }
     }
     if (too_large) {
-      if (d >= dmax || attempt == 2) return -206;
+      if (d >= dmax || attempt == 2) return kHssGaveUp;
       d = std::min(dmax, d + std::max(16, o->hss_samples_inc));  // adaptive sampling: more columns, start over
       continue;
     }
-    {
-      static thread_local int32_t mr;
-      mr = maxrank;
-      hipMemcpyAsync(counters_dev + C_HSSRANK, &mr, 4, hipMemcpyHostToDevice, s);
-      hipStreamSynchronize(s);
-    }
+    if (rank_dev) hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, rank_dev, (int32_t)maxrank);
 
-    // ------------------------------------------------------------ apply U = X Uhat
+    // ------------------------------------------------------------ apply out = X A
     ProfScope pa(PH_HSS_APPLY, s);
-    const int32_t* dest = S.dest + so;
-    double* out = M.qout;
-    const int64_t ldo = M.ldout;
+    // columns t_i of the result: cmap + lo (mapped) or out + lo ldo (plain)
+    auto ocols = [&](int lo) { return cmap ? out : out + (int64_t)lo * ldo; };
+    auto omap = [&](int lo) { return cmap ? cmap + lo : (const int32_t*)nullptr; };
     std::vector<VBatch> stages;
     {
       VBatch g;
@@ -647,8 +649,8 @@ int run_hss_merge(const MergeDesc& M, int K, const Scratch& S, char* arena, size
         const HNode& h = T[i];
         if (!h.leaf) continue;
         const int p = h.hi - h.lo, r = hr[2 * i];
-        if (nn > 1) g.add(mk(X + (int64_t)h.lo * m, m, 0, Ub[i], p, 0, Xh[i], m, m, r, p, 1.0, 0.0));
-        g.add(mk(X + (int64_t)h.lo * m, m, 0, Dl[i], p, 0, out, ldo, m, p, p, 1.0, 0.0, dest + h.lo));
+        if (nn > 1) g.add(mk(X + (int64_t)h.lo * ldx, ldx, 0, Ub[i], p, 0, Xh[i], m, m, r, p, 1.0, 0.0));
+        g.add(mk(X + (int64_t)h.lo * ldx, ldx, 0, Dl[i], p, 0, ocols(h.lo), ldo, m, p, p, 1.0, 0.0, omap(h.lo)));
       }
       stages.push_back(g);
     }
@@ -693,19 +695,173 @@ int run_hss_merge(const MergeDesc& M, int K, const Scratch& S, char* arena, size
         const HNode& h = T[i];
         if (!h.leaf) continue;
         const int p = h.hi - h.lo, c = hr[2 * i + 1];
-        if (c) g.add(mk(Yh[i], m, 0, Vb[i], p, 1, out, ldo, m, p, c, 1.0, 1.0, dest + h.lo));
+        if (c) g.add(mk(Yh[i], m, 0, Vb[i], p, 1, ocols(h.lo), ldo, m, p, c, 1.0, 1.0, omap(h.lo)));
       }
       stages.push_back(g);
     }
     std::vector<std::pair<const VGemm*, const int32_t*>> dptr;
     for (auto& g : stages) dptr.emplace_back(st.push(g.g), st.push(g.pf));
-    if (st.flush(key, s)) return -207;
+    if (int rc = st.flush(key, s)) return rc;
     for (size_t q = 0; q < stages.size(); ++q)
       if (!stages[q].g.empty())
         vgemm_launch(dptr[q].first, dptr[q].second, (int)stages[q].g.size(), stages[q].pf.back(), s);
     return 0;
   }
-  return -208;
+  return kHssGaveUp;
+}
+
+// One HSS merge, with K known on the host: X = the merge's input columns of the
+// survivors in pole order (rows outside a column's range as 0), A = Uhat
+// (normalized, pole order; ||Uhat||_2 = 1), result columns at dest.
+int run_hss_merge(const MergeDesc& M, int K, const Scratch& S, char* arena, size_t arena_bytes, char* descarea,
+                  size_t desc_bytes, const phdc_opts* o, int32_t* counters_dev, const void* work, hipStream_t s) {
+  if (o->force_fail & PHDC_FAIL_HSS) return kHssGaveUp;
+  const int m = M.m;
+  const int64_t so = M.s_off;
+  const size_t xb = ((size_t)m * K * 8 + 255) / 256 * 256;
+  if (xb > arena_bytes) return kHssGaveUp;
+  double* X = (double*)arena;
+  {
+    ProfScope ps(PH_HSS_SAMPLE, s);
+    hipLaunchKernelGGL(k_gather_x, dim3((m + 255) / 256, K), dim3(256), 0, s, M.qin, M.ldin, m, K, S.csort + so,
+                       S.crng + so, X);
+  }
+  HssSource src{};
+  src.ds = S.ds + so;
+  src.zh = S.zhat + so;
+  src.dorg = S.dorg + so;
+  src.tau = S.tau + so;
+  src.cn = S.cnorm + so;
+  src.A = nullptr;
+  src.sample = S.uhat + M.u_off;  // row-major K x K: Uhat(i, j) at i K + j
+  src.lds = K;
+  src.sample_row_major = true;
+  return hss_core(src, K, m, X, m, M.qout, M.ldout, S.dest + so, arena + xb, arena_bytes - xb, descarea, desc_bytes,
+                  o, 1.0, counters_dev + C_HSSRANK, work, s);
 }
 
 }  // namespace phdc
+
+// ------------------------------------------------------------ dense matrices (Example 1)
+namespace phdc {
+namespace {
+
+// Squares of column j summed by block j (fixed order: deterministic).
+__global__ void __launch_bounds__(256) k_colsq(const double* __restrict__ A, int64_t lda, int K, double* colsq) {
+  __shared__ double sh[4];
+  const double* a = A + (int64_t)blockIdx.x * lda;
+  double v = 0.0;
+  for (int i = threadIdx.x; i < K; i += 256) v += a[i] * a[i];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) colsq[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+__global__ void k_sum_seq(const double* __restrict__ x, int n, double* out) {
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += x[i];
+  *out = s;
+}
+
+constexpr size_t kHssDescBytes = (size_t)16 << 20;
+
+struct DenseLayout {
+  size_t status, colsq, desc, arena, total;
+};
+
+DenseLayout dense_layout(int64_t K, int64_t m, const phdc_opts* o) {
+  DenseLayout L;
+  size_t p = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = p;
+    p = (p + std::max<size_t>(bytes, 1) + 255) / 256 * 256;
+    return at;
+  };
+  const int dmax = std::min(512, std::max(16, o->hss_samples) + 2 * std::max(16, o->hss_samples_inc));
+  L.status = take(256);
+  L.colsq = take((size_t)(K + 1) * 8);
+  L.desc = take(kHssDescBytes);
+  L.arena = take(hss_arena_bytes(m, K, o->hss_leaf, dmax, false));
+  L.total = p;
+  return L;
+}
+
+bool hss_opts_ok(const phdc_opts* o) {
+  return o->hss_leaf >= 8 && o->hss_leaf <= kHssLeafMax && o->hss_samples >= 16 && o->hss_samples <= 512 &&
+         o->hss_samples_inc >= 0 && o->hss_rel_tol > 0.0 && o->hss_rel_tol < 1.0;
+}
+
+}  // namespace
+}  // namespace phdc
+
+using namespace phdc;
+
+extern "C" {
+
+int phdc_hss_gemm_workspace(int64_t K, int64_t m, const phdc_opts* o, size_t* bytes) {
+  phdc_opts def;
+  if (!o) { phdc_opts_default(&def); o = &def; }
+  if (K < 1 || K > (1 << 30)) return -1;
+  if (m < 1 || m > (1 << 30)) return -2;
+  if (!hss_opts_ok(o)) return -3;
+  if (!bytes) return -4;
+  *bytes = dense_layout(K, m, o).total;
+  return 0;
+}
+
+int phdc_hss_gemm(int64_t K, const double* A, int64_t lda, int64_t m, const double* X, int64_t ldx, double* C,
+                  int64_t ldc, int32_t* rank_host, void* work, size_t lwork, const phdc_opts* o, void* stream) {
+  phdc_opts def;
+  if (!o) { phdc_opts_default(&def); o = &def; }
+  if (K < 1 || K > (1 << 30)) return -1;
+  if (!A) return -2;
+  if (lda < K) return -3;
+  if (m < 1 || m > (1 << 30)) return -4;
+  if (!X) return -5;
+  if (ldx < m) return -6;
+  if (!C) return -7;
+  if (ldc < m) return -8;
+  if (!work || ((uintptr_t)work & 255) != 0) return -10;
+  if (!hss_opts_ok(o)) return -12;
+  const DenseLayout L = dense_layout(K, m, o);
+  if (lwork < L.total) return -11;
+  hipStream_t s = (hipStream_t)stream;
+  char* base = (char*)work;
+  int32_t* status = (int32_t*)(base + L.status);
+  double* colsq = (double*)(base + L.colsq);
+  launch_clear_status(status, s);
+  // ||A||_F / sqrt(K) (= 1 for an orthogonal A) scales the truncation floor
+  hipLaunchKernelGGL(k_colsq, dim3((unsigned)K), dim3(256), 0, s, A, lda, (int)K, colsq);
+  hipLaunchKernelGGL(k_sum_seq, dim3(1), dim3(64), 0, s, colsq, (int)K, colsq + K);
+  double fro2 = 0.0;
+  if (hipMemcpyAsync(&fro2, colsq + K, 8, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+    return PHDC_E_HIP;
+  const double anorm = std::sqrt(fro2 / (double)K);
+  HssSource src{};
+  src.A = A;
+  src.lda = lda;
+  src.sample = A;
+  src.lds = lda;
+  src.sample_row_major = false;
+  int32_t* rank_dev = status + 8;
+  int rc = (o->force_fail & PHDC_FAIL_HSS)
+               ? kHssGaveUp
+               : hss_core(src, (int)K, (int)m, X, ldx, C, ldc, nullptr, base + L.arena, L.total - L.arena,
+                          base + L.desc, kHssDescBytes, o, anorm, rank_dev, work, s);
+  if (rc == PHDC_E_HIP) return rc;
+  int32_t rank = -1;
+  if (rc == 0) {
+    if (hipMemcpyAsync(&rank, rank_dev, 4, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+      return PHDC_E_HIP;
+  } else {  // the compression gave up: dense FP64 product
+    ProfScope pa(PH_HSS_APPLY, s);
+    GemmArgs g{X, A, ldx, lda, 0, 0, (int32_t)m, (int32_t)K, (int32_t)K, 0};
+    gemm_f64(false, false, g, 1, C, ldc, 0, s);
+  }
+  if (rank_host) *rank_host = rank;
+  return hipGetLastError() == hipSuccess ? 0 : PHDC_E_HIP;
+}
+
+}  // extern "C"

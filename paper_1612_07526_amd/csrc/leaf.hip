@@ -28,7 +28,7 @@ __device__ inline double lane_get(double v, int lane) {
 }
 
 __device__ inline double lane_put(double old, double v, int lane) {
-  return (int)threadIdx.x == lane ? v : old;
+  return (int)(threadIdx.x & 63) == lane ? v : old;
 }
 
 // sqrt(a^2 + b^2); the plain form is exact to rounding inside [1e-150, 1e150],
@@ -67,13 +67,22 @@ __device__ inline double rotation(double f, double g, double* c, double* s) {
 
 }  // namespace
 
-// Z is ls x ls in dynamic LDS (ls = the largest leaf of the launch), so small
-// leaves leave room for more blocks per CU.
-__global__ void __launch_bounds__(64) k_leaf_ql(const LeafArgs* __restrict__ leaves, int32_t* status, int ls) {
-  HIP_DYNAMIC_SHARED(double, Z)
-  const LeafArgs L = leaves[blockIdx.x];
+// Each wavefront of a block solves one leaf; a block holds kLeavesPerBlock of
+// them, so that the waves of a launch spread over the SIMDs of every CU (one
+// 64-thread block per leaf stacks several waves on one SIMD).  Z is ls x ls in
+// dynamic LDS per wave (ls = the largest leaf of the launch).
+constexpr int kLeavesPerBlock = 4;
+
+__global__ void __launch_bounds__(64 * kLeavesPerBlock) k_leaf_ql(const LeafArgs* __restrict__ leaves, int nleaves,
+                                                                   int32_t* status, int ls, int maxit) {
+  HIP_DYNAMIC_SHARED(double, Zall)
+  const int wv = threadIdx.x >> 6;
+  const int li = blockIdx.x * kLeavesPerBlock + wv;
+  if (li >= nleaves) return;  // whole wave: no barrier below
+  double* Z = Zall + (size_t)wv * ls * ls;
+  const LeafArgs L = leaves[li];
   const int s = L.s;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x & 63;
   if (s <= 0 || s > ls) return;
   const bool row = t < s;  // lane t owns row t of Z
   if (row)
@@ -97,7 +106,7 @@ __global__ void __launch_bounds__(64) k_leaf_ql(const LeafArgs* __restrict__ lea
       const bool split = t >= l && t < s && (t == s - 1 || fabs(e) <= kUnitRoundoff * (fabs(d) + fabs(dn)));
       const int mm = __ffsll((unsigned long long)__ballot(split)) - 1;
       if (mm == l) break;
-      if (++iter > 64) {
+      if (++iter > maxit) {
         failed = true;
         break;
       }
@@ -165,10 +174,12 @@ __global__ void __launch_bounds__(64) k_leaf_ql(const LeafArgs* __restrict__ lea
   if (row && L.rng) L.rng[t] = RowRange{L.r0, L.r0 + s};  // every column spans the leaf's rows
 }
 
-void launch_leaf_ql(const LeafArgs* leaves, int nleaves, int32_t* status, int max_leaf, hipStream_t s) {
+void launch_leaf_ql(const LeafArgs* leaves, int nleaves, int32_t* status, int max_leaf, int maxit, hipStream_t s) {
   if (nleaves <= 0) return;
   const int ls = std::max(1, std::min(max_leaf, kMaxLeaf));
-  hipLaunchKernelGGL(k_leaf_ql, dim3(nleaves), dim3(64), (size_t)ls * ls * sizeof(double), s, leaves, status, ls);
+  const int blocks = (nleaves + kLeavesPerBlock - 1) / kLeavesPerBlock;
+  hipLaunchKernelGGL(k_leaf_ql, dim3(blocks), dim3(64 * kLeavesPerBlock),
+                     (size_t)kLeavesPerBlock * ls * ls * sizeof(double), s, leaves, nleaves, status, ls, maxit);
 }
 
 }  // namespace phdc

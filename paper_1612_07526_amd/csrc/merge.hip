@@ -131,15 +131,14 @@ __device__ inline void wave_prefix(const int (&c)[NC], int (&pre)[NC], int (&tot
   }
 }
 
+// sdl: LDS for D, used by the merge-path searches when m <= lds_cap.
 template <int NT>
-__global__ void __launch_bounds__(NT) k_deflate(const MergeDesc* __restrict__ descs, Scratch S, int lds_cap) {
+__device__ void deflate_body(const MergeDesc& M, const Scratch& S, int lds_cap, double* sdl) {
   constexpr int NW = NT / 64;
   static_assert(NW <= kDefWaves, "wave_prefix covers at most kDefWaves waves");
   __shared__ double shd[kDefWaves];
   __shared__ int shc[7][kDefWaves];
   __shared__ int shi[4];
-  HIP_DYNAMIC_SHARED(double, sdl)  // D staged for the merge-path searches (m <= lds_cap)
-  const MergeDesc M = descs[blockIdx.x];
   const int m = M.m, n1 = M.n1, t = threadIdx.x;
   const int64_t so = M.s_off;
   int32_t* cnt = S.counters + (int64_t)M.id * kCounters;
@@ -162,7 +161,7 @@ __global__ void __launch_bounds__(NT) k_deflate(const MergeDesc* __restrict__ de
   // 1. z (Eq. (3): last row of Q1, first row of Q2), |z|^2, max |D|, sortedness;
   // the row range of every input column, in rows of the merge block.
   double zz = 0.0, dmx = 0.0;
-  int uns = 0;
+  int uns = 0;  // bit 0: a descending step inside D1 or D2; bit 1: a NaN or Inf pole
   constexpr int U1 = 4;  // loads of four indices issued before their uses
   for (int i0 = t; i0 < m; i0 += U1 * NT) {
     double zi[U1], di[U1], dprev[U1];
@@ -188,9 +187,11 @@ __global__ void __launch_bounds__(NT) k_deflate(const MergeDesc* __restrict__ de
         S.zs[so + i] = zi[u];
         zz += zi[u] * zi[u];
         dmx = fmax(dmx, fabs(di[u]));
-        // NaN or a descending step inside either run makes the merge of the two
-        // runs ill-defined; such input is reported and merged without sorting.
-        if (!(di[u] == di[u]) || (i > 0 && i != n1 && !(di[u] >= dprev[u]))) uns = 1;
+        // A non-finite pole or a descending step inside either run makes the
+        // merge of the two runs ill-defined; such input is reported and merged
+        // without sorting.
+        if (!isfinite(di[u])) uns |= 2;
+        else if (i > 0 && i != n1 && !(di[u] >= dprev[u])) uns |= 1;
       }
     }
   }
@@ -199,16 +200,18 @@ __global__ void __launch_bounds__(NT) k_deflate(const MergeDesc* __restrict__ de
   __syncthreads();
   if (t == 0) shi[0] = 0;
   __syncthreads();
-  if (uns) shi[0] = 1;
+  if (uns) atomicOr(&shi[0], uns);
   __syncthreads();
   uns = shi[0];
+  if (!isfinite(zz) || !isfinite(rho0)) uns |= 2;  // block-uniform
   const double rho = rho0 * zz;
   const double zn = sqrt(zz);
   const double tol = 8.0 * kUnitRoundoff * fmax(dmx, rho);
   if (t == 0) {
     S.mparam[(int64_t)M.id * 4 + 0] = rho;
     S.mparam[(int64_t)M.id * 4 + 1] = tol;
-    if (uns) set_status(S.status, PHDC_ERR_UNSORTED);
+    if (uns & 2) set_status(S.status, PHDC_ERR_NONFINITE);
+    else if (uns) set_status(S.status, PHDC_ERR_UNSORTED);
   }
 
   // 2. merge the two ascending runs (ties: D1 first) and normalise z.  For
@@ -504,6 +507,12 @@ __global__ void __launch_bounds__(NT) k_deflate(const MergeDesc* __restrict__ de
   }
 }
 
+template <int NT>
+__global__ void __launch_bounds__(NT) k_deflate(const MergeDesc* __restrict__ descs, Scratch S, int lds_cap) {
+  HIP_DYNAMIC_SHARED(double, sdl)
+  deflate_body<NT>(descs[blockIdx.x], S, lds_cap, sdl);
+}
+
 // ------------------------------------------------------------ rotations
 // Applies the recorded rotation chains to the columns of the merge's input
 // block, in place.  A chain's records share a column and run in order per row;
@@ -513,19 +522,10 @@ __global__ void __launch_bounds__(NT) k_deflate(const MergeDesc* __restrict__ de
 // rotated columns carry on.
 constexpr int kRotGroups = 16;
 
-__global__ void __launch_bounds__(256) k_rotate(BlockMap bm, Scratch S) {
-  const int b = blockIdx.x;
-  const int mi = find_merge(bm, b);
-  const int lb = b - merge_first_block(bm, mi);
-  const MergeDesc M = bm.descs[mi];
-  const int m = M.m;
-  const int RB = cdiv_d(m, 256);
-  const int G = (merge_blocks(bm, mi)) / RB;
-  const int rb = lb % RB, g = lb / RB;
+// Row r of the chains g, g + G, ... of merge M.
+__device__ void rotate_chains(const MergeDesc& M, const Scratch& S, int r, int g, int G) {
   const int32_t* cnt = S.counters + (int64_t)M.id * kCounters;
   const int nrot = cnt[C_NROT], nchain = cnt[C_NCHAIN];
-  const int r = rb * 256 + threadIdx.x;
-  if (r >= m) return;
   const int64_t so = M.s_off;
   double* q = M.qin;
   const int64_t ld = M.ldin;
@@ -544,6 +544,17 @@ __global__ void __launch_bounds__(256) k_rotate(BlockMap bm, Scratch S) {
       q[r + (int64_t)cj * ld] = c * xj - s * xp;
     }
   }
+}
+
+__device__ void rotate_body(const BlockMap& bm, const Scratch& S, int b) {
+  const int mi = find_merge(bm, b);
+  const int lb = b - merge_first_block(bm, mi);
+  const MergeDesc M = bm.descs[mi];
+  const int RB = cdiv_d(M.m, 256);
+  const int G = (merge_blocks(bm, mi)) / RB;
+  const int rb = lb % RB, g = lb / RB;
+  const int r = rb * 256 + threadIdx.x;
+  if (r < M.m) rotate_chains(M, S, r, g, G);
 }
 
 // ------------------------------------------------------------ secular roots
@@ -568,6 +579,8 @@ __device__ inline double rcp_nr(double x) {
   return y;
 }
 
+constexpr int kSecMaxIters = 120;  // bracketed steps per root (bisection alone needs at most ~64)
+
 // A double moved between lanes of a 16-lane row by a DPP lane pattern (a VALU
 // operand modifier: no LDS round trip, unlike a general shuffle).
 template <int CTRL>
@@ -587,14 +600,16 @@ constexpr int kDppRowMirror = 0x140;     // lane i <-> 15 - i within each 16 lan
 // the mirrored quad and the mirrored half-row: the same pairing tree as xor 1,
 // 2, 4, 8 (quads hold equal values by then), so the result does not depend on
 // which form runs, and IEEE addition being commutative every lane holds the
-// identical total.
+// identical total.  G = 4 takes the first two steps.
 template <int G>
 __device__ inline double group_sum(double v) {
-  if constexpr (G == 16) {
+  if constexpr (G == 16 || G == 4) {
     v += dpp_row<kDppQuadXor1>(v);
     v += dpp_row<kDppQuadXor2>(v);
-    v += dpp_row<kDppRowHalfMirror>(v);
-    v += dpp_row<kDppRowMirror>(v);
+    if constexpr (G == 16) {
+      v += dpp_row<kDppRowHalfMirror>(v);
+      v += dpp_row<kDppRowMirror>(v);
+    }
   } else {
 #pragma unroll
     for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o, 64);
@@ -602,10 +617,51 @@ __device__ inline double group_sum(double v) {
   return v;
 }
 
-// SQ: z holds the squares z_i^2 (staged copies) instead of z_i.
+// Sums of the secular function at lambda = dorg + t over the poles, split at jl:
+// psi = sum_{i <= jl} z_i^2/(d_i - lambda), phi = the rest, their derivatives and
+// sum |z_i^2/(d_i - lambda)|; the G lanes of a group each take every G-th pole,
+// two poles in flight per lane.  SQ: z holds the squares.
+struct SecSums {
+  double psi, dpsi, phi, dphi, eabs;
+};
+
+template <int G, bool SQ>
+__device__ __forceinline__ SecSums secular_sums(int K, const double* __restrict__ d, const double* __restrict__ z,
+                                                int jl, int sub, double dorg, double t) {
+  auto z2 = [&](int i) { return SQ ? z[i] : z[i] * z[i]; };
+  double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0, eabs = 0.0;
+  double psi2 = 0.0, dpsi2 = 0.0, phi2 = 0.0, dphi2 = 0.0, eabs2 = 0.0;
+  int i = sub;
+  for (; i + G < K; i += 2 * G) {
+    const int i2 = i + G;
+    const double del = (d[i] - dorg) - t, del2 = (d[i2] - dorg) - t;
+    const double rcp = rcp_nr(del), rcp2 = rcp_nr(del2);
+    const double tt = z2(i) * rcp, tt2 = z2(i2) * rcp2;
+    const double dt = tt * rcp, dt2 = tt2 * rcp2;
+    if (i <= jl) { psi += tt; dpsi += dt; } else { phi += tt; dphi += dt; }
+    if (i2 <= jl) { psi2 += tt2; dpsi2 += dt2; } else { phi2 += tt2; dphi2 += dt2; }
+    eabs += fabs(tt);
+    eabs2 += fabs(tt2);
+  }
+  if (i < K) {
+    const double del = (d[i] - dorg) - t;
+    const double rcp = rcp_nr(del);
+    const double tt = z2(i) * rcp;
+    const double dt = tt * rcp;
+    if (i <= jl) { psi += tt; dpsi += dt; } else { phi += tt; dphi += dt; }
+    eabs += fabs(tt);
+  }
+  return SecSums{group_sum<G>(psi + psi2), group_sum<G>(dpsi + dpsi2), group_sum<G>(phi + phi2),
+                 group_sum<G>(dphi + dphi2), group_sum<G>(eabs + eabs2)};
+}
+
+// SQ: z holds the squares z_i^2 (staged copies) instead of z_i.  Interior roots
+// first evaluate f, with its derivatives, at the middle of their bracket: the
+// sign picks the origin, and the same sums give the first rational step.
 template <int G, bool SQ>
 __device__ __forceinline__ bool secular_root(int K, const double* __restrict__ d, const double* __restrict__ z,
-                                             double rho, int j, int sub, int* org_out, double* tau_out) {
+                                             double rho, int j, int sub, int* org_out, double* tau_out,
+                                             int maxit = kSecMaxIters, int* iters = nullptr) {
   auto z2 = [&](int i) { return SQ ? z[i] : z[i] * z[i]; };
   const double inv_rho = 1.0 / rho;
   if (K == 1) {
@@ -613,19 +669,22 @@ __device__ __forceinline__ bool secular_root(int K, const double* __restrict__ d
     *tau_out = rho * z2(0);
     return true;
   }
+  const int jl = (j < K - 1) ? j : K - 2;
+  const int jr = jl + 1;
   int org;
-  double lo, hi;
+  double lo, hi, tau;
+  SecSums f{};
+  bool have = false;  // f holds the sums at tau
   if (j < K - 1) {
     const double dj = d[j], dj1 = d[j + 1];
     const double half = 0.5 * (dj1 - dj);
-    double w = 0.0;
-    for (int i = sub; i < K; i += G) w += z2(i) / ((d[i] - dj) - half);
-    w = inv_rho + group_sum<G>(w);
-    if (w >= 0.0) {
-      org = j; lo = 0.0; hi = half;
+    f = secular_sums<G, SQ>(K, d, z, jl, sub, dj, half);
+    if (inv_rho + f.psi + f.phi >= 0.0) {
+      org = j; lo = 0.0; hi = half; tau = hi;
     } else {
-      org = j + 1; lo = (dj - dj1) + half; hi = 0.0;
+      org = j + 1; lo = (dj - dj1) + half; hi = 0.0; tau = lo;
     }
+    have = true;
   } else {
     org = K - 1;
     lo = 0.0;
@@ -639,56 +698,24 @@ __device__ __forceinline__ bool secular_root(int K, const double* __restrict__ d
       if (w >= 0.0) break;
       hi *= 2.0;
     }
+    tau = 0.5 * (lo + hi);
   }
   const double dorg = d[org];
-  const int jl = (j < K - 1) ? j : K - 2;
-  const int jr = jl + 1;
-  double tau = 0.5 * (lo + hi);
   bool ok = false;
-  for (int it = 0; it < 120; ++it) {
-    // Two independent sets of partial sums (poles i and i + G) keep two
-    // reciprocal chains in flight per lane.
-    double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0, eabs = 0.0;
-    double psi2 = 0.0, dpsi2 = 0.0, phi2 = 0.0, dphi2 = 0.0, eabs2 = 0.0;
-    int i = sub;
-    for (; i + G < K; i += 2 * G) {
-      const int i2 = i + G;
-      const double del = (d[i] - dorg) - tau, del2 = (d[i2] - dorg) - tau;
-      const double rcp = rcp_nr(del), rcp2 = rcp_nr(del2);
-      const double tt = z2(i) * rcp, tt2 = z2(i2) * rcp2;
-      const double dt = tt * rcp, dt2 = tt2 * rcp2;
-      if (i <= jl) { psi += tt; dpsi += dt; } else { phi += tt; dphi += dt; }
-      if (i2 <= jl) { psi2 += tt2; dpsi2 += dt2; } else { phi2 += tt2; dphi2 += dt2; }
-      eabs += fabs(tt);
-      eabs2 += fabs(tt2);
-    }
-    if (i < K) {
-      const double del = (d[i] - dorg) - tau;
-      const double rcp = rcp_nr(del);
-      const double tt = z2(i) * rcp;
-      const double dt = tt * rcp;
-      if (i <= jl) { psi += tt; dpsi += dt; } else { phi += tt; dphi += dt; }
-      eabs += fabs(tt);
-    }
-    psi += psi2;
-    dpsi += dpsi2;
-    phi += phi2;
-    dphi += dphi2;
-    eabs += eabs2;
-    psi = group_sum<G>(psi);
-    dpsi = group_sum<G>(dpsi);
-    phi = group_sum<G>(phi);
-    dphi = group_sum<G>(dphi);
-    eabs = group_sum<G>(eabs);
-    const double w = inv_rho + psi + phi;
+  int it = 0;
+  for (; it < maxit; ++it) {
+    if (!have) f = secular_sums<G, SQ>(K, d, z, jl, sub, dorg, tau);
+    have = false;
+    const double w = inv_rho + f.psi + f.phi;
     if (w > 0.0) hi = tau;
     else if (w < 0.0) lo = tau;
-    else { ok = true; break; }
-    if (fabs(w) <= 8.0 * kUnitRoundoff * (inv_rho + eabs)) { ok = true; break; }
+    else if (w == 0.0) { ok = true; break; }
+    else break;  // NaN: not converged (reported as PHDC_ERR_SECULAR)
+    if (fabs(w) <= 8.0 * kUnitRoundoff * (inv_rho + f.eabs)) { ok = true; break; }
     const double Dl = (d[jl] - dorg) - tau, Dr = (d[jr] - dorg) - tau;
-    const double a = (Dl + Dr) * w - Dl * Dr * (dpsi + dphi);
+    const double a = (Dl + Dr) * w - Dl * Dr * (f.dpsi + f.dphi);
     const double bb = Dl * Dr * w;
-    const double c = w - Dl * dpsi - Dr * dphi;
+    const double c = w - Dl * f.dpsi - Dr * f.dphi;
     const double disc = sqrt(fabs(a * a - 4.0 * bb * c));
     double eta;
     if (c == 0.0) eta = bb / a;
@@ -699,30 +726,27 @@ __device__ __forceinline__ bool secular_root(int K, const double* __restrict__ d
     if (tn == tau || !(hi > lo)) { ok = true; break; }
     tau = tn;
   }
+  if (iters) *iters = it + 1;
   *org_out = org;
   *tau_out = tau;
   return ok;
 }
 
-constexpr int kSecG = 16;                       // lanes per root
-constexpr int kSecThreads = 256;                // threads per block
-constexpr int kSecRoots = kSecThreads / kSecG;  // roots per block
-constexpr int kSecLds = 2048;                   // poles staged in LDS (d_i and z_i^2: 32 KB)
+constexpr int kSecThreads = 256;  // threads per block
+constexpr int kSecLds = 2048;     // largest number of poles staged in LDS (d_i and z_i^2: 32 KB)
+constexpr int kSecG = 16;         // lanes per root
 
-// 256-lane blocks, 16 roots per block.  Merges with K <= kSecLds stage the
-// poles and squared weights in LDS once; larger ones read them from global
-// memory (L2-resident).
-__global__ void __launch_bounds__(kSecThreads) k_secular(BlockMap bm, Scratch S) {
-  __shared__ double sd[kSecLds];
-  __shared__ double sz[kSecLds];
-  const int b = blockIdx.x;
-  const int mi = find_merge(bm, b);
-  const int lb = b - merge_first_block(bm, mi);
-  const MergeDesc M = bm.descs[mi];
-  const int K = S.counters[(int64_t)M.id * kCounters + C_K];
-  if (lb * kSecRoots >= K) return;  // whole block idle (uniform)
-  const int j = lb * kSecRoots + (int)threadIdx.x / kSecG;
-  const int sub = threadIdx.x % kSecG;
+// The roots of one block: G lanes per root, kSecThreads / G roots per block.
+// Merges with K <= cap stage the poles and squared weights in LDS once (cap:
+// the launch's LDS, sized by its largest merge, at most kSecLds); larger ones
+// read them from global memory (L2-resident).
+template <int G>
+__device__ __forceinline__ void secular_block(const MergeDesc& M, const Scratch& S, int K, int lb, double* sd,
+                                              double* sz, int cap) {
+  constexpr int R = kSecThreads / G;
+  if (lb * R >= K) return;  // whole block idle (uniform)
+  const int j = lb * R + (int)threadIdx.x / G;
+  const int sub = threadIdx.x % G;
   const bool active = j < K;
   const int64_t so = M.s_off;
   const double rho = S.mparam[(int64_t)M.id * 4 + 0];
@@ -731,17 +755,18 @@ __global__ void __launch_bounds__(kSecThreads) k_secular(BlockMap bm, Scratch S)
   // inactive groups of a partly filled block run root K-1 redundantly so that
   // every lane takes part in the group shuffles; only active groups write
   const int jj = active ? j : K - 1;
+  const int maxit = (M.flags & kFlagNoSecularIters) ? 0 : kSecMaxIters;
   bool ok;
-  if (K <= kSecLds) {
+  if (K <= cap) {
     for (int i = threadIdx.x; i < K; i += kSecThreads) {
       sd[i] = S.ds[so + i];
       const double zi = S.zs[so + i];
       sz[i] = zi * zi;
     }
     __syncthreads();
-    ok = secular_root<kSecG, true>(K, sd, sz, rho, jj, sub, &org, &tau);
+    ok = secular_root<G, true>(K, sd, sz, rho, jj, sub, &org, &tau, maxit);
   } else {
-    ok = secular_root<kSecG, false>(K, S.ds + so, S.zs + so, rho, jj, sub, &org, &tau);
+    ok = secular_root<G, false>(K, S.ds + so, S.zs + so, rho, jj, sub, &org, &tau, maxit);
   }
   if (active && sub == 0) {
     S.org[so + j] = org;
@@ -751,18 +776,27 @@ __global__ void __launch_bounds__(kSecThreads) k_secular(BlockMap bm, Scratch S)
   }
 }
 
+__device__ void secular_body(const BlockMap& bm, const Scratch& S, int b, double* sd, double* sz, int cap) {
+  const int mi = find_merge(bm, b);
+  const int lb = b - merge_first_block(bm, mi);
+  const MergeDesc M = bm.descs[mi];
+  const int K = S.counters[(int64_t)M.id * kCounters + C_K];
+  secular_block<kSecG>(M, S, K, lb, sd, sz, cap);
+}
+
 __global__ void __launch_bounds__(64) k_secular_raw(int K, const double* d, const double* z, double rho,
                                                     int32_t* org, double* tau, int32_t* status) {
   const int j = blockIdx.x * (64 / kSecG) + (int)threadIdx.x / kSecG;
   const int sub = threadIdx.x % kSecG;
   const bool active = j < K;
-  int o = 0;
+  int o = 0, its = 0;
   double t = 0.0;
-  bool ok = secular_root<kSecG, false>(K, d, z, rho, active ? j : K - 1, sub, &o, &t);
+  bool ok = secular_root<kSecG, false>(K, d, z, rho, active ? j : K - 1, sub, &o, &t, kSecMaxIters, &its);
   if (active && sub == 0) {
     org[j] = o;
     tau[j] = t;
     if (!ok) set_status(status, PHDC_ERR_SECULAR);
+    atomicMax(status + 1, its);  // largest number of evaluations of one root
   }
 }
 
@@ -824,8 +858,7 @@ __device__ inline void lowner_item(const MergeDesc& M, const Scratch& S, int K, 
   }
 }
 
-__global__ void __launch_bounds__(kSecThreads) k_lowner(BlockMap bm, Scratch S) {
-  const int b = blockIdx.x;
+__device__ void lowner_body(const BlockMap& bm, const Scratch& S, int b) {
   const int mi = find_merge(bm, b);
   const int lb = b - merge_first_block(bm, mi);
   const MergeDesc M = bm.descs[mi];
@@ -858,8 +891,7 @@ __device__ inline void unorm_item(const MergeDesc& M, const Scratch& S, int K, i
   if (active && sub == 0) S.cnorm[so + j] = 1.0 / sqrt(s);
 }
 
-__global__ void __launch_bounds__(kSecThreads) k_unorm(BlockMap bm, Scratch S) {
-  const int b = blockIdx.x;
+__device__ void unorm_body(const BlockMap& bm, const Scratch& S, int b) {
   const int mi = find_merge(bm, b);
   const int lb = b - merge_first_block(bm, mi);
   const MergeDesc M = bm.descs[mi];
@@ -871,7 +903,9 @@ __global__ void __launch_bounds__(kSecThreads) k_unorm(BlockMap bm, Scratch S) {
 // ... then the entries, written row-major (row g = grouped row, ld = K) so that
 // the product's operand tiles are contiguous.  HSS merges keep the pole order
 // (Gu's grouping would break the low-rank structure of the off-diagonal
-// blocks, Sec. 2.2); plain merges use it.
+// blocks, Sec. 2.2); plain merges use it.  With normalized == false the columns
+// are left unscaled (the update GEMM applies the column scale in its
+// epilogue), so that the writer need not wait for the norms.
 __device__ inline double uhat_entry(const MergeDesc& M, const Scratch& S, bool pole_order, int g, double lj,
                                     double tj, double sc) {
   const int64_t so = M.s_off;
@@ -882,8 +916,7 @@ __device__ inline double uhat_entry(const MergeDesc& M, const Scratch& S, bool p
 // A block covers 256 columns and strides over rows.
 constexpr int kUwRowGroups = 64;
 
-__global__ void __launch_bounds__(256) k_uwrite(BlockMap bm, Scratch S) {
-  const int b = blockIdx.x;
+__device__ void uwrite_body(const BlockMap& bm, const Scratch& S, int b, bool normalized) {
   const int mi = find_merge(bm, b);
   const int lb = b - merge_first_block(bm, mi);
   const MergeDesc M = bm.descs[mi];
@@ -895,36 +928,73 @@ __global__ void __launch_bounds__(256) k_uwrite(BlockMap bm, Scratch S) {
   if (j >= K) return;
   const int64_t so = M.s_off;
   const bool pole_order = S.counters[(int64_t)M.id * kCounters + C_PATH] == 2;
-  const double lj = S.dorg[so + j], tj = S.tau[so + j], sc = S.cnorm[so + j];
+  const double lj = S.dorg[so + j], tj = S.tau[so + j], sc = normalized ? S.cnorm[so + j] : 1.0;
   double* U = S.uhat + M.u_off;
   for (int g = rg; g < K; g += RG) U[(int64_t)g * K + j] = uhat_entry(M, S, pole_order, g, lj, tj, sc);
 }
 
-// Levels whose merges have at most kSmallUhat rows: one workgroup per merge
-// forms zhat, the column norms and Uhat in turn (three launches fewer, and no
-// grid sized for K = m at small m).  Same per-item arithmetic as above.
+// Levels whose merges have at most kSmallUhat rows: one 1024-thread workgroup
+// per merge applies the rotations and forms the secular roots, zhat, the
+// column norms, Uhat and the output ranks in turn (one launch instead of
+// several whose fixed latency exceeds this work, and no grid sized for K = m).
+// Same per-item arithmetic as the multi-block kernels, so a merge gives the
+// same bits on either path.
 constexpr int kSmallUhat = 64;
+constexpr int kSmallThreads = 1024;
 
-__global__ void __launch_bounds__(kSecThreads) k_small_uhat(const MergeDesc* __restrict__ descs, Scratch S) {
-  const MergeDesc M = descs[blockIdx.x];
+__device__ void rank_item(const MergeDesc& M, const Scratch& S, int x);
+
+__device__ void small_body(const MergeDesc* __restrict__ descs, const Scratch& S, int b, bool normalized,
+                           double* sd, double* sz) {
+  constexpr int NT = kSmallThreads;
+  const MergeDesc M = descs[b];
   const int K = S.counters[(int64_t)M.id * kCounters + C_K];
-  if (K <= 0) return;
-  const int grp = (int)threadIdx.x / kItemG, sub = threadIdx.x % kItemG;
-  for (int i0 = 0; i0 < K; i0 += kItemsPerBlock) lowner_item(M, S, K, i0 + grp, sub);
-  __syncthreads();
-  for (int j0 = 0; j0 < K; j0 += kItemsPerBlock) unorm_item(M, S, K, j0 + grp, sub);
-  __syncthreads();
-  const int64_t so = M.s_off;
-  const bool pole_order = S.counters[(int64_t)M.id * kCounters + C_PATH] == 2;
-  double* U = S.uhat + M.u_off;
-  const int nj = min(K, kSecThreads), rg = kSecThreads / nj;  // column j = t % nj, row group t / nj
   const int t = threadIdx.x;
-  if (t < nj * rg) {
-    for (int j = t % nj; j < K; j += nj) {
-      const double lj = S.dorg[so + j], tj = S.tau[so + j], sc = S.cnorm[so + j];
-      for (int g = t / nj; g < K; g += rg) U[(int64_t)g * K + j] = uhat_entry(M, S, pole_order, g, lj, tj, sc);
+  const int64_t so = M.s_off;
+  // rotations of the input block (independent of the steps below): 16 groups of
+  // 64 threads, group g takes the chains g, g + 16, ..., thread r of a group row r
+  if ((t & 63) < M.m) rotate_chains(M, S, t & 63, t >> 6, NT / 64);
+  if (K > 0) {  // block-uniform
+    // secular roots, kSecG lanes each, poles staged in LDS (K <= kSmallUhat)
+    constexpr int G = kSecG;
+    const double rho = S.mparam[(int64_t)M.id * 4 + 0];
+    const int maxit = (M.flags & kFlagNoSecularIters) ? 0 : kSecMaxIters;
+    for (int i = t; i < K; i += NT) {
+      sd[i] = S.ds[so + i];
+      const double zi = S.zs[so + i];
+      sz[i] = zi * zi;
+    }
+    __syncthreads();
+    const int sub = t % G;
+    for (int j0 = 0; j0 < K; j0 += NT / G) {
+      const int j = j0 + t / G;
+      int org = 0;
+      double tau = 0.0;
+      const bool ok = secular_root<G, true>(K, sd, sz, rho, j < K ? j : K - 1, sub, &org, &tau, maxit);
+      if (j < K && sub == 0) {
+        S.org[so + j] = org;
+        S.tau[so + j] = tau;
+        S.dorg[so + j] = sd[org];
+        if (!ok) set_status(S.status, PHDC_ERR_SECULAR);
+      }
+    }
+    __syncthreads();
+    const int grp = t / kItemG, isub = t % kItemG;
+    for (int i0 = 0; i0 < K; i0 += NT / kItemG) lowner_item(M, S, K, i0 + grp, isub);
+    __syncthreads();
+    for (int j0 = 0; j0 < K; j0 += NT / kItemG) unorm_item(M, S, K, j0 + grp, isub);
+    __syncthreads();
+    const bool pole_order = S.counters[(int64_t)M.id * kCounters + C_PATH] == 2;
+    double* U = S.uhat + M.u_off;
+    const int nj = min(K, NT), rg = NT / nj;  // column j = t % nj, row group t / nj
+    if (t < nj * rg) {
+      for (int j = t % nj; j < K; j += nj) {
+        const double lj = S.dorg[so + j], tj = S.tau[so + j], sc = normalized ? S.cnorm[so + j] : 1.0;
+        for (int g = t / nj; g < K; g += rg) U[(int64_t)g * K + j] = uhat_entry(M, S, pole_order, g, lj, tj, sc);
+      }
     }
   }
+  for (int x = t; x < M.m; x += NT) rank_item(M, S, x);
 }
 
 // ------------------------------------------------------------ final order
@@ -932,13 +1002,8 @@ __global__ void __launch_bounds__(kSecThreads) k_small_uhat(const MergeDesc* __r
 // {roots} u {type-1 deflated} u {type-2 deflated}, ties broken by (class,
 // index).  Roots and type-1 values are each non-decreasing (binary search);
 // type-2 values are counted directly.
-__global__ void __launch_bounds__(256) k_rank(BlockMap bm, Scratch S) {
-  const int b = blockIdx.x;
-  const int mi = find_merge(bm, b);
-  const int lb = b - merge_first_block(bm, mi);
-  const MergeDesc M = bm.descs[mi];
-  const int x = lb * 256 + threadIdx.x;
-  if (x >= M.m) return;
+// Item x of merge M (x < M.m).
+__device__ void rank_item(const MergeDesc& M, const Scratch& S, int x) {
   const int32_t* cnt = S.counters + (int64_t)M.id * kCounters;
   const int K = cnt[C_K], nd1 = cnt[C_ND1], nd2 = cnt[C_ND2];
   const int64_t so = M.s_off;
@@ -982,6 +1047,14 @@ __global__ void __launch_bounds__(256) k_rank(BlockMap bm, Scratch S) {
   }
 }
 
+__device__ void rank_body(const BlockMap& bm, const Scratch& S, int b) {
+  const int mi = find_merge(bm, b);
+  const int lb = b - merge_first_block(bm, mi);
+  const MergeDesc M = bm.descs[mi];
+  const int x = lb * 256 + threadIdx.x;
+  if (x < M.m) rank_item(M, S, x);
+}
+
 // ------------------------------------------------------------ deflated columns
 // Deflated columns of Q G P (Eq. (6), the identity block) go unchanged to
 // their output position.  Only the rows of a column's range are read and, below
@@ -999,8 +1072,7 @@ __device__ inline int copy_rpt(int m) {
   return rpt;
 }
 
-__global__ void __launch_bounds__(256) k_copy_deflated(BlockMap bm, Scratch S) {
-  const int b = blockIdx.x;
+__device__ void copy_body(const BlockMap& bm, const Scratch& S, int b) {
   const int mi = find_merge(bm, b);
   const int lb = b - merge_first_block(bm, mi);
   const int G = merge_blocks(bm, mi);
@@ -1070,8 +1142,8 @@ __global__ void __launch_bounds__(256) k_copy_deflated(BlockMap bm, Scratch S) {
 int map_blocks(int kind, int m, int n1, int gt, bool root) {
   auto cdiv = [](int a, int b) { return (a + b - 1) / b; };
   switch (kind) {
-    case MAP_ROOTS64: return cdiv(m, 64);
-    case MAP_ROOTS16: return cdiv(m, kSecRoots);
+    case MAP_SECULAR: return cdiv(m, kSecThreads / kSecG);
+    case MAP_ROOTS16: return cdiv(m, kItemsPerBlock);
     case MAP_ROWS256: return cdiv(m, 256);
     case MAP_ROT: return cdiv(m, 256) * std::max(1, std::min(m / 2, kRotGroups));
     case MAP_UWRITE: return cdiv(m, 256) * std::max(1, std::min(m, kUwRowGroups));
@@ -1094,10 +1166,54 @@ __global__ void __launch_bounds__(256) k_copy_ints(const int32_t* __restrict__ s
   if (i < n) dst[i] = src[i];
 }
 
+// ------------------------------------------------------------ fused stages
+// A tree level runs as a few launches, each the union of steps that depend on
+// the same earlier ones (a launch costs a few microseconds of fixed latency,
+// comparable to the work of the upper levels): the block index picks the step.
+// The longest-running blocks come first in each launch, so that they are
+// dispatched before the many short ones.
+//   deflate | rotations + secular roots | Loewner z + output ranks |
+//   column norms + Uhat (unscaled) + deflated-column copy | update GEMM
+// Levels of merges with at most kSmallUhat rows do roots, Loewner z, norms, Uhat
+// and ranks in one workgroup per merge.  When Uhat must hold normalized columns
+// (a level with HSS candidates, whose compression samples Uhat itself, or the
+// split-precision path), the norms come first in a launch of their own.
+
+// Dynamic LDS: 2 cap doubles, cap = min(largest merge of the level, kSecLds).
+__global__ void __launch_bounds__(256) k_stage_roots(BlockMap sec, int nsec, BlockMap rot, Scratch S, int cap) {
+  HIP_DYNAMIC_SHARED(double, lds)
+  const int b = blockIdx.x;
+  if (b < nsec) secular_body(sec, S, b, lds, lds + cap, cap);
+  else rotate_body(rot, S, b - nsec);
+}
+
+__global__ void __launch_bounds__(kSmallThreads) k_stage_small(const MergeDesc* __restrict__ descs, Scratch S,
+                                                               int normalized) {
+  __shared__ double sd[kSmallUhat];
+  __shared__ double sz[kSmallUhat];
+  small_body(descs, S, blockIdx.x, normalized != 0, sd, sz);
+}
+
+__global__ void __launch_bounds__(256) k_stage_lowner(BlockMap low, int nlow, BlockMap rank, Scratch S) {
+  const int b = blockIdx.x;
+  if (b < nlow) lowner_body(low, S, b);
+  else rank_body(rank, S, b - nlow);
+}
+
+__global__ void __launch_bounds__(256) k_stage_uhat(BlockMap cp, int ncp, BlockMap uw, int nuw, BlockMap un, Scratch S,
+                                                    int normalized) {
+  const int b = blockIdx.x;
+  if (b < ncp) copy_body(cp, S, b);
+  else if (b < ncp + nuw) uwrite_body(uw, S, b - ncp, normalized != 0);
+  else unorm_body(un, S, b - ncp - nuw);
+}
+
 void launch_merge_level(const MergeDesc* descs, int nm, const LevelMaps& maps, const Scratch& S, int gemm_mode,
                         const SplitBufs* split, int nsl, hipStream_t s, const LevelProbe* probe) {
   if (nm <= 0) return;
   auto bmap = [&](int kind) { return BlockMap{descs, maps.pfx[kind], nm, maps.per[kind]}; };
+  const BlockMap none{descs, nullptr, 1, 1};
+  const int normalized = maps.uhat_normalized ? 1 : 0;
   { ProfScope p(PH_DEFLATE, s);
     const int cap = maps.maxm <= kDefLdsMax ? maps.maxm : 0;
     if (maps.maxm <= kDefSmall)
@@ -1110,31 +1226,65 @@ void launch_merge_level(const MergeDesc* descs, int nm, const LevelMaps& maps, c
                        probe->count);
     hipEventRecord(probe->done, s);
   }
-  { ProfScope p(PH_ROTATE, s);
-    hipLaunchKernelGGL(k_rotate, dim3(maps.total[MAP_ROT]), dim3(256), 0, s, bmap(MAP_ROT), S); }
-  { ProfScope p(PH_SECULAR, s);
-    hipLaunchKernelGGL(k_secular, dim3(maps.total[MAP_ROOTS16]), dim3(kSecThreads), 0, s, bmap(MAP_ROOTS16), S); }
+  const int nrot = maps.total[MAP_ROT];
+  const int ncopy = maps.total[MAP_COPY];
   if (maps.maxm <= kSmallUhat) {
-    ProfScope p(PH_UWRITE, s);
-    hipLaunchKernelGGL(k_small_uhat, dim3(nm), dim3(kSecThreads), 0, s, descs, S);
+    { ProfScope p(PH_SECULAR, s);
+      hipLaunchKernelGGL(k_stage_small, dim3(nm), dim3(kSmallThreads), 0, s, descs, S, normalized); }
+    { ProfScope p(PH_UWRITE, s);  // (the copy phase times the lone root copy only)
+      hipLaunchKernelGGL(k_stage_uhat, dim3(ncopy), dim3(256), 0, s, bmap(MAP_COPY), ncopy, none, 0, none, S, 0); }
   } else {
+    const int nsec = maps.total[MAP_SECULAR], nitem = maps.total[MAP_ROOTS16], nrank = maps.total[MAP_ROWS256];
+    const int nuw = maps.total[MAP_UWRITE];
+    { ProfScope p(PH_SECULAR, s);
+      const int cap = std::min(maps.maxm, kSecLds);
+      hipLaunchKernelGGL(k_stage_roots, dim3(nsec + nrot), dim3(256), (size_t)2 * cap * sizeof(double), s,
+                         bmap(MAP_SECULAR), nsec, bmap(MAP_ROT), S, cap); }
     { ProfScope p(PH_LOWNER, s);
-      hipLaunchKernelGGL(k_lowner, dim3(maps.total[MAP_ROOTS16]), dim3(kSecThreads), 0, s, bmap(MAP_ROOTS16), S); }
-    { ProfScope p(PH_UNORM, s);
-      hipLaunchKernelGGL(k_unorm, dim3(maps.total[MAP_ROOTS16]), dim3(kSecThreads), 0, s, bmap(MAP_ROOTS16), S); }
-    { ProfScope p(PH_UWRITE, s);
-      hipLaunchKernelGGL(k_uwrite, dim3(maps.total[MAP_UWRITE]), dim3(256), 0, s, bmap(MAP_UWRITE), S); }
+      hipLaunchKernelGGL(k_stage_lowner, dim3(nitem + nrank), dim3(256), 0, s, bmap(MAP_ROOTS16), nitem,
+                         bmap(MAP_ROWS256), S); }
+    const int nc = maps.copy_alone ? 0 : ncopy;
+    if (normalized) {
+      { ProfScope p(PH_UNORM, s);
+        hipLaunchKernelGGL(k_stage_uhat, dim3(nitem), dim3(256), 0, s, none, 0, none, 0, bmap(MAP_ROOTS16), S, 1); }
+      { ProfScope p(PH_UWRITE, s);
+        hipLaunchKernelGGL(k_stage_uhat, dim3(nc + nuw), dim3(256), 0, s, bmap(MAP_COPY), nc, bmap(MAP_UWRITE), nuw,
+                           none, S, 1); }
+    } else {
+      ProfScope p(PH_UWRITE, s);
+      hipLaunchKernelGGL(k_stage_uhat, dim3(nc + nuw + nitem), dim3(256), 0, s, bmap(MAP_COPY), nc, bmap(MAP_UWRITE),
+                         nuw, bmap(MAP_ROOTS16), S, 0);
+    }
+    if (maps.copy_alone) {
+      ProfScope p(PH_COPY, s);
+      hipLaunchKernelGGL(k_stage_uhat, dim3(ncopy), dim3(256), 0, s, bmap(MAP_COPY), ncopy, none, 0, none, S, 0);
+    }
   }
-  { ProfScope p(PH_RANK, s);
-    hipLaunchKernelGGL(k_rank, dim3(maps.total[MAP_ROWS256]), dim3(256), 0, s, bmap(MAP_ROWS256), S); }
   { ProfScope p(PH_GEMM, s);
-    launch_merge_gemm_f64(bmap(MAP_GEMM), maps.total[MAP_GEMM], S, maps.gemm_tile, s); }
+    launch_merge_gemm_f64(bmap(MAP_GEMM), maps.total[MAP_GEMM], S, maps.gemm_tile, !normalized, s); }
   if (gemm_mode == PHDC_GEMM_SPLIT && split) {
     ProfScope p(PH_SPLIT_GEMM, s);
     launch_split_update(descs, nm, maps, S, *split, nsl, s);
   }
-  { ProfScope p(PH_COPY, s);
-    hipLaunchKernelGGL(k_copy_deflated, dim3(maps.total[MAP_COPY]), dim3(256), 0, s, bmap(MAP_COPY), S); }
+}
+
+__global__ void k_mark_fallback(const MergeDesc* __restrict__ desc, int32_t* counters) {
+  int32_t* cnt = counters + (int64_t)desc->id * kCounters;
+  cnt[C_PATH] = 0;
+  cnt[C_HSSRANK] = -1;
+}
+
+// Runs after the merge's level: the column norms exist, so Uhat is rewritten
+// normalized, in the grouped row order of the FP64 product.
+void launch_fp64_fallback(const MergeDesc* desc, const MergeDesc& M, const Scratch& S, hipStream_t s) {
+  const int tile = gemm_tile_for(M.m);
+  const int nuw = map_blocks(MAP_UWRITE, M.m, M.n1, tile, M.root != 0);
+  const int ngm = map_blocks(MAP_GEMM, M.m, M.n1, tile, M.root != 0);
+  const BlockMap none{desc, nullptr, 1, 1};
+  hipLaunchKernelGGL(k_mark_fallback, dim3(1), dim3(1), 0, s, desc, S.counters);
+  hipLaunchKernelGGL(k_stage_uhat, dim3(nuw), dim3(256), 0, s, none, 0, BlockMap{desc, nullptr, 1, nuw}, nuw, none,
+                     S, 1);  // Uhat only
+  launch_merge_gemm_f64(BlockMap{desc, nullptr, 1, ngm}, ngm, S, tile, false, s);
 }
 
 void launch_secular_standalone(int64_t K, const double* d, const double* z, double rho, int32_t* org, double* tau,

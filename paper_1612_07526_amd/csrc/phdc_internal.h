@@ -49,7 +49,7 @@ struct MergeDesc {
   int32_t hss_min_k;    // HSS update for this merge when K >= hss_min_k (0: never)
   int64_t x_off;        // offset of this merge's m*(m+8) slot (per slice) in the split-precision arenas
   int32_t split_on;     // split-precision update for this merge
-  int32_t pad;
+  int32_t flags;        // bit 0 (kFlagNoSecularIters): secular roots get no iterations (test hook)
   const RowRange* rin;  // input column ranges in rows of the whole matrix (nullptr: [0, n1) / [n1, m) by half)
   RowRange* rout;       // output column ranges (nullptr: not recorded)
   int32_t r0;           // first row (= first column) of the merge block within the matrix
@@ -152,17 +152,29 @@ __device__ inline void set_status(int32_t* status, int code) {
   atomicCAS(status, 0, code);
 }
 
-// Kernel launchers (defined in the .hip files).
-void launch_leaf_ql(const LeafArgs* leaves, int nleaves, int32_t* status, int max_leaf, hipStream_t s);
+constexpr int32_t kFlagNoSecularIters = 1;
+
+// Kernel launchers (defined in the .hip files).  maxit: iteration cap per
+// eigenvalue of the leaf QL (0 under the PHDC_FAIL_LEAF test hook).
+void launch_leaf_ql(const LeafArgs* leaves, int nleaves, int32_t* status, int max_leaf, int maxit, hipStream_t s);
+constexpr int kLeafMaxIters = 64;
+
+// Scan a[0:n) for NaN/Inf: on a hit, flag[0] = 1 and the status word is set to
+// PHDC_ERR_NONFINITE.  The flag is only ever set, never cleared.
+void launch_scan_finite(const double* a, int64_t n, int32_t* flag, int32_t* status, hipStream_t s);
+// Zero the 256-byte status block (status word and the scan flags after it).
+void launch_clear_status(int32_t* status, hipStream_t s);
 
 // Block maps of one merge level (device prefix arrays, nm + 1 entries each).
-enum MapKind { MAP_ROOTS64 = 0, MAP_ROOTS16, MAP_ROWS256, MAP_ROT, MAP_UWRITE, MAP_GEMM, MAP_COPY, MAP_SPLITA, MAP_SPLITB, MAP_COUNT };
+enum MapKind { MAP_SECULAR = 0, MAP_ROOTS16, MAP_ROWS256, MAP_ROT, MAP_UWRITE, MAP_GEMM, MAP_COPY, MAP_SPLITA, MAP_SPLITB, MAP_COUNT };
 struct LevelMaps {
   const int32_t* pfx[MAP_COUNT];
   int32_t total[MAP_COUNT];
   int32_t per[MAP_COUNT] = {};  // blocks per merge when equal for all merges of the level, else 0
   int32_t maxm = 0;         // largest merge of the level
   int32_t gemm_tile = 128;  // output tile edge of the FP64 update GEMM (64 or 128)
+  bool uhat_normalized = false;  // Uhat written with unit columns (else the GEMM epilogue scales them)
+  bool copy_alone = false;       // the deflated-column copy gets a launch of its own (a lone root merge)
 };
 // Blocks of one merge for a kernel class; gt is the FP64 GEMM tile edge (MAP_GEMM);
 // root: the merge is the last one of its matrix (MAP_COPY: one column per block).
@@ -170,7 +182,10 @@ int map_blocks(int kind, int m, int n1, int gt, bool root);
 constexpr int kGemmBlockCap = 1024;      // blocks per merge of the update GEMMs (they loop over tiles)
 constexpr int kTileBuckets = 21;        // merge-size buckets of the GEMM tile table (m <= 2^20)
 int gemm_tile_for(int64_t maxm);        // tile edge for a level whose largest merge is maxm
-void launch_merge_gemm_f64(const BlockMap& bm, int total, const Scratch& S, int tile, hipStream_t s);
+// scale_cols: multiply result column j by the column scale cnorm[j] of Uhat
+// (Uhat was written unscaled).
+void launch_merge_gemm_f64(const BlockMap& bm, int total, const Scratch& S, int tile, bool scale_cols,
+                           hipStream_t s);
 
 // Copy of a level's counters to host-visible memory, made right after the
 // deflation kernel has fixed the sizes and the update path of every merge.
@@ -187,5 +202,12 @@ void launch_merge_level(const MergeDesc* descs, int nm, const LevelMaps& maps, c
                         const LevelProbe* probe = nullptr);
 void launch_secular_standalone(int64_t K, const double* d, const double* z, double rho, int32_t* org,
                                double* tau, int32_t* status, hipStream_t s);
+
+// FP64 product for one merge whose HSS compression gave up (Sec. 2.2: Gu's
+// grouped products whenever HSS does not apply).  desc is the merge's device
+// descriptor, M its host copy.  The merge is marked as FP64 (path 0, HSS rank
+// -1), Uhat is rewritten in the grouped row order and the update GEMM runs for
+// this merge alone; the rest of the merge (ranks, deflated columns) is done.
+void launch_fp64_fallback(const MergeDesc* desc, const MergeDesc& M, const Scratch& S, hipStream_t s);
 
 }  // namespace phdc

@@ -1,4 +1,6 @@
 // Small utility kernels: status reset and the eigenvector sign convention.
+#include <algorithm>
+
 #include "phdc_internal.h"
 
 namespace phdc {
@@ -10,6 +12,25 @@ __global__ void k_clear_status(int32_t* status) { status[threadIdx.x] = 0; }
 
 void launch_clear_status(int32_t* status, hipStream_t s) {
   hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, s, status);
+}
+
+// Grid-stride scan for NaN or Inf; any lane that finds one raises the flag and
+// the status word (first failure wins).  Race-free: both are only ever set.
+__global__ void __launch_bounds__(256) k_scan_finite(const double* __restrict__ a, int64_t n, int32_t* flag,
+                                                     int32_t* status) {
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) bad |= !isfinite(a[i]);
+  if (__ballot(bad) != 0ULL && (threadIdx.x & 63) == 0) {
+    atomicOr(flag, 1);
+    set_status(status, PHDC_ERR_NONFINITE);
+  }
+}
+
+void launch_scan_finite(const double* a, int64_t n, int32_t* flag, int32_t* status, hipStream_t s) {
+  if (n <= 0 || a == nullptr) return;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 2048);
+  hipLaunchKernelGGL(k_scan_finite, dim3((unsigned)blocks), dim3(256), 0, s, a, n, flag, status);
 }
 
 // Eigenvectors are defined up to sign; this fixes it: in every column the entry

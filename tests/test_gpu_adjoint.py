@@ -23,6 +23,10 @@ def P():
     return P
 
 
+def _gen():
+    return torch.Generator(device="cuda").manual_seed(11)
+
+
 def _colstore(Q):
     """column-major storage of square matrices (B, n, n) -> contiguous (B, n, n) with [b, j, i] = Q_b(i, j)."""
     return torch.as_tensor(np.ascontiguousarray(np.transpose(Q, (0, 2, 1))), device="cuda")
@@ -89,21 +93,51 @@ def test_autograd_vs_fd_small(P):
     assert np.abs(g_all - fd).max() <= 1e-6 * np.abs(fd).max()
 
 
-@pytest.mark.parametrize("batch,n,ndir", [(4, 512, 4), (64, 4096, 4)])
-def test_autograd_batched_vs_solver_fd(P, batch, n, ndir):
-    # The differentiation workload: ramp matrices, loss = sum_k w_k lambda_k + <G, Q>,
-    # central differences (h = 1e-6) of the GPU solver itself along random unit
-    # directions in (d, e); normwise bound |g.v - FD| <= 1e-6 (|FD| + ||g||).
-    # Central differences of an eigenvector column are valid only if its eigenvalue
-    # gap is well above h (truncation error ~ (h/gap)^2/6) and its sign-defining
-    # entry is not nearly tied: G is restricted to columns with gap >= 1e-3 and a
-    # top-two magnitude ratio below 0.99 (at the unperturbed point); the
-    # eigenvalue term keeps every column.
-    d0, e0, w0, G0 = W.ramp_batch(batch, n, seed=0) if n <= 1024 else _ramp_big(batch, n)
+def _ramp_problem(batch, n):
+    """The differentiation workload: d_i = 4 i / n + U[-0.01, 0.01] (i = 1..n),
+    e_i ~ U[0.1, 0.5], loss weights w ~ N(0, 1) (numpy, seed 0) and G ~ N(0, 1) (torch,
+    seed 11, drawn on the GPU)."""
+    g = np.random.default_rng(0)
+    d = 4.0 * np.arange(1, n + 1, dtype=np.float64)[None, :] / n + g.uniform(-0.01, 0.01, (batch, n))
+    e = g.uniform(0.1, 0.5, (batch, n - 1))
+    w = g.standard_normal((batch, n))
+    G = torch.randn(batch, n, n, dtype=torch.float64, device="cuda", generator=_gen())
+    return d, e, w, G
+
+
+def _losses(P, dd, ee, bidx, w, G, chunk=32):
+    """Per-row loss sum_k w_k lambda_k + <G, Q> for rows of perturbed matrices:
+    dd (R, n), ee (R, n-1) device tensors; row r uses the weights w[bidx[r]], G[bidx[r]]."""
+    out = []
+    with torch.no_grad():
+        for a in range(0, dd.shape[0], chunk):
+            lam, Q = P.eigh_tridiagonal(dd[a:a + chunk], ee[a:a + chunk])
+            ix = bidx[a:a + chunk]
+            out.append((w[ix] * lam).sum(1) + (G[ix] * Q).sum((1, 2)))
+            del lam, Q
+    return torch.cat(out)
+
+
+@pytest.mark.parametrize("batch,n", [(4, 512), (64, 4096)])
+def test_autograd_vs_solver_fd(P, batch, n):
+    # The differentiation workload: loss = sum_k w_k lambda_k + <G, Q> over the batch;
+    # gradients on (d, e) from the adjoint kernels against central differences
+    # (h = 1e-6) of the GPU solver itself:
+    #  * 8 unit directions, each spanning all (d, e) entries of one matrix of the batch
+    #    (the loss is a sum over matrices, so a direction inside one matrix is a
+    #    direction of the batch's input space): |g.v - FD| <= 1e-6 |FD| for each;
+    #  * 256 random coordinates: normwise ||g_S - FD_S||_inf <= 1e-6 ||FD_S||_inf.
+    # The eigenvector term of the loss keeps the columns whose eigenvalue gap is
+    # >= 1e-3 and whose two largest entry magnitudes differ by >= 1% (central
+    # differences of a column are valid only for gap >> h: their truncation error is
+    # about (h/gap)^2/6 of the column's derivative, below 2e-7 at gap 1e-3; and the
+    # sign convention must not flip under the perturbation).  The eigenvalue term
+    # keeps every column.  Coordinates whose perturbation moves some eigenvalue by more
+    # than a tenth of its gap (central differences there straddle a near-crossing) are
+    # reported, not checked.
+    d0, e0, w0, G = _ramp_problem(batch, n)
     dev = "cuda"
     w = torch.tensor(w0, device=dev)
-    G = torch.tensor(G0, device=dev) if G0 is not None else torch.randn(batch, n, n, dtype=torch.float64,
-                                                                         device=dev, generator=_gen())
     with torch.no_grad():
         lam0, Q0 = P.eigh_tridiagonal(torch.tensor(d0, device=dev), torch.tensor(e0, device=dev))
         gap = torch.full_like(lam0, float("inf"))
@@ -111,45 +145,81 @@ def test_autograd_batched_vs_solver_fd(P, batch, n, ndir):
         gap[:, 1:] = torch.minimum(gap[:, 1:], dl)
         gap[:, :-1] = torch.minimum(gap[:, :-1], dl)
         top2 = Q0.abs().topk(2, dim=1).values  # (B, 2, n)
-        ok = (gap >= 1e-3) & (top2[:, 1, :] < 0.99 * top2[:, 0, :])
-        G = G * ok[:, None, :].to(G.dtype)
-    assert ok.float().mean().item() > 0.1
+        keep = (gap >= 1e-3) & (top2[:, 1, :] < 0.99 * top2[:, 0, :])
+        G = G * keep[:, None, :].to(G.dtype)
+    kept = keep.float().mean().item()
+    print(f"\n[fd] eigenvector-term columns kept: {kept:.3f}")
+    assert kept > 0.05
     d = torch.tensor(d0, device=dev, requires_grad=True)
     e = torch.tensor(e0, device=dev, requires_grad=True)
-    L = _loss(P, d, e, w, G)
-    L.backward()
+    lam, Q = P.eigh_tridiagonal(d, e)
+    ((w * lam).sum() + (G * Q).sum()).backward()
     gd, ge = d.grad.detach(), e.grad.detach()
-    gnorm = float(torch.sqrt((gd ** 2).sum() + (ge ** 2).sum()))
-    g = torch.Generator(device=dev).manual_seed(7)
     h = 1e-6
-    with torch.no_grad():
-        for k in range(ndir):
-            vd = torch.randn(batch, n, dtype=torch.float64, device=dev, generator=g)
-            ve = torch.randn(batch, n - 1, dtype=torch.float64, device=dev, generator=g)
-            nv = torch.sqrt((vd ** 2).sum() + (ve ** 2).sum())
-            vd, ve = vd / nv, ve / nv
-            Lp = _loss(P, d.detach() + h * vd, e.detach() + h * ve, w, G)
-            Lm = _loss(P, d.detach() - h * vd, e.detach() - h * ve, w, G)
-            fd = float((Lp - Lm) / (2 * h))
-            an = float((gd * vd).sum() + (ge * ve).sum())
-            assert abs(an - fd) <= 1e-6 * (abs(fd) + gnorm), (k, an, fd, gnorm)
+    rng = np.random.default_rng(7)
+    base_d, base_e = torch.tensor(d0, device=dev), torch.tensor(e0, device=dev)
 
+    # directions, one matrix each
+    bdir = rng.choice(batch, 8, replace=batch < 8)
+    vd = torch.tensor(rng.standard_normal((8, n)), device=dev)
+    ve = torch.tensor(rng.standard_normal((8, n - 1)), device=dev)
+    nv = torch.sqrt((vd ** 2).sum(1) + (ve ** 2).sum(1))[:, None]
+    vd, ve = vd / nv, ve / nv
+    bt = torch.tensor(bdir, device=dev)
+    dd = torch.cat([base_d[bt] + h * vd, base_d[bt] - h * vd])
+    ee = torch.cat([base_e[bt] + h * ve, base_e[bt] - h * ve])
+    L = _losses(P, dd, ee, torch.cat([bt, bt]), w, G)
+    fd = ((L[:8] - L[8:]) / (2 * h)).cpu().numpy()
+    an = ((gd[bt] * vd).sum(1) + (ge[bt] * ve).sum(1)).cpu().numpy()
+    rel = np.abs(an - fd) / np.abs(fd)
+    print("[fd] directions: |g.v - FD| / |FD| =", np.array2string(rel, precision=2))
+    assert np.all(rel <= 1e-6), rel
 
-def _gen():
-    return torch.Generator(device="cuda").manual_seed(11)
-
-
-def _ramp_big(batch, n):
-    g = np.random.default_rng(0)
-    d = 4.0 * np.arange(1, n + 1, dtype=np.float64)[None, :] / n + g.uniform(-0.01, 0.01, (batch, n))
-    e = g.uniform(0.1, 0.5, (batch, n - 1))
-    w = g.standard_normal((batch, n))
-    return d, e, w, None
+    # coordinates
+    nc = 256
+    bc = rng.integers(0, batch, nc)
+    is_d = rng.random(nc) < n / (2 * n - 1)
+    ic = np.where(is_d, rng.integers(0, n, nc), rng.integers(0, n - 1, nc))
+    bct = torch.tensor(bc, device=dev)
+    dd = base_d[bct].clone().repeat(2, 1)
+    ee = base_e[bct].clone().repeat(2, 1)
+    rows = np.arange(nc)
+    for sgn, off in ((1.0, 0), (-1.0, nc)):
+        dd[torch.tensor(off + rows[is_d], device=dev), torch.tensor(ic[is_d], device=dev)] += sgn * h
+        ee[torch.tensor(off + rows[~is_d], device=dev), torch.tensor(ic[~is_d], device=dev)] += sgn * h
+    L = _losses(P, dd, ee, bct.repeat(2), w, G)
+    fd = ((L[:nc] - L[nc:]) / (2 * h)).cpu().numpy()
+    gdh, geh = gd.cpu().numpy(), ge.cpu().numpy()
+    an = np.where(is_d, gdh[bc, np.minimum(ic, n - 1)], geh[bc, np.minimum(ic, n - 2)])
+    # eigenvalue shifts of each coordinate's perturbation: h q_ik^2 (d_i), 2 h |q_ik q_i+1,k| (e_i)
+    ict = torch.tensor(ic, device=dev)
+    r0 = Q0[bct, ict, :]                                   # row i of each coordinate's Q, over k
+    r1 = Q0[bct, torch.clamp(ict + 1, max=n - 1), :]
+    isd = torch.tensor(is_d, device=dev)[:, None]
+    shift = torch.where(isd, h * r0 ** 2, 2 * h * (r0 * r1).abs())
+    near = (shift > gap[bct] / 10).any(1).cpu().numpy()
+    ok = ~near
+    err = np.abs(an - fd)
+    normwise = err[ok].max() / np.abs(fd[ok]).max()
+    print(f"[fd] coordinates: {ok.sum()} checked, {near.sum()} near a crossing (reported); "
+          f"normwise {normwise:.2e}; elementwise relative median {np.median(err[ok] / np.abs(fd[ok])):.1e}")
+    if near.any():
+        print("[fd] near-crossing coordinates, relative error:",
+              np.array2string(err[near] / np.maximum(np.abs(fd[near]), 1e-300), precision=2))
+    assert ok.sum() >= 0.9 * nc
+    assert normwise <= 1e-6
 
 
 def test_backward_full_size_vs_formula_from_oracle(P, orc):
-    # one matrix of the differentiation workload (n = 4096): the library's gradient for the
-    # library's eigenpairs vs the plain formula (numpy products) on the oracle's eigenpairs
+    # One matrix of the differentiation workload (n = 4096): the library's gradient for
+    # the library's eigenpairs vs the plain formula (numpy products) on the oracle's
+    # eigenpairs.  G keeps the columns whose eigenvalue gap is >= 1e-3 (as in the FD
+    # check).  The two solvers' eigenpairs agree up to rotations inside near-degenerate
+    # pairs (gaps down to ~3e-7), determined to ~u ||T|| / gap ~ 2e-9; both gradient
+    # terms are invariant under such rotations to first order (the eigenvalue term
+    # changes by |w_j - w_k| times the rotation, the eigenvector term through the
+    # reduced resolvent sum_j q_j q_j^T / (lambda_k - lambda_j), whose pair terms differ
+    # by gap_pair / (lambda_k - lambda_j)^2 <= 0.3 of the rotation): 1e-8 relative.
     n = 4096
     g = np.random.default_rng(5)
     d, e = W.ramp(n, seed=5)
@@ -157,6 +227,10 @@ def test_backward_full_size_vs_formula_from_oracle(P, orc):
     Qr = canon(Qr)
     w = g.standard_normal(n)
     G = g.standard_normal((n, n))
+    gapr = np.full(n, np.inf)
+    gapr[1:] = np.minimum(gapr[1:], np.diff(lr))
+    gapr[:-1] = np.minimum(gapr[:-1], np.diff(lr))
+    G[:, gapr < 1e-3] = 0.0
     M = Qr.T @ G
     F = lr[None, :] - lr[:, None]
     np.fill_diagonal(F, 1.0)
@@ -171,6 +245,6 @@ def test_backward_full_size_vs_formula_from_oracle(P, orc):
     L.backward()
     gd, ge = dt.grad.cpu().numpy(), et.grad.cpu().numpy()
     scale = max(np.abs(dref).max(), np.abs(eref).max())
-    # the two eigen-decompositions agree to ~1e-13; gradients amplify by 1/gap (min gap ~ 3e-7)
-    assert np.abs(gd - dref).max() <= 1e-5 * scale
-    assert np.abs(ge - eref).max() <= 1e-5 * scale
+    errd, erre = np.abs(gd - dref).max() / scale, np.abs(ge - eref).max() / scale
+    print(f"\n[adjoint n=4096] relative error d {errd:.2e} e {erre:.2e}")
+    assert errd <= 1e-8 and erre <= 1e-8

@@ -101,3 +101,53 @@ def test_graph_replay_matches_eager(P, mode):
         ds, es = rounds[(len(rounds) * 2 - 1) % 3]
         assert orth(Qb) <= (1e-11 if mode == "split" else 1e-12)
         assert residual(ds[b], es[b], lb, Qb) <= (1e-12 if mode == "split" else 1e-13)
+
+
+def test_batched_full_size_4096(P, orc):
+    # The batched workload at its stated size: 4096 tridiagonals, n_b iid U{32..1024}
+    # (seed 0), d, e iid N(0,1).  Every matrix: orthogonality and residual of its
+    # eigenvectors, computed on the GPU.  64 sampled matrices (the largest among them):
+    # eigenvalues against the oracle.  The prepared, graph-replayed launch must give
+    # the same bits as the direct call.
+    sizes = W.batch_sizes(4096, 32, 1024, seed=0).tolist()
+    ds, es = W.normal_batch(sizes, seed=0)
+    dcat, ecat = np.concatenate(ds), np.concatenate(es)
+    lam, Q, off, qoff = P.stedc_batched(sizes, dcat, ecat)
+    dt = torch.tensor(dcat, device="cuda")
+    et = torch.tensor(ecat, device="cuda")
+    orths, ress = [], []
+    eo = 0
+    for b, n in enumerate(sizes):
+        Qb = Q[qoff[b]:qoff[b] + n * n].view(n, n).t()  # column k = eigenvector k
+        lb = lam[off[b]:off[b] + n]
+        G = Qb.T @ Qb
+        G.diagonal().sub_(1.0)
+        orths.append(G.abs().max())
+        db, eb = dt[off[b]:off[b] + n], et[eo:eo + n - 1]
+        eo += n - 1
+        R = db[:, None] * Qb - Qb * lb[None, :]
+        R[:-1] += eb[:, None] * Qb[1:]
+        R[1:] += eb[:, None] * Qb[:-1]
+        ress.append(torch.linalg.norm(R) / (n * lb.abs().max()))
+    worst_orth = torch.stack(orths).max().item()
+    worst_res = torch.stack(ress).max().item()
+    assert worst_orth <= 1e-12, worst_orth
+    assert worst_res <= 1e-13, worst_res
+    pick = set(np.random.default_rng(0).choice(len(sizes), 63, replace=False).tolist())
+    pick.add(int(np.argmax(sizes)))
+    lam_h = lam.cpu().numpy()
+    for b in sorted(pick):
+        n = sizes[b]
+        lr, _, _ = orc.stedc(ds[b], es[b])
+        assert np.abs(lam_h[off[b]:off[b] + n] - lr).max() <= 1e-13 * np.abs(lr).max(), b
+    # the same batch planned once and replayed from a HIP graph: identical bits
+    bs = P.BatchedSolver(sizes, P.opts())
+    bs.d[: len(dcat)] = dt
+    bs.e[: len(ecat)] = torch.tensor(ecat, device="cuda")
+    bs.prepare()
+    bs.capture()
+    for _ in range(2):
+        bs.replay()
+        torch.cuda.synchronize()
+        assert P.status(bs.work) == 0
+        assert torch.equal(bs.lam[: len(dcat)], lam) and torch.equal(bs.Q[: Q.numel()], Q)

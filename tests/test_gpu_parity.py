@@ -4,16 +4,19 @@ Tolerances (fixed by the target of the build; relative to ||T|| = max |lambda|):
   max |lambda - lambda_ref|      <= 1e-13 ||T||
   ||Q^T Q - I||_max              <= 1e-12
   ||T Q - Q Lambda||_F/(n ||T||) <= 1e-13
-Eigenvector columns are compared entry by entry only where the eigenvalue is
-separated from its neighbours (an eigenvector is determined up to sign, and
-only to about u ||T|| / gap); signs are aligned to the oracle's first.
+Eigenvector columns are compared entry by entry, each within
+max(1e-14 / gap_k, 1e-13) where gap_k ||T|| separates its eigenvalue from the
+nearest other one (an eigenvector is determined up to sign, and only to about
+u ||T|| / gap; 1e-11 at gap_k = 1e-3), skipping tight clusters whose bound
+exceeds 1e-3; signs are aligned to the oracle's first.
 """
 import numpy as np
 import pytest
 import torch
 
 import workloads as W
-from checks import align, isolated_columns, orth, residual, toeplitz_121_exact, tri_dense
+from checks import (align, column_gaps, isolated_columns, orth, residual, toeplitz_121_exact, tri_dense,
+                    vec_tol, vector_error_ratio)
 
 pytestmark = pytest.mark.gpu
 
@@ -34,7 +37,7 @@ def _np(t):
     return t.detach().cpu().numpy()
 
 
-def _check_eig(d, e, lam, Q, lref=None, Qref=None, vec_tol=1e-9, orth_tol=ORTH_TOL, res_tol=RES_TOL):
+def _check_eig(d, e, lam, Q, lref=None, Qref=None, vfac=1.0, orth_tol=ORTH_TOL, res_tol=RES_TOL):
     d = np.asarray(d, dtype=np.float64)
     e = np.asarray(e, dtype=np.float64)
     nrm = max(np.abs(lam).max(), 1e-300) if lam.size else 1.0
@@ -45,10 +48,8 @@ def _check_eig(d, e, lam, Q, lref=None, Qref=None, vec_tol=1e-9, orth_tol=ORTH_T
     assert orth(Q) <= orth_tol
     assert residual(d, e, lam, Q) <= res_tol
     if Qref is not None and lam.size:
-        iso = isolated_columns(lref, 1e-3 * nrm)
-        if iso.any():
-            diff = np.abs(align(Q, Qref)[:, iso] - Qref[:, iso]).max()
-            assert diff <= vec_tol, f"eigenvector difference {diff:.3e}"
+        ratio, ncols = vector_error_ratio(Q, Qref, lref, factor=vfac)
+        assert ratio <= 1.0, f"eigenvector error {ratio:.2f} x the gap bound ({ncols} columns)"
 
 
 # ---------------------------------------------------------------- secular roots
@@ -107,8 +108,8 @@ def test_merge_parity(P, orc, n1, n2, dup, tiny, seed):
     assert np.abs(lam - lref).max() <= LAM_TOL * nrm
     assert orth(Q) <= ORTH_TOL
     assert np.linalg.norm(A @ Q - Q * lam) / (m * nrm) <= RES_TOL
-    iso = isolated_columns(lref, 1e-3 * nrm)
-    assert np.abs(align(Q, Qref)[:, iso] - Qref[:, iso]).max() <= 1e-9
+    ratio, ncols = vector_error_ratio(Q, Qref, lref)
+    assert ratio <= 1.0, f"eigenvector error {ratio:.2f} x the gap bound ({ncols} columns)"
     # deflation decisions are integer results: identical to the oracle's
     assert list(st[:6]) == list(st_ref[:6])
 
@@ -122,7 +123,8 @@ def test_merge_fig3(P, orc):
     assert P.merge_stats(work)[0] == 1000 == st_ref[0]
     assert np.abs(lam - lref).max() <= LAM_TOL * np.abs(lref).max()
     assert orth(Q) <= ORTH_TOL
-    assert np.abs(align(Q, Qref) - Qref).max() <= 1e-9
+    ratio, ncols = vector_error_ratio(Q, Qref, lref)
+    assert ratio <= 1.0 and ncols > 900, (ratio, ncols)
 
 
 def test_merge_all_deflated(P):
@@ -175,7 +177,8 @@ def test_stedc_toeplitz_2048_vs_oracle(P, orc):
     lam, Q, work = P.stedc(d, e, return_work=True)
     assert list(P.merge_stats(work)[:6]) == list(st_ref[:6]) == [1024, 0, 1024, 0, 0, 1024]
     lr, Vr = toeplitz_121_exact(2048, -1.0)
-    _check_eig(d, e, _np(lam), _np(Q), lr, Vr, vec_tol=1e-8)
+    _check_eig(d, e, _np(lam), _np(Q), lr, Vr)
+    assert vector_error_ratio(_np(Q), Vr, lr)[1] == 2048  # every column compared
 
 
 @pytest.mark.parametrize("gen,n,seed", [("uniform", 500, 0), ("normal_pos", 777, 1), ("normal", 1024, 2),
@@ -198,7 +201,7 @@ def test_stedc_deflation_stress(P, orc, gen, n, leaf, mode):
     lref, Qref, _ = orc.stedc(d, e, leaf=leaf)
     lam, Q = P.stedc(d, e, o=o)
     loose = mode == "split"  # the split-precision update is held to 10x the FP64 bounds
-    _check_eig(d, e, _np(lam), _np(Q), lref, Qref, vec_tol=1e-8 if loose else 1e-9,
+    _check_eig(d, e, _np(lam), _np(Q), lref, Qref, vfac={"fp64": 1.0, "hss": 10.0, "split": 10.0}[mode],
                orth_tol=10 * ORTH_TOL if loose else ORTH_TOL, res_tol=10 * RES_TOL if loose else RES_TOL)
 
 
@@ -219,13 +222,16 @@ def test_stedc_decoupled(P, orc):
     _check_eig(d, e, _np(lam), _np(Q), lref)
 
 
-def test_stedc_uniform_16384_full_size(P, orc):
-    # the headline workload: n = 16384, d, e ~ U[-1, 1]; eigenvalues vs the oracle,
-    # orthogonality and residual of the full Q on the GPU, sampled columns vs the oracle
+@pytest.mark.parametrize("leaf", [32, 16])
+def test_stedc_uniform_16384_full_size(P, orc, leaf):
+    # the headline workload: n = 16384, d, e ~ U[-1, 1], at the library's default leaf
+    # size and at the benchmarked one; eigenvalues vs the oracle (same split tree),
+    # orthogonality and residual of the full Q on the GPU, sampled isolated columns vs
+    # the oracle
     n = 16384
     d, e = W.uniform(n, 0)
-    lref, Qref, st_ref = orc.stedc(d, e)
-    lam, Q, work = P.stedc(d, e, return_work=True)
+    lref, Qref, st_ref = orc.stedc(d, e, leaf=leaf)
+    lam, Q, work = P.stedc(d, e, o=P.opts(leaf_size=leaf), return_work=True)
     assert list(P.merge_stats(work)[:6]) == list(st_ref[:6])
     lam_h = _np(lam)
     nrm = np.abs(lref).max()
@@ -241,13 +247,14 @@ def test_stedc_uniform_16384_full_size(P, orc):
     R[1:] += et[:, None] * Qd[:-1]
     assert (torch.linalg.norm(R) / (n * nrm)).item() <= RES_TOL
     del R
-    # eigenvector entries are determined to about u ||T|| / gap: compare columns whose
-    # eigenvalue is separated from both neighbours by at least 1e-5 ||T||
-    iso = np.flatnonzero(isolated_columns(lref, 1e-5 * nrm))
-    cols = np.random.default_rng(0).choice(iso, min(64, iso.size), replace=False)
-    assert cols.size >= 32
+    # 128 sampled columns, each within max(1e-14 / gap_k, 1e-13) of the oracle's
+    gap = column_gaps(lref) / nrm
+    cand = np.flatnonzero(1e-14 / gap <= 1e-3)
+    cols = np.sort(np.random.default_rng(0).choice(cand, 128, replace=False))
     Qs = _np(Q[:, torch.tensor(cols, device=Q.device)])
-    assert np.abs(align(Qs, Qref[:, cols]) - Qref[:, cols]).max() <= 1e-9
+    diff = np.abs(align(Qs, Qref[:, cols]) - Qref[:, cols]).max(axis=0)
+    bound = np.maximum(1e-14 / gap[cols], 1e-13)
+    assert np.all(diff <= bound), float((diff / bound).max())
 
 
 def test_stedc_canonical_sign(P):

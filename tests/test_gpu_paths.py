@@ -14,7 +14,7 @@ import pytest
 import torch
 
 import workloads as W
-from checks import align, isolated_columns, orth, residual, toeplitz_121_exact
+from checks import align, isolated_columns, orth, residual, toeplitz_121_exact, vec_tol, vector_error_ratio
 
 pytestmark = pytest.mark.gpu
 
@@ -30,11 +30,17 @@ def _np(t):
     return t.detach().cpu().numpy()
 
 
+# The HSS product adds the compression error (entries of Uhat truncated at about
+# hss_rel_tol sqrt(d) ~ 1e-13, d = 192 samples) to every update column, independent of
+# the eigenvalue gap: eigenvector bounds are 10x those of the FP64 path.
+HSS_FACTOR = 10.0
+
+
 def _hss(P, min_k, leaf=128, d=192):
     return P.opts(gemm_mode=P.GEMM_HSS, hss_min_K=min_k, hss_leaf=leaf, hss_samples=d, hss_samples_inc=64)
 
 
-def _merge_check(P, orc, D, z, rho, Q1, Q2, o, orth_tol, res_tol, vec_tol):
+def _merge_check(P, orc, D, z, rho, Q1, Q2, o, orth_tol, res_tol, vec_factor=1.0):
     lref, Qref, st_ref = orc.merge(D, z, rho, Q1, Q2)
     lam, Q, work = P.merge(D, z, rho, torch.tensor(Q1), torch.tensor(Q2), o=o, return_work=True)
     st = P.merge_stats(work)
@@ -49,8 +55,8 @@ def _merge_check(P, orc, D, z, rho, Q1, Q2, o, orth_tol, res_tol, vec_tol):
     assert np.abs(lam - lref).max() <= 1e-13 * nrm
     assert orth(Q) <= orth_tol
     assert np.linalg.norm(A @ Q - Q * lam) / (m * nrm) <= res_tol
-    iso = isolated_columns(lref, 1e-3 * nrm)
-    assert np.abs(align(Q, Qref)[:, iso] - Qref[:, iso]).max() <= vec_tol
+    ratio, ncols = vector_error_ratio(Q, Qref, lref, factor=vec_factor)
+    assert ratio <= 1.0, f"eigenvector error {ratio:.2f} x the gap bound ({ncols} columns)"
     assert list(st[:6]) == list(st_ref[:6])
     return st
 
@@ -62,19 +68,19 @@ def _merge_check(P, orc, D, z, rho, Q1, Q2, o, orth_tol, res_tol, vec_tol):
 def test_hss_merge_fig3(P, orc, N, leaf, seed):
     # the rank-one merge of Sec. 2.2: poles i/N, rho = 1, random unit z, no deflation
     D, z, rho, Q1, Q2 = W.fig3_merge(N, seed=seed)
-    st = _merge_check(P, orc, D, z, rho, Q1, Q2, _hss(P, 256, leaf), 1e-12, 1e-13, 1e-10)
+    st = _merge_check(P, orc, D, z, rho, Q1, Q2, _hss(P, 256, leaf), 1e-12, 1e-13, HSS_FACTOR)
     assert st[6] == 2 and 0 < st[7] < 192  # HSS path taken, ranks found below the sample count
 
 
 def test_hss_merge_with_deflation(P, orc):
     D, z, rho, Q1, Q2 = W.random_merge(700, 650, seed=9, dup=50, tiny=40)
-    st = _merge_check(P, orc, D, z, rho, Q1, Q2, _hss(P, 256, 128), 1e-12, 1e-13, 1e-10)
+    st = _merge_check(P, orc, D, z, rho, Q1, Q2, _hss(P, 256, 128), 1e-12, 1e-13, HSS_FACTOR)
     assert st[6] == 2
 
 
 def test_hss_below_threshold_is_plain(P, orc):
     D, z, rho, Q1, Q2 = W.random_merge(100, 90, seed=3)
-    st = _merge_check(P, orc, D, z, rho, Q1, Q2, _hss(P, 4096), 1e-12, 1e-13, 1e-9)
+    st = _merge_check(P, orc, D, z, rho, Q1, Q2, _hss(P, 4096), 1e-12, 1e-13)
     assert st[6] == 0
 
 
@@ -90,7 +96,8 @@ def test_hss_stedc_toeplitz_odd(P, n):
     assert np.abs(lam - lr).max() <= 1e-13 * 4
     assert orth(Q) <= 1e-12
     assert residual(d, e, lam, Q) <= 1e-13
-    assert np.abs(align(Q, Vr) - Vr).max() <= 1e-9
+    ratio, ncols = vector_error_ratio(Q, Vr, lr)
+    assert ratio <= 1.0 and ncols == n, (ratio, ncols)
 
 
 @pytest.mark.parametrize("gen,n", [("clement", 2047), ("hermite", 2048)])
@@ -111,13 +118,13 @@ def test_hss_stedc_example3(P, orc, gen, n):
                                                  (300, 513, 0, 0, 8), (700, 650, 50, 40, 9)])
 def test_split_merge(P, orc, n1, n2, dup, tiny, seed):
     D, z, rho, Q1, Q2 = W.random_merge(n1, n2, seed=seed, dup=dup, tiny=tiny)
-    st = _merge_check(P, orc, D, z, rho, Q1, Q2, P.opts(gemm_mode=P.GEMM_SPLIT), 1e-11, 1e-12, 1e-8)
+    st = _merge_check(P, orc, D, z, rho, Q1, Q2, P.opts(gemm_mode=P.GEMM_SPLIT), 1e-11, 1e-12, 10.0)
     assert st[6] == 1
 
 
 def test_split_fig3(P, orc):
     D, z, rho, Q1, Q2 = W.fig3_merge(2000, seed=4)
-    _merge_check(P, orc, D, z, rho, Q1, Q2, P.opts(gemm_mode=P.GEMM_SPLIT), 1e-11, 1e-12, 1e-8)
+    _merge_check(P, orc, D, z, rho, Q1, Q2, P.opts(gemm_mode=P.GEMM_SPLIT), 1e-11, 1e-12, 10.0)
 
 
 def test_split_error_shrinks_with_slices(P, orc):
