@@ -115,6 +115,29 @@ int phdc_stedc_workspace(int64_t n, const phdc_opts *o, size_t *bytes);
 int phdc_stedc(int64_t n, const double *d, const double *e, double *lambda, double *Q, int64_t ldq,
                void *work, size_t lwork, const phdc_opts *o, void *stream);
 
+/* ---------------------------------------------------------------- stedc without allocation
+ * For callers that cannot allocate memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same solve as phdc_stedc,
+ * with the workspace taken from a static device array of
+ * PHDC_NOALLOC_SCRATCH_BYTES bytes that the library holds on every GPU it runs
+ * on until the process ends (enough for n up to about 2450 in the FP64 form
+ * and 1500 in the split-precision form).  The call makes no hipMalloc,
+ * hipHostMalloc or hipFree and no other allocating library call; it uploads the
+ * solve's plan from pageable host memory and waits for that upload, then
+ * enqueues the kernels.  Every call on a GPU shares that GPU's array, which
+ * keeps the last call's contents (each call starts by clearing what must start
+ * at zero): calls that overlap on one GPU (two streams, two threads) race,
+ * calls in sequence on one stream are safe.
+ *   n, d, e, lambda, Q, ldq, o, stream: as for phdc_stedc
+ *   info   device, 1 int32: receives the call's status word (enum phdc_info)
+ * Returns 0; -1 if n < 0 or the solve needs more than PHDC_NOALLOC_SCRATCH_BYTES
+ * of workspace; -(argument index) for other invalid arguments, -8 also for
+ * PHDC_GEMM_HSS (whose host read-back uses pinned memory) or invalid options;
+ * PHDC_E_HIP. */
+#define PHDC_NOALLOC_SCRATCH_BYTES ((size_t)96 << 20)
+int phdc_stedc_noalloc(int64_t n, const double *d, const double *e, double *lambda, double *Q, int64_t ldq,
+                       int32_t *info, const phdc_opts *o, void *stream);
+
 /* ---------------------------------------------------------------- merge
  * One rank-one merge (Eq. (3)-(6)): the eigen-decomposition of
  *     diag(Q1, Q2) (D + rho z z^T) diag(Q1, Q2)^T,   D = diag(D[0:n1], D[n1:n1+n2]).

@@ -23,6 +23,7 @@ STATUS_OK, STATUS_LEAF, STATUS_SECULAR, STATUS_UNSORTED, STATUS_NONFINITE = 0, 1
 STATUS_TEXT = {0: "ok", 1: "leaf QL did not converge", 2: "secular root did not converge",
                3: "merge input D1/D2 not ascending", 4: "non-finite input"}
 E_HIP = -100  # host-side return code: a HIP runtime call failed
+NOALLOC_SCRATCH_BYTES = 96 << 20  # static workspace of phdc_stedc_noalloc (PHDC_NOALLOC_SCRATCH_BYTES)
 # bits of Opts.force_fail (test hooks)
 FAIL_LEAF, FAIL_SECULAR, FAIL_HSS = 1, 2, 4
 
@@ -90,6 +91,7 @@ def load():
     lib.phdc_autotune_gemm_workspace.argtypes = [_i64, P(_sz)]
     lib.phdc_autotune_gemm.argtypes = [_i64, _vp, _sz, _vp]
     lib.phdc_gemm_tile_table.argtypes = [P(ctypes.c_int32), ctypes.c_int]
+    lib.phdc_stedc_noalloc.argtypes = [_i64, _vp, _vp, _vp, _vp, _i64, _vp, P(Opts), _vp]
     lib.phdc_hss_gemm_workspace.argtypes = [_i64, _i64, P(Opts), P(_sz)]
     lib.phdc_hss_gemm.argtypes = [_i64, _vp, _i64, _i64, _vp, _i64, _vp, _i64, P(ctypes.c_int32), _vp, _sz, P(Opts),
                                   _vp]
@@ -102,7 +104,7 @@ EXPORTS = ["phdc_stedc_batched_prepare", "phdc_launch_prepared", "phdc_opts_defa
            "phdc_stedc_backward", "phdc_status", "phdc_release", "phdc_merge_stats", "phdc_secular", "phdc_merge_table",
            "phdc_profile_enable", "phdc_profile_read", "phdc_profile_select", "phdc_autotune_gemm_workspace",
            "phdc_autotune_gemm",
-           "phdc_gemm_tile_table", "phdc_hss_gemm_workspace", "phdc_hss_gemm"]
+           "phdc_gemm_tile_table", "phdc_hss_gemm_workspace", "phdc_hss_gemm", "phdc_stedc_noalloc"]
 
 
 def autotune_gemm(max_m: int = 4096, device="cuda", stream=None) -> list:

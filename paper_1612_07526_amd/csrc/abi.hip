@@ -439,8 +439,10 @@ void launch_prepared_all(char* base, const Prepared& P, hipStream_t s) {
 // Build the device plan (descriptors, leaves, block maps), upload it and
 // launch every kernel of the solve.  With prepare_only the plan is uploaded
 // synchronously and kept for phdc_launch_prepared instead.
+// no_alloc: upload the plan from pageable host memory and wait for the upload
+// (no pinned staging buffer is allocated); the HSS path is not taken.
 int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n, void* work, const phdc_opts* o,
-              hipStream_t s, bool prepare_only = false) {
+              hipStream_t s, bool prepare_only = false, bool no_alloc = false) {
   const Tree& T = SU.T;
   const Sizes& z = SU.z;
   const Layout& L = SU.L;
@@ -580,6 +582,14 @@ int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n,
   }
   forget_prepared(work);  // the plan on the device is about to change
   P.o.check_finite = 0;   // the entry point has scanned the inputs already
+  if (no_alloc) {
+    if (hss_threshold(o) > 0) return -9;
+    if (hipMemcpyAsync(base + plan0, plan.data(), plan.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return PHDC_E_HIP;
+    launch_prepared_all(base, P, s);
+    return hipGetLastError() == hipSuccess ? 0 : PHDC_E_HIP;
+  }
   if (hss_threshold(o) <= 0) {
     if (upload(work, base + plan0, plan, s) != 0) return PHDC_E_HIP;
     launch_prepared_all(base, P, s);
@@ -674,6 +684,14 @@ int phdc_stedc_workspace(int64_t n, const phdc_opts* o, size_t* bytes) {
 
 int phdc_stedc(int64_t n, const double* d, const double* e, double* lambda, double* Q, int64_t ldq, void* work,
                size_t lwork, const phdc_opts* o, void* stream) {
+  return stedc_impl(n, d, e, lambda, Q, ldq, work, lwork, o, (hipStream_t)stream, false);
+}
+
+}  // extern "C"
+
+// phdc_stedc; no_alloc: the plan upload allocates nothing (phdc_stedc_noalloc).
+int phdc::stedc_impl(int64_t n, const double* d, const double* e, double* lambda, double* Q, int64_t ldq, void* work,
+                     size_t lwork, const phdc_opts* o, hipStream_t stream, bool no_alloc) {
   phdc_opts def;
   if (!o) { phdc_opts_default(&def); o = &def; }
   if (n < 0) return -1;
@@ -714,8 +732,10 @@ int phdc_stedc(int64_t n, const double* d, const double* e, double* lambda, doub
   BF.qoff = {0};
   BF.ld[0] = {ldq};
   BF.ld[1] = {n};
-  return run_solve(SU, BF, {n}, work, o, (hipStream_t)stream);
+  return run_solve(SU, BF, {n}, work, o, stream, false, no_alloc);
 }
+
+extern "C" {
 
 int phdc_stedc_batched_workspace(int64_t B, const int64_t* n_host, const phdc_opts* o, size_t* bytes) {
   phdc_opts def;

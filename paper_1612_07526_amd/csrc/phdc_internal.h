@@ -203,6 +203,11 @@ void launch_merge_level(const MergeDesc* descs, int nm, const LevelMaps& maps, c
 void launch_secular_standalone(int64_t K, const double* d, const double* z, double rho, int32_t* org,
                                double* tau, int32_t* status, hipStream_t s);
 
+// phdc_stedc; no_alloc: the plan is uploaded from pageable host memory (no
+// pinned staging buffer), the call waits for it, and the HSS path is refused.
+int stedc_impl(int64_t n, const double* d, const double* e, double* lambda, double* Q, int64_t ldq, void* work,
+               size_t lwork, const phdc_opts* o, hipStream_t s, bool no_alloc);
+
 // FP64 product for one merge whose HSS compression gave up (Sec. 2.2: Gu's
 // grouped products whenever HSS does not apply).  desc is the merge's device
 // descriptor, M its host copy.  The merge is marked as FP64 (path 0, HSS rank
