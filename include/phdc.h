@@ -219,10 +219,12 @@ int phdc_merge_stats(const void *work, int32_t *stats_host);
  * the recorded events, returns per-phase milliseconds and launch counts in
  * ms[0:nphase], count[0:nphase] (phase order: leaf, deflate, rotate, secular,
  * loewner, uhat-norm, uhat-write, rank, gemm, copy, sign, split-slice,
- * split-gemm, hss-sample, hss-compress, hss-apply, adjoint-gemm, adjoint-band)
- * and forgets them.  A merge level runs some steps in one launch, timed under
- * one phase: "secular" = rotations + secular roots (merges of at most 64 rows:
- * also Loewner z, column norms, Uhat and output ranks); "loewner" = Loewner z +
+ * split-gemm, hss-sample, hss-compress, hss-apply, adjoint-gemm, adjoint-band,
+ * small-merge) and forgets them.  A merge level runs some steps in one launch,
+ * timed under one phase: "small-merge" = every step of the merges of at most 64
+ * rows on the FP64 path (one workgroup each); "secular" = rotations + secular
+ * roots (levels whose merges have at most 64 rows on the other paths: also
+ * Loewner z, column norms, Uhat and output ranks); "loewner" = Loewner z +
  * output ranks; "uhat-write" = column norms + Uhat + the deflated-column copy
  * ("uhat-norm" when the norms run first, for normalized Uhat); "copy" = the
  * deflated-column copy of a lone root merge (the caller's whole Q); "rotate"

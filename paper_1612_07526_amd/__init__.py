@@ -125,7 +125,8 @@ def gemm_tile_table() -> list:
     return list(buf)[:max(n, 0)]
 
 PHASES = ["leaf", "deflate", "rotate", "secular", "loewner", "uhat_norm", "uhat_write", "rank", "gemm", "copy",
-          "sign", "split_slice", "split_gemm", "hss_sample", "hss_compress", "hss_apply", "adj_gemm", "adj_band"]
+          "sign", "split_slice", "split_gemm", "hss_sample", "hss_compress", "hss_apply", "adj_gemm", "adj_band",
+          "small_merge"]
 
 
 def profile_phases(fn, reps: int = 1, phases=None) -> dict:

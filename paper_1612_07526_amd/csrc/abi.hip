@@ -492,7 +492,8 @@ int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n,
     D.hss_min_k = hss_threshold(o);
     D.x_off = xoff[i];
     D.split_on = z.nsl > 0 ? 1 : 0;
-    D.flags = (o->force_fail & PHDC_FAIL_SECULAR) ? kFlagNoSecularIters : 0;
+    D.flags = ((o->force_fail & PHDC_FAIL_SECULAR) ? kFlagNoSecularIters : 0) |
+              (small_merge(nd.m, o) ? kFlagSmallMerge : 0);
     D.rin = BF.rng[pin] + BF.off[b] + nd.r0;
     D.rout = BF.rng[pout] + BF.off[b] + nd.r0;
     D.r0 = (int32_t)nd.r0;
@@ -544,7 +545,8 @@ int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n,
       bool equal = true;
       maps.push_back(0);
       for (int i = a; i < e; ++i) {
-        const int32_t bl = map_blocks(k, T.merges[i].m, T.merges[i].n1, lm[h].gemm_tile, T.merges[i].depth == 0);
+        const int32_t bl = map_blocks(k, T.merges[i].m, T.merges[i].n1, lm[h].gemm_tile, T.merges[i].depth == 0,
+                                      small_merge(T.merges[i].m, o));
         if (first < 0) first = bl;
         else if (bl != first) equal = false;
         acc += bl;
@@ -959,7 +961,8 @@ int phdc_merge(int64_t n1, int64_t n2, const double* D, const double* z, double 
   Dd.hss_min_k = hss_threshold(o);
   Dd.x_off = 0;
   Dd.split_on = zs.nsl > 0 ? 1 : 0;
-  Dd.flags = (o->force_fail & PHDC_FAIL_SECULAR) ? kFlagNoSecularIters : 0;
+  Dd.flags = ((o->force_fail & PHDC_FAIL_SECULAR) ? kFlagNoSecularIters : 0) |
+             (small_merge((int)m, o) ? kFlagSmallMerge : 0);
   Dd.rin = nullptr;  // Q1 and Q2 fill their halves
   Dd.rout = nullptr;
   Dd.r0 = 0;
@@ -980,7 +983,7 @@ int phdc_merge(int64_t n1, int64_t n2, const double* D, const double* z, double 
   lm.copy_alone = true;
   for (int k = 0; k < MAP_COUNT; ++k) {
     lm.pfx[k] = (const int32_t*)(base + L.maps) + maps.size();
-    lm.total[k] = map_blocks(k, (int)m, (int)n1, lm.gemm_tile, true);
+    lm.total[k] = map_blocks(k, (int)m, (int)n1, lm.gemm_tile, true, small_merge((int)m, o));
     lm.per[k] = lm.total[k] > 0 ? lm.total[k] : 0;
     maps.push_back(0);
     maps.push_back(lm.total[k]);

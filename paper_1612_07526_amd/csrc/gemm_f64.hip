@@ -26,33 +26,25 @@ typedef __attribute__((address_space(1))) double gdouble_t;  // a double in glob
 constexpr int GK = 16;        // k per LDS stage
 constexpr int GPAD = 4;       // LDS row padding (doubles)
 
-// GT x GT output tile, 256 threads (4 waves in 2 x 2), each wave a GT/2 x GT/2
-// quadrant of 16 x 16 MFMA blocks.  The k loop runs in the same order for
-// every tile size, so the result does not depend on GT.
+// GT x GT output tiles, 256 threads (4 waves in 2 x 2), each wave a GT/2 x
+// GT/2 quadrant of 16 x 16 MFMA blocks; block lb of the merge's G blocks
+// computes tiles lb, lb + G, ...  lds holds the double-buffered A and B
+// stages.  The k loop runs in the same order for every tile size, so the
+// result does not depend on GT.
 template <int GT>
-__global__ void __launch_bounds__(256) k_merge_gemm(BlockMap bm, Scratch S, int scale_cols) {
+__device__ __forceinline__ void gemm_merge_tiles(const MergeDesc& M, const Scratch& S, int K, int k1, int k2, int k3,
+                                                 int lb, int G, int scale_cols, double* lds) {
   constexpr int GLD = GT + GPAD;
   constexpr int E = GT * GK / 256;  // elements of A (and of B) each thread stages per k-step
   constexpr int WT = GT / 2;        // wave tile edge
   constexpr int NB = WT / 16;       // MFMA blocks per wave tile edge
-  __shared__ double As[2][GK][GLD];
-  __shared__ double Bs[2][GK][GLD];
-  const int b = blockIdx.x;
-  const int mi = find_merge(bm, b);
-  const int lb = b - merge_first_block(bm, mi);
-  const MergeDesc M = bm.descs[mi];
-  const int32_t* cnt = S.counters + (int64_t)M.id * kCounters;
-  if (cnt[C_PATH] != 0) return;  // formed by another update path
-  const int K = cnt[C_K], k1 = cnt[C_K1], k2 = cnt[C_K2], k3 = cnt[C_K3];
+  double (*As)[GK][GLD] = reinterpret_cast<double (*)[GK][GLD]>(lds);
+  double (*Bs)[GK][GLD] = reinterpret_cast<double (*)[GK][GLD]>(lds + 2 * GK * GLD);
   const int n1 = M.n1, n2 = M.m - M.n1;
   const int tmt = (n1 + GT - 1) / GT, tmb = (n2 + GT - 1) / GT;
   const int TM = tmt + tmb;
   const int TN = (K + GT - 1) / GT;  // column tiles with work (the grid covers m columns)
   const int nact = TM * TN;
-  if (lb >= nact) return;
-  // A block computes tiles lb, lb + G, ... (G = the merge's blocks, at most
-  // kGemmBlockCap), so merges whose K is far below m launch few idle blocks.
-  const int G = merge_blocks(bm, mi);
   for (int tile = lb; tile < nact; tile += G) {
     // Tile order.  Workgroups are dispatched round-robin over the 8 XCDs, each
     // with its own L2: hand XCD (tile mod 8) a contiguous range of tiles, and walk
@@ -192,6 +184,33 @@ __global__ void __launch_bounds__(256) k_merge_gemm(BlockMap bm, Scratch S, int 
   }
 }
 
+// Tile edge of one merge: 128 (if the launch allows it) when the merge has at
+// least kGemmWideTiles tiles of that edge, else 64: a merge that keeps few
+// columns gets four times more, smaller, tiles, so that more CUs share it.  The
+// grid of every merge is sized for edge 64 (at most kGemmBlockCap blocks).
+constexpr int kGemmWideTiles = 512;
+
+template <int GTMAX>
+__global__ void __launch_bounds__(256) k_merge_gemm(BlockMap bm, Scratch S, int scale_cols) {
+  __shared__ double lds[4 * GK * (GTMAX + GPAD)];
+  const int b = blockIdx.x;
+  const int mi = find_merge(bm, b);
+  const int lb = b - merge_first_block(bm, mi);
+  const MergeDesc M = bm.descs[mi];
+  const int32_t* cnt = S.counters + (int64_t)M.id * kCounters;
+  if (cnt[C_PATH] != 0) return;  // formed by another update path
+  const int K = cnt[C_K], k1 = cnt[C_K1], k2 = cnt[C_K2], k3 = cnt[C_K3];
+  const int G = merge_blocks(bm, mi);
+  if constexpr (GTMAX == 128) {
+    const int tiles128 = ((M.n1 + 127) / 128 + (M.m - M.n1 + 127) / 128) * ((K + 127) / 128);
+    if (tiles128 >= kGemmWideTiles) {
+      gemm_merge_tiles<128>(M, S, K, k1, k2, k3, lb, G, scale_cols, lds);
+      return;
+    }
+  }
+  gemm_merge_tiles<64>(M, S, K, k1, k2, k3, lb, G, scale_cols, lds);
+}
+
 void launch_merge_gemm_f64(const BlockMap& bm, int total, const Scratch& S, int tile, bool scale_cols,
                            hipStream_t s) {
   if (total <= 0) return;
@@ -313,7 +332,7 @@ int phdc_autotune_gemm(int64_t max_m, void* work, size_t lwork, void* stream) {
     const int tiles[2] = {64, 128};
     for (int v = 0; v < 2 && rc == 0; ++v) {
       const int gt = tiles[v];
-      const int total = (int)(((n1 + gt - 1) / gt + (m - n1 + gt - 1) / gt) * ((m + gt - 1) / gt));
+      const int total = map_blocks(MAP_GEMM, (int)m, n1, gt, false);
       const int32_t hp[2] = {0, total};
       if (hipMemcpyAsync(desc, &D, sizeof(D), hipMemcpyHostToDevice, s) != hipSuccess ||
           hipMemcpyAsync(pfx, hp, sizeof(hp), hipMemcpyHostToDevice, s) != hipSuccess) {

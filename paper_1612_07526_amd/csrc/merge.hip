@@ -510,7 +510,9 @@ __device__ void deflate_body(const MergeDesc& M, const Scratch& S, int lds_cap, 
 template <int NT>
 __global__ void __launch_bounds__(NT) k_deflate(const MergeDesc* __restrict__ descs, Scratch S, int lds_cap) {
   HIP_DYNAMIC_SHARED(double, sdl)
-  deflate_body<NT>(descs[blockIdx.x], S, lds_cap, sdl);
+  const MergeDesc M = descs[blockIdx.x];
+  if (M.flags & kFlagSmallMerge) return;  // deflated by k_merge_small
+  deflate_body<NT>(M, S, lds_cap, sdl);
 }
 
 // ------------------------------------------------------------ rotations
@@ -944,10 +946,8 @@ constexpr int kSmallThreads = 1024;
 
 __device__ void rank_item(const MergeDesc& M, const Scratch& S, int x);
 
-__device__ void small_body(const MergeDesc* __restrict__ descs, const Scratch& S, int b, bool normalized,
-                           double* sd, double* sz) {
+__device__ void small_body(const MergeDesc& M, const Scratch& S, bool normalized, double* sd, double* sz) {
   constexpr int NT = kSmallThreads;
-  const MergeDesc M = descs[b];
   const int K = S.counters[(int64_t)M.id * kCounters + C_K];
   const int t = threadIdx.x;
   const int64_t so = M.s_off;
@@ -1139,15 +1139,21 @@ __device__ void copy_body(const BlockMap& bm, const Scratch& S, int b) {
 
 // ------------------------------------------------------------ block maps
 
-int map_blocks(int kind, int m, int n1, int gt, bool root) {
+bool small_merge(int m, const phdc_opts* o) {
+  if (m > kSmallMergeMax || o->gemm_mode == PHDC_GEMM_SPLIT) return false;
+  return !(o->gemm_mode == PHDC_GEMM_HSS && m >= std::max<int64_t>(o->hss_min_K, 1));
+}
+
+int map_blocks(int kind, int m, int n1, int gt, bool root, bool small) {
   auto cdiv = [](int a, int b) { return (a + b - 1) / b; };
+  if (small || kind == MAP_SMALL) return (small && kind == MAP_SMALL) ? 1 : 0;
   switch (kind) {
     case MAP_SECULAR: return cdiv(m, kSecThreads / kSecG);
     case MAP_ROOTS16: return cdiv(m, kItemsPerBlock);
     case MAP_ROWS256: return cdiv(m, 256);
     case MAP_ROT: return cdiv(m, 256) * std::max(1, std::min(m / 2, kRotGroups));
     case MAP_UWRITE: return cdiv(m, 256) * std::max(1, std::min(m, kUwRowGroups));
-    case MAP_GEMM: return std::min((cdiv(n1, gt) + cdiv(m - n1, gt)) * cdiv(m, gt), kGemmBlockCap);
+    case MAP_GEMM: return std::min((cdiv(n1, 64) + cdiv(m - n1, 64)) * cdiv(m, 64), kGemmBlockCap);  // edge-64 tiles
     case MAP_COPY: {  // root: one column per block; else 256 / (m rounded up to a power of two, at most 64)
       if (root) return std::max(1, std::min(m, kCopyBlocks));
       int rpt = 1;
@@ -1191,7 +1197,78 @@ __global__ void __launch_bounds__(kSmallThreads) k_stage_small(const MergeDesc* 
                                                                int normalized) {
   __shared__ double sd[kSmallUhat];
   __shared__ double sz[kSmallUhat];
-  small_body(descs, S, blockIdx.x, normalized != 0, sd, sz);
+  const MergeDesc M = descs[blockIdx.x];
+  if (M.flags & kFlagSmallMerge) return;  // done by k_merge_small
+  small_body(M, S, normalized != 0, sd, sz);
+}
+
+// ------------------------------------------------------------ one-workgroup merges
+// A merge of at most kSmallMergeMax rows on the FP64 path runs in one
+// 1024-thread workgroup from deflation to the eigenvector update: the update
+// product's operands (the gathered input columns and Uhat) are staged in LDS
+// and each output entry is a plain sum over k in order (at these sizes the
+// product is a few hundred thousand flops, less than the latency of one more
+// launch); then the deflated columns are copied.
+constexpr int kSmallLd = kSmallMergeMax + 1;  // LDS row stride of the staged operand (no bank conflicts)
+
+__device__ void small_update(const MergeDesc& M, const Scratch& S, double* Ag, double* Us) {
+  const int t = threadIdx.x, m = M.m, n1 = M.n1;
+  const int32_t* cnt = S.counters + (int64_t)M.id * kCounters;
+  const int K = cnt[C_K], k1 = cnt[C_K1], k2 = cnt[C_K2], k3 = cnt[C_K3];
+  const int64_t so = M.s_off;
+  // Ag(r, k): row r of the merge block, column k of the half's column list
+  // (rows outside the column's range as 0); Us(g, j) = Uhat in grouped rows
+  for (int x = t; x < m * kSmallMergeMax; x += kSmallThreads) {
+    const int r = x / kSmallMergeMax, k = x % kSmallMergeMax;
+    const bool top = r < n1;
+    double v = 0.0;
+    if (k < (top ? k1 + k2 : k2 + k3)) {
+      const int c = top ? S.coltop[so + k] : S.colbot[so + k];
+      const RowRange g = top ? S.rgtop[so + k] : S.rgbot[so + k];
+      if (r >= g.lo && r < g.hi) v = M.qin[r + (int64_t)c * M.ldin];
+    }
+    Ag[r * kSmallLd + k] = v;
+  }
+  const double* U = S.uhat + M.u_off;
+  for (int x = t; x < K * K; x += kSmallThreads) Us[(x / K) * kSmallMergeMax + x % K] = U[x];
+  __syncthreads();
+  // output (r, j): consecutive threads take consecutive rows of one column
+  for (int x = t; x < m * K; x += kSmallThreads) {
+    const int r = x % m, j = x / m;
+    const bool top = r < n1;
+    const int kd = top ? k1 + k2 : k2 + k3;
+    const double* a = Ag + r * kSmallLd;
+    const double* u = Us + (top ? 0 : k1) * kSmallMergeMax + j;
+    double acc = 0.0;
+    for (int k = 0; k < kd; ++k) acc = fma(a[k], u[k * kSmallMergeMax], acc);
+    M.qout[r + (int64_t)S.dest[so + j] * M.ldout] = acc;
+  }
+  // deflated columns: over their range (every row when the merge is a root)
+  const int nd1 = cnt[C_ND1], nd = nd1 + cnt[C_ND2];
+  for (int x = t; x < nd * kSmallMergeMax; x += kSmallThreads) {
+    const int q = x / kSmallMergeMax, r = x % kSmallMergeMax;
+    if (r >= m) continue;
+    int c, dst;
+    if (q < nd1) { c = S.dfc1[so + q]; dst = S.destd1[so + q]; }
+    else { c = S.dfc2[so + q - nd1]; dst = S.destd2[so + q - nd1]; }
+    const RowRange g = S.crng[so + c];
+    const bool in = r >= g.lo && r < g.hi;
+    if (in || M.root) M.qout[r + (int64_t)dst * M.ldout] = in ? M.qin[r + (int64_t)c * M.ldin] : 0.0;
+  }
+}
+
+__global__ void __launch_bounds__(kSmallThreads) k_merge_small(BlockMap bm, Scratch S) {
+  __shared__ double Ag[kSmallMergeMax * kSmallLd];
+  __shared__ double Us[kSmallMergeMax * kSmallMergeMax];
+  __shared__ double sd[kSmallUhat];
+  __shared__ double sz[kSmallUhat];
+  const int mi = find_merge(bm, blockIdx.x);
+  const MergeDesc M = bm.descs[mi];
+  deflate_body<kSmallThreads>(M, S, M.m, Ag);  // (Ag doubles as the poles' staging area)
+  __syncthreads();
+  small_body(M, S, true, sd, sz);
+  __syncthreads();
+  small_update(M, S, Ag, Us);
 }
 
 __global__ void __launch_bounds__(256) k_stage_lowner(BlockMap low, int nlow, BlockMap rank, Scratch S) {
@@ -1214,6 +1291,12 @@ void launch_merge_level(const MergeDesc* descs, int nm, const LevelMaps& maps, c
   auto bmap = [&](int kind) { return BlockMap{descs, maps.pfx[kind], nm, maps.per[kind]}; };
   const BlockMap none{descs, nullptr, 1, 1};
   const int normalized = maps.uhat_normalized ? 1 : 0;
+  const int nsmall = maps.total[MAP_SMALL];
+  if (nsmall > 0) {  // merges that run in one workgroup each, deflation included
+    ProfScope p(PH_SMALL_MERGE, s);
+    hipLaunchKernelGGL(k_merge_small, dim3(nsmall), dim3(kSmallThreads), 0, s, bmap(MAP_SMALL), S);
+    if (nsmall == nm) return;  // (no HSS candidate in such a level: no probe needed)
+  }
   { ProfScope p(PH_DEFLATE, s);
     const int cap = maps.maxm <= kDefLdsMax ? maps.maxm : 0;
     if (maps.maxm <= kDefSmall)

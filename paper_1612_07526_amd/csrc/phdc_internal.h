@@ -49,7 +49,7 @@ struct MergeDesc {
   int32_t hss_min_k;    // HSS update for this merge when K >= hss_min_k (0: never)
   int64_t x_off;        // offset of this merge's m*(m+8) slot (per slice) in the split-precision arenas
   int32_t split_on;     // split-precision update for this merge
-  int32_t flags;        // bit 0 (kFlagNoSecularIters): secular roots get no iterations (test hook)
+  int32_t flags;        // kFlagNoSecularIters (test hook), kFlagSmallMerge
   const RowRange* rin;  // input column ranges in rows of the whole matrix (nullptr: [0, n1) / [n1, m) by half)
   RowRange* rout;       // output column ranges (nullptr: not recorded)
   int32_t r0;           // first row (= first column) of the merge block within the matrix
@@ -152,7 +152,10 @@ __device__ inline void set_status(int32_t* status, int code) {
   atomicCAS(status, 0, code);
 }
 
-constexpr int32_t kFlagNoSecularIters = 1;
+constexpr int32_t kFlagNoSecularIters = 1;  // secular roots get no iterations (test hook)
+constexpr int32_t kFlagSmallMerge = 2;      // the whole merge runs in one workgroup (k_merge_small)
+// Merges of at most this many rows on the FP64 path run in one workgroup each.
+constexpr int kSmallMergeMax = 64;
 
 // Kernel launchers (defined in the .hip files).  maxit: iteration cap per
 // eigenvalue of the leaf QL (0 under the PHDC_FAIL_LEAF test hook).
@@ -166,7 +169,10 @@ void launch_scan_finite(const double* a, int64_t n, int32_t* flag, int32_t* stat
 void launch_clear_status(int32_t* status, hipStream_t s);
 
 // Block maps of one merge level (device prefix arrays, nm + 1 entries each).
-enum MapKind { MAP_SECULAR = 0, MAP_ROOTS16, MAP_ROWS256, MAP_ROT, MAP_UWRITE, MAP_GEMM, MAP_COPY, MAP_SPLITA, MAP_SPLITB, MAP_COUNT };
+enum MapKind {
+  MAP_SECULAR = 0, MAP_ROOTS16, MAP_ROWS256, MAP_ROT, MAP_UWRITE, MAP_GEMM, MAP_COPY, MAP_SPLITA, MAP_SPLITB, MAP_SMALL,
+  MAP_COUNT
+};
 struct LevelMaps {
   const int32_t* pfx[MAP_COUNT];
   int32_t total[MAP_COUNT];
@@ -177,8 +183,12 @@ struct LevelMaps {
   bool copy_alone = false;       // the deflated-column copy gets a launch of its own (a lone root merge)
 };
 // Blocks of one merge for a kernel class; gt is the FP64 GEMM tile edge (MAP_GEMM);
-// root: the merge is the last one of its matrix (MAP_COPY: one column per block).
-int map_blocks(int kind, int m, int n1, int gt, bool root);
+// root: the merge is the last one of its matrix (MAP_COPY: one column per block);
+// small: the merge runs in one workgroup of k_merge_small (MAP_SMALL: 1 block,
+// every other class 0).
+int map_blocks(int kind, int m, int n1, int gt, bool root, bool small = false);
+// Whether a merge of m rows takes the one-workgroup path for these options.
+bool small_merge(int m, const phdc_opts* o);
 constexpr int kGemmBlockCap = 1024;      // blocks per merge of the update GEMMs (they loop over tiles)
 constexpr int kTileBuckets = 21;        // merge-size buckets of the GEMM tile table (m <= 2^20)
 int gemm_tile_for(int64_t maxm);        // tile edge for a level whose largest merge is maxm
