@@ -10,7 +10,9 @@ for `value`; the plain FP64-MFMA form is timed beside it.
 Also on the same JSON line (each section can be skipped with --skip):
   roofline     -- dominant kernel of the timed workload, HIP events on the launch stream
   merge_gemm   -- the large-K rank-one merge of Sec. 2.2 (poles i/N, N = 16384, K = N):
-                  FP64-MFMA update TFLOP/s vs peak; HSS and split-precision update times
+                  FP64-MFMA update TFLOP/s vs peak; HSS and split-precision update times;
+                  eigenvalues against the oracle's secular roots; the same merge at N = 32768
+                  (FP64 and HSS; skip with merge32k)
   toeplitz     -- diagonal 2 / off-diagonal 1 at n = 16383 (no deflation at the top)
   examples     -- the paper's Examples 3-4 (Clement, Hermite, Toeplitz-type, SHT) at n = 30000,
                   plain vs HSS for merges with K >= 20000
@@ -20,7 +22,8 @@ Also on the same JSON line (each section can be skipped with --skip):
   batch        -- 4096 matrices of sizes U{32..1024}: graph-replayed batched launches vs
                   one solve call per matrix
   adjoint      -- batch 64 x n = 4096 ramp matrices: forward + backward
-  cpu_baseline -- the CPU oracle solving the headline matrix on the host cores
+  cpu_baseline -- the CPU oracle solving the headline matrix on the host cores, with LAPACK's
+                  dstevd on the same matrix and cores as context
 """
 from __future__ import annotations
 
@@ -183,6 +186,34 @@ def measured_traffic(phase, leaf):
     return float(fields["traffic_bytes_per_launch"])
 
 
+def lapack_dstevd(d, e):
+    """Context only: LAPACK's divide-and-conquer dstevd (eigenvalues and eigenvectors) on the same
+    matrix and host, from the OpenBLAS build that ships with scipy, through its LAPACKE interface."""
+    import glob
+    try:
+        import scipy
+        libs = glob.glob(os.path.join(os.path.dirname(os.path.dirname(scipy.__file__)), "scipy.libs",
+                                      "libscipy_openblas*.so"))
+        lib = ctypes.CDLL(libs[0])
+        f = lib.scipy_LAPACKE_dstevd
+        f.restype = ctypes.c_int
+        f.argtypes = [ctypes.c_int, ctypes.c_char, ctypes.c_int] + [ctypes.c_void_p] * 3 + [ctypes.c_int]
+        nth = lib.scipy_openblas_get_num_threads
+        nth.restype = ctypes.c_int
+        n = len(d)
+        dd = np.array(d, dtype=np.float64)
+        ee = np.array(e, dtype=np.float64)
+        Z = np.empty((n, n), order="F")
+        t0 = time.perf_counter()
+        info = f(102, b"V", n, dd.ctypes.data, ee.ctypes.data, Z.ctypes.data, n)
+        t = time.perf_counter() - t0
+        log(f"[bench] LAPACK dstevd {t:.2f} s on {nth()} threads (info {info})")
+        return {"value": round(t, 3), "unit": "s", "threads": int(nth()), "info": int(info),
+                "library": "OpenBLAS LAPACKE_dstevd (scipy's bundled build)"}
+    except Exception as ex:  # context only: never fail the bench for it
+        return {"error": repr(ex)}
+
+
 def timed_profiled(P, fn, steps, warmup, phases):
     """Time `steps` calls with the library's HIP events recorded on the launch stream around
     the kernels of `phases` only, inside the same timed region: returns
@@ -269,22 +300,28 @@ def sec_value(P, W, args, out):
                alg=alg, table=table, lam=lam_gpu, d=d, e=e)
 
 
-def sec_merge_gemm(P, W, args):
+def merge_forms(P, W, args, N, forms, lam_ref=None):
+    """The rank-one merge of Sec. 2.2 (poles i/N, rho = 1, random unit z, Q1 and Q2 random orthogonal)
+    through phdc_merge in each of `forms`; Q1 and Q2 are orthonormalised on the GPU (input generation)."""
     import torch
-    N = 16384
-    D, z, rho, Q1, Q2 = W.fig3_merge(N, seed=0, with_q=True)
+    D, z, rho, G1, G2 = W.fig3_merge(N, seed=0, with_q="gaussian")
     lib = P.load()
     Dt = torch.tensor(D, device="cuda")
     zt = torch.tensor(z, device="cuda")
-    Q1c, ld1 = P._colmajor(torch.tensor(Q1, device="cuda"))
-    Q2c, ld2 = P._colmajor(torch.tensor(Q2, device="cuda"))
-    del Q1, Q2
+    qs = []
+    for G in (G1, G2):
+        Q, R = torch.linalg.qr(torch.tensor(G, device="cuda"))
+        Q *= torch.sign(torch.diagonal(R))[None, :]
+        qs.append(P._colmajor(Q))
+        del R
+    (Q1c, ld1), (Q2c, ld2) = qs
+    del G1, G2, qs
     res = {"workload": f"rank-one merge of Sec. 2.2: poles i/N, rho=1, random unit z, N={N}"}
-    for name, o in (("fp64", P.opts(gemm_mode=P.GEMM_FP64)),
-                    ("hss", P.opts(gemm_mode=P.GEMM_HSS, hss_min_K=4096)),
-                    ("split", P.opts(gemm_mode=P.GEMM_SPLIT))):
+    for name in forms:
         if name in args.skip_paths:
             continue
+        o = {"fp64": P.opts(gemm_mode=P.GEMM_FP64), "hss": P.opts(gemm_mode=P.GEMM_HSS, hss_min_K=4096),
+             "split": P.opts(gemm_mode=P.GEMM_SPLIT)}[name]
         lam = torch.empty(N, dtype=torch.float64, device="cuda")
         qm = torch.empty((N, N), dtype=torch.float64, device="cuda")
         nb = ctypes.c_size_t()
@@ -307,22 +344,45 @@ def sec_merge_gemm(P, W, args):
         del Gm
         entry = {"merge_s": round(t, 5), "orth": orth, "K": int(tab[0, 2]), "path": int(tab[0, 8]),
                  "hss_rank": int(tab[0, 9])}
+        if lam_ref is not None:
+            lg = np.sort(lam.cpu().numpy())
+            entry["lambda_err_vs_oracle"] = float(np.abs(lg - lam_ref).max() / np.abs(lam_ref).max())
         if name == "fp64":
             alg = algorithmic(tab)
             gemm_ms = ph["gemm"][0]
             tf = alg["gemm_flops"] / (gemm_ms * 1e-3) / 1e12
-            entry.update(gemm_ms=round(gemm_ms, 3), gemm_tflops=round(tf, 2),
+            entry.update(gemm_flops=alg["gemm_flops"], gemm_ms=round(gemm_ms, 3), gemm_tflops=round(tf, 2),
                          gemm_frac_fp64_peak=round(tf / FP64_PEAK_TFLOPS, 4))
         if name == "split":
             sg = ph.get("split_gemm", (0.0, 0))[0]
-            flops_exec = 2.0 * N / 2 * N / 2 * N * 2 * (7 * 8 / 2)  # both halves, 28 slice pairs
-            entry.update(update_ms=round(sg, 3), bf16_tflops_executed=round(flops_exec / (sg * 1e-3) / 1e12, 1))
+            ns = o.split_slices
+            flops_exec = 2.0 * N / 2 * N / 2 * N * 2 * (ns * (ns + 1) / 2)  # both halves, the kept slice pairs
+            entry.update(slices=ns, update_ms=round(sg, 3),
+                         bf16_tflops_executed=round(flops_exec / (sg * 1e-3) / 1e12, 1))
         if name == "hss":
             entry.update(hss_ms={k: round(ph[k][0], 3) for k in ("hss_sample", "hss_compress", "hss_apply") if k in ph})
         log(f"[bench]   {name}: {entry}")
         res[name] = entry
         del wm, qm
         torch.cuda.empty_cache()
+    if "fp64" in res and "hss" in res:
+        res["hss_speedup"] = round(res["fp64"]["merge_s"] / res["hss"]["merge_s"], 3)
+    if "fp64" in res and "split" in res:
+        res["split_speedup"] = round(res["fp64"]["merge_s"] / res["split"]["merge_s"], 3)
+    return res
+
+
+def sec_merge_gemm(P, W, args):
+    N = 16384
+    D, z, rho = W.fig3_merge(N, seed=0, with_q=False)[:3]
+    lam_ref = None
+    if "cpu" not in args.skip:
+        import oracle  # eigenvalues of the merge (the secular roots, the same for every update form)
+        o, tau = oracle.get().secular(D, z, rho)
+        lam_ref = np.sort(D[o] + tau)
+    res = merge_forms(P, W, args, N, ("fp64", "hss", "split"), lam_ref)
+    if "merge32k" not in args.skip:
+        res["N32768"] = merge_forms(P, W, args, 32768, ("fp64", "hss"))
     return res
 
 
@@ -330,6 +390,8 @@ def sec_toeplitz(P, W, args):
     import torch
     ns = 16383
     ds, es = W.toeplitz_121(ns, 1.0)
+    # eigenvalues 2 - 2 cos(k pi / (n + 1)), k = 1..n (the closed form the oracle is pinned to)
+    lam_cf = np.sort(2.0 - 2.0 * np.cos(np.arange(1, ns + 1) * np.pi / (ns + 1)))
     res = {"workload": f"toeplitz121_n{ns} (top merge K = n)"}
     for name, o in (("fp64", P.opts(gemm_mode=P.GEMM_FP64)), ("hss", P.opts(gemm_mode=P.GEMM_HSS)),
                     ("split", P.opts(gemm_mode=P.GEMM_SPLIT))):
@@ -340,8 +402,10 @@ def sec_toeplitz(P, W, args):
         orth, rr = s.accuracy()
         tab = merge_table(P, s.work)
         ph = profile_phases(P, s, reps=1)
-        entry = {"solve_s": round(t, 5), "orth": orth, "residual": rr, "top_K": int(tab[-1, 2]),
-                 "top_path": int(tab[-1, 8]), "hss_rank": int(tab[-1, 9])}
+        lg = np.sort(s.lam.cpu().numpy())
+        entry = {"solve_s": round(t, 5), "orth": orth, "residual": rr,
+                 "lambda_err_vs_closed_form": float(np.abs(lg - lam_cf).max() / np.abs(lam_cf).max()),
+                 "top_K": int(tab[-1, 2]), "top_path": int(tab[-1, 8]), "hss_rank": int(tab[-1, 9])}
         if name == "fp64":
             alg = algorithmic(tab)
             tf = alg["gemm_flops"] / (ph["gemm"][0] * 1e-3) / 1e12
@@ -362,8 +426,11 @@ def sec_examples(P, W, args):
     for gen in ("clement", "hermite", "toeplitz_121", "sht"):
         d, e = W.tridiag(gen, n)
         entry = {}
-        for name, o in (("fp64", P.opts(gemm_mode=P.GEMM_FP64)),
-                        ("hss", P.opts(gemm_mode=P.GEMM_HSS, hss_min_K=20000))):
+        forms = [("fp64", P.opts(gemm_mode=P.GEMM_FP64)), ("hss", P.opts(gemm_mode=P.GEMM_HSS, hss_min_K=20000))]
+        if gen in ("clement", "toeplitz_121"):
+            # their top merge keeps K = n/2 (below): HSS at a threshold these matrices reach
+            forms.append(("hss_K4096", P.opts(gemm_mode=P.GEMM_HSS, hss_min_K=4096)))
+        for name, o in forms:
             s = Solver(P, d, e, o)
             t = timed(s, 1, 1)
             orth, rr = s.accuracy()
@@ -374,6 +441,12 @@ def sec_examples(P, W, args):
             torch.cuda.empty_cache()
         if "fp64" in entry and "hss" in entry:
             entry["hss_speedup"] = round(entry["fp64"]["solve_s"] / entry["hss"]["solve_s"], 3)
+        if "fp64" in entry and "hss_K4096" in entry:
+            entry["hss_K4096_speedup"] = round(entry["fp64"]["solve_s"] / entry["hss_K4096"]["solve_s"], 3)
+            # Clement and the 2-1 Toeplitz matrix are persymmetric: under the k = n/2 split the two
+            # halves are mirror images with equal eigenvalues, so type-2 deflation removes one of
+            # each pair and the top merge keeps K = n/2 = 15000, below the paper's 20000
+            entry["note"] = "persymmetric: the halves of the top split share their eigenvalues, so K = n/2"
         log(f"[bench] example {gen} n={n}: {entry}")
         res[gen] = entry
     return res
@@ -440,11 +513,20 @@ def sec_split(P, W, args):
     n = 32768
     d, e = W.normal_pos(n, seed=0)
     res = {"workload": f"normal_pos_n{n}: d~N(0,1), e~U[0.1,1]"}
+    lam_ref = None
+    if "cpu" not in args.skip:
+        import oracle
+        t0 = time.perf_counter()
+        lam_ref = np.sort(oracle.get().stedc(d, e)[0])
+        res["oracle_s"] = round(time.perf_counter() - t0, 2)
     for name, o in (("fp64", P.opts(gemm_mode=P.GEMM_FP64)), ("split", P.opts(gemm_mode=P.GEMM_SPLIT))):
         s = Solver(P, d, e, o)
         t = timed(s, 2, 1)
         orth, rr = s.accuracy()
         res[name] = {"solve_s": round(t, 5), "orth": orth, "residual": rr, "top_K": int(merge_table(P, s.work)[-1, 2])}
+        if lam_ref is not None:
+            lg = np.sort(s.lam.cpu().numpy())
+            res[name]["lambda_err_vs_oracle"] = float(np.abs(lg - lam_ref).max() / np.abs(lam_ref).max())
         log(f"[bench] n=32768 {name}: {res[name]}")
         del s
         torch.cuda.empty_cache()
@@ -535,7 +617,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--skip", default="",
-                    help="comma list of sections: merge_gemm,toeplitz,examples,example1,split,batch,adjoint,cpu")
+                    help="comma list of sections: merge_gemm,merge32k,toeplitz,examples,example1,split,batch,adjoint,cpu")
     ap.add_argument("--skip-paths", default="", help="comma list of update paths to leave out: hss,split")
     ap.add_argument("--only-value", action="store_true", help="time the headline solve only (profiling runs)")
     ap.add_argument("--leaf", type=int, default=16,
@@ -552,7 +634,8 @@ def main():
     args.skip = set(x for x in args.skip.split(",") if x)
     args.skip_paths = set(x for x in args.skip_paths.split(",") if x)
     if args.only_value:
-        args.skip |= {"merge_gemm", "toeplitz", "examples", "example1", "split", "batch", "adjoint", "cpu"}
+        args.skip |= {"merge_gemm", "merge32k", "toeplitz", "examples", "example1", "split", "batch", "adjoint",
+                      "cpu"}
 
     import paper_1612_07526_amd as P
     import workloads as W
@@ -616,6 +699,7 @@ def main():
                "sample": "one full solve of the uniform n=16384 matrix (the whole workload)",
                "max_abs_dlambda_vs_gpu": err}
         log(f"[bench] oracle {tc:.2f} s; max |lambda_gpu - lambda_oracle| = {err:.2e}")
+        cpu["lapack_dstevd_context"] = lapack_dstevd(v["d"], v["e"])
 
     line = {
         "metric": "n=16384 eigensolve time (s) + merge-GEMM % MFMA peak, plain vs chosen form",

@@ -546,7 +546,7 @@ int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n,
       maps.push_back(0);
       for (int i = a; i < e; ++i) {
         const int32_t bl = map_blocks(k, T.merges[i].m, T.merges[i].n1, lm[h].gemm_tile, T.merges[i].depth == 0,
-                                      small_merge(T.merges[i].m, o));
+                                      small_merge(T.merges[i].m, o), e - a);
         if (first < 0) first = bl;
         else if (bl != first) equal = false;
         acc += bl;

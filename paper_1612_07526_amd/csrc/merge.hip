@@ -743,38 +743,40 @@ constexpr int kSecG = 16;         // lanes per root
 // the launch's LDS, sized by its largest merge, at most kSecLds); larger ones
 // read them from global memory (L2-resident).
 template <int G>
-__device__ __forceinline__ void secular_block(const MergeDesc& M, const Scratch& S, int K, int lb, double* sd,
+__device__ __forceinline__ void secular_block(const MergeDesc& M, const Scratch& S, int K, int lb, int nb, double* sd,
                                               double* sz, int cap) {
   constexpr int R = kSecThreads / G;
   if (lb * R >= K) return;  // whole block idle (uniform)
-  const int j = lb * R + (int)threadIdx.x / G;
   const int sub = threadIdx.x % G;
-  const bool active = j < K;
   const int64_t so = M.s_off;
   const double rho = S.mparam[(int64_t)M.id * 4 + 0];
-  int org = 0;
-  double tau = 0.0;
-  // inactive groups of a partly filled block run root K-1 redundantly so that
-  // every lane takes part in the group shuffles; only active groups write
-  const int jj = active ? j : K - 1;
   const int maxit = (M.flags & kFlagNoSecularIters) ? 0 : kSecMaxIters;
-  bool ok;
-  if (K <= cap) {
+  const bool staged = K <= cap;  // block-uniform
+  if (staged) {
     for (int i = threadIdx.x; i < K; i += kSecThreads) {
       sd[i] = S.ds[so + i];
       const double zi = S.zs[so + i];
       sz[i] = zi * zi;
     }
     __syncthreads();
-    ok = secular_root<G, true>(K, sd, sz, rho, jj, sub, &org, &tau, maxit);
-  } else {
-    ok = secular_root<G, false>(K, S.ds + so, S.zs + so, rho, jj, sub, &org, &tau, maxit);
   }
-  if (active && sub == 0) {
-    S.org[so + j] = org;
-    S.tau[so + j] = tau;
-    S.dorg[so + j] = S.ds[so + org];
-    if (!ok) set_status(S.status, PHDC_ERR_SECULAR);
+  // roots lb R .. lb R + R - 1, then nb R further on (nb: the merge's blocks)
+  for (int j0 = lb * R; j0 < K; j0 += nb * R) {
+    const int j = j0 + (int)threadIdx.x / G;
+    const bool active = j < K;
+    // inactive groups of a partly filled block run root K-1 redundantly so that
+    // every lane takes part in the group shuffles; only active groups write
+    const int jj = active ? j : K - 1;
+    int org = 0;
+    double tau = 0.0;
+    const bool ok = staged ? secular_root<G, true>(K, sd, sz, rho, jj, sub, &org, &tau, maxit)
+                           : secular_root<G, false>(K, S.ds + so, S.zs + so, rho, jj, sub, &org, &tau, maxit);
+    if (active && sub == 0) {
+      S.org[so + j] = org;
+      S.tau[so + j] = tau;
+      S.dorg[so + j] = S.ds[so + org];
+      if (!ok) set_status(S.status, PHDC_ERR_SECULAR);
+    }
   }
 }
 
@@ -783,7 +785,7 @@ __device__ void secular_body(const BlockMap& bm, const Scratch& S, int b, double
   const int lb = b - merge_first_block(bm, mi);
   const MergeDesc M = bm.descs[mi];
   const int K = S.counters[(int64_t)M.id * kCounters + C_K];
-  secular_block<kSecG>(M, S, K, lb, sd, sz, cap);
+  secular_block<kSecG>(M, S, K, lb, merge_blocks(bm, mi), sd, sz, cap);
 }
 
 __global__ void __launch_bounds__(64) k_secular_raw(int K, const double* d, const double* z, double rho,
@@ -828,6 +830,7 @@ constexpr int kItemsPerBlock = kSecThreads / kItemG;
 // A lane's partial product is a product of factors in (0, 1], so none
 // underflows before the full product does.  Item i0 of a merge with K poles,
 // computed by the 16 lanes of a group (sub = lane within the group).
+template <int IG = kItemG>
 __device__ inline void lowner_item(const MergeDesc& M, const Scratch& S, int K, int i0, int sub) {
   const bool active = i0 < K;
   const int i = active ? i0 : K - 1;  // idle groups repeat the last item (group shuffles)
@@ -839,8 +842,8 @@ __device__ inline void lowner_item(const MergeDesc& M, const Scratch& S, int K, 
   const double di = ds[i];
   double w1 = 1.0, w2 = 1.0;
   int j = sub;
-  for (; j + kItemG < K - 1; j += 2 * kItemG) {
-    const int j2 = j + kItemG;
+  for (; j + IG < K - 1; j += 2 * IG) {
+    const int j2 = j + IG;
     const double num = (di - dorg[j]) - tau[j], num2 = (di - dorg[j2]) - tau[j2];
     const double den = (j < i) ? (di - ds[j]) : (di - ds[j + 1]);
     const double den2 = (j2 < i) ? (di - ds[j2]) : (di - ds[j2 + 1]);
@@ -852,7 +855,7 @@ __device__ inline void lowner_item(const MergeDesc& M, const Scratch& S, int K, 
     const double den = (j < i) ? (di - ds[j]) : (di - ds[j + 1]);
     w1 *= num / den;
   }
-  double w = group_prod<kItemG>(w1 * w2);
+  double w = group_prod<IG>(w1 * w2);
   w *= -((di - dorg[K - 1]) - tau[K - 1]);
   if (active && sub == 0) {
     const double mag = sqrt(fabs(w) / rho);
@@ -865,11 +868,13 @@ __device__ void lowner_body(const BlockMap& bm, const Scratch& S, int b) {
   const int lb = b - merge_first_block(bm, mi);
   const MergeDesc M = bm.descs[mi];
   const int K = S.counters[(int64_t)M.id * kCounters + C_K];
-  if (lb * kItemsPerBlock >= K) return;
-  lowner_item(M, S, K, lb * kItemsPerBlock + (int)threadIdx.x / kItemG, threadIdx.x % kItemG);
+  const int G = merge_blocks(bm, mi);
+  for (int i0 = lb * kItemsPerBlock; i0 < K; i0 += G * kItemsPerBlock)  // (block-uniform bound)
+    lowner_item(M, S, K, i0 + (int)threadIdx.x / kItemG, threadIdx.x % kItemG);
 }
 
 // Reciprocal 2-norms of the columns zhat_i / (d_i - lambda_j) of Uhat (Eq. (4)).
+template <int IG = kItemG>
 __device__ inline void unorm_item(const MergeDesc& M, const Scratch& S, int K, int j0, int sub) {
   const bool active = j0 < K;
   const int j = active ? j0 : K - 1;
@@ -879,8 +884,8 @@ __device__ inline void unorm_item(const MergeDesc& M, const Scratch& S, int K, i
   const double lj = S.dorg[so + j], tj = S.tau[so + j];
   double s1 = 0.0, s2 = 0.0;
   int i = sub;
-  for (; i + kItemG < K; i += 2 * kItemG) {
-    const int i2 = i + kItemG;
+  for (; i + IG < K; i += 2 * IG) {
+    const int i2 = i + IG;
     const double v = zh[i] / ((ds[i] - lj) - tj), v2 = zh[i2] / ((ds[i2] - lj) - tj);
     s1 += v * v;
     s2 += v2 * v2;
@@ -889,7 +894,7 @@ __device__ inline void unorm_item(const MergeDesc& M, const Scratch& S, int K, i
     const double v = zh[i] / ((ds[i] - lj) - tj);
     s1 += v * v;
   }
-  const double s = group_sum<kItemG>(s1 + s2);
+  const double s = group_sum<IG>(s1 + s2);
   if (active && sub == 0) S.cnorm[so + j] = 1.0 / sqrt(s);
 }
 
@@ -898,8 +903,9 @@ __device__ void unorm_body(const BlockMap& bm, const Scratch& S, int b) {
   const int lb = b - merge_first_block(bm, mi);
   const MergeDesc M = bm.descs[mi];
   const int K = S.counters[(int64_t)M.id * kCounters + C_K];
-  if (lb * kItemsPerBlock >= K) return;
-  unorm_item(M, S, K, lb * kItemsPerBlock + (int)threadIdx.x / kItemG, threadIdx.x % kItemG);
+  const int G = merge_blocks(bm, mi);
+  for (int j0 = lb * kItemsPerBlock; j0 < K; j0 += G * kItemsPerBlock)  // (block-uniform bound)
+    unorm_item(M, S, K, j0 + (int)threadIdx.x / kItemG, threadIdx.x % kItemG);
 }
 
 // ... then the entries, written row-major (row g = grouped row, ld = K) so that
@@ -935,28 +941,29 @@ __device__ void uwrite_body(const BlockMap& bm, const Scratch& S, int b, bool no
   for (int g = rg; g < K; g += RG) U[(int64_t)g * K + j] = uhat_entry(M, S, pole_order, g, lj, tj, sc);
 }
 
-// Levels whose merges have at most kSmallUhat rows: one 1024-thread workgroup
-// per merge applies the rotations and forms the secular roots, zhat, the
-// column norms, Uhat and the output ranks in turn (one launch instead of
-// several whose fixed latency exceeds this work, and no grid sized for K = m).
-// Same per-item arithmetic as the multi-block kernels, so a merge gives the
-// same bits on either path.
+// Levels whose merges have at most kSmallUhat rows: one workgroup of NT
+// threads per merge applies the rotations and forms the secular roots, zhat,
+// the column norms, Uhat and the output ranks in turn (one launch instead of
+// several whose fixed latency exceeds this work, and no grid sized for K = m),
+// with G lanes per root or item.  With G = kSecG (the levels that take this
+// step alone) the per-item arithmetic is that of the multi-block kernels, so a
+// merge gives the same bits on either path.
 constexpr int kSmallUhat = 64;
-constexpr int kSmallThreads = 1024;
+constexpr int kStageSmallThreads = 1024;
 
 __device__ void rank_item(const MergeDesc& M, const Scratch& S, int x);
 
+template <int NT, int G>
 __device__ void small_body(const MergeDesc& M, const Scratch& S, bool normalized, double* sd, double* sz) {
-  constexpr int NT = kSmallThreads;
+  static_assert(NT % 64 == 0 && NT / G >= kSmallUhat, "one pass over the roots");
   const int K = S.counters[(int64_t)M.id * kCounters + C_K];
   const int t = threadIdx.x;
   const int64_t so = M.s_off;
-  // rotations of the input block (independent of the steps below): 16 groups of
-  // 64 threads, group g takes the chains g, g + 16, ..., thread r of a group row r
+  // rotations of the input block (independent of the steps below): NT / 64 groups
+  // of 64 threads, group g takes the chains g, g + NT / 64, ..., thread r of a group row r
   if ((t & 63) < M.m) rotate_chains(M, S, t & 63, t >> 6, NT / 64);
   if (K > 0) {  // block-uniform
-    // secular roots, kSecG lanes each, poles staged in LDS (K <= kSmallUhat)
-    constexpr int G = kSecG;
+    // secular roots, G lanes each, poles staged in LDS (K <= kSmallUhat)
     const double rho = S.mparam[(int64_t)M.id * 4 + 0];
     const int maxit = (M.flags & kFlagNoSecularIters) ? 0 : kSecMaxIters;
     for (int i = t; i < K; i += NT) {
@@ -979,10 +986,10 @@ __device__ void small_body(const MergeDesc& M, const Scratch& S, bool normalized
       }
     }
     __syncthreads();
-    const int grp = t / kItemG, isub = t % kItemG;
-    for (int i0 = 0; i0 < K; i0 += NT / kItemG) lowner_item(M, S, K, i0 + grp, isub);
+    const int grp = t / G, isub = t % G;
+    for (int i0 = 0; i0 < K; i0 += NT / G) lowner_item<G>(M, S, K, i0 + grp, isub);
     __syncthreads();
-    for (int j0 = 0; j0 < K; j0 += NT / kItemG) unorm_item(M, S, K, j0 + grp, isub);
+    for (int j0 = 0; j0 < K; j0 += NT / G) unorm_item<G>(M, S, K, j0 + grp, isub);
     __syncthreads();
     const bool pole_order = S.counters[(int64_t)M.id * kCounters + C_PATH] == 2;
     double* U = S.uhat + M.u_off;
@@ -1062,6 +1069,7 @@ __device__ void rank_body(const BlockMap& bm, const Scratch& S, int b) {
 // merge writes every row (zeros outside the range), since its output is the
 // caller's eigenvector matrix.
 constexpr int kCopyBlocks = 16384;  // cap on column blocks per merge
+constexpr int kCopyWideRows = 2048;  // root merges from this many rows copy a column per block
 
 // Below the root, each block streams whole columns: a column group of RPT
 // lanes (RPT = m rounded up to a power of two, at most 64) walks the range, 256
@@ -1082,11 +1090,15 @@ __device__ void copy_body(const BlockMap& bm, const Scratch& S, int b) {
   const int nd1 = cnt[C_ND1], nd = nd1 + cnt[C_ND2];
   const int64_t so = M.s_off;
   if (M.root) {
-    // The caller's Q: every row is written.  A whole block per column, rows
-    // in pairs with 16-byte stores (a scalar first row when the column starts
-    // at an odd 8-byte offset, a scalar last row when the rest is odd).
+    // The caller's Q: every row is written.  A whole block per column (a wave
+    // per column below kCopyWideRows rows), rows in pairs with 16-byte stores
+    // (a scalar first row when the column starts at an odd 8-byte offset, a
+    // scalar last row when the rest is odd).
     typedef double d2_t __attribute__((ext_vector_type(2)));
-    for (int q = lb; q < nd; q += G) {
+    const bool wide = m >= kCopyWideRows;
+    const int lane = wide ? threadIdx.x : (threadIdx.x & 63), step = wide ? 256 : 64;
+    const int q0 = wide ? lb : lb * 4 + (threadIdx.x >> 6), qs = wide ? G : G * 4;
+    for (int q = q0; q < nd; q += qs) {
       int c, dst;
       if (q < nd1) { c = S.dfc1[so + q]; dst = S.destd1[so + q]; }
       else { const int q2 = q - nd1; c = S.dfc2[so + q2]; dst = S.destd2[so + q2]; }
@@ -1096,13 +1108,13 @@ __device__ void copy_body(const BlockMap& bm, const Scratch& S, int b) {
       const int a = (int)(((uintptr_t)out >> 3) & 1);
       const int np = (m - a) >> 1;
       auto val = [&](int r) { return (r >= g.lo && r < g.hi) ? src[r] : 0.0; };
-      if (threadIdx.x == 0) {
+      if (lane == 0) {
         if (a) out[0] = val(0);
         if ((m - a) & 1) out[m - 1] = val(m - 1);
       }
       d2_t* o2 = (d2_t*)(out + a);
 #pragma unroll 4
-      for (int p = threadIdx.x; p < np; p += 256) {
+      for (int p = lane; p < np; p += step) {
         const int r = a + 2 * p;
         o2[p] = d2_t{val(r), val(r + 1)};
       }
@@ -1144,21 +1156,28 @@ bool small_merge(int m, const phdc_opts* o) {
   return !(o->gemm_mode == PHDC_GEMM_HSS && m >= std::max<int64_t>(o->hss_min_K, 1));
 }
 
-int map_blocks(int kind, int m, int n1, int gt, bool root, bool small) {
+int map_blocks(int kind, int m, int n1, int gt, bool root, bool small, int nm) {
   auto cdiv = [](int a, int b) { return (a + b - 1) / b; };
   if (small || kind == MAP_SMALL) return (small && kind == MAP_SMALL) ? 1 : 0;
+  const int share = cdiv(kLevelBlocks, std::max(nm, 1));  // this merge's part of a full level launch
+  auto trim = [&](int full, int unit) {  // at least one unit, whole units, at most full
+    return full <= share ? full : unit * std::max(1, share / unit);
+  };
   switch (kind) {
-    case MAP_SECULAR: return cdiv(m, kSecThreads / kSecG);
-    case MAP_ROOTS16: return cdiv(m, kItemsPerBlock);
+    case MAP_SECULAR: return trim(cdiv(m, kSecThreads / kSecG), 1);
+    case MAP_ROOTS16: return trim(cdiv(m, kItemsPerBlock), 1);
     case MAP_ROWS256: return cdiv(m, 256);
-    case MAP_ROT: return cdiv(m, 256) * std::max(1, std::min(m / 2, kRotGroups));
-    case MAP_UWRITE: return cdiv(m, 256) * std::max(1, std::min(m, kUwRowGroups));
-    case MAP_GEMM: return std::min((cdiv(n1, 64) + cdiv(m - n1, 64)) * cdiv(m, 64), kGemmBlockCap);  // edge-64 tiles
-    case MAP_COPY: {  // root: one column per block; else 256 / (m rounded up to a power of two, at most 64)
-      if (root) return std::max(1, std::min(m, kCopyBlocks));
+    case MAP_ROT: return trim(cdiv(m, 256) * std::max(1, std::min(m / 2, kRotGroups)), cdiv(m, 256));
+    case MAP_UWRITE: return trim(cdiv(m, 256) * std::max(1, std::min(m, kUwRowGroups)), cdiv(m, 256));
+    case MAP_GEMM:  // edge-64 tiles
+      return trim(std::min((cdiv(n1, 64) + cdiv(m - n1, 64)) * cdiv(m, 64), kGemmBlockCap), 1);
+    case MAP_COPY: {
+      // root: a block per column from kCopyWideRows rows, else a wave per column;
+      // below the root, 256 / (m rounded up to a power of two, at most 64) per block
+      if (root) return trim(std::max(1, std::min(m >= kCopyWideRows ? m : cdiv(m, 4), kCopyBlocks)), 1);
       int rpt = 1;
       while (rpt < m && rpt < 64) rpt <<= 1;
-      return std::max(1, std::min(cdiv(m, 256 / rpt), kCopyBlocks));
+      return trim(std::max(1, std::min(cdiv(m, 256 / rpt), kCopyBlocks)), 1);
     }
     case MAP_SPLITA: return cdiv(m, 256) * kSplitKGroups;
     case MAP_SPLITB: return cdiv(m + 8, 256) * kSplitRGroups;
@@ -1193,59 +1212,95 @@ __global__ void __launch_bounds__(256) k_stage_roots(BlockMap sec, int nsec, Blo
   else rotate_body(rot, S, b - nsec);
 }
 
-__global__ void __launch_bounds__(kSmallThreads) k_stage_small(const MergeDesc* __restrict__ descs, Scratch S,
-                                                               int normalized) {
+__global__ void __launch_bounds__(kStageSmallThreads) k_stage_small(const MergeDesc* __restrict__ descs, Scratch S,
+                                                                    int normalized) {
   __shared__ double sd[kSmallUhat];
   __shared__ double sz[kSmallUhat];
   const MergeDesc M = descs[blockIdx.x];
   if (M.flags & kFlagSmallMerge) return;  // done by k_merge_small
-  small_body(M, S, normalized != 0, sd, sz);
+  small_body<kStageSmallThreads, kSecG>(M, S, normalized != 0, sd, sz);
 }
 
 // ------------------------------------------------------------ one-workgroup merges
 // A merge of at most kSmallMergeMax rows on the FP64 path runs in one
-// 1024-thread workgroup from deflation to the eigenvector update: the update
-// product's operands (the gathered input columns and Uhat) are staged in LDS
-// and each output entry is a plain sum over k in order (at these sizes the
-// product is a few hundred thousand flops, less than the latency of one more
-// launch); then the deflated columns are copied.
-constexpr int kSmallLd = kSmallMergeMax + 1;  // LDS row stride of the staged operand (no bank conflicts)
+// workgroup from deflation to the eigenvector update.  Two shapes: levels of
+// many such merges (at least kSmallManyMerges: the GPU is full and throughput
+// counts) take 256 threads and four lanes per secular root -- at these sizes
+// the sums over the poles are short, so fewer lanes per root waste fewer
+// instructions on the group sums and the rational step, and several merges
+// share a CU; levels of fewer merges take 1024 threads and kSecG lanes per
+// root, for the shortest latency per merge (with merges of at most 32 rows,
+// 256 threads are faster there too).  The update product runs on the FP64
+// matrix cores, one wave per 16 x 16 output tile: Uhat (grouped rows) and the
+// two column lists are staged in LDS, the input columns are read directly;
+// then the deflated columns are copied.
+constexpr int kSmallManyMerges = 2048;
+typedef double d4s_t __attribute__((ext_vector_type(4)));
 
-__device__ void small_update(const MergeDesc& M, const Scratch& S, double* Ag, double* Us) {
-  const int t = threadIdx.x, m = M.m, n1 = M.n1;
+// Us: LDS for K rows of ldu doubles; cl, rl: LDS for 2 kSmallMergeMax columns
+// and row ranges (top list, then bottom list).
+template <int NT>
+__device__ void small_update(const MergeDesc& M, const Scratch& S, double* Us, int ldu, int32_t* cl, RowRange* rl) {
+  const int t = threadIdx.x, m = M.m, n1 = M.n1, n2 = M.m - M.n1;
   const int32_t* cnt = S.counters + (int64_t)M.id * kCounters;
   const int K = cnt[C_K], k1 = cnt[C_K1], k2 = cnt[C_K2], k3 = cnt[C_K3];
+  const int kt = k1 + k2, kb = k2 + k3;
   const int64_t so = M.s_off;
-  // Ag(r, k): row r of the merge block, column k of the half's column list
-  // (rows outside the column's range as 0); Us(g, j) = Uhat in grouped rows
-  for (int x = t; x < m * kSmallMergeMax; x += kSmallThreads) {
-    const int r = x / kSmallMergeMax, k = x % kSmallMergeMax;
-    const bool top = r < n1;
-    double v = 0.0;
-    if (k < (top ? k1 + k2 : k2 + k3)) {
-      const int c = top ? S.coltop[so + k] : S.colbot[so + k];
-      const RowRange g = top ? S.rgtop[so + k] : S.rgbot[so + k];
-      if (r >= g.lo && r < g.hi) v = M.qin[r + (int64_t)c * M.ldin];
-    }
-    Ag[r * kSmallLd + k] = v;
+  for (int x = t; x < kt; x += NT) {
+    cl[x] = S.coltop[so + x];
+    rl[x] = S.rgtop[so + x];
+  }
+  for (int x = t; x < kb; x += NT) {
+    cl[kSmallMergeMax + x] = S.colbot[so + x];
+    rl[kSmallMergeMax + x] = S.rgbot[so + x];
   }
   const double* U = S.uhat + M.u_off;
-  for (int x = t; x < K * K; x += kSmallThreads) Us[(x / K) * kSmallMergeMax + x % K] = U[x];
+  for (int x = t; x < K * K; x += NT) Us[(x / K) * ldu + x % K] = U[x];
   __syncthreads();
-  // output (r, j): consecutive threads take consecutive rows of one column
-  for (int x = t; x < m * K; x += kSmallThreads) {
-    const int r = x % m, j = x / m;
-    const bool top = r < n1;
-    const int kd = top ? k1 + k2 : k2 + k3;
-    const double* a = Ag + r * kSmallLd;
-    const double* u = Us + (top ? 0 : k1) * kSmallMergeMax + j;
-    double acc = 0.0;
-    for (int k = 0; k < kd; ++k) acc = fma(a[k], u[k * kSmallMergeMax], acc);
-    M.qout[r + (int64_t)S.dest[so + j] * M.ldout] = acc;
+  // Row tiles of 16 per half (a tile never straddles the halves), column tiles
+  // of 16 roots.  v_mfma_f64_16x16x4f64: A(i, k) from lane 16 k + i, B(k, j)
+  // from lane 16 k + j, result element q of lane l at (l / 16 + 4 q, l % 16).
+  const int tt = (n1 + 15) / 16, tb = (n2 + 15) / 16, TM = tt + tb, TN = (K + 15) / 16;
+  const int lane = t & 63, li = lane & 15, lk = lane >> 4;
+  constexpr int NS = kSmallMergeMax / 4;  // k-steps of 4
+  for (int tile = t >> 6; tile < TM * TN; tile += NT / 64) {
+    const int mt = tile % TM, nt = tile / TM;
+    const bool top = mt < tt;
+    const int r0 = top ? mt * 16 : n1 + (mt - tt) * 16;  // first merge row of the tile
+    const int rend = top ? n1 : m;
+    const int kd = top ? kt : kb;
+    const int off = top ? 0 : k1;  // first grouped row of Uhat this half uses
+    const int32_t* ca = cl + (top ? 0 : kSmallMergeMax);
+    const RowRange* ra = rl + (top ? 0 : kSmallMergeMax);
+    const int r = r0 + li, j = nt * 16 + li;
+    double av[NS], bv[NS];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+      const int k = 4 * q + lk;
+      av[q] = 0.0;
+      bv[q] = 0.0;
+      if (k < kd) {
+        const RowRange g = ra[k];
+        if (r < rend && r >= g.lo && r < g.hi) av[q] = M.qin[r + (int64_t)ca[k] * M.ldin];
+        if (j < K) bv[q] = Us[(off + k) * ldu + j];
+      }
+    }
+    d4s_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < NS; ++q)
+      if (4 * q < kd) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[q], acc, 0, 0, 0);  // (wave-uniform)
+    if (j < K) {
+      double* oc = M.qout + (int64_t)S.dest[so + j] * M.ldout;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int rr = r0 + lk + 4 * q;
+        if (rr < rend) oc[rr] = acc[q];
+      }
+    }
   }
   // deflated columns: over their range (every row when the merge is a root)
   const int nd1 = cnt[C_ND1], nd = nd1 + cnt[C_ND2];
-  for (int x = t; x < nd * kSmallMergeMax; x += kSmallThreads) {
+  for (int x = t; x < nd * kSmallMergeMax; x += NT) {
     const int q = x / kSmallMergeMax, r = x % kSmallMergeMax;
     if (r >= m) continue;
     int c, dst;
@@ -1257,18 +1312,22 @@ __device__ void small_update(const MergeDesc& M, const Scratch& S, double* Ag, d
   }
 }
 
-__global__ void __launch_bounds__(kSmallThreads) k_merge_small(BlockMap bm, Scratch S) {
-  __shared__ double Ag[kSmallMergeMax * kSmallLd];
-  __shared__ double Us[kSmallMergeMax * kSmallMergeMax];
+// Dynamic LDS: kmax (ldu = kmax + 1) doubles, kmax = the largest such merge of
+// the level (at most kSmallMergeMax); it holds the poles during deflation.
+template <int NT, int G>
+__global__ void __launch_bounds__(NT) k_merge_small(BlockMap bm, Scratch S, int ldu) {
+  HIP_DYNAMIC_SHARED(double, Us)
   __shared__ double sd[kSmallUhat];
   __shared__ double sz[kSmallUhat];
+  __shared__ int32_t cl[2 * kSmallMergeMax];
+  __shared__ RowRange rl[2 * kSmallMergeMax];
   const int mi = find_merge(bm, blockIdx.x);
   const MergeDesc M = bm.descs[mi];
-  deflate_body<kSmallThreads>(M, S, M.m, Ag);  // (Ag doubles as the poles' staging area)
+  deflate_body<NT>(M, S, M.m, Us);
   __syncthreads();
-  small_body(M, S, true, sd, sz);
+  small_body<NT, G>(M, S, true, sd, sz);
   __syncthreads();
-  small_update(M, S, Ag, Us);
+  small_update<NT>(M, S, Us, ldu, cl, rl);
 }
 
 __global__ void __launch_bounds__(256) k_stage_lowner(BlockMap low, int nlow, BlockMap rank, Scratch S) {
@@ -1294,7 +1353,12 @@ void launch_merge_level(const MergeDesc* descs, int nm, const LevelMaps& maps, c
   const int nsmall = maps.total[MAP_SMALL];
   if (nsmall > 0) {  // merges that run in one workgroup each, deflation included
     ProfScope p(PH_SMALL_MERGE, s);
-    hipLaunchKernelGGL(k_merge_small, dim3(nsmall), dim3(kSmallThreads), 0, s, bmap(MAP_SMALL), S);
+    const int kmax = std::min(maps.maxm, kSmallMergeMax);
+    const size_t lds = (size_t)kmax * (kmax + 1) * sizeof(double);
+    if (nsmall >= kSmallManyMerges || kmax <= 32)
+      hipLaunchKernelGGL((k_merge_small<256, 4>), dim3(nsmall), dim3(256), lds, s, bmap(MAP_SMALL), S, kmax + 1);
+    else
+      hipLaunchKernelGGL((k_merge_small<1024, kSecG>), dim3(nsmall), dim3(1024), lds, s, bmap(MAP_SMALL), S, kmax + 1);
     if (nsmall == nm) return;  // (no HSS candidate in such a level: no probe needed)
   }
   { ProfScope p(PH_DEFLATE, s);
@@ -1313,7 +1377,7 @@ void launch_merge_level(const MergeDesc* descs, int nm, const LevelMaps& maps, c
   const int ncopy = maps.total[MAP_COPY];
   if (maps.maxm <= kSmallUhat) {
     { ProfScope p(PH_SECULAR, s);
-      hipLaunchKernelGGL(k_stage_small, dim3(nm), dim3(kSmallThreads), 0, s, descs, S, normalized); }
+      hipLaunchKernelGGL(k_stage_small, dim3(nm), dim3(kStageSmallThreads), 0, s, descs, S, normalized); }
     { ProfScope p(PH_UWRITE, s);  // (the copy phase times the lone root copy only)
       hipLaunchKernelGGL(k_stage_uhat, dim3(ncopy), dim3(256), 0, s, bmap(MAP_COPY), ncopy, none, 0, none, S, 0); }
   } else {

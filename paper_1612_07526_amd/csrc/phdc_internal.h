@@ -186,7 +186,12 @@ struct LevelMaps {
 // root: the merge is the last one of its matrix (MAP_COPY: one column per block);
 // small: the merge runs in one workgroup of k_merge_small (MAP_SMALL: 1 block,
 // every other class 0).
-int map_blocks(int kind, int m, int n1, int gt, bool root, bool small = false);
+// Blocks of merge (m, n1) in a level of nm merges.  Kinds whose blocks loop
+// over their items get fewer blocks per merge once a level would launch more
+// than kLevelBlocks (levels of many small merges: the trimmed blocks would
+// mostly find no work, yet each costs a dispatch).
+constexpr int kLevelBlocks = 16384;
+int map_blocks(int kind, int m, int n1, int gt, bool root, bool small = false, int nm = 1);
 // Whether a merge of m rows takes the one-workgroup path for these options.
 bool small_merge(int m, const phdc_opts* o);
 constexpr int kGemmBlockCap = 1024;      // blocks per merge of the update GEMMs (they loop over tiles)

@@ -116,17 +116,22 @@ def random_orthogonal(n: int, g: np.random.Generator):
     return Q * np.sign(np.diag(R))[None, :]
 
 
-def fig3_merge(N: int, seed: int = 0, with_q: bool = True):
+def fig3_merge(N: int, seed: int = 0, with_q: bool | str = True):
     """Rank-one merge of Sec. 2.2: d_i = i/N (i = 1..N), rho = 1, z a random unit vector.
 
     Split in halves n1 = N//2, n2 = N - n1; Q1, Q2 random orthogonal (QR of Gaussian).
+    with_q="gaussian" returns the two Gaussian matrices instead, for a caller that
+    orthonormalises them elsewhere (large N, where a host QR takes minutes).
     """
     g = rng(seed)
     D = np.arange(1, N + 1, dtype=np.float64) / N
     z = g.standard_normal(N)
     z /= np.linalg.norm(z)
     n1 = N // 2
-    if with_q:
+    if with_q == "gaussian":
+        Q1 = g.standard_normal((n1, n1))
+        Q2 = g.standard_normal((N - n1, N - n1))
+    elif with_q:
         Q1 = random_orthogonal(n1, g)
         Q2 = random_orthogonal(N - n1, g)
     else:
