@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Benchmark: n = 16384 tridiagonal eigensolve on one MI355X, plain vs chosen form.
 
-value: d, e iid Uniform[-1, 1] (seed 0), n = 16384, leaf 16 (--leaf; the library default is 32).  One step = one
+value: d, e iid Uniform[-1, 1] (seed 0), n = 16384, leaf 16 (--leaf; the library default).  One step = one
 complete divide-and-conquer solve (leaves, every merge level, eigenvalues and
 the full n x n eigenvector matrix), inputs resident in HBM.  The chosen form
 (HSS-compressed Uhat for merges with K >= 4096, FP64 MFMA otherwise) is timed
@@ -278,7 +278,7 @@ def sec_value(P, W, args, out):
     del pl
     l32 = Solver(P, d, e, P.opts(gemm_mode=P.GEMM_FP64, leaf_size=32))
     t_l32 = timed(l32, args.steps, 1)
-    log(f"[bench] plain FP64 with the library's default leaf size 32: {t_l32 * 1e3:.3f} ms/solve")
+    log(f"[bench] plain FP64 with leaf size 32: {t_l32 * 1e3:.3f} ms/solve")
     del l32
     # the same solve planned once (prepare) and replayed from a HIP graph: GPU time without
     # the per-call host planning and plan upload

@@ -77,7 +77,7 @@ enum phdc_force_fail {
 };
 
 typedef struct phdc_opts {
-    int32_t leaf_size;      /* largest block solved directly (default 32, range 2..64) */
+    int32_t leaf_size;      /* largest block solved directly (default 16, range 2..64) */
     int32_t gemm_mode;      /* enum phdc_gemm_mode (default PHDC_GEMM_FP64) */
     int64_t hss_min_K;      /* HSS only for merges with at least this many surviving poles (default 4096) */
     double hss_rel_tol;     /* ID truncation tolerance for HSS compression (default 1e-14): a node's

@@ -657,7 +657,7 @@ extern "C" {
 void phdc_opts_default(phdc_opts* o) {
   if (!o) return;
   std::memset(o, 0, sizeof(*o));
-  o->leaf_size = 32;
+  o->leaf_size = 16;
   o->gemm_mode = PHDC_GEMM_FP64;
   o->hss_min_K = 4096;
   o->hss_rel_tol = 1e-14;

@@ -109,17 +109,19 @@ __device__ __forceinline__ void gemm_merge_tiles(const MergeDesc& M, const Scrat
         for (int e = 0; e < E; ++e) ra[e] = (e >= lo && e < hi) ? src[e] : 0.0;
         const double* bs = Bm + (int64_t)kk * K + ncol0 + l8;
   #pragma unroll
-        for (int e = 0; e < E; ++e) rb[e] = (ncol0 + l8 + e < K) ? bs[e] * csc[e] : 0.0;
+        for (int e = 0; e < E; ++e) rb[e] = (ncol0 + l8 + e < K) ? bs[e] : 0.0;
       } else {
   #pragma unroll
         for (int e = 0; e < E; ++e) { ra[e] = 0.0; rb[e] = 0.0; }
       }
     };
+    // (the column scale is applied here, after the step's MFMAs, not right after
+    // the load: there it would make the step wait for its loads before computing)
     auto lstore = [&](int buf) {
   #pragma unroll
       for (int e = 0; e < E; ++e) {
         As[buf][lkc][l8 + e] = ra[e];
-        Bs[buf][lkc][l8 + e] = rb[e];
+        Bs[buf][lkc][l8 + e] = rb[e] * csc[e];
       }
     };
 

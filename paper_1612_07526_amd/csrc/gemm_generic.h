@@ -58,8 +58,10 @@ struct VGemm {
 };
 
 // Launch a batch of products described by `descs` (device) with tile prefix
-// `pfx` (device, nd + 1 entries, pfx[nd] == total tiles of 128 x 128).
-void vgemm_launch(const VGemm* descs, const int32_t* pfx, int nd, int total, hipStream_t s);
+// `pfx` (device, nd + 1 entries, pfx[nd] == total tiles of 128 x 128).  The
+// products are ordered by transposition group q = ta + 2 tb, whose tiles are
+// [bound[q], bound[q + 1]) (host array of 5).
+void vgemm_launch(const VGemm* descs, const int32_t* pfx, int nd, const int* bound, hipStream_t s);
 int vgemm_tiles(int m, int n);
 
 }  // namespace phdc

@@ -159,57 +159,61 @@ int vgemm_tiles(int m, int n) {
   return ((m + QT - 1) / QT) * ((n + QT - 1) / QT);
 }
 
-// Variable-size batch: every block finds its product by binary search in the
-// tile prefix and computes one 128 x 128 tile of it.
-__global__ void __launch_bounds__(256) k_vgemm(const VGemm* __restrict__ descs, const int32_t* __restrict__ pfx,
-                                               int nd) {
-  __shared__ double As[2][QBUF];
-  __shared__ double Bs[2][QBUF];
-  const int bid = blockIdx.x;
-  int lo = 0, hi = nd - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (pfx[mid] <= bid) lo = mid; else hi = mid - 1;
-  }
-  const VGemm g = descs[lo];
-  const int tile = bid - pfx[lo];
+// Variable-size batch: the products are grouped by their transpositions, one
+// launch per group compiled for it (the staging layout is then fixed at compile
+// time, as in k_gemm_f64); every block finds its product by binary search in the
+// tile prefix and computes one 128 x 128 tile of it.  alpha scales the staged A entries and beta C
+// enters through the matrix cores, so the epilogue is a plain store (arithmetic
+// there would pull all 64 accumulators into VGPRs at once).
+template <bool TA, bool TB>
+__device__ __forceinline__ void vgemm_tile(const VGemm& g, int tile, double (*As)[QBUF], double (*Bs)[QBUF]) {
+  constexpr bool AKC = TA, BKC = !TB;  // operands with k contiguous in memory are staged [row][k]
   const int tmn = (g.m + QT - 1) / QT;
   const int i0 = (tile % tmn) * QT, j0 = (tile / tmn) * QT;
   const int t = threadIdx.x;
-  const bool akc = g.ta, bkc = !g.tb;  // operands with k contiguous in memory are staged [row][k]
-  auto at = [](bool kc, int k, int r) { return kc ? r * QKP + k : k * QLD + r; };
   double ra[8], rb[8];
   auto gload = [&](int kt) {
     const int kb = kt * QK;
-    if (!g.ta) {
+    if (!TA) {
       const int k = kb + (t >> 4), i = i0 + (t & 15) * 8;
       const double* src = g.A + (int64_t)k * g.lda + i;
+#pragma unroll
       for (int e = 0; e < 8; ++e) ra[e] = (k < g.k && i + e < g.m) ? src[e] : 0.0;
     } else {
       const int i = i0 + (t >> 1), k = kb + (t & 1) * 8;
       const double* src = g.A + (int64_t)i * g.lda + k;
+#pragma unroll
       for (int e = 0; e < 8; ++e) ra[e] = (i < g.m && k + e < g.k) ? src[e] : 0.0;
     }
-    if (!g.tb) {
+    if (!TB) {
       const int j = j0 + (t >> 1), k = kb + (t & 1) * 8;
       const double* src = g.B + (int64_t)j * g.ldb + k;
+#pragma unroll
       for (int e = 0; e < 8; ++e) rb[e] = (j < g.n && k + e < g.k) ? src[e] : 0.0;
     } else {
       const int k = kb + (t >> 4), j = j0 + (t & 15) * 8;
       const double* src = g.B + (int64_t)k * g.ldb + j;
+#pragma unroll
       for (int e = 0; e < 8; ++e) rb[e] = (k < g.k && j + e < g.n) ? src[e] : 0.0;
     }
+    if (g.alpha != 1.0)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) ra[e] *= g.alpha;
   };
   auto lstore = [&](int buf) {
-    if (!g.ta) {
-      for (int e = 0; e < 8; ++e) As[buf][at(akc, t >> 4, (t & 15) * 8 + e)] = ra[e];
+    if (!TA) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) As[buf][lds_at<AKC>(t >> 4, (t & 15) * 8 + e)] = ra[e];
     } else {
-      for (int e = 0; e < 8; ++e) As[buf][at(akc, (t & 1) * 8 + e, t >> 1)] = ra[e];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) As[buf][lds_at<AKC>((t & 1) * 8 + e, t >> 1)] = ra[e];
     }
-    if (!g.tb) {
-      for (int e = 0; e < 8; ++e) Bs[buf][at(bkc, (t & 1) * 8 + e, t >> 1)] = rb[e];
+    if (!TB) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) Bs[buf][lds_at<BKC>((t & 1) * 8 + e, t >> 1)] = rb[e];
     } else {
-      for (int e = 0; e < 8; ++e) Bs[buf][at(bkc, t >> 4, (t & 15) * 8 + e)] = rb[e];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) Bs[buf][lds_at<BKC>(t >> 4, (t & 15) * 8 + e)] = rb[e];
     }
   };
   const int w = t >> 6, lane = t & 63;
@@ -234,9 +238,9 @@ __global__ void __launch_bounds__(256) k_vgemm(const VGemm* __restrict__ descs, 
       const int kr = ks * 4 + lk;
       double av[4], bv[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = As[buf][at(akc, kr, wm + i * 16 + li)];
+      for (int i = 0; i < 4; ++i) av[i] = As[buf][lds_at<AKC>(kr, wm + i * 16 + li)];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = Bs[buf][at(bkc, kr, wn + j * 16 + li)];
+      for (int j = 0; j < 4; ++j) bv[j] = Bs[buf][lds_at<BKC>(kr, wn + j * 16 + li)];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -244,6 +248,27 @@ __global__ void __launch_bounds__(256) k_vgemm(const VGemm* __restrict__ descs, 
     }
     if (kt + 1 < nkt) lstore(buf ^ 1);
     __syncthreads();
+  }
+  {
+    // acc += beta C on the matrix cores: four more k-steps per 16 x 16 block with
+    // A = the columns 4q..4q+3 of the identity and B = rows 4q..4q+3 of beta C,
+    // so each entry gains beta C(i, j) in one rounding, as acc + beta C would.
+    // (Run for beta == 0 too, adding zeros: a branch around these steps makes the
+    // compiler move the accumulators out of their registers.)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int cj = j0 + wn + j * 16 + li;
+      const double* col = (cj < g.n) ? g.C + (int64_t)(g.cmap ? g.cmap[cj] : cj) * g.ldc : nullptr;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int ri = i0 + wm + i * 16 + 4 * q + lk;
+          const double bq = (g.beta != 0.0 && col && ri < g.m) ? g.beta * col[ri] : 0.0;
+          const double aq = (li == 4 * q + lk) ? 1.0 : 0.0;
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(aq, bq, acc[i][j], 0, 0, 0);
+        }
+    }
   }
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -255,17 +280,36 @@ __global__ void __launch_bounds__(256) k_vgemm(const VGemm* __restrict__ descs, 
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int ri = i0 + wm + i * 16 + lk + 4 * r;
-        if (ri < g.m) {
-          const double v = g.alpha * acc[i][j][r];
-          col[ri] = (g.beta == 0.0) ? v : v + g.beta * col[ri];
-        }
+        if (ri < g.m) col[ri] = acc[i][j][r];
       }
   }
 }
 
-void vgemm_launch(const VGemm* descs, const int32_t* pfx, int nd, int total, hipStream_t s) {
-  if (nd <= 0 || total <= 0) return;
-  hipLaunchKernelGGL(k_vgemm, dim3(total), dim3(256), 0, s, descs, pfx, nd);
+template <bool TA, bool TB>
+__global__ void __launch_bounds__(256) k_vgemm(const VGemm* __restrict__ descs, const int32_t* __restrict__ pfx,
+                                               int nd, int base) {
+  __shared__ double As[2][QBUF];
+  __shared__ double Bs[2][QBUF];
+  const int bid = base + blockIdx.x;
+  int lo = 0, hi = nd - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (pfx[mid] <= bid) lo = mid; else hi = mid - 1;
+  }
+  const VGemm g = descs[lo];
+  vgemm_tile<TA, TB>(g, bid - pfx[lo], As, Bs);
+}
+
+void vgemm_launch(const VGemm* descs, const int32_t* pfx, int nd, const int* bound, hipStream_t s) {
+  if (nd <= 0) return;
+  for (int q = 0; q < 4; ++q) {
+    const int nb = bound[q + 1] - bound[q];
+    if (nb <= 0) continue;
+    if (q == 0) hipLaunchKernelGGL((k_vgemm<false, false>), dim3(nb), dim3(256), 0, s, descs, pfx, nd, bound[q]);
+    else if (q == 1) hipLaunchKernelGGL((k_vgemm<true, false>), dim3(nb), dim3(256), 0, s, descs, pfx, nd, bound[q]);
+    else if (q == 2) hipLaunchKernelGGL((k_vgemm<false, true>), dim3(nb), dim3(256), 0, s, descs, pfx, nd, bound[q]);
+    else hipLaunchKernelGGL((k_vgemm<true, true>), dim3(nb), dim3(256), 0, s, descs, pfx, nd, bound[q]);
+  }
 }
 
 }  // namespace phdc

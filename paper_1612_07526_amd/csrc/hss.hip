@@ -122,12 +122,16 @@ __global__ void __launch_bounds__(256) k_skel(const SkelDesc* __restrict__ sd) {
 constexpr int kIdMax = kHssLeafMax;  // rows p of one decomposition; the sample count d <= 512 < kIdMax
 constexpr int kIdThreads = 1024;
 constexpr int kIdWaves = kIdThreads / 64;
-constexpr int kIdLanes = 4;                     // lanes per column in the reflector update
+constexpr int kIdLanes = 16;                    // lanes per column in the reflector update
 constexpr int kIdCols = kIdThreads / kIdLanes;  // columns updated at a time
+constexpr int kIdRegs = 16;                     // entries of a column a lane keeps in registers
+constexpr int kIdSpan = kIdLanes * kIdRegs;     // rows j .. j + kIdSpan - 1 of a column stay in registers
 
 __device__ inline double id_group_sum(double s) {
   s += __shfl_xor(s, 1, 64);
   s += __shfl_xor(s, 2, 64);
+  s += __shfl_xor(s, 4, 64);
+  s += __shfl_xor(s, 8, 64);
   return s;
 }
 
@@ -252,32 +256,57 @@ __global__ void __launch_bounds__(kIdThreads) k_row_id(const IdDesc* __restrict_
     if (t == 0) v[j] = x0 - alpha;
     __syncthreads();
     if (vtv > 0.0) {
-      // Apply the reflector to the remaining columns, four lanes per column.
+      // Apply the reflector to the remaining columns, kIdLanes lanes per column:
+      // a lane loads its entries of the column's first kIdSpan rows (from j) once,
+      // all in flight together, and keeps them in registers for the dot product,
+      // the update and, when needed, the recomputed norm; rows beyond (only with
+      // more than kIdSpan samples) are read again for the update.  (Offsets into
+      // the work copy fit in 32 bits: p d <= kIdMax * 512.)
       for (int c0 = j + 1; c0 < p; c0 += kIdCols) {
         const int c = c0 + cg;
         const bool on = c < p;
+        double x[kIdRegs];
+#pragma unroll
+        for (int u = 0; u < kIdRegs; ++u) {
+          const int k = j + sub + u * kIdLanes;
+          x[u] = (on && k < d) ? W[c + k * p] : 0.0;
+        }
         double dot = 0.0;
+#pragma unroll
+        for (int u = 0; u < kIdRegs; ++u) {
+          const int k = j + sub + u * kIdLanes;
+          if (k < d) dot += v[k] * x[u];
+        }
         if (on)
-          for (int k = j + sub; k < d; k += kIdLanes) dot += v[k] * W[c + (int64_t)k * p];
+          for (int k = j + kIdSpan + sub; k < d; k += kIdLanes) dot += v[k] * W[c + k * p];
         dot = id_group_sum(dot);
         const double f = 2.0 * dot / vtv;
         double rjc = 0.0;
-        if (on)
-          for (int k = j + sub; k < d; k += kIdLanes) {
-            const double x = W[c + (int64_t)k * p] - f * v[k];
-            W[c + (int64_t)k * p] = x;
-            if (k == j) rjc = x;  // R_jc, held by lane sub == 0
+#pragma unroll
+        for (int u = 0; u < kIdRegs; ++u) {
+          const int k = j + sub + u * kIdLanes;
+          if (on && k < d) {
+            x[u] -= f * v[k];
+            W[c + k * p] = x[u];
+            if (k == j) rjc = x[u];  // R_jc, held by lane sub == 0
           }
+        }
+        if (on)
+          for (int k = j + kIdSpan + sub; k < d; k += kIdLanes) W[c + k * p] -= f * v[k];
         rjc = id_group_sum(rjc);
         double nc = on ? cn[c] - rjc * rjc : 0.0;
-        const bool redo = on && nc <= 1e-2 * cn0[c];  // same decision in all four lanes
+        const bool redo = on && nc <= 1e-2 * cn0[c];  // same decision in all lanes of the group
         if (redo) {  // cancellation: recompute the remaining norm
           double q = 0.0;
-          for (int k = j + sub; k < d; k += kIdLanes)
-            if (k > j) {
-              const double x = W[c + (int64_t)k * p];
-              q += x * x;
-            }
+#pragma unroll
+          for (int u = 0; u < kIdRegs; ++u) {
+            const int k = j + sub + u * kIdLanes;
+            if (k > j && k < d) q += x[u] * x[u];
+          }
+          for (int k = j + kIdSpan + sub; k < d; k += kIdLanes) {
+            const double y = W[c + k * p];
+            q += y * y;
+          }
           nc = q;
         }
         const double nred = id_group_sum(redo ? nc : 0.0);
@@ -364,13 +393,25 @@ struct Stage {
   }
 };
 
+// A batch of independent products, kept ordered by transposition group
+// (ta + 2 tb) for vgemm_launch; bound[q] is the first tile of group q.
 struct VBatch {
   std::vector<VGemm> g;
   std::vector<int32_t> pf{0};
+  int bound[5] = {0, 0, 0, 0, 0};
+  static int group(const VGemm& x) { return (x.ta ? 1 : 0) + (x.tb ? 2 : 0); }
   void add(const VGemm& x) {
     if (x.m <= 0 || x.n <= 0) return;
-    g.push_back(x);
-    pf.push_back(pf.back() + vgemm_tiles(x.m, x.n));
+    const int q = group(x);
+    size_t pos = 0;
+    while (pos < g.size() && group(g[pos]) <= q) ++pos;
+    g.insert(g.begin() + pos, x);
+    pf.assign(1, 0);
+    for (int b = 0; b < 5; ++b) bound[b] = 0;
+    for (const VGemm& y : g) {
+      pf.push_back(pf.back() + vgemm_tiles(y.m, y.n));
+      for (int b = group(y) + 1; b < 5; ++b) bound[b] = pf.back();
+    }
   }
 };
 
@@ -551,7 +592,7 @@ int hss_core(const HssSource& src, int K, int m, const double* X, int64_t ldx, d
                              src.lda);
         if (root_only) break;
         if (drc) hipLaunchKernelGGL(k_rows, dim3((unsigned)rc.size()), dim3(256), 0, s, drc);
-        if (dg1) vgemm_launch(dg1, dp1, (int)g1.g.size(), g1.pf.back(), s);
+        if (dg1) vgemm_launch(dg1, dp1, (int)g1.g.size(), g1.bound, s);
         VBatch g2;
         for (int i : nodes) {
           const HNode& h = T[i];
@@ -574,7 +615,7 @@ int hss_core(const HssSource& src, int K, int m, const double* X, int64_t ldx, d
         const int32_t* dp2 = st.push(g2.pf);
         const IdDesc* did = st.push(idd);
         if (int rc = st.flush(key, s)) return rc;
-        if (dg2) vgemm_launch(dg2, dp2, (int)g2.g.size(), g2.pf.back(), s);
+        if (dg2) vgemm_launch(dg2, dp2, (int)g2.g.size(), g2.bound, s);
         hipLaunchKernelGGL(k_row_id, dim3((unsigned)idd.size()), dim3(kIdThreads), 0, s, did, o->hss_rel_tol,
                            o->hss_rel_tol * std::sqrt((double)d) * anorm);
         if (hipMemcpyAsync(hr.data(), ranks, hr.size() * 4, hipMemcpyDeviceToHost, s) != hipSuccess) return PHDC_E_HIP;
@@ -626,8 +667,8 @@ int hss_core(const HssSource& src, int K, int m, const double* X, int64_t ldx, d
         hipLaunchKernelGGL(k_rows, dim3((unsigned)rs.size()), dim3(256), 0, s, drs);
         if (dic) hipLaunchKernelGGL(k_ints, dim3((unsigned)ic.size()), dim3(256), 0, s, dic);
         hipLaunchKernelGGL(k_skel, dim3((unsigned)sk.size()), dim3(256), 0, s, dsk);
-        if (dg3) vgemm_launch(dg3, dp3, (int)g3.g.size(), g3.pf.back(), s);
-        if (dg4) vgemm_launch(dg4, dp4, (int)g4.g.size(), g4.pf.back(), s);
+        if (dg3) vgemm_launch(dg3, dp3, (int)g3.g.size(), g3.bound, s);
+        if (dg4) vgemm_launch(dg4, dp4, (int)g4.g.size(), g4.bound, s);
       }
     }
     if (too_large) {
@@ -704,7 +745,7 @@ int hss_core(const HssSource& src, int K, int m, const double* X, int64_t ldx, d
     if (int rc = st.flush(key, s)) return rc;
     for (size_t q = 0; q < stages.size(); ++q)
       if (!stages[q].g.empty())
-        vgemm_launch(dptr[q].first, dptr[q].second, (int)stages[q].g.size(), stages[q].pf.back(), s);
+        vgemm_launch(dptr[q].first, dptr[q].second, (int)stages[q].g.size(), stages[q].bound, s);
     return 0;
   }
   return kHssGaveUp;

@@ -40,7 +40,7 @@ def test_version_and_defaults():
     P, lib = _lib()
     assert lib.phdc_version() >= 1
     o = P.opts()
-    assert o.leaf_size == 32 and o.gemm_mode == P.GEMM_FP64 and o.hss_min_K == 4096
+    assert o.leaf_size == 16 and o.gemm_mode == P.GEMM_FP64 and o.hss_min_K == 4096
     assert o.hss_rel_tol == 1e-14
 
 

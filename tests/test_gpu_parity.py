@@ -174,7 +174,7 @@ def test_stedc_toeplitz_2048_vs_oracle(P, orc):
     # 1-2-1 Toeplitz, n = 2048, leaf 32: every merge deflates exactly half its poles by rotation
     d, e = W.toeplitz_121(2048, -1.0)
     lref, Qref, st_ref = orc.stedc(d, e, leaf=32)
-    lam, Q, work = P.stedc(d, e, return_work=True)
+    lam, Q, work = P.stedc(d, e, o=P.opts(leaf_size=32), return_work=True)
     assert list(P.merge_stats(work)[:6]) == list(st_ref[:6]) == [1024, 0, 1024, 0, 0, 1024]
     lr, Vr = toeplitz_121_exact(2048, -1.0)
     _check_eig(d, e, _np(lam), _np(Q), lr, Vr)
