@@ -85,7 +85,8 @@ typedef struct phdc_opts {
     int32_t hss_leaf;       /* HSS leaf block size, 8..1024 (default 256) */
     int32_t hss_samples;    /* initial number of random sample columns d, 16..512 (default 256) */
     int32_t hss_samples_inc;/* extra sample columns when a rank reaches d - 8, >= 0 (default 128) */
-    int32_t split_slices;   /* number of BF16 slices per operand for PHDC_GEMM_SPLIT, 1..7 (default 7) */
+    int32_t split_slices;   /* number of BF16 slices per operand for PHDC_GEMM_SPLIT, 1..7 (default 6: the
+                               fewest that meet 10x the FP64 bounds) */
     uint64_t seed;          /* seed of the counter-based Gaussian generator used by HSS sampling */
     int32_t canonical_sign; /* if nonzero: each eigenvector's largest-magnitude entry is made positive */
     int32_t check_finite;   /* if nonzero: scan the input arrays for NaN/Inf on the device first; the

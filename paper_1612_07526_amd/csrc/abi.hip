@@ -664,7 +664,7 @@ void phdc_opts_default(phdc_opts* o) {
   o->hss_leaf = 256;
   o->hss_samples = 256;
   o->hss_samples_inc = 128;
-  o->split_slices = 7;
+  o->split_slices = 6;
   o->seed = 0x9e3779b97f4a7c15ULL;
   o->canonical_sign = 0;
   o->check_finite = 0;

@@ -84,14 +84,18 @@ __device__ __forceinline__ void gemm_merge_tiles(const MergeDesc& M, const Scrat
     for (int e = 0; e < E; ++e)
       csc[e] = (scale_cols && ncol0 + l8 + e < K) ? S.cnorm[M.s_off + ncol0 + l8 + e] : 1.0;
 
-    // The column index and row range of the A column a thread stages are read
-    // two k-steps ahead of its data (gidx), so the data load of a step waits on
-    // one memory latency, not on two dependent ones.
+    // With 64-wide tiles (merges with few columns: latency counts), the column
+    // index and row range of the A column a thread stages are read two k-steps
+    // ahead of its data (gidx), so the data load of a step waits on one memory
+    // latency, not on two dependent ones.  With 128-wide tiles (large merges)
+    // they are read with the data: the early reads would make a step's MFMAs
+    // wait for that step's loads (measured: 10% slower at K = 16384).
+    constexpr bool kIdxAhead = GT == 64;
     int nxc = 0;
     RowRange nxg{0, 0};
     auto gidx = [&](int kt) {
       const int kk = kt * GK + lkc;
-      if (kk < kd) {
+      if (kIdxAhead && kk < kd) {
         nxc = colA[kk];
         nxg = rgA[kk];
       }
@@ -102,8 +106,9 @@ __device__ __forceinline__ void gemm_merge_tiles(const MergeDesc& M, const Scrat
       if (kk < kd) {
         // The input block is global memory: say so, so that the loads are
         // global (not flat) ones and the waits can count them separately.
-        const gdouble_t* src = (const gdouble_t*)(A + (int64_t)nxc * lda + mrow0 + l8);
-        const RowRange g = nxg;
+        const int cidx = kIdxAhead ? nxc : colA[kk];
+        const gdouble_t* src = (const gdouble_t*)(A + (int64_t)cidx * lda + mrow0 + l8);
+        const RowRange g = kIdxAhead ? nxg : rgA[kk];
         const int lo = g.lo - (rowoff + mrow0 + l8), hi = min(g.hi - rowoff, Mrows) - (mrow0 + l8);
   #pragma unroll
         for (int e = 0; e < E; ++e) ra[e] = (e >= lo && e < hi) ? src[e] : 0.0;

@@ -533,12 +533,28 @@ int hss_core(const HssSource& src, int K, int m, const double* X, int64_t ldx, d
       hipLaunchKernelGGL(k_gauss, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, cnt, sd, Om1);
       hipLaunchKernelGGL(k_gauss, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, cnt, sd ^ 0x5bd1e9955bd1e995ULL,
                          Om2);
-      // Y = A Omega1, Z = A^T Omega2; a row-major A read column-major is A^T
+      // Y = A Omega1, Z = A^T Omega2; a row-major A read column-major is A^T.
+      // The two products (each K/128 x d/128 tiles: too few blocks to fill the
+      // GPU alone) run side by side, Z on the auxiliary stream.
       const bool rm = src.sample_row_major;
       GemmArgs gy{src.sample, Om1, src.lds, K, 0, 0, K, d, K, 0};
-      gemm_f64(rm, false, gy, 1, Y, K, 0, s);
       GemmArgs gz{src.sample, Om2, src.lds, K, 0, 0, K, d, K, 0};
-      gemm_f64(!rm, false, gz, 1, Z, K, 0, s);
+      struct Events {  // destroyed on every exit (a destroyed event is released once its work completes)
+        hipEvent_t fork = nullptr, join = nullptr;
+        ~Events() {
+          if (fork) (void)hipEventDestroy(fork);
+          if (join) (void)hipEventDestroy(join);
+        }
+      } ev;
+      hipStream_t a = aux_stream();
+      if (a && (hipEventCreateWithFlags(&ev.fork, hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&ev.join, hipEventDisableTiming) != hipSuccess ||
+                hipEventRecord(ev.fork, s) != hipSuccess || hipStreamWaitEvent(a, ev.fork, 0) != hipSuccess))
+        return PHDC_E_HIP;
+      gemm_f64(rm, false, gy, 1, Y, K, 0, s);
+      gemm_f64(!rm, false, gz, 1, Z, K, 0, a ? a : s);
+      if (a && (hipEventRecord(ev.join, a) != hipSuccess || hipStreamWaitEvent(s, ev.join, 0) != hipSuccess))
+        return PHDC_E_HIP;
     }
 
     std::vector<int32_t> hr(2 * nn + 2, 0), hp(2 * nn + 2, 0);

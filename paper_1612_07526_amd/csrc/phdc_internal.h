@@ -167,6 +167,7 @@ constexpr int kLeafMaxIters = 64;
 void launch_scan_finite(const double* a, int64_t n, int32_t* flag, int32_t* status, hipStream_t s);
 // Zero the 256-byte status block (status word and the scan flags after it).
 void launch_clear_status(int32_t* status, hipStream_t s);
+hipStream_t aux_stream();
 
 // Block maps of one merge level (device prefix arrays, nm + 1 entries each).
 enum MapKind {

@@ -1,9 +1,28 @@
-// Small utility kernels: status reset and the eigenvector sign convention.
+// Small utility kernels: status reset and the eigenvector sign convention;
+// the library's auxiliary streams.
 #include <algorithm>
+#include <mutex>
 
 #include "phdc_internal.h"
 
 namespace phdc {
+
+// One non-blocking stream per device, created on first use at the default
+// priority, for work that runs beside the caller's stream between an event
+// fork and join.  nullptr if it cannot be created (the caller then runs the
+// work on its own stream).
+hipStream_t aux_stream() {
+  static std::mutex mu;
+  static hipStream_t streams[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess) {
+    streams[dev] = nullptr;
+    (void)hipGetLastError();
+  }
+  return streams[dev];
+}
 
 
 // Zero the 256-byte status block with a kernel (not a memset node), so the
