@@ -158,7 +158,7 @@ def reference_copy_gbs():
 
 # Kernel phase -> (counter summary under profiles/, source file the kernel is built from).
 TRAFFIC_SUMMARIES = {
-    "copy": ("profiles/k_copy_deflated_uniform_n16384_traffic.md", "paper_1612_07526_amd/csrc/merge.hip"),
+    "copy": ("profiles/k_stage_uhat_root_copy_uniform_n16384_traffic.md", "paper_1612_07526_amd/csrc/merge.hip"),
 }
 
 
