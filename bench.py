@@ -553,6 +553,23 @@ def sec_batch(P, W, args):
     if st != 0:
         raise RuntimeError(f"batched status {st}")
     log(f"[bench] batch of {len(sizes)}: graph replay {t_graph * 1e3:.1f} ms")
+    # the GEMM tile autotuner (candidates: 32-, 64- and 128-wide tiles per merge-size bucket),
+    # then the same batch planned again with the measured table
+    lam0 = bs.lam.clone()
+    t0 = time.perf_counter()
+    table = P.autotune_gemm(1024)
+    t_tune = time.perf_counter() - t0
+    bs.prepare()
+    bs.launch()
+    sync()
+    t_tuned_eager = timed(bs.launch, 3, 1)
+    bs.capture()
+    t_tuned = timed(bs.replay, 3, 1)
+    if P.status(bs.work) != 0 or not torch.equal(bs.lam, lam0):
+        raise RuntimeError("the tuned batch differs from the untuned one")
+    buckets = {f"m<={1 << b}": int(v) for b, v in enumerate(table) if v}
+    log(f"[bench] batch: autotuned tiles {buckets} in {t_tune:.2f} s; graph replay {t_tuned * 1e3:.1f} ms "
+        f"(default {t_graph * 1e3:.1f} ms)")
     # one solve call per matrix (each call plans, uploads and launches its own kernels)
     lib = P.load()
     o = P.opts()
@@ -575,6 +592,9 @@ def sec_batch(P, W, args):
     log(f"[bench] batch: per-matrix calls {t_pm * 1e3:.1f} ms")
     res = {"workload": "4096 tridiagonals, n_b ~ U{32..1024}, d,e ~ N(0,1)", "graph_s": round(t_graph, 5),
            "eager_launch_s": round(t_eager, 5), "phases_ms": {k: round(v[0], 3) for k, v in phases.items()},
+           "autotuned": {"tile_by_bucket": buckets, "tune_s": round(t_tune, 3), "graph_s": round(t_tuned, 5),
+                         "eager_launch_s": round(t_tuned_eager, 5),
+                         "candidates": "tile edge 32, 64, 128 (128: adaptive 64/128 per merge)"},
            "per_matrix_s": round(t_pm, 5), "speedup": round(t_pm / t_graph, 2),
            "matrices_per_s": round(len(sizes) / t_graph, 1)}
     del bs, work

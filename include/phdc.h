@@ -288,12 +288,14 @@ int phdc_secular(int64_t K, const double *d, const double *z, double rho, int32_
 
 /* ---------------------------------------------------------------- GEMM tile autotuner
  * The FP64 update GEMM (Eq. (6)) of every tree level uses square output tiles
- * of edge 64 or 128, looked up per merge-size bucket (2^(b-1) < m <= 2^b) in a
- * process-wide table when a solve is planned.  phdc_autotune_gemm times both
- * edges with HIP events on a synthetic merge of each size m = 64, 128, ...,
- * max_m (no deflation, K = m) and records the faster one; untimed buckets use
- * 64 up to m = 256 and 128 above.  The tile changes the speed only: both edges
- * accumulate in the same k order, so results are bitwise identical.
+ * whose rule is looked up per merge-size bucket (2^(b-1) < m <= 2^b) in a
+ * process-wide table when a solve is planned: 32 or 64 (every merge of the
+ * level in tiles of that edge) or 128 (128-wide tiles for merges with at least
+ * 512 of them, 64 for the others).  phdc_autotune_gemm times the three rules
+ * with HIP events on a synthetic merge of each size m = 64, 128, ..., max_m (no
+ * deflation, K = m) and records the fastest; untimed buckets use 64 up to
+ * m = 256 and 128 above.  The tile changes the speed only: every edge
+ * accumulates in the same k order, so results are bitwise identical.
  *   max_m   largest merge size to time, 2 <= max_m <= 2^20
  *   work    device scratch of at least phdc_autotune_gemm_workspace(max_m) bytes
  *           (three max_m x max_m FP64 arrays and index arrays), 256-byte aligned

@@ -108,8 +108,9 @@ EXPORTS = ["phdc_stedc_batched_prepare", "phdc_launch_prepared", "phdc_opts_defa
 
 
 def autotune_gemm(max_m: int = 4096, device="cuda", stream=None) -> list:
-    """Time both FP64 update-GEMM tile edges on synthetic merges of size 64..max_m and
-    record the faster per size bucket (used by every solve planned afterwards).
+    """Time the FP64 update-GEMM tile rules (32-, 64- and 128-wide tiles) on synthetic merges
+    of size 64..max_m and record the fastest per size bucket (used by every solve planned
+    afterwards).
     Returns the tile table (entry b: bucket 2^(b-1) < m <= 2^b; 0 = not timed)."""
     lib = load()
     nb = _sz()

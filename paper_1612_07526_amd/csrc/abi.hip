@@ -493,7 +493,7 @@ int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n,
     D.x_off = xoff[i];
     D.split_on = z.nsl > 0 ? 1 : 0;
     D.flags = ((o->force_fail & PHDC_FAIL_SECULAR) ? kFlagNoSecularIters : 0) |
-              (small_merge(nd.m, o) ? kFlagSmallMerge : 0);
+              (small_merge(nd.m, o) ? kFlagSmallMerge : 0) | (nd.m >= kDefPrepRows ? kFlagPrepDeflate : 0);
     D.rin = BF.rng[pin] + BF.off[b] + nd.r0;
     D.rout = BF.rng[pout] + BF.off[b] + nd.r0;
     D.r0 = (int32_t)nd.r0;
@@ -962,7 +962,7 @@ int phdc_merge(int64_t n1, int64_t n2, const double* D, const double* z, double 
   Dd.x_off = 0;
   Dd.split_on = zs.nsl > 0 ? 1 : 0;
   Dd.flags = ((o->force_fail & PHDC_FAIL_SECULAR) ? kFlagNoSecularIters : 0) |
-             (small_merge((int)m, o) ? kFlagSmallMerge : 0);
+             (small_merge((int)m, o) ? kFlagSmallMerge : 0) | (m >= kDefPrepRows ? kFlagPrepDeflate : 0);
   Dd.rin = nullptr;  // Q1 and Q2 fill their halves
   Dd.rout = nullptr;
   Dd.r0 = 0;

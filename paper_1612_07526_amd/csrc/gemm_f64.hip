@@ -84,13 +84,13 @@ __device__ __forceinline__ void gemm_merge_tiles(const MergeDesc& M, const Scrat
     for (int e = 0; e < E; ++e)
       csc[e] = (scale_cols && ncol0 + l8 + e < K) ? S.cnorm[M.s_off + ncol0 + l8 + e] : 1.0;
 
-    // With 64-wide tiles (merges with few columns: latency counts), the column
+    // With 64-wide (or 32-wide) tiles (merges with few columns: latency counts), the column
     // index and row range of the A column a thread stages are read two k-steps
     // ahead of its data (gidx), so the data load of a step waits on one memory
     // latency, not on two dependent ones.  With 128-wide tiles (large merges)
     // they are read with the data: the early reads would make a step's MFMAs
     // wait for that step's loads (measured: 10% slower at K = 16384).
-    constexpr bool kIdxAhead = GT == 64;
+    constexpr bool kIdxAhead = GT <= 64;
     int nxc = 0;
     RowRange nxg{0, 0};
     auto gidx = [&](int kt) {
@@ -197,6 +197,8 @@ __device__ __forceinline__ void gemm_merge_tiles(const MergeDesc& M, const Scrat
 // grid of every merge is sized for edge 64 (at most kGemmBlockCap blocks).
 constexpr int kGemmWideTiles = 512;
 
+// GTMAX = 32 runs every merge of the launch in 32-wide tiles (more, smaller
+// tiles for levels of many small merges; an autotuner candidate).
 template <int GTMAX>
 __global__ void __launch_bounds__(256) k_merge_gemm(BlockMap bm, Scratch S, int scale_cols) {
   __shared__ double lds[4 * GK * (GTMAX + GPAD)];
@@ -208,6 +210,10 @@ __global__ void __launch_bounds__(256) k_merge_gemm(BlockMap bm, Scratch S, int 
   if (cnt[C_PATH] != 0) return;  // formed by another update path
   const int K = cnt[C_K], k1 = cnt[C_K1], k2 = cnt[C_K2], k3 = cnt[C_K3];
   const int G = merge_blocks(bm, mi);
+  if constexpr (GTMAX == 32) {
+    gemm_merge_tiles<32>(M, S, K, k1, k2, k3, lb, G, scale_cols, lds);
+    return;
+  }
   if constexpr (GTMAX == 128) {
     const int tiles128 = ((M.n1 + 127) / 128 + (M.m - M.n1 + 127) / 128) * ((K + 127) / 128);
     if (tiles128 >= kGemmWideTiles) {
@@ -221,13 +227,16 @@ __global__ void __launch_bounds__(256) k_merge_gemm(BlockMap bm, Scratch S, int 
 void launch_merge_gemm_f64(const BlockMap& bm, int total, const Scratch& S, int tile, bool scale_cols,
                            hipStream_t s) {
   if (total <= 0) return;
-  if (tile == 64) hipLaunchKernelGGL(k_merge_gemm<64>, dim3(total), dim3(256), 0, s, bm, S, scale_cols ? 1 : 0);
+  if (tile == 32) hipLaunchKernelGGL(k_merge_gemm<32>, dim3(total), dim3(256), 0, s, bm, S, scale_cols ? 1 : 0);
+  else if (tile == 64) hipLaunchKernelGGL(k_merge_gemm<64>, dim3(total), dim3(256), 0, s, bm, S, scale_cols ? 1 : 0);
   else hipLaunchKernelGGL(k_merge_gemm<128>, dim3(total), dim3(256), 0, s, bm, S, scale_cols ? 1 : 0);
 }
 
 // ------------------------------------------------------------ tile choice
-// Tile edge per merge-size bucket (bucket b holds 2^(b-1) < m <= 2^b); 0 means
-// not measured, in which case 64 is used up to m = 256 and 128 above.
+// Tile rule per merge-size bucket (bucket b holds 2^(b-1) < m <= 2^b): 32 or 64
+// (every merge of the launch in tiles of that edge) or 128 (128-wide tiles for
+// merges with at least kGemmWideTiles of them, 64 for the others); 0 means not
+// measured, in which case 64 is used up to m = 256 and 128 above.
 namespace {
 std::atomic<int> g_tile[kTileBuckets];
 
@@ -275,7 +284,7 @@ size_t autotune_bytes(int64_t max_m) {
 
 int gemm_tile_for(int64_t maxm) {
   const int v = g_tile[bucket_of(maxm)].load();
-  if (v == 64 || v == 128) return v;
+  if (v == 32 || v == 64 || v == 128) return v;
   return maxm <= 256 ? 64 : 128;
 }
 
@@ -335,9 +344,10 @@ int phdc_autotune_gemm(int64_t max_m, void* work, size_t lwork, void* stream) {
     S.rgbot = rgbot;
     S.dest = dest;
     S.uhat = u;
-    float best[2] = {1e30f, 1e30f};
-    const int tiles[2] = {64, 128};
-    for (int v = 0; v < 2 && rc == 0; ++v) {
+    constexpr int NC = 3;
+    float best[NC] = {1e30f, 1e30f, 1e30f};
+    const int tiles[NC] = {32, 64, 128};
+    for (int v = 0; v < NC && rc == 0; ++v) {
       const int gt = tiles[v];
       const int total = map_blocks(MAP_GEMM, (int)m, n1, gt, false);
       const int32_t hp[2] = {0, total};
@@ -361,7 +371,12 @@ int phdc_autotune_gemm(int64_t max_m, void* work, size_t lwork, void* stream) {
         best[v] = std::min(best[v], ms);
       }
     }
-    if (rc == 0) g_tile[bucket_of(m)].store(best[0] < best[1] ? 64 : 128);
+    if (rc == 0) {
+      int bv = 0;
+      for (int v = 1; v < NC; ++v)
+        if (best[v] < best[bv]) bv = v;
+      g_tile[bucket_of(m)].store(tiles[bv]);
+    }
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);

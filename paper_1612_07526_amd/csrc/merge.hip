@@ -131,8 +131,69 @@ __device__ inline void wave_prefix(const int (&c)[NC], int (&pre)[NC], int (&tot
   }
 }
 
-// sdl: LDS for D, used by the merge-path searches when m <= lds_cap.
+// Steps 1 and 2 of the deflation below for merges of at least kDefPrepRows
+// rows, one element per thread over many workgroups (one workgroup per merge
+// spends most of its time on these two steps' memory round trips): the row
+// range, the z entry, the sortedness check and the merged position of every
+// element.  z is written unnormalised; each block leaves its partial |z|^2,
+// max |D| and sortedness flags in the merge's slot of tau, dorg and org, which
+// the secular roots overwrite only later.  If the runs are not ascending the
+// positions may collide: the deflation kernel then places every element again.
+constexpr int kPrepThreads = 256;
+
 template <int NT>
+__device__ double block_sum(double v, double* sh);
+template <int NT>
+__device__ double block_max(double v, double* sh);
+
+__global__ void __launch_bounds__(kPrepThreads) k_deflate_prep(BlockMap bm, Scratch S) {
+  __shared__ double shd[kPrepThreads / 64];
+  __shared__ int shu;
+  const int mi = find_merge(bm, blockIdx.x);
+  const int lb = blockIdx.x - merge_first_block(bm, mi);
+  const MergeDesc M = bm.descs[mi];
+  const int m = M.m, n1 = M.n1, t = threadIdx.x;
+  const int64_t so = M.s_off;
+  double zsign = M.zsign;
+  if (M.ecoup != nullptr) zsign = (*M.ecoup < 0.0) ? -1.0 : 1.0;
+  const int i = lb * kPrepThreads + t;
+  double zi = 0.0, di = 0.0;
+  int uns = 0;
+  if (i < m) {
+    RowRange g = (i < n1) ? RowRange{0, n1} : RowRange{n1, m};
+    if (M.rin) g = RowRange{M.rin[i].lo - M.r0, M.rin[i].hi - M.r0};
+    S.crng[so + i] = g;
+    const int zr = (i < n1) ? n1 - 1 : n1;
+    if (M.zgiven) zi = M.zgiven[i];
+    else if (zr >= g.lo && zr < g.hi) zi = ((i < n1) ? 1.0 : zsign) * M.qin[zr + (int64_t)i * M.ldin];
+    di = M.lin[i];
+    const double dprev = (i > 0) ? M.lin[i - 1] : 0.0;
+    S.zs[so + i] = zi;
+    if (!isfinite(di)) uns = 2;
+    else if (i > 0 && i != n1 && !(di >= dprev)) uns = 1;
+    const int pos = (i < n1) ? i + count_lt(M.lin + n1, m - n1, di) : (i - n1) + count_le(M.lin, n1, di);
+    S.dv[so + pos] = di;
+    S.zv[so + pos] = zi;
+    S.col[so + pos] = i;
+    S.part[so + pos] = (i < n1) ? 1 : 3;
+  }
+  const double zzb = block_sum<kPrepThreads>(zi * zi, shd);
+  const double dmb = block_max<kPrepThreads>(fabs(di), shd);
+  if (t == 0) shu = 0;
+  __syncthreads();
+  if (uns) atomicOr(&shu, uns);
+  __syncthreads();
+  if (t == 0) {
+    S.tau[so + lb] = zzb;
+    S.dorg[so + lb] = dmb;
+    S.org[so + lb] = shu;
+  }
+}
+
+// sdl: LDS for D, used by the merge-path searches when m <= lds_cap.  UN: the
+// elements per thread (chunks of 64 per wave) whose loads each pass issues
+// together (more registers); 1 where a merge fits one pass anyway.
+template <int NT, int UN = 4>
 __device__ void deflate_body(const MergeDesc& M, const Scratch& S, int lds_cap, double* sdl) {
   constexpr int NW = NT / 64;
   static_assert(NW <= kDefWaves, "wave_prefix covers at most kDefWaves waves");
@@ -159,11 +220,22 @@ __device__ void deflate_body(const MergeDesc& M, const Scratch& S, int lds_cap, 
   }
 
   // 1. z (Eq. (3): last row of Q1, first row of Q2), |z|^2, max |D|, sortedness;
-  // the row range of every input column, in rows of the merge block.
+  // the row range of every input column, in rows of the merge block.  Large
+  // merges ran this step and step 2 element-wise in k_deflate_prep (many
+  // workgroups): here its per-block partial sums are combined.
   double zz = 0.0, dmx = 0.0;
   int uns = 0;  // bit 0: a descending step inside D1 or D2; bit 1: a NaN or Inf pole
-  constexpr int U1 = 4;  // loads of four indices issued before their uses
-  for (int i0 = t; i0 < m; i0 += U1 * NT) {
+  const bool prepared = (M.flags & kFlagPrepDeflate) != 0;  // block-uniform
+  constexpr int U1 = UN;  // loads of UN indices issued before their uses
+  if (prepared) {
+    const int nb = (m + kPrepThreads - 1) / kPrepThreads;
+    for (int b = t; b < nb; b += NT) {
+      zz += S.tau[so + b];
+      dmx = fmax(dmx, S.dorg[so + b]);
+      uns |= S.org[so + b];
+    }
+  }
+  for (int i0 = t; !prepared && i0 < m; i0 += U1 * NT) {
     double zi[U1], di[U1], dprev[U1];
 #pragma unroll
     for (int u = 0; u < U1; ++u) {
@@ -216,7 +288,10 @@ __device__ void deflate_body(const MergeDesc& M, const Scratch& S, int lds_cap, 
 
   // 2. merge the two ascending runs (ties: D1 first) and normalise z.  For
   // valid input the positions form a permutation of [0, m); otherwise keep the
-  // input order so every slot is still written exactly once.
+  // input order so every slot is still written exactly once.  (Prepared merges:
+  // already placed, z normalised in step 3's first pass; placed again here in
+  // input order if the runs were not ascending.)
+  const bool norm_in_pass = prepared && !uns;
   auto place = [&](const double* D) {
     for (int i = t; i < m; i += NT) {
       const double di = D[i];
@@ -227,7 +302,8 @@ __device__ void deflate_body(const MergeDesc& M, const Scratch& S, int lds_cap, 
       part[pos] = (i < n1) ? 1 : 3;
     }
   };
-  if (m <= lds_cap) {
+  if (norm_in_pass) {
+  } else if (m <= lds_cap) {
     for (int i = t; i < m; i += NT) sdl[i] = M.lin[i];
     __syncthreads();
     place(sdl);
@@ -243,7 +319,7 @@ __device__ void deflate_body(const MergeDesc& M, const Scratch& S, int lds_cap, 
   int ns, nd1;
   // The passes below load UC chunks of 64 before using any of them (the chunks
   // are then consumed in order), so a wave waits on memory once per UC chunks.
-  constexpr int UC = 4;
+  constexpr int UC = UN;
   {
     int c[2] = {0, 0}, pre[2], tot[2];
     for (int b0 = seg0; b0 < seg1; b0 += 64 * UC) {
@@ -253,6 +329,15 @@ __device__ void deflate_body(const MergeDesc& M, const Scratch& S, int lds_cap, 
         const int k = b0 + u * 64 + lane;
         zk[u] = (k < seg1) ? zv[k] : 0.0;
       }
+      if (norm_in_pass)
+#pragma unroll
+        for (int u = 0; u < UC; ++u) {
+          const int k = b0 + u * 64 + lane;
+          if (k < seg1) {
+            zk[u] = (zn > 0.0) ? zk[u] / zn : 0.0;
+            zv[k] = zk[u];
+          }
+        }
 #pragma unroll
       for (int u = 0; u < UC; ++u) {
         const int k = b0 + u * 64 + lane;
@@ -1181,6 +1266,7 @@ int map_blocks(int kind, int m, int n1, int gt, bool root, bool small, int nm) {
     }
     case MAP_SPLITA: return cdiv(m, 256) * kSplitKGroups;
     case MAP_SPLITB: return cdiv(m + 8, 256) * kSplitRGroups;
+    case MAP_PREP: return m >= kDefPrepRows ? cdiv(m, kPrepThreads) : 0;
   }
   return 0;
 }
@@ -1273,22 +1359,28 @@ __device__ void small_update(const MergeDesc& M, const Scratch& S, double* Us, i
     const int32_t* ca = cl + (top ? 0 : kSmallMergeMax);
     const RowRange* ra = rl + (top ? 0 : kSmallMergeMax);
     const int r = r0 + li, j = nt * 16 + li;
-    double av[NS], bv[NS];
-#pragma unroll
-    for (int q = 0; q < NS; ++q) {
-      const int k = 4 * q + lk;
-      av[q] = 0.0;
-      bv[q] = 0.0;
-      if (k < kd) {
-        const RowRange g = ra[k];
-        if (r < rend && r >= g.lo && r < g.hi) av[q] = M.qin[r + (int64_t)ca[k] * M.ldin];
-        if (j < K) bv[q] = Us[(off + k) * ldu + j];
-      }
-    }
     d4s_t acc = {0.0, 0.0, 0.0, 0.0};
+    // k-steps in two halves: each half's loads are issued together, then its MFMAs
 #pragma unroll
-    for (int q = 0; q < NS; ++q)
-      if (4 * q < kd) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[q], acc, 0, 0, 0);  // (wave-uniform)
+    for (int h = 0; h < 2; ++h) {
+      constexpr int NH = NS / 2;
+      double av[NH], bv[NH];
+#pragma unroll
+      for (int qq = 0; qq < NH; ++qq) {
+        const int k = 4 * (h * NH + qq) + lk;
+        av[qq] = 0.0;
+        bv[qq] = 0.0;
+        if (k < kd) {
+          const RowRange g = ra[k];
+          if (r < rend && r >= g.lo && r < g.hi) av[qq] = M.qin[r + (int64_t)ca[k] * M.ldin];
+          if (j < K) bv[qq] = Us[(off + k) * ldu + j];
+        }
+      }
+#pragma unroll
+      for (int qq = 0; qq < NH; ++qq)
+        if (4 * (h * NH + qq) < kd)  // (wave-uniform)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[qq], bv[qq], acc, 0, 0, 0);
+    }
     if (j < K) {
       double* oc = M.qout + (int64_t)S.dest[so + j] * M.ldout;
 #pragma unroll
@@ -1314,8 +1406,11 @@ __device__ void small_update(const MergeDesc& M, const Scratch& S, double* Us, i
 
 // Dynamic LDS: kmax (ldu = kmax + 1) doubles, kmax = the largest such merge of
 // the level (at most kSmallMergeMax); it holds the poles during deflation.
+// (Five waves per SIMD: the register budget that fits five 256-thread merges per
+// CU where LDS allows, without spilling.)
 template <int NT, int G>
-__global__ void __launch_bounds__(NT) k_merge_small(BlockMap bm, Scratch S, int ldu) {
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(5))) k_merge_small(BlockMap bm, Scratch S,
+                                                                                           int ldu) {
   HIP_DYNAMIC_SHARED(double, Us)
   __shared__ double sd[kSmallUhat];
   __shared__ double sz[kSmallUhat];
@@ -1323,7 +1418,7 @@ __global__ void __launch_bounds__(NT) k_merge_small(BlockMap bm, Scratch S, int 
   __shared__ RowRange rl[2 * kSmallMergeMax];
   const int mi = find_merge(bm, blockIdx.x);
   const MergeDesc M = bm.descs[mi];
-  deflate_body<NT>(M, S, M.m, Us);
+  deflate_body<NT, 1>(M, S, M.m, Us);  // (m <= 64: one element per thread, one chunk per wave)
   __syncthreads();
   small_body<NT, G>(M, S, true, sd, sz);
   __syncthreads();
@@ -1362,6 +1457,8 @@ void launch_merge_level(const MergeDesc* descs, int nm, const LevelMaps& maps, c
     if (nsmall == nm) return;  // (no HSS candidate in such a level: no probe needed)
   }
   { ProfScope p(PH_DEFLATE, s);
+    if (maps.total[MAP_PREP] > 0)
+      hipLaunchKernelGGL(k_deflate_prep, dim3(maps.total[MAP_PREP]), dim3(kPrepThreads), 0, s, bmap(MAP_PREP), S);
     const int cap = maps.maxm <= kDefLdsMax ? maps.maxm : 0;
     if (maps.maxm <= kDefSmall)
       hipLaunchKernelGGL(k_deflate<256>, dim3(nm), dim3(256), (size_t)cap * sizeof(double), s, descs, S, cap);

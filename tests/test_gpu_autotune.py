@@ -28,7 +28,7 @@ def test_autotune_fills_table_and_keeps_results(P):
     l0, Q0 = P.stedc(d, e)
     table = P.autotune_gemm(2048)
     for b in range(6, 12):  # buckets of m = 64 .. 2048
-        assert table[b] in (64, 128)
+        assert table[b] in (32, 64, 128)
     l1, Q1 = P.stedc(d, e)
     assert torch.equal(l0, l1)
     assert torch.equal(Q0, Q1)
