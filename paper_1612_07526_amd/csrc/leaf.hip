@@ -174,8 +174,147 @@ __global__ void __launch_bounds__(64 * kLeavesPerBlock) k_leaf_ql(const LeafArgs
   if (row && L.rng) L.rng[t] = RowRange{L.r0, L.r0 + s};  // every column spans the leaf's rows
 }
 
+// Leaves of at most LG rows (LG = 8 or 16): LG lanes per leaf, 64 / LG leaves
+// per wavefront.  Lane t of a group owns row t of the leaf's eigenvector matrix
+// Z in registers (z[c] = Z(t, c)), so the rotation of columns (i, i+1) is two
+// multiply-adds per lane with no communication.  d and e sit in LDS, one copy
+// per group, and every lane of the group runs the same scalar recurrence on
+// broadcast reads; lanes of one group compute bit-identical values, so each
+// lane's reads follow its own writes.  The sweep is unrolled over i with the
+// step taken under the mask l <= i < mm: groups in different states share one
+// instruction stream, and a step that no group of the wave needs is branched
+// over.  The whole iteration (find the unreduced block, shift, sweep) is one
+// loop per group, so a group does not wait for the others between eigenvalues.
+struct alignas(16) LeafDE {
+  double d, e;
+};
+
+template <int LG>
+__global__ void __launch_bounds__(64) k_leaf_ql_grouped(const LeafArgs* __restrict__ leaves, int nleaves,
+                                                        int32_t* status, int maxit) {
+  constexpr int GPW = 64 / LG;  // leaves per wavefront (= per block)
+  __shared__ LeafDE desh[GPW][LG + 1];
+  __shared__ int rsh[GPW][LG];
+  const int gi = threadIdx.x / LG;
+  const int t = threadIdx.x % LG;
+  const int li = blockIdx.x * GPW + gi;
+  if (li >= nleaves) return;  // whole group; no block barrier below
+  const LeafArgs L = leaves[li];
+  const int s = L.s;
+  if (s <= 0 || s > LG) return;
+  LeafDE* de = desh[gi];
+  {
+    double dv = 0.0, ev = 0.0;
+    if (t < s) {
+      dv = L.d[t];
+      if (t == 0 && (L.couple & 1)) dv -= fabs(L.e[-1]);
+      if (t == s - 1 && (L.couple & 2)) dv -= fabs(L.e[s - 1]);
+      ev = (t < s - 1) ? L.e[t] : 0.0;
+    }
+    de[t] = LeafDE{dv, ev};
+    if (t == 0) de[LG] = LeafDE{0.0, 0.0};
+  }
+  __builtin_amdgcn_wave_barrier();
+  double z[LG];
+#pragma unroll
+  for (int c = 0; c < LG; ++c) z[c] = (c == t) ? 1.0 : 0.0;
+  const int gshift = gi * LG;
+  constexpr unsigned long long gmask = (1ull << LG) - 1;
+  int l = 0, iter = 0;
+  bool failed = false;
+  for (;;) {
+    // Bit k of U: row k < s-1 is still coupled to row k+1 (|e_k| above the
+    // negligibility threshold).
+    const double dk = de[t].d, ek = de[t].e, dk1 = de[t + 1].d;
+    const bool coupled = t < s - 1 && !(fabs(ek) <= kUnitRoundoff * (fabs(dk) + fabs(dk1)));
+    const unsigned U = (unsigned)((__ballot(coupled) >> gshift) & gmask);
+    const unsigned rem = U & (~0u << l);
+    if (rem == 0) break;  // every eigenvalue of the leaf has converged
+    const int nl = __builtin_ctz(rem);
+    if (nl != l) {
+      l = nl;
+      iter = 0;
+    }
+    // The unreduced block is rows l..mm.
+    const int mm = __builtin_ctz(~U & (~0u << l));
+    if (++iter > maxit) {
+      failed = true;
+      break;
+    }
+    // Shift: the eigenvalue of [d_l e_l; e_l d_{l+1}] nearer d_l, folded into
+    // the starting value g of the bulge chase.
+    const double dl = de[l].d, el = de[l].e;
+    const double dmm = de[mm].d;
+    double g = (de[l + 1].d - dl) / (2.0 * el);
+    double r = hyp(g, 1.0);
+    g = dmm - dl + el / (g + copysign(r, g));
+    double sn = 1.0, cs = 1.0, p = 0.0;
+    double dnext = dmm;  // d_{i+1} as it was before this sweep
+    bool live = true;    // false once a rotation underflows
+#pragma unroll
+    for (int i = LG - 2; i >= 0; --i) {
+      const LeafDE cur = de[i];  // untouched by this sweep so far
+      if (live && i >= l && i < mm) {
+        const double f = sn * cur.e, b = cs * cur.e;
+        double c2 = 1.0, s2 = 0.0;
+        const double rr = rotation(f, g, &c2, &s2);
+        if (rr == 0.0) {
+          // The block has split at i+1: undo the pending shift correction and
+          // look for the split again (e_mm is cleared after the sweep).
+          de[i + 1] = LeafDE{dnext - p, 0.0};
+          live = false;
+        } else {
+          sn = s2;
+          cs = c2;
+          g = dnext - p;
+          r = (cur.d - g) * sn + 2.0 * cs * b;
+          p = sn * r;
+          de[i + 1] = LeafDE{g + p, rr};
+          g = cs * r - b;
+          const double zi = z[i], zj = z[i + 1];
+          z[i + 1] = sn * zi + cs * zj;
+          z[i] = cs * zi - sn * zj;
+        }
+        dnext = cur.d;
+      }
+    }
+    if (live) {
+      de[l].d = de[l].d - p;
+      de[l].e = g;
+    }
+    de[mm].e = 0.0;
+  }
+  if (failed && t == 0) set_status(status, PHDC_ERR_LEAF);
+  // Ascending order: rank of each eigenvalue (ties by index); column c of Z
+  // goes to output column rank(c).
+  const double dt = de[t].d;
+  int rank = 0;
+#pragma unroll
+  for (int j = 0; j < LG; ++j) {
+    const double dj = de[j].d;
+    rank += (j < s && (dj < dt || (dj == dt && j < t))) ? 1 : 0;
+  }
+  rsh[gi][t] = rank;
+  __builtin_amdgcn_wave_barrier();
+  if (t < s) {
+    L.lam[rank] = dt;
+#pragma unroll
+    for (int c = 0; c < LG; ++c)
+      if (c < s) L.q[t + (int64_t)rsh[gi][c] * L.ldq] = z[c];
+    if (L.rng) L.rng[t] = RowRange{L.r0, L.r0 + s};
+  }
+}
+
 void launch_leaf_ql(const LeafArgs* leaves, int nleaves, int32_t* status, int max_leaf, int maxit, hipStream_t s) {
   if (nleaves <= 0) return;
+  if (max_leaf <= 8) {
+    hipLaunchKernelGGL(k_leaf_ql_grouped<8>, dim3((nleaves + 7) / 8), dim3(64), 0, s, leaves, nleaves, status, maxit);
+    return;
+  }
+  if (max_leaf <= 16) {
+    hipLaunchKernelGGL(k_leaf_ql_grouped<16>, dim3((nleaves + 3) / 4), dim3(64), 0, s, leaves, nleaves, status, maxit);
+    return;
+  }
   const int ls = std::max(1, std::min(max_leaf, kMaxLeaf));
   const int blocks = (nleaves + kLeavesPerBlock - 1) / kLeavesPerBlock;
   hipLaunchKernelGGL(k_leaf_ql, dim3(blocks), dim3(64 * kLeavesPerBlock),

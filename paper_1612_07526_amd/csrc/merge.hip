@@ -610,6 +610,16 @@ __global__ void __launch_bounds__(NT) k_deflate(const MergeDesc* __restrict__ de
 constexpr int kRotGroups = 16;
 
 // Row r of the chains g, g + G, ... of merge M.
+// A chain is a run of rotations (c_0, c_1), (c_1, c_2), ... : the type-2 scan
+// carries each rotated survivor on as the predecessor of the next test, so
+// column cj of one rotation is column cp of the next and no column appears in
+// two chains.  Row r keeps the running column in a register and reads each
+// fresh column once; the reads of kRotBatch rotations are issued before their
+// arithmetic, so a chain costs one memory round trip per batch rather than two
+// dependent accesses per rotation.  Rows outside both ranges of a rotation
+// are neither read nor written (they stay zero for every later reader).
+constexpr int kRotBatch = 4;
+
 __device__ void rotate_chains(const MergeDesc& M, const Scratch& S, int r, int g, int G) {
   const int32_t* cnt = S.counters + (int64_t)M.id * kCounters;
   const int nrot = cnt[C_NROT], nchain = cnt[C_NCHAIN];
@@ -619,17 +629,44 @@ __device__ void rotate_chains(const MergeDesc& M, const Scratch& S, int r, int g
   for (int ci = g; ci < nchain; ci += G) {
     const int a = S.chain[so + ci];
     const int e = (ci + 1 < nchain) ? S.chain[so + ci + 1] : nrot;
-    for (int x = a; x < e; ++x) {
-      const int cp = S.rcolp[so + x], cj = S.rcolj[so + x];
-      const RowRange gp = S.rrp[so + x], gj = S.rrj[so + x];
-      if (r < min(gp.lo, gj.lo) || r >= max(gp.hi, gj.hi)) continue;
-      const bool vp = r >= gp.lo && r < gp.hi, vj = r >= gj.lo && r < gj.hi;
-      const double c = S.rc[so + x], s = S.rs[so + x];
-      const double xp = vp ? q[r + (int64_t)cp * ld] : 0.0;
-      const double xj = vj ? q[r + (int64_t)cj * ld] : 0.0;
-      q[r + (int64_t)cp * ld] = c * xp + s * xj;
-      q[r + (int64_t)cj * ld] = c * xj - s * xp;
+    int cp = S.rcolp[so + a];
+    RowRange gp = S.rrp[so + a];
+    double xp = (r >= gp.lo && r < gp.hi) ? q[r + (int64_t)cp * ld] : 0.0;
+    for (int x0 = a; x0 < e; x0 += kRotBatch) {
+      int cj[kRotBatch];
+      RowRange gj[kRotBatch];
+      double cs[kRotBatch], sn[kRotBatch], xj[kRotBatch];
+#pragma unroll
+      for (int u = 0; u < kRotBatch; ++u) {
+        const int x = x0 + u;
+        cj[u] = 0;
+        gj[u] = RowRange{0, 0};
+        cs[u] = 1.0;
+        sn[u] = 0.0;
+        xj[u] = 0.0;
+        if (x < e) {
+          cj[u] = S.rcolj[so + x];
+          gj[u] = S.rrj[so + x];
+          cs[u] = S.rc[so + x];
+          sn[u] = S.rs[so + x];
+          if (r >= gj[u].lo && r < gj[u].hi) xj[u] = q[r + (int64_t)cj[u] * ld];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kRotBatch; ++u) {
+        if (x0 + u < e) {
+          // rows of the hull of both ranges carry the rotated values on
+          const bool in = r >= min(gp.lo, gj[u].lo) && r < max(gp.hi, gj[u].hi);
+          const double np = cs[u] * xp + sn[u] * xj[u];
+          const double nj = cs[u] * xj[u] - sn[u] * xp;
+          if (in) q[r + (int64_t)cp * ld] = np;
+          xp = in ? nj : 0.0;
+          cp = cj[u];
+          gp = RowRange{min(gp.lo, gj[u].lo), max(gp.hi, gj[u].hi)};
+        }
+      }
     }
+    if (r >= gp.lo && r < gp.hi) q[r + (int64_t)cp * ld] = xp;
   }
 }
 
@@ -1176,9 +1213,10 @@ __device__ void copy_body(const BlockMap& bm, const Scratch& S, int b) {
   const int64_t so = M.s_off;
   if (M.root) {
     // The caller's Q: every row is written.  A whole block per column (a wave
-    // per column below kCopyWideRows rows), rows in pairs with 16-byte stores
-    // (a scalar first row when the column starts at an odd 8-byte offset, a
-    // scalar last row when the rest is odd).
+    // per column below kCopyWideRows rows), rows in pairs with 16-byte
+    // nontemporal stores (nothing here reads Q again, so the lines need not
+    // stay in the caches), a scalar first row when the column starts at an odd
+    // 8-byte offset, a scalar last row when the rest is odd.
     typedef double d2_t __attribute__((ext_vector_type(2)));
     const bool wide = m >= kCopyWideRows;
     const int lane = wide ? threadIdx.x : (threadIdx.x & 63), step = wide ? 256 : 64;
@@ -1201,7 +1239,7 @@ __device__ void copy_body(const BlockMap& bm, const Scratch& S, int b) {
 #pragma unroll 4
       for (int p = lane; p < np; p += step) {
         const int r = a + 2 * p;
-        o2[p] = d2_t{val(r), val(r + 1)};
+        __builtin_nontemporal_store(d2_t{val(r), val(r + 1)}, &o2[p]);
       }
     }
     return;
