@@ -1347,24 +1347,24 @@ __global__ void __launch_bounds__(kStageSmallThreads) k_stage_small(const MergeD
 
 // ------------------------------------------------------------ one-workgroup merges
 // A merge of at most kSmallMergeMax rows on the FP64 path runs in one
-// workgroup from deflation to the eigenvector update.  Two shapes: levels of
+// workgroup from deflation to the eigenvector update.  Three shapes: levels of
 // many such merges (at least kSmallManyMerges: the GPU is full and throughput
-// counts) take 256 threads and four lanes per secular root -- at these sizes
-// the sums over the poles are short, so fewer lanes per root waste fewer
-// instructions on the group sums and the rational step, and several merges
-// share a CU; levels of fewer merges take 1024 threads and kSecG lanes per
-// root, for the shortest latency per merge (with merges of at most 32 rows,
-// 256 threads are faster there too).  The update product runs on the FP64
-// matrix cores, one wave per 16 x 16 output tile: Uhat (grouped rows) and the
-// two column lists are staged in LDS, the input columns are read directly;
-// then the deflated columns are copied.
+// counts) take one wavefront per merge and one lane per secular root -- at
+// these sizes every loop is a single pass, the block barriers cost nothing,
+// and a CU holds up to twenty merges; levels of fewer merges take 1024
+// threads and kSecG lanes per root, for the shortest latency per merge, or
+// 256 threads and four lanes per root when the merges have at most 32 rows.
+// The update product runs on the FP64 matrix cores, one wave per 16 x 16
+// output tile: the two column lists are staged in LDS, Uhat (grouped rows)
+// and the input columns are read directly; then the deflated columns are
+// copied.
 constexpr int kSmallManyMerges = 2048;
 typedef double d4s_t __attribute__((ext_vector_type(4)));
 
-// Us: LDS for K rows of ldu doubles; cl, rl: LDS for 2 kSmallMergeMax columns
-// and row ranges (top list, then bottom list).
+// cl, rl: LDS for 2 kSmallMergeMax columns and row ranges (top list, then
+// bottom list).  Uhat is read where this workgroup wrote it (cache-resident).
 template <int NT>
-__device__ void small_update(const MergeDesc& M, const Scratch& S, double* Us, int ldu, int32_t* cl, RowRange* rl) {
+__device__ void small_update(const MergeDesc& M, const Scratch& S, int32_t* cl, RowRange* rl) {
   const int t = threadIdx.x, m = M.m, n1 = M.n1, n2 = M.m - M.n1;
   const int32_t* cnt = S.counters + (int64_t)M.id * kCounters;
   const int K = cnt[C_K], k1 = cnt[C_K1], k2 = cnt[C_K2], k3 = cnt[C_K3];
@@ -1378,8 +1378,7 @@ __device__ void small_update(const MergeDesc& M, const Scratch& S, double* Us, i
     cl[kSmallMergeMax + x] = S.colbot[so + x];
     rl[kSmallMergeMax + x] = S.rgbot[so + x];
   }
-  const double* U = S.uhat + M.u_off;
-  for (int x = t; x < K * K; x += NT) Us[(x / K) * ldu + x % K] = U[x];
+  const double* U = S.uhat + M.u_off;  // (written by this workgroup before the barrier)
   __syncthreads();
   // Row tiles of 16 per half (a tile never straddles the halves), column tiles
   // of 16 roots.  v_mfma_f64_16x16x4f64: A(i, k) from lane 16 k + i, B(k, j)
@@ -1411,7 +1410,7 @@ __device__ void small_update(const MergeDesc& M, const Scratch& S, double* Us, i
         if (k < kd) {
           const RowRange g = ra[k];
           if (r < rend && r >= g.lo && r < g.hi) av[qq] = M.qin[r + (int64_t)ca[k] * M.ldin];
-          if (j < K) bv[qq] = Us[(off + k) * ldu + j];
+          if (j < K) bv[qq] = U[(off + k) * K + j];
         }
       }
 #pragma unroll
@@ -1442,13 +1441,12 @@ __device__ void small_update(const MergeDesc& M, const Scratch& S, double* Us, i
   }
 }
 
-// Dynamic LDS: kmax (ldu = kmax + 1) doubles, kmax = the largest such merge of
-// the level (at most kSmallMergeMax); it holds the poles during deflation.
-// (Five waves per SIMD: the register budget that fits five 256-thread merges per
-// CU where LDS allows, without spilling.)
+// Dynamic LDS: kmax doubles, kmax = the largest such merge of the level (at
+// most kSmallMergeMax); it holds the poles during deflation.  (Five waves per
+// SIMD: the register budget that fits five 256-thread merges per CU, or twenty
+// one-wave merges, without spilling.)
 template <int NT, int G>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(5))) k_merge_small(BlockMap bm, Scratch S,
-                                                                                           int ldu) {
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(5))) k_merge_small(BlockMap bm, Scratch S) {
   HIP_DYNAMIC_SHARED(double, Us)
   __shared__ double sd[kSmallUhat];
   __shared__ double sz[kSmallUhat];
@@ -1460,7 +1458,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(5))) k_
   __syncthreads();
   small_body<NT, G>(M, S, true, sd, sz);
   __syncthreads();
-  small_update<NT>(M, S, Us, ldu, cl, rl);
+  small_update<NT>(M, S, cl, rl);
 }
 
 __global__ void __launch_bounds__(256) k_stage_lowner(BlockMap low, int nlow, BlockMap rank, Scratch S) {
@@ -1487,11 +1485,13 @@ void launch_merge_level(const MergeDesc* descs, int nm, const LevelMaps& maps, c
   if (nsmall > 0) {  // merges that run in one workgroup each, deflation included
     ProfScope p(PH_SMALL_MERGE, s);
     const int kmax = std::min(maps.maxm, kSmallMergeMax);
-    const size_t lds = (size_t)kmax * (kmax + 1) * sizeof(double);
-    if (nsmall >= kSmallManyMerges || kmax <= 32)
-      hipLaunchKernelGGL((k_merge_small<256, 4>), dim3(nsmall), dim3(256), lds, s, bmap(MAP_SMALL), S, kmax + 1);
+    const size_t lds = (size_t)kmax * sizeof(double);
+    if (nsmall >= kSmallManyMerges)
+      hipLaunchKernelGGL((k_merge_small<64, 1>), dim3(nsmall), dim3(64), lds, s, bmap(MAP_SMALL), S);
+    else if (kmax <= 32)
+      hipLaunchKernelGGL((k_merge_small<256, 4>), dim3(nsmall), dim3(256), lds, s, bmap(MAP_SMALL), S);
     else
-      hipLaunchKernelGGL((k_merge_small<1024, kSecG>), dim3(nsmall), dim3(1024), lds, s, bmap(MAP_SMALL), S, kmax + 1);
+      hipLaunchKernelGGL((k_merge_small<1024, kSecG>), dim3(nsmall), dim3(1024), lds, s, bmap(MAP_SMALL), S);
     if (nsmall == nm) return;  // (no HSS candidate in such a level: no probe needed)
   }
   { ProfScope p(PH_DEFLATE, s);
