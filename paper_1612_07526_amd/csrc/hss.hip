@@ -347,6 +347,319 @@ __global__ void __launch_bounds__(kIdThreads) k_row_id(const IdDesc* __restrict_
   if (t == 0) *D.rank = r;
 }
 
+// The same decomposition with the whole work matrix on chip, for p <= 32 NS
+// rows of Phi and d <= kRfRows samples.  Column c of Phi^T (row c of Phi) is
+// owned by a group of kRfLanes lanes; lane sub keeps its entries k = sub +
+// kRfLanes u in registers for the whole factorization (zero past d), so a
+// pivot step moves no matrix data through memory: the pivot's owners publish
+// the reflector in LDS, zero outside rows j..d-1, and every lane then applies
+// it to all of its columns at once (one LDS read of v per row for every slot,
+// no per-row predicates), and downdates the norms (recomputing them on
+// cancellation, as above); row j of a column is picked out by a dot product
+// with the unit vector e_j, also in LDS.  Columns are not swapped: a
+// pivoted column is only marked, and ties in the pivot choice go to the lowest
+// column index.  R11 (the rows of the pivoted columns up to their step) goes
+// to LDS -- to the work copy past kRfR11 pivots -- and every unpivoted column
+// solves R11 t = R12(:, c) in its registers by back substitution.
+constexpr int kRfThreads = 512;
+constexpr int kRfLanes = 16;
+constexpr int kRfGroups = kRfThreads / kRfLanes;  // columns in flight per slot
+constexpr int kRfRegs = 16;
+constexpr int kRfRows = kRfLanes * kRfRegs;  // largest sample count d
+constexpr int kRfR11 = 128;
+
+template <int CTRL>
+__device__ __forceinline__ double rf_dpp(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 16 lanes of a row (quad xor 1, quad xor 2, half-row mirror,
+// row mirror): every lane receives the same total.
+__device__ __forceinline__ double rf_sum16(double v) {
+  v += rf_dpp<0xB1>(v);
+  v += rf_dpp<0x4E>(v);
+  v += rf_dpp<0x141>(v);
+  v += rf_dpp<0x140>(v);
+  return v;
+}
+
+// Value of lane `src` of the caller's 16-lane row.
+__device__ __forceinline__ double rf_lane(double v, int src) {
+  return __shfl(v, (int)(threadIdx.x & 48) + src, 64);
+}
+
+struct RfShared {
+  double* cn;
+  double* cn0;
+  double* v;   // reflector, zero outside rows j..d-1
+  double* ej;  // unit vector of row j
+  int* stp;
+  int* chosen;
+  double* vtv;
+};
+
+// The pivot column's owners build the reflector of its rows j..: v = x -
+// alpha e_j, alpha = -sign(x_j) |x|; the column keeps R_jj = alpha.
+template <int NS>
+__device__ __forceinline__ void rf_reflect(double (&x)[NS][kRfRegs], const RfShared& sh, int piv, int j, int cg,
+                                           int sub) {
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    if (cg + kRfGroups * s == piv) {
+      double q = 0.0, xj = 0.0;
+#pragma unroll
+      for (int u = 0; u < kRfRegs; ++u) {
+        const int k = sub + kRfLanes * u;
+        q += (k >= j) ? x[s][u] * x[s][u] : 0.0;
+        xj += (k == j) ? x[s][u] : 0.0;
+      }
+      q = rf_sum16(q);
+      const double x0 = rf_sum16(xj);  // (one nonzero term: exact)
+      const double xn = sqrt(q);
+      const double alpha = (x0 >= 0.0) ? -xn : xn;
+#pragma unroll
+      for (int u = 0; u < kRfRegs; ++u) {
+        const int k = sub + kRfLanes * u;
+        sh.v[k] = (k > j) ? x[s][u] : (k == j ? x0 - alpha : 0.0);
+        sh.ej[k] = (k == j) ? 1.0 : 0.0;
+        if (k == j) x[s][u] = alpha;
+      }
+      if (sub == 0) {
+        *sh.vtv = 2.0 * xn * (xn + fabs(x0));  // |x - alpha e_j|^2
+        sh.cn[piv] = -1.0;
+        sh.stp[piv] = j;
+        sh.chosen[j] = piv;
+      }
+    }
+  }
+}
+
+// Every remaining column c: x -= (2 v.x / v.v) v, and the norm of its rows
+// j+1.. downdated by R_jc^2.  The rows below j see v = 0 and stay unchanged;
+// whole registers below row j are skipped.
+template <int NS>
+__device__ __forceinline__ void rf_update(double (&x)[NS][kRfRegs], const RfShared& sh, int j, int p, int cg,
+                                          int sub) {
+  const int uj = j / kRfLanes;
+  double f[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) f[s] = 0.0;
+#pragma unroll
+  for (int u = 0; u < kRfRegs; ++u) {
+    if (u >= uj) {
+      const double vk = sh.v[sub + kRfLanes * u];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) f[s] = fma(vk, x[s][u], f[s]);
+    }
+  }
+  const double g = 2.0 / *sh.vtv;
+  bool on[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int c = cg + kRfGroups * s;
+    on[s] = c < p && sh.stp[c] < 0;
+    f[s] = on[s] ? rf_sum16(f[s]) * g : 0.0;
+  }
+  double xj[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) xj[s] = 0.0;
+#pragma unroll
+  for (int u = 0; u < kRfRegs; ++u) {
+    if (u >= uj) {
+      const double vk = sh.v[sub + kRfLanes * u], ek = sh.ej[sub + kRfLanes * u];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        x[s][u] = fma(-f[s], vk, x[s][u]);
+        xj[s] = fma(ek, x[s][u], xj[s]);
+      }
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    if (on[s]) {  // (uniform in the group)
+      const int c = cg + kRfGroups * s;
+      const double rj = rf_sum16(xj[s]);  // R_jc (one nonzero term: exact)
+      double nc = sh.cn[c] - rj * rj;
+      const bool redo = nc <= 1e-2 * sh.cn0[c];
+      if (redo) {  // cancellation: recompute the remaining norm
+        double q = 0.0;
+#pragma unroll
+        for (int u = 0; u < kRfRegs; ++u) {
+          const int k = sub + kRfLanes * u;
+          q += (k > j) ? x[s][u] * x[s][u] : 0.0;
+        }
+        nc = rf_sum16(q);
+      }
+      if (sub == 0) {
+        sh.cn[c] = nc;
+        if (redo) sh.cn0[c] = nc;
+      }
+    }
+  }
+}
+
+template <int NS>
+__global__ void __launch_bounds__(kRfThreads) k_row_id_rf(const IdDesc* __restrict__ ids, double tol,
+                                                          double abs_tol) {
+  constexpr int PM = NS * kRfGroups;
+  constexpr int RM = PM < kRfR11 ? PM : kRfR11;
+  __shared__ double cn[PM], cn0[PM];
+  __shared__ double v[kRfRows], ej[kRfRows];
+  __shared__ int stp[PM];     // pivot step of column c, -1 while unpivoted
+  __shared__ int chosen[PM];  // column pivoted at step j
+  __shared__ int lpos[PM];    // rank of an unpivoted column among the unpivoted
+  __shared__ double rl[RM * RM];
+  __shared__ double sh_vtv, sh_r00;
+  __shared__ int sh_piv, sh_stop;
+  const RfShared sh{cn, cn0, v, ej, stp, chosen, &sh_vtv};
+  const IdDesc D = ids[blockIdx.x];
+  const int p = D.p, d = D.d;
+  const int t = threadIdx.x;
+  const int sub = t % kRfLanes, cg = t / kRfLanes;
+  double x[NS][kRfRegs];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int c = cg + kRfGroups * s;
+#pragma unroll
+    for (int u = 0; u < kRfRegs; ++u) {
+      const int k = sub + kRfLanes * u;
+      x[s][u] = (c < p && k < d) ? D.phi[c + (int64_t)k * D.ldphi] : 0.0;
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int c = cg + kRfGroups * s;
+    double q = 0.0;
+#pragma unroll
+    for (int u = 0; u < kRfRegs; ++u) q += x[s][u] * x[s][u];
+    q = rf_sum16(q);
+    if (sub == 0) {
+      cn[c] = (c < p) ? q : -1.0;  // -1: not a candidate
+      cn0[c] = q;
+      stp[c] = -1;
+    }
+  }
+  if (t == 0) sh_r00 = 0.0;
+  __syncthreads();
+  const int kmax = min(p, d);
+  int r = 0;
+  for (int j = 0; j < kmax; ++j) {
+    // pivot: the largest remaining norm (one wave)
+    if (t < 64) {
+      double bv = -1.0;
+      int bi = 0x7fffffff;
+      for (int c = t; c < p; c += 64) {
+        const double q = cn[c];
+        if (q > bv) {
+          bv = q;
+          bi = c;
+        }
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(bv, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        if (ob > bv || (ob == bv && oi < bi)) {
+          bv = ob;
+          bi = oi;
+        }
+      }
+      if (t == 0) {
+        const double nrm = sqrt(fmax(bv, 0.0));
+        if (j == 0) sh_r00 = nrm;
+        sh_piv = bi;
+        sh_stop = (bv < 0.0 || sh_r00 == 0.0 || nrm <= fmax(tol * sh_r00, abs_tol)) ? 1 : 0;
+      }
+    }
+    __syncthreads();
+    if (sh_stop) break;
+    const int piv = sh_piv;
+    rf_reflect<NS>(x, sh, piv, j, cg, sub);
+    __syncthreads();
+    if (sh_vtv > 0.0) {
+      rf_update<NS>(x, sh, j, p, cg, sub);
+    }
+    __syncthreads();
+    r = j + 1;
+  }
+  // R11 (column a = the column pivoted at step a, rows 0..a), in LDS or, past
+  // RM pivots, in the work copy
+  double* R11 = (r <= RM) ? rl : D.work;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int c = cg + kRfGroups * s;
+    const int a = (c < p) ? stp[c] : -1;
+    if (a >= 0) {
+#pragma unroll
+      for (int u = 0; u < kRfRegs; ++u) {
+        const int k = sub + kRfLanes * u;
+        if (k <= a) R11[k + (int64_t)a * r] = x[s][u];
+      }
+    }
+  }
+  for (int c = t; c < p; c += kRfThreads)
+    if (stp[c] < 0) {
+      int q = 0;
+      for (int c2 = 0; c2 < c; ++c2) q += (stp[c2] < 0) ? 1 : 0;
+      lpos[c] = q;
+    }
+  __syncthreads();
+  // T(:, c) = R11^{-1} R12(:, c) for the unpivoted columns, in place in rows
+  // 0..r-1 (row a: register a / 16 of lane a % 16); the other slots compute
+  // along and are ignored
+#pragma unroll
+  for (int ua = kRfRegs - 1; ua >= 0; --ua) {
+    if (kRfLanes * ua >= r) continue;
+    for (int sa = kRfLanes - 1; sa >= 0; --sa) {
+      const int a = kRfLanes * ua + sa;
+      if (a >= r) continue;
+      const double inv = 1.0 / R11[a + (int64_t)a * r];
+      double ta[NS];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        ta[s] = rf_lane(x[s][ua], sa) * inv;
+        if (sub == sa) x[s][ua] = ta[s];
+      }
+#pragma unroll
+      for (int ub = 0; ub <= ua; ++ub) {
+        const int b = sub + kRfLanes * ub;
+        const double rba = (b < a) ? R11[b + (int64_t)a * r] : 0.0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) x[s][ub] = fma(-rba, ta[s], x[s][ub]);
+      }
+    }
+  }
+  // U (p x r): the identity on the pivoted rows, T^T on the others
+  double* U = D.U;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int c = cg + kRfGroups * s;
+    if (c < p) {
+      const int a0 = stp[c];
+#pragma unroll
+      for (int u = 0; u < kRfRegs; ++u) {
+        const int k = sub + kRfLanes * u;
+        if (k < r) U[c + (int64_t)k * p] = (a0 >= 0) ? (k == a0 ? 1.0 : 0.0) : x[s][u];
+      }
+    }
+  }
+  for (int a = t; a < r; a += kRfThreads) D.perm[a] = chosen[a];
+  for (int c = t; c < p; c += kRfThreads)
+    if (stp[c] < 0) D.perm[r + lpos[c]] = c;
+  if (t == 0) *D.rank = r;
+}
+
+// Slots per column group for p rows of Phi (0: the on-chip form does not apply).
+static int row_id_slots(int p, int d) {
+  if (d > kRfRows) return 0;
+  if (p <= 2 * kRfGroups) return 2;
+  if (p <= 4 * kRfGroups) return 4;
+  if (p <= 6 * kRfGroups) return 6;
+  return 0;
+}
+
 // ------------------------------------------------------------ host orchestration
 
 namespace {
@@ -627,13 +940,29 @@ int hss_core(const HssSource& src, int K, int m, const double* X, int64_t ldx, d
           idd.push_back(IdDesc{Phi[i], Wk[i], Ub[i], permU[i], &ranks[2 * i], hp[2 * i], hp[2 * i], d});
           idd.push_back(IdDesc{Theta[i], Wk2[i], Vb[i], permV[i], &ranks[2 * i + 1], hp[2 * i + 1], hp[2 * i + 1], d});
         }
+        int cnt[4] = {0, 0, 0, 0}, first[4];
+        std::vector<IdDesc> sorted;
+        for (int f = 0; f < 4; ++f) {
+          first[f] = (int)sorted.size();
+          for (const IdDesc& q : idd)
+            if (row_id_slots(q.p, q.d) / 2 == f) sorted.push_back(q);
+          cnt[f] = (int)sorted.size() - first[f];
+        }
         const VGemm* dg2 = st.push(g2.g);
         const int32_t* dp2 = st.push(g2.pf);
-        const IdDesc* did = st.push(idd);
+        const IdDesc* did = st.push(sorted);
         if (int rc = st.flush(key, s)) return rc;
         if (dg2) vgemm_launch(dg2, dp2, (int)g2.g.size(), g2.bound, s);
-        hipLaunchKernelGGL(k_row_id, dim3((unsigned)idd.size()), dim3(kIdThreads), 0, s, did, o->hss_rel_tol,
-                           o->hss_rel_tol * std::sqrt((double)d) * anorm);
+        // each decomposition by the on-chip form for its size, else by the
+        // global-memory one (descriptors grouped by form)
+        const double atol = o->hss_rel_tol * std::sqrt((double)d) * anorm;
+        if (cnt[0]) hipLaunchKernelGGL(k_row_id, dim3(cnt[0]), dim3(kIdThreads), 0, s, did + first[0], o->hss_rel_tol, atol);
+        if (cnt[1])
+          hipLaunchKernelGGL(k_row_id_rf<2>, dim3(cnt[1]), dim3(kRfThreads), 0, s, did + first[1], o->hss_rel_tol, atol);
+        if (cnt[2])
+          hipLaunchKernelGGL(k_row_id_rf<4>, dim3(cnt[2]), dim3(kRfThreads), 0, s, did + first[2], o->hss_rel_tol, atol);
+        if (cnt[3])
+          hipLaunchKernelGGL(k_row_id_rf<6>, dim3(cnt[3]), dim3(kRfThreads), 0, s, did + first[3], o->hss_rel_tol, atol);
         if (hipMemcpyAsync(hr.data(), ranks, hr.size() * 4, hipMemcpyDeviceToHost, s) != hipSuccess) return PHDC_E_HIP;
         if (hipStreamSynchronize(s) != hipSuccess) return PHDC_E_HIP;
         for (int i : nodes) {
