@@ -466,7 +466,7 @@ def sec_example1(P, W, args):
     for which in (1, 2):
         A = torch.tensor(np.ascontiguousarray(W.example1(n, which).T), device="cuda").t()
         entry = {}
-        for name, o in (("hss", P.opts(hss_leaf=256, hss_samples=256, hss_samples_inc=128)),
+        for name, o in (("hss", P.opts(hss_leaf=256)),
                         ("dense_fp64_mfma", P.opts(force_fail=P.FAIL_HSS))):
             nb = ctypes.c_size_t()
             lib.phdc_hss_gemm_workspace(n, n, ctypes.byref(o), ctypes.byref(nb))

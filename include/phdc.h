@@ -83,7 +83,7 @@ typedef struct phdc_opts {
     double hss_rel_tol;     /* ID truncation tolerance for HSS compression (default 1e-14): a node's
                                rank ends at |R_kk| <= tol * max(|R_00|, sqrt(d)), d samples */
     int32_t hss_leaf;       /* HSS leaf block size, 8..1024 (default 256) */
-    int32_t hss_samples;    /* initial number of random sample columns d, 16..512 (default 256) */
+    int32_t hss_samples;    /* initial number of random sample columns d, 16..512 (default 192) */
     int32_t hss_samples_inc;/* extra sample columns when a rank reaches d - 8, >= 0 (default 128) */
     int32_t split_slices;   /* number of BF16 slices per operand for PHDC_GEMM_SPLIT, 1..7 (default 6: the
                                fewest that meet 10x the FP64 bounds) */

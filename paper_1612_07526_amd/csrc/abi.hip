@@ -662,7 +662,7 @@ void phdc_opts_default(phdc_opts* o) {
   o->hss_min_K = 4096;
   o->hss_rel_tol = 1e-14;
   o->hss_leaf = 256;
-  o->hss_samples = 256;
+  o->hss_samples = 192;
   o->hss_samples_inc = 128;
   o->split_slices = 6;
   o->seed = 0x9e3779b97f4a7c15ULL;

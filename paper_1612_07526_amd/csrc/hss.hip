@@ -348,9 +348,9 @@ __global__ void __launch_bounds__(kIdThreads) k_row_id(const IdDesc* __restrict_
 }
 
 // The same decomposition with the whole work matrix on chip, for p <= 32 NS
-// rows of Phi and d <= kRfRows samples.  Column c of Phi^T (row c of Phi) is
+// rows of Phi and d <= 16 NR samples.  Column c of Phi^T (row c of Phi) is
 // owned by a group of kRfLanes lanes; lane sub keeps its entries k = sub +
-// kRfLanes u in registers for the whole factorization (zero past d), so a
+// kRfLanes u (u < NR) in registers for the whole factorization (zero past d), so a
 // pivot step moves no matrix data through memory: the pivot's owners publish
 // the reflector in LDS, zero outside rows j..d-1, and every lane then applies
 // it to all of its columns at once (one LDS read of v per row for every slot,
@@ -364,8 +364,7 @@ __global__ void __launch_bounds__(kIdThreads) k_row_id(const IdDesc* __restrict_
 constexpr int kRfThreads = 512;
 constexpr int kRfLanes = 16;
 constexpr int kRfGroups = kRfThreads / kRfLanes;  // columns in flight per slot
-constexpr int kRfRegs = 16;
-constexpr int kRfRows = kRfLanes * kRfRegs;  // largest sample count d
+constexpr int kRfRowsMax = kRfLanes * 16;  // largest sample count d of the on-chip form
 constexpr int kRfR11 = 128;
 
 template <int CTRL>
@@ -403,15 +402,15 @@ struct RfShared {
 
 // The pivot column's owners build the reflector of its rows j..: v = x -
 // alpha e_j, alpha = -sign(x_j) |x|; the column keeps R_jj = alpha.
-template <int NS>
-__device__ __forceinline__ void rf_reflect(double (&x)[NS][kRfRegs], const RfShared& sh, int piv, int j, int cg,
+template <int NS, int NR>
+__device__ __forceinline__ void rf_reflect(double (&x)[NS][NR], const RfShared& sh, int piv, int j, int cg,
                                            int sub) {
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     if (cg + kRfGroups * s == piv) {
       double q = 0.0, xj = 0.0;
 #pragma unroll
-      for (int u = 0; u < kRfRegs; ++u) {
+      for (int u = 0; u < NR; ++u) {
         const int k = sub + kRfLanes * u;
         q += (k >= j) ? x[s][u] * x[s][u] : 0.0;
         xj += (k == j) ? x[s][u] : 0.0;
@@ -421,7 +420,7 @@ __device__ __forceinline__ void rf_reflect(double (&x)[NS][kRfRegs], const RfSha
       const double xn = sqrt(q);
       const double alpha = (x0 >= 0.0) ? -xn : xn;
 #pragma unroll
-      for (int u = 0; u < kRfRegs; ++u) {
+      for (int u = 0; u < NR; ++u) {
         const int k = sub + kRfLanes * u;
         sh.v[k] = (k > j) ? x[s][u] : (k == j ? x0 - alpha : 0.0);
         sh.ej[k] = (k == j) ? 1.0 : 0.0;
@@ -440,15 +439,15 @@ __device__ __forceinline__ void rf_reflect(double (&x)[NS][kRfRegs], const RfSha
 // Every remaining column c: x -= (2 v.x / v.v) v, and the norm of its rows
 // j+1.. downdated by R_jc^2.  The rows below j see v = 0 and stay unchanged;
 // whole registers below row j are skipped.
-template <int NS>
-__device__ __forceinline__ void rf_update(double (&x)[NS][kRfRegs], const RfShared& sh, int j, int p, int cg,
+template <int NS, int NR>
+__device__ __forceinline__ void rf_update(double (&x)[NS][NR], const RfShared& sh, int j, int p, int cg,
                                           int sub) {
   const int uj = j / kRfLanes;
   double f[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) f[s] = 0.0;
 #pragma unroll
-  for (int u = 0; u < kRfRegs; ++u) {
+  for (int u = 0; u < NR; ++u) {
     if (u >= uj) {
       const double vk = sh.v[sub + kRfLanes * u];
 #pragma unroll
@@ -467,7 +466,7 @@ __device__ __forceinline__ void rf_update(double (&x)[NS][kRfRegs], const RfShar
 #pragma unroll
   for (int s = 0; s < NS; ++s) xj[s] = 0.0;
 #pragma unroll
-  for (int u = 0; u < kRfRegs; ++u) {
+  for (int u = 0; u < NR; ++u) {
     if (u >= uj) {
       const double vk = sh.v[sub + kRfLanes * u], ek = sh.ej[sub + kRfLanes * u];
 #pragma unroll
@@ -487,7 +486,7 @@ __device__ __forceinline__ void rf_update(double (&x)[NS][kRfRegs], const RfShar
       if (redo) {  // cancellation: recompute the remaining norm
         double q = 0.0;
 #pragma unroll
-        for (int u = 0; u < kRfRegs; ++u) {
+        for (int u = 0; u < NR; ++u) {
           const int k = sub + kRfLanes * u;
           q += (k > j) ? x[s][u] * x[s][u] : 0.0;
         }
@@ -501,13 +500,13 @@ __device__ __forceinline__ void rf_update(double (&x)[NS][kRfRegs], const RfShar
   }
 }
 
-template <int NS>
+template <int NS, int NR>
 __global__ void __launch_bounds__(kRfThreads) k_row_id_rf(const IdDesc* __restrict__ ids, double tol,
                                                           double abs_tol) {
   constexpr int PM = NS * kRfGroups;
   constexpr int RM = PM < kRfR11 ? PM : kRfR11;
   __shared__ double cn[PM], cn0[PM];
-  __shared__ double v[kRfRows], ej[kRfRows];
+  __shared__ double v[kRfLanes * NR], ej[kRfLanes * NR];
   __shared__ int stp[PM];     // pivot step of column c, -1 while unpivoted
   __shared__ int chosen[PM];  // column pivoted at step j
   __shared__ int lpos[PM];    // rank of an unpivoted column among the unpivoted
@@ -519,12 +518,12 @@ __global__ void __launch_bounds__(kRfThreads) k_row_id_rf(const IdDesc* __restri
   const int p = D.p, d = D.d;
   const int t = threadIdx.x;
   const int sub = t % kRfLanes, cg = t / kRfLanes;
-  double x[NS][kRfRegs];
+  double x[NS][NR];
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const int c = cg + kRfGroups * s;
 #pragma unroll
-    for (int u = 0; u < kRfRegs; ++u) {
+    for (int u = 0; u < NR; ++u) {
       const int k = sub + kRfLanes * u;
       x[s][u] = (c < p && k < d) ? D.phi[c + (int64_t)k * D.ldphi] : 0.0;
     }
@@ -534,7 +533,7 @@ __global__ void __launch_bounds__(kRfThreads) k_row_id_rf(const IdDesc* __restri
     const int c = cg + kRfGroups * s;
     double q = 0.0;
 #pragma unroll
-    for (int u = 0; u < kRfRegs; ++u) q += x[s][u] * x[s][u];
+    for (int u = 0; u < NR; ++u) q += x[s][u] * x[s][u];
     q = rf_sum16(q);
     if (sub == 0) {
       cn[c] = (c < p) ? q : -1.0;  // -1: not a candidate
@@ -576,10 +575,10 @@ __global__ void __launch_bounds__(kRfThreads) k_row_id_rf(const IdDesc* __restri
     __syncthreads();
     if (sh_stop) break;
     const int piv = sh_piv;
-    rf_reflect<NS>(x, sh, piv, j, cg, sub);
+    rf_reflect<NS, NR>(x, sh, piv, j, cg, sub);
     __syncthreads();
     if (sh_vtv > 0.0) {
-      rf_update<NS>(x, sh, j, p, cg, sub);
+      rf_update<NS, NR>(x, sh, j, p, cg, sub);
     }
     __syncthreads();
     r = j + 1;
@@ -593,7 +592,7 @@ __global__ void __launch_bounds__(kRfThreads) k_row_id_rf(const IdDesc* __restri
     const int a = (c < p) ? stp[c] : -1;
     if (a >= 0) {
 #pragma unroll
-      for (int u = 0; u < kRfRegs; ++u) {
+      for (int u = 0; u < NR; ++u) {
         const int k = sub + kRfLanes * u;
         if (k <= a) R11[k + (int64_t)a * r] = x[s][u];
       }
@@ -610,7 +609,7 @@ __global__ void __launch_bounds__(kRfThreads) k_row_id_rf(const IdDesc* __restri
   // 0..r-1 (row a: register a / 16 of lane a % 16); the other slots compute
   // along and are ignored
 #pragma unroll
-  for (int ua = kRfRegs - 1; ua >= 0; --ua) {
+  for (int ua = NR - 1; ua >= 0; --ua) {
     if (kRfLanes * ua >= r) continue;
     for (int sa = kRfLanes - 1; sa >= 0; --sa) {
       const int a = kRfLanes * ua + sa;
@@ -639,7 +638,7 @@ __global__ void __launch_bounds__(kRfThreads) k_row_id_rf(const IdDesc* __restri
     if (c < p) {
       const int a0 = stp[c];
 #pragma unroll
-      for (int u = 0; u < kRfRegs; ++u) {
+      for (int u = 0; u < NR; ++u) {
         const int k = sub + kRfLanes * u;
         if (k < r) U[c + (int64_t)k * p] = (a0 >= 0) ? (k == a0 ? 1.0 : 0.0) : x[s][u];
       }
@@ -651,13 +650,33 @@ __global__ void __launch_bounds__(kRfThreads) k_row_id_rf(const IdDesc* __restri
   if (t == 0) *D.rank = r;
 }
 
-// Slots per column group for p rows of Phi (0: the on-chip form does not apply).
-static int row_id_slots(int p, int d) {
-  if (d > kRfRows) return 0;
-  if (p <= 2 * kRfGroups) return 2;
-  if (p <= 4 * kRfGroups) return 4;
-  if (p <= 6 * kRfGroups) return 6;
+// Forms of the decomposition: 0 the global-memory kernel, then the on-chip
+// one by (slots, registers): d <= 192 takes 12 registers per lane (up to 256
+// rows of Phi), d <= 256 takes 16 (up to 192 rows).
+constexpr int kRfForms = 8;
+static int row_id_form(int p, int d) {
+  if (d <= 12 * kRfLanes) {
+    for (int f = 1; f <= 4; ++f)
+      if (p <= 2 * f * kRfGroups) return f;
+  } else if (d <= 16 * kRfLanes) {
+    for (int f = 5; f <= 7; ++f)
+      if (p <= 2 * (f - 4) * kRfGroups) return f;
+  }
   return 0;
+}
+
+static void launch_row_id(int form, int n, const IdDesc* ids, double tol, double atol, hipStream_t s) {
+  if (n <= 0) return;
+  switch (form) {
+    case 0: hipLaunchKernelGGL(k_row_id, dim3(n), dim3(kIdThreads), 0, s, ids, tol, atol); break;
+    case 1: hipLaunchKernelGGL((k_row_id_rf<2, 12>), dim3(n), dim3(kRfThreads), 0, s, ids, tol, atol); break;
+    case 2: hipLaunchKernelGGL((k_row_id_rf<4, 12>), dim3(n), dim3(kRfThreads), 0, s, ids, tol, atol); break;
+    case 3: hipLaunchKernelGGL((k_row_id_rf<6, 12>), dim3(n), dim3(kRfThreads), 0, s, ids, tol, atol); break;
+    case 4: hipLaunchKernelGGL((k_row_id_rf<8, 12>), dim3(n), dim3(kRfThreads), 0, s, ids, tol, atol); break;
+    case 5: hipLaunchKernelGGL((k_row_id_rf<2, 16>), dim3(n), dim3(kRfThreads), 0, s, ids, tol, atol); break;
+    case 6: hipLaunchKernelGGL((k_row_id_rf<4, 16>), dim3(n), dim3(kRfThreads), 0, s, ids, tol, atol); break;
+    default: hipLaunchKernelGGL((k_row_id_rf<6, 16>), dim3(n), dim3(kRfThreads), 0, s, ids, tol, atol); break;
+  }
 }
 
 // ------------------------------------------------------------ host orchestration
@@ -940,12 +959,12 @@ int hss_core(const HssSource& src, int K, int m, const double* X, int64_t ldx, d
           idd.push_back(IdDesc{Phi[i], Wk[i], Ub[i], permU[i], &ranks[2 * i], hp[2 * i], hp[2 * i], d});
           idd.push_back(IdDesc{Theta[i], Wk2[i], Vb[i], permV[i], &ranks[2 * i + 1], hp[2 * i + 1], hp[2 * i + 1], d});
         }
-        int cnt[4] = {0, 0, 0, 0}, first[4];
+        int cnt[kRfForms], first[kRfForms];
         std::vector<IdDesc> sorted;
-        for (int f = 0; f < 4; ++f) {
+        for (int f = 0; f < kRfForms; ++f) {
           first[f] = (int)sorted.size();
           for (const IdDesc& q : idd)
-            if (row_id_slots(q.p, q.d) / 2 == f) sorted.push_back(q);
+            if (row_id_form(q.p, q.d) == f) sorted.push_back(q);
           cnt[f] = (int)sorted.size() - first[f];
         }
         const VGemm* dg2 = st.push(g2.g);
@@ -956,13 +975,7 @@ int hss_core(const HssSource& src, int K, int m, const double* X, int64_t ldx, d
         // each decomposition by the on-chip form for its size, else by the
         // global-memory one (descriptors grouped by form)
         const double atol = o->hss_rel_tol * std::sqrt((double)d) * anorm;
-        if (cnt[0]) hipLaunchKernelGGL(k_row_id, dim3(cnt[0]), dim3(kIdThreads), 0, s, did + first[0], o->hss_rel_tol, atol);
-        if (cnt[1])
-          hipLaunchKernelGGL(k_row_id_rf<2>, dim3(cnt[1]), dim3(kRfThreads), 0, s, did + first[1], o->hss_rel_tol, atol);
-        if (cnt[2])
-          hipLaunchKernelGGL(k_row_id_rf<4>, dim3(cnt[2]), dim3(kRfThreads), 0, s, did + first[2], o->hss_rel_tol, atol);
-        if (cnt[3])
-          hipLaunchKernelGGL(k_row_id_rf<6>, dim3(cnt[3]), dim3(kRfThreads), 0, s, did + first[3], o->hss_rel_tol, atol);
+        for (int f = 0; f < kRfForms; ++f) launch_row_id(f, cnt[f], did + first[f], o->hss_rel_tol, atol, s);
         if (hipMemcpyAsync(hr.data(), ranks, hr.size() * 4, hipMemcpyDeviceToHost, s) != hipSuccess) return PHDC_E_HIP;
         if (hipStreamSynchronize(s) != hipSuccess) return PHDC_E_HIP;
         for (int i : nodes) {
