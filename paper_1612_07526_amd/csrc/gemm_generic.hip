@@ -21,20 +21,25 @@ __device__ inline int lds_at(int k, int r) {
   return KC ? r * QKP + k : k * QLD + r;
 }
 
-template <bool TA, bool TB, class Epi>
+// TN = 128 or 64 output columns per tile (64 for a product of at most 512
+// columns whose last 128-column tile would be at most half used, such as the
+// 192 sample columns of the HSS compression: each wave then holds 64 x 32).
+template <bool TA, bool TB, class Epi, int TN = QT>
 __global__ void __launch_bounds__(256) k_gemm_f64(GemmArgs g, Epi epi) {
   __shared__ double As[2][QBUF];
   __shared__ double Bs[2][QBUF];
   constexpr bool AKC = TA;   // op(A)(i, k) = A[k + i lda]: k contiguous
   constexpr bool BKC = !TB;  // op(B)(k, j) = B[k + j ldb]: k contiguous
+  constexpr int NB = TN / 32;  // 16-column MFMA blocks per wave
+  constexpr int BE = TN / 16;  // B entries staged per thread per k-step
   const int bz = blockIdx.y;
   const double* A = g.A + (int64_t)bz * g.strideA;
   const double* B = g.B + (int64_t)bz * g.strideB;
   const int tmn = (g.m + QT - 1) / QT;
   const int mt = blockIdx.x % tmn, nt = blockIdx.x / tmn;
-  const int i0 = mt * QT, j0 = nt * QT;
+  const int i0 = mt * QT, j0 = nt * TN;
   const int t = threadIdx.x;
-  double ra[8], rb[8];
+  double ra[8], rb[BE];
 
   auto gload = [&](int kt) {
     const int kb = kt * QK;
@@ -49,16 +54,16 @@ __global__ void __launch_bounds__(256) k_gemm_f64(GemmArgs g, Epi epi) {
 #pragma unroll
       for (int e = 0; e < 8; ++e) ra[e] = (i < g.m && k + e < g.k) ? src[e] : 0.0;
     }
-    if (!TB) {  // B(k,j) = B[k + j ldb]: thread stages column j = t/2, k = kb + 8*(t%2) ..
-      const int j = j0 + (t >> 1), k = kb + (t & 1) * 8;
+    if (!TB) {  // B(k,j) = B[k + j ldb]: thread stages column j = t / (16 / BE), BE consecutive k
+      const int j = j0 + t / (QK / BE), k = kb + (t % (QK / BE)) * BE;
       const double* src = B + (int64_t)j * g.ldb + k;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) rb[e] = (j < g.n && k + e < g.k) ? src[e] : 0.0;
-    } else {    // op(B)(k,j) = B[j + k ldb]
-      const int k = kb + (t >> 4), j = j0 + (t & 15) * 8;
+      for (int e = 0; e < BE; ++e) rb[e] = (j < g.n && k + e < g.k) ? src[e] : 0.0;
+    } else {    // op(B)(k,j) = B[j + k ldb]: thread stages k = t/16, BE consecutive j
+      const int k = kb + (t >> 4), j = j0 + (t & 15) * BE;
       const double* src = B + (int64_t)k * g.ldb + j;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) rb[e] = (k < g.k && j + e < g.n) ? src[e] : 0.0;
+      for (int e = 0; e < BE; ++e) rb[e] = (k < g.k && j + e < g.n) ? src[e] : 0.0;
     }
   };
   auto lstore = [&](int buf) {
@@ -71,21 +76,21 @@ __global__ void __launch_bounds__(256) k_gemm_f64(GemmArgs g, Epi epi) {
     }
     if (!TB) {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) Bs[buf][lds_at<BKC>((t & 1) * 8 + e, t >> 1)] = rb[e];
+      for (int e = 0; e < BE; ++e) Bs[buf][lds_at<BKC>((t % (QK / BE)) * BE + e, t / (QK / BE))] = rb[e];
     } else {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) Bs[buf][lds_at<BKC>(t >> 4, (t & 15) * 8 + e)] = rb[e];
+      for (int e = 0; e < BE; ++e) Bs[buf][lds_at<BKC>(t >> 4, (t & 15) * BE + e)] = rb[e];
     }
   };
 
   const int w = t >> 6, lane = t & 63;
-  const int wm = (w & 1) * 64, wn = (w >> 1) * 64;
+  const int wm = (w & 1) * 64, wn = (w >> 1) * (TN / 2);
   const int li = lane & 15, lk = lane >> 4;
-  d4g_t acc[4][4];
+  d4g_t acc[4][NB];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = d4g_t{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < NB; ++j) acc[i][j] = d4g_t{0.0, 0.0, 0.0, 0.0};
 
   const int nkt = (g.k + QK - 1) / QK;
   if (nkt > 0) {
@@ -99,21 +104,21 @@ __global__ void __launch_bounds__(256) k_gemm_f64(GemmArgs g, Epi epi) {
 #pragma unroll
     for (int ks = 0; ks < QK / 4; ++ks) {
       const int kr = ks * 4 + lk;
-      double av[4], bv[4];
+      double av[4], bv[NB];
 #pragma unroll
       for (int i = 0; i < 4; ++i) av[i] = As[buf][lds_at<AKC>(kr, wm + i * 16 + li)];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = Bs[buf][lds_at<BKC>(kr, wn + j * 16 + li)];
+      for (int j = 0; j < NB; ++j) bv[j] = Bs[buf][lds_at<BKC>(kr, wn + j * 16 + li)];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < NB; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
     }
     if (kt + 1 < nkt) lstore(buf ^ 1);
     __syncthreads();
   }
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < NB; ++j) {
     const int cj = j0 + wn + j * 16 + li;
     if (cj >= g.n) continue;
 #pragma unroll
@@ -129,8 +134,15 @@ __global__ void __launch_bounds__(256) k_gemm_f64(GemmArgs g, Epi epi) {
 template <bool TA, bool TB, class Epi>
 void launch_gemm(const GemmArgs& g, int batch, const Epi& epi, hipStream_t s) {
   if (g.m <= 0 || g.n <= 0 || batch <= 0) return;
-  dim3 grid(((g.m + QT - 1) / QT) * ((g.n + QT - 1) / QT), batch);
-  hipLaunchKernelGGL((k_gemm_f64<TA, TB, Epi>), grid, dim3(256), 0, s, g, epi);
+  const int tm = (g.m + QT - 1) / QT;
+  const int rem = g.n % QT, tn = (g.n + QT - 1) / QT;
+  if (rem > 0 && rem <= QT / 2 && tn <= 4) {  // a narrow product whose last column tile would be mostly empty
+    dim3 grid(tm * ((g.n + QT / 2 - 1) / (QT / 2)), batch);
+    hipLaunchKernelGGL((k_gemm_f64<TA, TB, Epi, QT / 2>), grid, dim3(256), 0, s, g, epi);
+    return;
+  }
+  dim3 grid(tm * ((g.n + QT - 1) / QT), batch);
+  hipLaunchKernelGGL((k_gemm_f64<TA, TB, Epi, QT>), grid, dim3(256), 0, s, g, epi);
 }
 
 // C = op(A) op(B), plain store.

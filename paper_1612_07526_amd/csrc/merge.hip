@@ -1216,16 +1216,48 @@ __device__ void copy_body(const BlockMap& bm, const Scratch& S, int b) {
     // per column below kCopyWideRows rows), rows in pairs with 16-byte
     // nontemporal stores (nothing here reads Q again, so the lines need not
     // stay in the caches), a scalar first row when the column starts at an odd
-    // 8-byte offset, a scalar last row when the rest is odd.
+    // 8-byte offset, a scalar last row when the rest is odd.  On the short
+    // columns of a wave, up to 4 row pairs per lane are read before any is
+    // written, and the next column's list entry and destination are read while
+    // the current one is in flight.
     typedef double d2_t __attribute__((ext_vector_type(2)));
-    const bool wide = m >= kCopyWideRows;
-    const int lane = wide ? threadIdx.x : (threadIdx.x & 63), step = wide ? 256 : 64;
-    const int q0 = wide ? lb : lb * 4 + (threadIdx.x >> 6), qs = wide ? G : G * 4;
-    for (int q = q0; q < nd; q += qs) {
-      int c, dst;
+    if (m >= kCopyWideRows) {
+      for (int q = lb; q < nd; q += G) {
+        int c, dst;
+        if (q < nd1) { c = S.dfc1[so + q]; dst = S.destd1[so + q]; }
+        else { const int q2 = q - nd1; c = S.dfc2[so + q2]; dst = S.destd2[so + q2]; }
+        const RowRange g = S.crng[so + c];
+        const double* src = M.qin + (int64_t)c * M.ldin;
+        double* out = M.qout + (int64_t)dst * M.ldout;
+        const int a = (int)(((uintptr_t)out >> 3) & 1);
+        const int np = (m - a) >> 1;
+        auto val = [&](int r) { return (r >= g.lo && r < g.hi) ? src[r] : 0.0; };
+        if (threadIdx.x == 0) {
+          if (a) out[0] = val(0);
+          if ((m - a) & 1) out[m - 1] = val(m - 1);
+        }
+        d2_t* o2 = (d2_t*)(out + a);
+#pragma unroll 4
+        for (int p = threadIdx.x; p < np; p += 256) {
+          const int r = a + 2 * p;
+          __builtin_nontemporal_store(d2_t{val(r), val(r + 1)}, &o2[p]);
+        }
+      }
+      return;
+    }
+    constexpr int U = 4;
+    const int lane = threadIdx.x & 63;
+    const int q0 = lb * 4 + (threadIdx.x >> 6), qs = G * 4;
+    auto entry = [&](int q, int& c, int& dst) {
       if (q < nd1) { c = S.dfc1[so + q]; dst = S.destd1[so + q]; }
       else { const int q2 = q - nd1; c = S.dfc2[so + q2]; dst = S.destd2[so + q2]; }
+    };
+    int c = 0, dst = 0;
+    if (q0 < nd) entry(q0, c, dst);
+    for (int q = q0; q < nd; q += qs) {
       const RowRange g = S.crng[so + c];
+      int cn = 0, dn = 0;
+      if (q + qs < nd) entry(q + qs, cn, dn);
       const double* src = M.qin + (int64_t)c * M.ldin;
       double* out = M.qout + (int64_t)dst * M.ldout;
       const int a = (int)(((uintptr_t)out >> 3) & 1);
@@ -1236,11 +1268,19 @@ __device__ void copy_body(const BlockMap& bm, const Scratch& S, int b) {
         if ((m - a) & 1) out[m - 1] = val(m - 1);
       }
       d2_t* o2 = (d2_t*)(out + a);
-#pragma unroll 4
-      for (int p = lane; p < np; p += step) {
-        const int r = a + 2 * p;
-        __builtin_nontemporal_store(d2_t{val(r), val(r + 1)}, &o2[p]);
+      for (int p0 = lane; p0 < np; p0 += U * 64) {
+        d2_t v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int r = a + 2 * (p0 + u * 64);
+          v[u] = (p0 + u * 64 < np) ? d2_t{val(r), val(r + 1)} : d2_t{0.0, 0.0};
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (p0 + u * 64 < np) __builtin_nontemporal_store(v[u], &o2[p0 + u * 64]);
       }
+      c = cn;
+      dst = dn;
     }
     return;
   }
