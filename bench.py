@@ -72,23 +72,30 @@ def algorithmic(table):
     gemm_flops: 2 [n1 (k1+k2) + n2 (k2+k3)] K over merges on the FP64 path (Gu's
                 grouped products, Eq. (6));
     copy_bytes: each deflated column read once over the rows it can be nonzero in and
-                written once over the same rows, or over all m rows at the last merge
-                of the matrix (whose output is the caller's Q), 8 bytes per entry;
+                written once over the same rows, or at the last merge of the matrix
+                (whose output is the caller's Q) over all m rows -- or, when that merge's
+                off-diagonal quadrants were zero-filled beforehand, over the rows of its
+                destination's half and of its range -- 8 bytes per entry;
     root_copy_bytes: the same for the last merge only (the copy the library launches on
                 its own when a solve has a single root: the "copy" phase);
+    fill_bytes: 8 * 2 n1 (m - n1) per last merge whose off-diagonal quadrants were
+                zero-filled (the "fill" phase);
     uhat_write_bytes: 8 K^2 bytes per merge.
     """
     t = table.astype(np.float64)
     m, n1, K, k1, k2, k3, nt1, nt2, path, root = (t[:, i] for i in (0, 1, 2, 3, 4, 5, 6, 7, 8, 15))
     rows = ((table[:, 13].astype(np.int64) & 0xFFFFFFFF) + (table[:, 14].astype(np.int64) << 32)).astype(np.float64)
+    pre = table[:, 16] > 0
+    copied = ((table[:, 17].astype(np.int64) & 0xFFFFFFFF) + (table[:, 18].astype(np.int64) << 32)).astype(np.float64)
     n2 = m - n1
     plain = path == 0
-    written = np.where(root > 0, m * (nt1 + nt2), rows)
+    written = np.where(root > 0, np.where(pre, copied, m * (nt1 + nt2)), rows)
     moved = 8 * (rows + written)
     return {
         "gemm_flops": float(np.sum((2 * (n1 * (k1 + k2) + n2 * (k2 + k3)) * K)[plain])),
         "copy_bytes": float(np.sum(moved)),
         "root_copy_bytes": float(np.sum(moved[root > 0])),
+        "fill_bytes": float(np.sum((16 * n1 * n2)[pre])),
         "uhat_write_bytes": float(np.sum(K * K * 8)),
     }
 
@@ -159,6 +166,7 @@ def reference_copy_gbs():
 # Kernel phase -> (counter summary under profiles/, source file the kernel is built from).
 TRAFFIC_SUMMARIES = {
     "copy": ("profiles/k_stage_uhat_root_copy_uniform_n16384_traffic.md", "paper_1612_07526_amd/csrc/merge.hip"),
+    "fill": ("profiles/k_fill_offblocks_uniform_n16384_traffic.md", "paper_1612_07526_amd/csrc/merge.hip"),
 }
 
 
@@ -249,7 +257,9 @@ def sec_value(P, W, args, out):
         ch()
     # every phase, in an untimed pass: the breakdown and the dominant kernel
     phases = profile_phases(P, ch, reps=2)
-    dom = max(phases.items(), key=lambda kv: kv[1][0])[0]
+    # the roofline kernel: the longest of the launch classes with a defined algorithmic
+    # measure (the rest are latency-bound chains of small steps)
+    dom = max((kv for kv in phases.items() if kv[0] in ("copy", "fill", "gemm")), key=lambda kv: kv[1][0])[0]
     log("[bench] phases (ms/solve, untimed pass with events around every phase): "
         + ", ".join(f"{k}={v[0]:.3f}" for k, v in phases.items()))
     log(f"[bench] value: timing {args.steps} solves of uniform n={n} (chosen form, no events)")
@@ -688,8 +698,8 @@ def main():
     if dom == "gemm":
         roof = {"bound": "mfma", "achieved": alg["gemm_flops"] / (ms_dom * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s"}
-    elif dom == "copy":
-        byts = alg["root_copy_bytes"]
+    elif dom in ("copy", "fill"):
+        byts = alg["root_copy_bytes" if dom == "copy" else "fill_bytes"]
         roof = {"bound": "hbm", "achieved": byts / (ms_dom * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     else:
         # latency-bound kernel classes: report the copy kernel's HBM rate alongside
@@ -701,8 +711,9 @@ def main():
         roof["frac"] = None
     roof.update(traffic=measured_traffic(dom, args.leaf), kernel=dom, launches_per_step=int(cnt_dom),
                 ms_per_step=round(ms_dom, 4))
-    if dom == "copy":
-        roof["algorithmic_bytes_per_launch"] = round(alg["root_copy_bytes"] / max(cnt_dom, 1))
+    if dom in ("copy", "fill"):
+        roof["algorithmic_bytes_per_launch"] = round(alg["root_copy_bytes" if dom == "copy" else "fill_bytes"]
+                                                     / max(cnt_dom, 1))
     if roof["bound"] == "hbm":
         roof["reference_copy_gbs"] = reference_copy_gbs()
 
@@ -747,6 +758,7 @@ def main():
         "plain_fp64_leaf32_s": v["t_l32"] and round(v["t_l32"], 6),
         "accuracy": {"orth_max": v["orth"], "residual": v["res"]},
         "phases_ms": {k: round(x[0], 4) for k, x in phases.items()},
+        "algorithmic_per_solve": {k: round(x) for k, x in alg.items()},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

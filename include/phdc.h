@@ -221,15 +221,18 @@ int phdc_merge_stats(const void *work, int32_t *stats_host);
  * ms[0:nphase], count[0:nphase] (phase order: leaf, deflate, rotate, secular,
  * loewner, uhat-norm, uhat-write, rank, gemm, copy, sign, split-slice,
  * split-gemm, hss-sample, hss-compress, hss-apply, adjoint-gemm, adjoint-band,
- * small-merge) and forgets them.  A merge level runs some steps in one launch,
+ * small-merge, fill) and forgets them.  A merge level runs some steps in one launch,
  * timed under one phase: "small-merge" = every step of the merges of at most 64
  * rows on the FP64 path (one workgroup each); "secular" = rotations + secular
  * roots (levels whose merges have at most 64 rows on the other paths: also
  * Loewner z, column norms, Uhat and output ranks); "loewner" = Loewner z +
  * output ranks; "uhat-write" = column norms + Uhat + the deflated-column copy
  * ("uhat-norm" when the norms run first, for normalized Uhat); "copy" = the
- * deflated-column copy of a lone root merge (the caller's whole Q); "rotate"
- * and "rank" are no longer recorded separately.  Returns 0. */
+ * deflated-column copy of a lone root merge (the caller's whole Q); "fill" =
+ * the zero fill of the caller's Q outside the four diagonal blocks of depth 2,
+ * on a second stream while the tree below runs (its events are recorded on
+ * that stream); "rotate" and "rank" are no longer recorded separately.
+ * Returns 0. */
 int phdc_profile_enable(int on);
 int phdc_profile_read(double *ms, int64_t *count, int nphase);
 /* Restrict the recorded phases to the set bits of mask (bit i = phase i in the
@@ -245,10 +248,16 @@ int phdc_profile_select(uint32_t mask);
  *  sample count, or opts.force_fail -- and the merge took the FP64 product),
  *  deflated columns nonzero in the Q1 rows only, in both halves, in the Q2 rows only,
  *  rows the deflated columns can be nonzero in, summed: low 32 bits (as unsigned), high bits,
- *  1 for the last merge of its matrix (which writes every row of its output) else 0}.
+ *  1 for the last merge of its matrix (which writes every row of its output) else 0,
+ *  1 for a last merge whose off-diagonal quadrants (rows of one half of its split,
+ *  columns of the other) were zero-filled on a second stream while the tree below
+ *  ran, else 0,
+ *  for such a merge: the rows its deflated-column copy writes (the destination
+ *  column's half and the part of the range outside it), summed: low 32 bits (as
+ *  unsigned), high bits; else 0, 0}.
  * Rows are in the order the merges were planned (leaves upward, the root last).
  * *rows_out receives the number of merges.  Returns 0 or -1. */
-#define PHDC_MERGE_TABLE_COLS 16
+#define PHDC_MERGE_TABLE_COLS 19
 int phdc_merge_table(const void *work, int64_t max_rows, int32_t *table_host, int64_t *rows_out);
 
 /* ---------------------------------------------------------------- HSS product of a dense matrix

@@ -127,7 +127,7 @@ def gemm_tile_table() -> list:
 
 PHASES = ["leaf", "deflate", "rotate", "secular", "loewner", "uhat_norm", "uhat_write", "rank", "gemm", "copy",
           "sign", "split_slice", "split_gemm", "hss_sample", "hss_compress", "hss_apply", "adj_gemm", "adj_band",
-          "small_merge"]
+          "small_merge", "fill"]
 
 
 def profile_phases(fn, reps: int = 1, phases=None) -> dict:
@@ -202,16 +202,18 @@ def merge_stats(work: torch.Tensor) -> list:
     return list(buf)
 
 
-MERGE_TABLE_COLS = 16
+MERGE_TABLE_COLS = 19
 
 
 def merge_table(work: torch.Tensor):
-    """Per-merge sizes of the last solve on `work` as an (nmerges, 16) int32 numpy array:
+    """Per-merge sizes of the last solve on `work` as an (nmerges, 19) int32 numpy array:
     m, n1, K, k1, k2, k3, type-1 deflations, type-2 deflations, path (0 FP64, 1 split,
     2 HSS), HSS rank, deflated columns nonzero in the Q1 rows only / both halves / the
     Q2 rows only, rows the deflated columns can be nonzero in (summed; low 32 bits as
-    unsigned, then the high bits: see deflated_rows), 1 for the last merge of its matrix.
-    Rows follow the planning order (the root merge last)."""
+    unsigned, then the high bits: see deflated_rows), 1 for the last merge of its matrix,
+    1 for a last merge whose off-diagonal quadrants were zero-filled beforehand, and for
+    such a merge the rows its deflated-column copy writes (summed, low / high bits: see
+    copied_rows).  Rows follow the planning order (the root merge last)."""
     import numpy as np
     lib = load()
     rows = ctypes.c_int64()
@@ -220,6 +222,14 @@ def merge_table(work: torch.Tensor):
     buf = (ctypes.c_int32 * max(n * MERGE_TABLE_COLS, 1))()
     _check(lib.phdc_merge_table(_ptr(work), n, buf, ctypes.byref(rows)), "phdc_merge_table")
     return np.frombuffer(buf, dtype=np.int32)[: n * MERGE_TABLE_COLS].reshape(n, MERGE_TABLE_COLS).copy()
+
+
+def copied_rows(table):
+    """Rows the deflated-column copy of each prefilled last merge writes, summed (int64
+    numpy array; 0 for other merges), from the two 32-bit columns of merge_table."""
+    import numpy as np
+    lo = table[:, 17].astype(np.int64) & 0xFFFFFFFF
+    return lo + (table[:, 18].astype(np.int64) << 32)
 
 
 def deflated_rows(table):

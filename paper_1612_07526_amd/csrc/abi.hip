@@ -88,8 +88,8 @@ struct Sizes {
 };
 
 struct Layout {
-  size_t status, hdr, counters, mparam, descs, leaves, canon, canon_pfx, maps, scratch, uhat, qtwin, ltwin, ranges,
-      hss, hss_desc, sa, sb, serow, sfcol, total;
+  size_t status, hdr, counters, mparam, descs, leaves, canon, canon_pfx, maps, fill, fill_pfx, scratch, uhat, qtwin,
+      ltwin, ranges, hss, hss_desc, sa, sb, serow, sfcol, total;
 };
 
 constexpr int kScratchD = 17, kScratchI = 18;  // 8-byte arrays (doubles, row ranges), int32 arrays
@@ -160,6 +160,8 @@ Layout layout_of(const Sizes& z) {
   L.canon = take((size_t)z.nmats * sizeof(CanonDesc));
   L.canon_pfx = take((size_t)(z.nmats + 1) * 4);
   L.maps = take((size_t)z.map_ints * 4);
+  L.fill = take((size_t)z.nmats * sizeof(FillDesc));
+  L.fill_pfx = take((size_t)(z.nmats + 2) * 4);
   L.scratch = take((size_t)z.n_total * (kScratchD * 8 + kScratchI * 4) + kScratchD * kAlign + kScratchI * kAlign);
   L.uhat = take((size_t)z.uhat * 8);
   L.qtwin = take((size_t)z.q_total * 8);
@@ -238,9 +240,28 @@ struct Probe {
 struct WorkState {
   Staging plan, hss;
   Probe probe;
+  hipEvent_t fill_fork = nullptr, fill_join = nullptr;  // the off-block fill's second stream
 };
 std::mutex g_mu;
 std::unordered_map<const void*, WorkState> g_state;
+
+// Fork/join events of the off-block fill of a workspace (created once; false
+// if they cannot be).
+bool fill_events(const void* work, hipEvent_t* fork, hipEvent_t* join) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  WorkState& w = g_state[work];
+  if (!w.fill_fork && hipEventCreateWithFlags(&w.fill_fork, hipEventDisableTiming) != hipSuccess) {
+    w.fill_fork = nullptr;
+    return false;
+  }
+  if (!w.fill_join && hipEventCreateWithFlags(&w.fill_join, hipEventDisableTiming) != hipSuccess) {
+    w.fill_join = nullptr;
+    return false;
+  }
+  *fork = w.fill_fork;
+  *join = w.fill_join;
+  return true;
+}
 
 void free_staging(Staging& st) {
   if (st.pending) hipEventSynchronize(st.done);
@@ -398,6 +419,9 @@ struct Prepared {
   std::vector<int32_t> hstart;
   std::vector<LevelMaps> lm;
   int nleaves = 0, nmat = 0, ncols = 0;
+  int nfill = 0, nfill_wide = 0;  // matrices of the off-block fill (the wide ones first)
+  int fill_cols_wide = 0, fill_cols = 0;
+  int fill_level = 1;  // the fill starts before this level
   phdc_opts o;
   const double* d = nullptr;  // inputs, for the optional non-finite scan
   const double* e = nullptr;
@@ -413,6 +437,27 @@ void forget_prepared(const void* work) {
 
 int leaf_iters(const phdc_opts* o) { return (o->force_fail & PHDC_FAIL_LEAF) ? 0 : kLeafMaxIters; }
 
+// Start the off-block fill: on the auxiliary stream after what s has queued
+// (returns true: s must wait for *join before the last level), or on s itself
+// when no second stream or event is available.
+bool start_fill(char* base, const Prepared& P, hipStream_t s, hipEvent_t* join) {
+  if (P.nfill <= 0) return false;
+  const FillDesc* fd = (const FillDesc*)(base + P.L.fill);
+  const int32_t* pfx = (const int32_t*)(base + P.L.fill_pfx);
+  hipStream_t a = aux_stream();
+  hipEvent_t fork = nullptr;
+  const bool forked = a && fill_events(base, &fork, join) && hipEventRecord(fork, s) == hipSuccess &&
+                      hipStreamWaitEvent(a, fork, 0) == hipSuccess;
+  hipStream_t fs = forked ? a : s;
+  {
+    ProfScope p(PH_FILL, fs);
+    launch_fill_offblocks(fd, pfx, P.nfill_wide, P.fill_cols_wide, true, kFillBlocksWide, fs);
+    launch_fill_offblocks(fd + P.nfill_wide, pfx + P.nfill_wide + 1, P.nfill - P.nfill_wide,
+                          P.fill_cols - P.fill_cols_wide, false, kFillBlocksNarrow, fs);
+  }
+  return forked && hipEventRecord(*join, a) == hipSuccess;
+}
+
 // Launch every kernel of a prepared solve: no host synchronisation, no memcpy,
 // no memset -- safe to capture in a HIP graph and replay.
 void launch_prepared_all(char* base, const Prepared& P, hipStream_t s) {
@@ -425,9 +470,13 @@ void launch_prepared_all(char* base, const Prepared& P, hipStream_t s) {
     ProfScope p(PH_LEAF, s);
     launch_leaf_ql((const LeafArgs*)(base + P.L.leaves), P.nleaves, P.S.status, P.o.leaf_size, leaf_iters(&P.o), s);
   }
+  hipEvent_t join = nullptr;
+  bool joined = false;
   const MergeDesc* dd = (const MergeDesc*)(base + P.L.descs);
   for (int h = 1; h <= P.z.H; ++h) {
     const int a = P.hstart[h - 1], e = P.hstart[h];
+    if (h == P.fill_level) joined = start_fill(base, P, s, &join);
+    if (h == P.z.H && joined) hipStreamWaitEvent(s, join, 0);
     launch_merge_level(dd + a, e - a, P.lm[h], P.S, P.o.gemm_mode, &P.SB, P.z.nsl, s);
   }
   if (P.o.canonical_sign && P.ncols > 0) {
@@ -498,6 +547,32 @@ int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n,
     D.rout = BF.rng[pout] + BF.off[b] + nd.r0;
     D.r0 = (int32_t)nd.r0;
     D.root = nd.depth == 0 ? 1 : 0;
+  }
+  // Roots in the last level: the caller's Q in the off-diagonal quadrants of
+  // such a root (rows of one half, columns of the other) is only ever written
+  // by the root itself -- every merge below writes and rotates in place only
+  // inside its own diagonal block -- so it is zero-filled on a second stream
+  // while the tree runs, and the root copy then writes only the rows of each
+  // column's half and range.  Wide matrices first, then narrow ones.
+  std::vector<FillDesc> fills;
+  int nfw = 0;
+  if (!no_alloc && z.H >= 1) {
+    for (int pass = 0; pass < 2; ++pass)
+      for (int i = T.hstart[z.H - 1]; i < T.hstart[z.H]; ++i) {
+        const Node& nd = T.merges[i];
+        if (nd.depth != 0 || nd.m < kFillMinRows) continue;
+        if ((nd.m >= kFillWideRows) != (pass == 0)) continue;
+        descs[i].flags |= kFlagPrefilled;
+        fills.push_back(FillDesc{BF.q[0] + BF.qoff[nd.b], BF.ld[0][nd.b], nd.m, nd.n1});
+        if (pass == 0) ++nfw;
+      }
+  }
+  std::vector<int32_t> fpfx(fills.size() + 2, 0);  // wide group [0, nfw], narrow group [nfw + 1, ...]
+  for (int i = 0; i < nfw; ++i) fpfx[i + 1] = fpfx[i] + fills[i].n;
+  for (size_t i = nfw; i < fills.size(); ++i) fpfx[i + 2] = fpfx[i + 1] + fills[i].n;
+  if (!fills.empty()) {
+    put(plan, L.fill - plan0, fills.data(), fills.size());
+    put(plan, L.fill_pfx - plan0, fpfx.data(), fpfx.size());
   }
   put(plan, L.descs - plan0, descs.data(), descs.size());
 
@@ -575,6 +650,15 @@ int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n,
   P.e = BF.e;
   P.nd = BF.nd;
   P.ne = BF.ne;
+  P.nfill = (int)fills.size();
+  P.nfill_wide = nfw;
+  P.fill_cols_wide = fpfx[nfw];
+  P.fill_cols = fpfx[nfw] + fpfx[fills.size() + 1];
+  // the fill starts once the levels of one-workgroup merges are queued (its
+  // traffic would stretch their steps), at the last level at latest
+  P.fill_level = 1;
+  while (P.fill_level < z.H && lm[P.fill_level].maxm <= kSmallMergeMax && small_merge(lm[P.fill_level].maxm, o))
+    ++P.fill_level;
   if (prepare_only) {
     if (hipStreamSynchronize(s) != hipSuccess) return PHDC_E_HIP;
     if (hipMemcpy(base + plan0, plan.data(), plan.size(), hipMemcpyHostToDevice) != hipSuccess) return PHDC_E_HIP;
@@ -600,6 +684,8 @@ int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n,
   // HSS: the host reads K back after each level that has eligible merges
   launch_clear_status(S.status, s);
   if (upload(work, base + plan0, plan, s) != 0) return PHDC_E_HIP;
+  hipEvent_t join = nullptr;
+  bool joined = false;
   {
     ProfScope p(PH_LEAF, s);
     launch_leaf_ql((const LeafArgs*)(base + L.leaves), (int)T.leaves.size(), S.status, o->leaf_size, leaf_iters(o),
@@ -608,6 +694,8 @@ int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n,
   const MergeDesc* dd = (const MergeDesc*)(base + L.descs);
   for (int h = 1; h <= z.H; ++h) {
     const int a = T.hstart[h - 1], e = T.hstart[h];
+    if (h == P.fill_level) joined = start_fill(base, P, s, &join);
+    if (h == z.H && joined) hipStreamWaitEvent(s, join, 0);
     int32_t lo = 0, hi = 0;
     LevelProbe lp{};
     const bool cand = hss_candidates(descs.data() + a, e - a, o, &lo, &hi);
@@ -803,6 +891,11 @@ int phdc_release(void* work) {
     hipEventSynchronize(w.probe.done);
     hipEventDestroy(w.probe.done);
   }
+  for (hipEvent_t ev : {w.fill_fork, w.fill_join})
+    if (ev) {
+      hipEventSynchronize(ev);
+      hipEventDestroy(ev);
+    }
   g_state.erase(it);
   return 0;
 }
@@ -1080,6 +1173,9 @@ int phdc_merge_table(const void* work, int64_t max_rows, int32_t* table_host, in
     r[13] = c[i * kCounters + C_DROWS_LO];
     r[14] = c[i * kCounters + C_DROWS_HI];
     r[15] = d[i].root;
+    r[16] = (d[i].flags & kFlagPrefilled) ? 1 : 0;
+    r[17] = c[i * kCounters + C_WROWS];
+    r[18] = c[i * kCounters + C_WROWS + 1];
   }
   return 0;
 }

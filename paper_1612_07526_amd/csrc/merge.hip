@@ -589,6 +589,8 @@ __device__ void deflate_body(const MergeDesc& M, const Scratch& S, int lds_cap, 
     cnt[C_DP3] = dp3;
     cnt[C_PATH] = M.split_on ? 1 : (M.hss_min_k > 0 && K >= M.hss_min_k) ? 2 : 0;
     cnt[C_HSSRANK] = 0;
+    cnt[C_WROWS] = 0;
+    cnt[C_WROWS + 1] = 0;
   }
 }
 
@@ -1073,7 +1075,7 @@ __device__ void uwrite_body(const BlockMap& bm, const Scratch& S, int b, bool no
 constexpr int kSmallUhat = 64;
 constexpr int kStageSmallThreads = 1024;
 
-__device__ void rank_item(const MergeDesc& M, const Scratch& S, int x);
+__device__ int rank_item(const MergeDesc& M, const Scratch& S, int x);
 
 template <int NT, int G>
 __device__ void small_body(const MergeDesc& M, const Scratch& S, bool normalized, double* sd, double* sz) {
@@ -1132,7 +1134,9 @@ __device__ void small_body(const MergeDesc& M, const Scratch& S, bool normalized
 // index).  Roots and type-1 values are each non-decreasing (binary search);
 // type-2 values are counted directly.
 // Item x of merge M (x < M.m).
-__device__ void rank_item(const MergeDesc& M, const Scratch& S, int x) {
+// Returns, for a deflated column of a prefilled root, the rows its copy
+// writes (its destination's half and the part of its range outside it), else 0.
+__device__ int rank_item(const MergeDesc& M, const Scratch& S, int x) {
   const int32_t* cnt = S.counters + (int64_t)M.id * kCounters;
   const int K = cnt[C_K], nd1 = cnt[C_ND1], nd2 = cnt[C_ND2];
   const int64_t so = M.s_off;
@@ -1169,11 +1173,12 @@ __device__ void rank_item(const MergeDesc& M, const Scratch& S, int x) {
   if (cls == 0) S.dest[so + idx] = r;
   else if (cls == 1) S.destd1[so + idx] = r;
   else S.destd2[so + idx] = r;
-  if (M.rout) {  // roots fill every row of the block; deflated columns keep their range
-    RowRange g{0, M.m};
-    if (cls > 0) g = S.crng[so + (cls == 1 ? S.dfc1[so + idx] : S.dfc2[so + idx])];
-    M.rout[r] = RowRange{g.lo + M.r0, g.hi + M.r0};
-  }
+  RowRange g{0, M.m};  // roots fill every row of the block; deflated columns keep their range
+  if (cls > 0) g = S.crng[so + (cls == 1 ? S.dfc1[so + idx] : S.dfc2[so + idx])];
+  if (M.rout) M.rout[r] = RowRange{g.lo + M.r0, g.hi + M.r0};
+  if (cls == 0 || !(M.flags & kFlagPrefilled)) return 0;
+  const int bl = r < M.n1 ? 0 : M.n1, bh = r < M.n1 ? M.n1 : M.m;
+  return (bh - bl) + max(0, min(g.hi, bl) - g.lo) + max(0, g.hi - max(g.lo, bh));
 }
 
 __device__ void rank_body(const BlockMap& bm, const Scratch& S, int b) {
@@ -1181,7 +1186,12 @@ __device__ void rank_body(const BlockMap& bm, const Scratch& S, int b) {
   const int lb = b - merge_first_block(bm, mi);
   const MergeDesc M = bm.descs[mi];
   const int x = lb * 256 + threadIdx.x;
-  if (x < M.m) rank_item(M, S, x);
+  unsigned long long w = (x < M.m) ? (unsigned long long)rank_item(M, S, x) : 0ULL;
+  if (M.flags & kFlagPrefilled) {  // (block-uniform) one atomic per wave
+    for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o, 64);
+    if ((threadIdx.x & 63) == 0 && w)
+      atomicAdd((unsigned long long*)(S.counters + (int64_t)M.id * kCounters + C_WROWS), w);
+  }
 }
 
 // ------------------------------------------------------------ deflated columns
@@ -1202,6 +1212,43 @@ __device__ inline int copy_rpt(int m) {
   return rpt;
 }
 
+// Rows [x, y) of an output column, val(r) each: 16-byte nontemporal stores on
+// the row pairs aligned to 16 bytes in memory, a scalar store at an unaligned
+// end.  Lanes lane, lane + step, ... take the pairs; on a wavefront's short
+// columns (!wide) four pairs per lane are read before any is written.
+template <class V>
+__device__ __forceinline__ void put_rows(double* out, int x, int y, int lane, int step, bool wide, V val) {
+  typedef double d2_t __attribute__((ext_vector_type(2)));
+  if (x >= y) return;
+  const int a = (int)(((uintptr_t)out >> 3) & 1);  // rows a, a + 2, ... start 16-byte pairs
+  const int p0 = (x - a + 1) >> 1, p1 = (y - a) >> 1;
+  if (lane == 0) {
+    if (x < a + 2 * p0) out[x] = val(x);
+    if (a + 2 * p1 < y) out[y - 1] = val(y - 1);
+  }
+  d2_t* o2 = (d2_t*)(out + a);
+  if (wide) {  // (long columns: this streaming loop keeps the memory system busy by itself)
+#pragma unroll 4
+    for (int p = p0 + lane; p < p1; p += step) {
+      const int r = a + 2 * p;
+      __builtin_nontemporal_store(d2_t{val(r), val(r + 1)}, &o2[p]);
+    }
+  } else {
+    constexpr int U = 4;
+    for (int pb = p0 + lane; pb < p1; pb += U * step) {
+      d2_t v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int r = a + 2 * (pb + u * step);
+        v[u] = (pb + u * step < p1) ? d2_t{val(r), val(r + 1)} : d2_t{0.0, 0.0};
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (pb + u * step < p1) __builtin_nontemporal_store(v[u], &o2[pb + u * step]);
+    }
+  }
+}
+
 __device__ void copy_body(const BlockMap& bm, const Scratch& S, int b) {
   const int mi = find_merge(bm, b);
   const int lb = b - merge_first_block(bm, mi);
@@ -1212,42 +1259,19 @@ __device__ void copy_body(const BlockMap& bm, const Scratch& S, int b) {
   const int nd1 = cnt[C_ND1], nd = nd1 + cnt[C_ND2];
   const int64_t so = M.s_off;
   if (M.root) {
-    // The caller's Q: every row is written.  A whole block per column (a wave
-    // per column below kCopyWideRows rows), rows in pairs with 16-byte
-    // nontemporal stores (nothing here reads Q again, so the lines need not
-    // stay in the caches), a scalar first row when the column starts at an odd
-    // 8-byte offset, a scalar last row when the rest is odd.  On the short
-    // columns of a wave, up to 4 row pairs per lane are read before any is
-    // written, and the next column's list entry and destination are read while
-    // the current one is in flight.
-    typedef double d2_t __attribute__((ext_vector_type(2)));
-    if (m >= kCopyWideRows) {
-      for (int q = lb; q < nd; q += G) {
-        int c, dst;
-        if (q < nd1) { c = S.dfc1[so + q]; dst = S.destd1[so + q]; }
-        else { const int q2 = q - nd1; c = S.dfc2[so + q2]; dst = S.destd2[so + q2]; }
-        const RowRange g = S.crng[so + c];
-        const double* src = M.qin + (int64_t)c * M.ldin;
-        double* out = M.qout + (int64_t)dst * M.ldout;
-        const int a = (int)(((uintptr_t)out >> 3) & 1);
-        const int np = (m - a) >> 1;
-        auto val = [&](int r) { return (r >= g.lo && r < g.hi) ? src[r] : 0.0; };
-        if (threadIdx.x == 0) {
-          if (a) out[0] = val(0);
-          if ((m - a) & 1) out[m - 1] = val(m - 1);
-        }
-        d2_t* o2 = (d2_t*)(out + a);
-#pragma unroll 4
-        for (int p = threadIdx.x; p < np; p += 256) {
-          const int r = a + 2 * p;
-          __builtin_nontemporal_store(d2_t{val(r), val(r + 1)}, &o2[p]);
-        }
-      }
-      return;
-    }
-    constexpr int U = 4;
-    const int lane = threadIdx.x & 63;
-    const int q0 = lb * 4 + (threadIdx.x >> 6), qs = G * 4;
+    // The caller's Q: every row is written -- rows [0, m), or, when the
+    // off-diagonal quadrants were zero-filled beforehand, the rows of the
+    // destination column's half and of the column's range.  A
+    // whole block per column (a wave per column below kCopyWideRows rows),
+    // rows in pairs with 16-byte nontemporal stores (nothing here reads Q
+    // again, so the lines need not stay in the caches).  On the short columns
+    // of a wave, up to 4 row pairs per lane are read before any is written,
+    // and the next column's list entry and destination are read while the
+    // current one is in flight.
+    const bool wide = m >= kCopyWideRows;
+    const bool pre = (M.flags & kFlagPrefilled) != 0;
+    const int lane = wide ? threadIdx.x : (threadIdx.x & 63), step = wide ? 256 : 64;
+    const int q0 = wide ? lb : lb * 4 + (threadIdx.x >> 6), qs = wide ? G : G * 4;
     auto entry = [&](int q, int& c, int& dst) {
       if (q < nd1) { c = S.dfc1[so + q]; dst = S.destd1[so + q]; }
       else { const int q2 = q - nd1; c = S.dfc2[so + q2]; dst = S.destd2[so + q2]; }
@@ -1257,27 +1281,24 @@ __device__ void copy_body(const BlockMap& bm, const Scratch& S, int b) {
     for (int q = q0; q < nd; q += qs) {
       const RowRange g = S.crng[so + c];
       int cn = 0, dn = 0;
-      if (q + qs < nd) entry(q + qs, cn, dn);
+      if (!wide && q + qs < nd) entry(q + qs, cn, dn);
       const double* src = M.qin + (int64_t)c * M.ldin;
       double* out = M.qout + (int64_t)dst * M.ldout;
-      const int a = (int)(((uintptr_t)out >> 3) & 1);
-      const int np = (m - a) >> 1;
       auto val = [&](int r) { return (r >= g.lo && r < g.hi) ? src[r] : 0.0; };
-      if (lane == 0) {
-        if (a) out[0] = val(0);
-        if ((m - a) & 1) out[m - 1] = val(m - 1);
+      // row intervals: [0, m); or the half [bl, bh) of the destination and the
+      // part of the range outside it
+      int bl = 0, bh = m;
+      if (pre) {
+        bl = dst < M.n1 ? 0 : M.n1;
+        bh = dst < M.n1 ? M.n1 : m;
       }
-      d2_t* o2 = (d2_t*)(out + a);
-      for (int p0 = lane; p0 < np; p0 += U * 64) {
-        d2_t v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int r = a + 2 * (p0 + u * 64);
-          v[u] = (p0 + u * 64 < np) ? d2_t{val(r), val(r + 1)} : d2_t{0.0, 0.0};
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-          if (p0 + u * 64 < np) __builtin_nontemporal_store(v[u], &o2[p0 + u * 64]);
+      for (int k = 0; k < (pre ? 3 : 1); ++k) {
+        const int x = k == 0 ? bl : k == 1 ? g.lo : max(g.lo, bh);
+        const int y = k == 0 ? bh : k == 1 ? min(g.hi, bl) : g.hi;
+        put_rows(out, x, y, lane, step, wide, val);
+      }
+      if (wide) {
+        if (q + qs < nd) entry(q + qs, cn, dn);
       }
       c = cn;
       dst = dn;
@@ -1349,6 +1370,38 @@ int map_blocks(int kind, int m, int n1, int gt, bool root, bool small, int nm) {
   return 0;
 }
 
+
+// Zero fill of the off-diagonal quadrants of the caller's Q (FillDesc): column
+// c < k gets zeros in rows [k, n), column c >= k in rows [0, k).  A block per
+// column (wide) or a wave per column; cpfx: prefix of the column counts of the
+// nd matrices.
+__global__ void __launch_bounds__(256) k_fill_offblocks(const FillDesc* __restrict__ fd,
+                                                        const int32_t* __restrict__ cpfx, int nd, int total,
+                                                        int wide) {
+  const int first = wide ? (int)blockIdx.x : (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+  const int stride = wide ? (int)gridDim.x : (int)gridDim.x * 4;
+  const int lane = wide ? (int)threadIdx.x : (int)(threadIdx.x & 63), step = wide ? 256 : 64;
+  auto zero = [](int) { return 0.0; };
+  for (int col = first; col < total; col += stride) {  // (uniform per wave or block)
+    int lo = 0, hi = nd - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (cpfx[mid] <= col) lo = mid; else hi = mid - 1;
+    }
+    const FillDesc F = fd[lo];
+    const int c = col - cpfx[lo];
+    double* out = F.q + (int64_t)c * F.ld;
+    if (c < F.k) put_rows(out, F.k, F.n, lane, step, wide != 0, zero);
+    else put_rows(out, 0, F.k, lane, step, wide != 0, zero);
+  }
+}
+
+void launch_fill_offblocks(const FillDesc* fd, const int32_t* cpfx, int nd, int total, bool wide, int max_blocks,
+                           hipStream_t s) {
+  if (nd <= 0 || total <= 0) return;
+  const int blocks = std::max(1, std::min(max_blocks, wide ? total : (total + 3) / 4));
+  hipLaunchKernelGGL(k_fill_offblocks, dim3(blocks), dim3(256), 0, s, fd, cpfx, nd, total, wide ? 1 : 0);
+}
 
 __global__ void __launch_bounds__(256) k_copy_ints(const int32_t* __restrict__ src, int32_t* dst, int n) {
   const int i = blockIdx.x * 256 + threadIdx.x;

@@ -12,14 +12,15 @@ constexpr double kUnitRoundoff = 1.1102230246251565e-16;  // 2^-53
 constexpr int kMaxLeaf = 64;
 constexpr int kHssLeafMax = 1024;    // largest HSS leaf (rows of one interpolative decomposition)
 constexpr int kSplitMaxSlices = 7;   // BF16 slices per operand on the split-precision path
-constexpr int kCounters = 18;  // per-merge int32 counters
+constexpr int kCounters = 20;  // per-merge int32 counters
 
 // Counter slots (per merge).
 enum : int {
   C_K = 0, C_K1 = 1, C_K2 = 2, C_K3 = 3, C_NT1 = 4, C_NT2 = 5, C_PATH = 6, C_HSSRANK = 7,
   C_NROT = 8, C_NCHAIN = 9, C_ND1 = 10, C_ND2 = 11,
   C_DP1 = 12, C_DP2 = 13, C_DP3 = 14,  // deflated columns nonzero in the Q1 half only / both / the Q2 half only
-  C_DROWS_LO = 15, C_DROWS_HI = 16     // sum over deflated columns of the rows in their range (64 bits)
+  C_DROWS_LO = 15, C_DROWS_HI = 16,    // sum over deflated columns of the rows in their range (64 bits)
+  C_WROWS = 18                         // prefilled root: rows the deflated-column copy writes (uint64 at 18..19)
 };
 
 // Rows [lo, hi) of an eigenvector column that can be nonzero; rows outside
@@ -54,6 +55,16 @@ struct MergeDesc {
   RowRange* rout;       // output column ranges (nullptr: not recorded)
   int32_t r0;           // first row (= first column) of the merge block within the matrix
   int32_t root;         // 1: last merge of its matrix (every output entry is written, zeros included)
+};
+
+// One matrix whose caller-side eigenvector matrix is zero-filled in its two
+// off-diagonal quadrants (rows of one half of the split, columns of the other)
+// while the tree below runs: those entries are written only by the root merge,
+// and there they are zeros unless a deflated column's range reaches them.
+struct FillDesc {
+  double* q;  // the matrix's Q (column-major)
+  int64_t ld;
+  int32_t n, k;  // size and first half (the root's n1)
 };
 
 // One leaf solve (one wavefront).
@@ -156,6 +167,9 @@ constexpr int32_t kFlagNoSecularIters = 1;  // secular roots get no iterations (
 constexpr int32_t kFlagSmallMerge = 2;      // the whole merge runs in one workgroup (k_merge_small)
 constexpr int32_t kFlagPrepDeflate = 4;     // deflation's element-wise first steps run in k_deflate_prep
 constexpr int kDefPrepRows = 2048;          // merges from this size take kFlagPrepDeflate
+constexpr int32_t kFlagPrefilled = 8;       // root: Q's off-diagonal quadrants are already zero
+constexpr int kFillMinRows = 256;           // roots from this size take the off-block zero fill
+constexpr int kFillWideRows = 2048;         // matrices from this size fill a column per block (else per wave)
 // Merges of at most this many rows on the FP64 path run in one workgroup each.
 constexpr int kSmallMergeMax = 64;
 
@@ -218,6 +232,15 @@ struct SplitBufs;
 void launch_merge_level(const MergeDesc* descs, int nm, const LevelMaps& maps, const Scratch& S,
                         int gemm_mode, const SplitBufs* split, int nsl, hipStream_t s,
                         const LevelProbe* probe = nullptr);
+// Zero-fill the off-diagonal quadrants of the Q of nd matrices (cpfx: prefix of
+// their column counts, total = cpfx[nd]); wide: a block per column, else a wave
+// per column; at most max_blocks workgroups, looping over the columns.
+void launch_fill_offblocks(const FillDesc* fd, const int32_t* cpfx, int nd, int total, bool wide, int max_blocks,
+                           hipStream_t s);
+// Workgroup caps of the fill (a block per column / a wave per column): they set
+// how much bandwidth it takes from the latency-bound levels it runs beside.
+constexpr int kFillBlocksWide = 128;
+constexpr int kFillBlocksNarrow = 512;
 void launch_secular_standalone(int64_t K, const double* d, const double* z, double rho, int32_t* org,
                                double* tau, int32_t* status, hipStream_t s);
 
