@@ -6,7 +6,10 @@
 // height 0, a merge one more than its taller child) and each height is one
 // batched launch per kernel.  A node at depth t writes its eigenvectors to the
 // caller's buffers when t is even and to the workspace twin when t is odd, so
-// a merge always reads its children from the other buffer than it writes.
+// a merge always reads its children from the other buffer than it writes --
+// except that a matrix whose root is zero-filled ahead of time (see run_solve)
+// keeps the eigenvectors of its even depths below the root in a third
+// workspace buffer, so that nothing but the root writes the caller's Q.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -77,6 +80,7 @@ Tree build_tree(const std::vector<int64_t>& n, int leaf) {
 struct Sizes {
   int64_t n_total = 0;     // rows over all matrices (scratch arrays)
   int64_t q_total = 0;     // elements of the eigenvector twin buffer
+  int64_t q3_total = 0;    // elements of the third eigenvector buffer (zero-filled roots' even depths)
   int64_t nmerges = 0, nleaves = 0, nmats = 0;
   int64_t uhat = 0;        // elements of the Uhat arena
   int64_t map_ints = 0;    // block-map prefix entries
@@ -89,7 +93,7 @@ struct Sizes {
 
 struct Layout {
   size_t status, hdr, counters, mparam, descs, leaves, canon, canon_pfx, maps, fill, fill_pfx, scratch, uhat, qtwin,
-      ltwin, ranges, hss, hss_desc, sa, sb, serow, sfcol, total;
+      ltwin, ranges, hss, hss_desc, sa, sb, serow, sfcol, qthird, total;
 };
 
 constexpr int kScratchD = 17, kScratchI = 18;  // 8-byte arrays (doubles, row ranges), int32 arrays
@@ -173,6 +177,7 @@ Layout layout_of(const Sizes& z) {
   L.sb = take((size_t)z.nsl * z.xslots * 2);
   L.serow = take(z.nsl ? (size_t)z.n_total * 4 : 0);
   L.sfcol = take(z.nsl ? (size_t)z.n_total * 4 : 0);
+  L.qthird = take((size_t)z.q3_total * 8);
   L.total = p;
   return L;
 }
@@ -240,24 +245,21 @@ struct Probe {
 struct WorkState {
   Staging plan, hss;
   Probe probe;
-  hipEvent_t fill_fork = nullptr, fill_join = nullptr;  // the off-block fill's second stream
+  hipEvent_t fill_fork = nullptr, fill_join = nullptr;  // the zero fill's second stream
 };
 std::mutex g_mu;
 std::unordered_map<const void*, WorkState> g_state;
 
-// Fork/join events of the off-block fill of a workspace (created once; false
-// if they cannot be).
+// Fork/join events of the zero fill of a workspace (created once; false if
+// they cannot be).
 bool fill_events(const void* work, hipEvent_t* fork, hipEvent_t* join) {
   std::lock_guard<std::mutex> lk(g_mu);
   WorkState& w = g_state[work];
-  if (!w.fill_fork && hipEventCreateWithFlags(&w.fill_fork, hipEventDisableTiming) != hipSuccess) {
-    w.fill_fork = nullptr;
-    return false;
-  }
-  if (!w.fill_join && hipEventCreateWithFlags(&w.fill_join, hipEventDisableTiming) != hipSuccess) {
-    w.fill_join = nullptr;
-    return false;
-  }
+  for (hipEvent_t* ev : {&w.fill_fork, &w.fill_join})
+    if (!*ev && hipEventCreateWithFlags(ev, hipEventDisableTiming) != hipSuccess) {
+      *ev = nullptr;
+      return false;
+    }
   *fork = w.fill_fork;
   *join = w.fill_join;
   return true;
@@ -316,12 +318,33 @@ struct Setup {
   Tree T;
   Sizes z;
   Layout L;
+  std::vector<int64_t> q3off;  // per matrix: its offset in the third eigenvector buffer, or -1
 };
 
-Setup setup_for(const std::vector<int64_t>& n, int64_t q_total, const phdc_opts* o) {
+// The third eigenvector buffer of an m-row matrix: the blocks of its two
+// depth-1 nodes (first half floor(m/2) rows), one after the other, each with
+// its own leading dimension.
+int64_t third_elems(int64_t m) {
+  const int64_t m1 = m / 2;
+  return m1 * m1 + (m - m1) * (m - m1);
+}
+
+// fill: roots of kFillMinRows to kFillWideRows - 1 rows in the last level are
+// zero-filled ahead of time (their matrices take the third buffer); off for
+// the allocation-free entry point, whose static workspace is sized without it.
+Setup setup_for(const std::vector<int64_t>& n, int64_t q_total, const phdc_opts* o, bool fill = true) {
   Setup S;
   S.T = build_tree(n, o->leaf_size);
   S.z = sizes_of(S.T, n, q_total, o);
+  S.q3off.assign(n.size(), -1);
+  const int H = S.z.H;
+  if (fill && H >= 1)
+    for (int i = S.T.hstart[H - 1]; i < S.T.hstart[H]; ++i) {
+      const Node& nd = S.T.merges[i];
+      if (nd.depth != 0 || nd.m < kFillMinRows || nd.m >= kFillWideRows) continue;
+      S.q3off[nd.b] = S.z.q3_total;
+      S.z.q3_total += third_elems(nd.m);
+    }
   S.L = layout_of(S.z);
   return S;
 }
@@ -335,7 +358,27 @@ struct Buffers {
   RowRange* rng[2];                      // column ranges of q[0], q[1] (indexed like lam)
   std::vector<int64_t> off, eoff, qoff;  // per matrix
   std::vector<int64_t> ld[2];            // per matrix
+  double* q3 = nullptr;                  // third eigenvector buffer
+  std::vector<int64_t> q3off;            // per matrix (Setup::q3off)
 };
+
+// Eigenvector block of the node of matrix b (mb rows) at depth t whose rows
+// start at r0, and its leading dimension: the caller's Q at even depth, the
+// twin at odd depth, or, for the even depths below a zero-filled root, the
+// third buffer (inside the block of the depth-1 node the rows belong to,
+// blocks of one depth on that block's diagonal like everywhere else).
+double* qblock(const Buffers& BF, int64_t b, int64_t mb, int t, int64_t r0, int64_t* ld) {
+  if (t >= 2 && (t & 1) == 0 && BF.q3off[b] >= 0) {
+    const int64_t m1 = mb / 2;
+    const bool second = r0 >= m1;
+    const int64_t w = second ? mb - m1 : m1, x = second ? r0 - m1 : r0;
+    *ld = w;
+    return BF.q3 + BF.q3off[b] + (second ? m1 * m1 : 0) + x + x * w;
+  }
+  const int p = t & 1;
+  *ld = BF.ld[p][b];
+  return BF.q[p] + BF.qoff[b] + r0 + r0 * *ld;
+}
 
 
 // The level's merges that may take the HSS path (m >= hss_min_K), as the id
@@ -437,9 +480,10 @@ void forget_prepared(const void* work) {
 
 int leaf_iters(const phdc_opts* o) { return (o->force_fail & PHDC_FAIL_LEAF) ? 0 : kLeafMaxIters; }
 
-// Start the off-block fill: on the auxiliary stream after what s has queued
-// (returns true: s must wait for *join before the last level), or on s itself
-// when no second stream or event is available.
+// Start the zero fill: on the auxiliary stream after what s has queued, its
+// completion recorded in *join (returns true: the last level waits for *join
+// before writing output blocks), or on s itself when no second stream or event
+// is available (returns false).
 bool start_fill(char* base, const Prepared& P, hipStream_t s, hipEvent_t* join) {
   if (P.nfill <= 0) return false;
   const FillDesc* fd = (const FillDesc*)(base + P.L.fill);
@@ -451,12 +495,25 @@ bool start_fill(char* base, const Prepared& P, hipStream_t s, hipEvent_t* join) 
   hipStream_t fs = forked ? a : s;
   {
     ProfScope p(PH_FILL, fs);
-    launch_fill_offblocks(fd, pfx, P.nfill_wide, P.fill_cols_wide, true, kFillBlocksWide, fs);
-    launch_fill_offblocks(fd + P.nfill_wide, pfx + P.nfill_wide + 1, P.nfill - P.nfill_wide,
-                          P.fill_cols - P.fill_cols_wide, false, kFillBlocksNarrow, fs);
+    launch_fill_zero(fd, pfx, P.nfill_wide, P.fill_cols_wide, true, kFillBlocksWide, fs);
+    launch_fill_zero(fd + P.nfill_wide, pfx + P.nfill_wide + 1, P.nfill - P.nfill_wide,
+                     P.fill_cols - P.fill_cols_wide, false, kFillBlocksNarrow, fs);
   }
   return forked && hipEventRecord(*join, a) == hipSuccess;
 }
+
+// The zero fill around the levels of a solve: it starts before level
+// P.fill_level, and the last level waits for it before writing output blocks.
+struct FillRun {
+  hipEvent_t join = nullptr;
+  bool joined = false;
+  // before launching level h; returns the level's qout_ready event
+  hipEvent_t before_level(char* base, const Prepared& P, hipStream_t s, int h) {
+    if (P.nfill <= 0) return nullptr;
+    if (h == P.fill_level) joined = start_fill(base, P, s, &join);
+    return h == P.z.H && joined ? join : nullptr;
+  }
+};
 
 // Launch every kernel of a prepared solve: no host synchronisation, no memcpy,
 // no memset -- safe to capture in a HIP graph and replay.
@@ -470,14 +527,12 @@ void launch_prepared_all(char* base, const Prepared& P, hipStream_t s) {
     ProfScope p(PH_LEAF, s);
     launch_leaf_ql((const LeafArgs*)(base + P.L.leaves), P.nleaves, P.S.status, P.o.leaf_size, leaf_iters(&P.o), s);
   }
-  hipEvent_t join = nullptr;
-  bool joined = false;
+  FillRun fill;
   const MergeDesc* dd = (const MergeDesc*)(base + P.L.descs);
   for (int h = 1; h <= P.z.H; ++h) {
     const int a = P.hstart[h - 1], e = P.hstart[h];
-    if (h == P.fill_level) joined = start_fill(base, P, s, &join);
-    if (h == P.z.H && joined) hipStreamWaitEvent(s, join, 0);
-    launch_merge_level(dd + a, e - a, P.lm[h], P.S, P.o.gemm_mode, &P.SB, P.z.nsl, s);
+    const hipEvent_t ready = fill.before_level(base, P, s, h);
+    launch_merge_level(dd + a, e - a, P.lm[h], P.S, P.o.gemm_mode, &P.SB, P.z.nsl, s, nullptr, ready);
   }
   if (P.o.canonical_sign && P.ncols > 0) {
     ProfScope p(PH_CANON, s);
@@ -523,10 +578,8 @@ int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n,
     MergeDesc& D = descs[i];
     std::memset(&D, 0, sizeof(D));
     const int64_t b = nd.b;
-    D.ldin = BF.ld[pin][b];
-    D.ldout = BF.ld[pout][b];
-    D.qin = BF.q[pin] + BF.qoff[b] + nd.r0 + nd.r0 * D.ldin;
-    D.qout = BF.q[pout] + BF.qoff[b] + nd.r0 + nd.r0 * D.ldout;
+    D.qin = qblock(BF, b, n[b], nd.depth + 1, nd.r0, &D.ldin);
+    D.qout = qblock(BF, b, n[b], nd.depth, nd.r0, &D.ldout);
     D.lin = BF.lam[pin] + BF.off[b] + nd.r0;
     D.lout = BF.lam[pout] + BF.off[b] + nd.r0;
     D.zgiven = nullptr;
@@ -548,12 +601,17 @@ int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n,
     D.r0 = (int32_t)nd.r0;
     D.root = nd.depth == 0 ? 1 : 0;
   }
-  // Roots in the last level: the caller's Q in the off-diagonal quadrants of
-  // such a root (rows of one half, columns of the other) is only ever written
-  // by the root itself -- every merge below writes and rotates in place only
-  // inside its own diagonal block -- so it is zero-filled on a second stream
-  // while the tree runs, and the root copy then writes only the rows of each
-  // column's half and range.  Wide matrices first, then narrow ones.
+  // Roots in the last level, zero-filled on a second stream while the tree
+  // below runs.  A root with a third buffer (Setup::q3off; below
+  // kFillWideRows rows): nothing but the root writes the caller's Q of its
+  // matrix, so the whole Q is filled and the root's copy of its deflated
+  // columns writes only the rows of each column's range.  A larger root: its
+  // off-diagonal quadrants (rows of one half, columns of the other), which
+  // every merge below leaves alone (they write and rotate in place only inside
+  // their own diagonal blocks); the copy then writes the rows of each
+  // column's half and range.  (Filling the whole of a large Q holds half the
+  // compute units for longer than the levels beside it can spare.)  Wide
+  // matrices first, then narrow ones.
   std::vector<FillDesc> fills;
   int nfw = 0;
   if (!no_alloc && z.H >= 1) {
@@ -562,8 +620,9 @@ int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n,
         const Node& nd = T.merges[i];
         if (nd.depth != 0 || nd.m < kFillMinRows) continue;
         if ((nd.m >= kFillWideRows) != (pass == 0)) continue;
-        descs[i].flags |= kFlagPrefilled;
-        fills.push_back(FillDesc{BF.q[0] + BF.qoff[nd.b], BF.ld[0][nd.b], nd.m, nd.n1});
+        const bool full = BF.q3off[nd.b] >= 0;
+        descs[i].flags |= full ? kFlagPrefilled : kFlagQuadFilled;
+        fills.push_back(FillDesc{BF.q[0] + BF.qoff[nd.b], BF.ld[0][nd.b], nd.m, full ? 0 : nd.n1});
         if (pass == 0) ++nfw;
       }
   }
@@ -585,8 +644,7 @@ int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n,
     std::memset(&A, 0, sizeof(A));
     A.d = BF.d + BF.off[b] + nd.r0;
     A.e = BF.e + BF.eoff[b] + nd.r0;
-    A.ldq = BF.ld[p][b];
-    A.q = BF.q[p] + BF.qoff[b] + nd.r0 + nd.r0 * A.ldq;
+    A.q = qblock(BF, b, n[b], nd.depth, nd.r0, &A.ldq);
     A.lam = BF.lam[p] + BF.off[b] + nd.r0;
     A.s = nd.m;
     A.couple = (nd.r0 > 0 ? 1 : 0) | (nd.r0 + nd.m < n[b] ? 2 : 0);
@@ -684,8 +742,7 @@ int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n,
   // HSS: the host reads K back after each level that has eligible merges
   launch_clear_status(S.status, s);
   if (upload(work, base + plan0, plan, s) != 0) return PHDC_E_HIP;
-  hipEvent_t join = nullptr;
-  bool joined = false;
+  FillRun fill;
   {
     ProfScope p(PH_LEAF, s);
     launch_leaf_ql((const LeafArgs*)(base + L.leaves), (int)T.leaves.size(), S.status, o->leaf_size, leaf_iters(o),
@@ -694,13 +751,12 @@ int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n,
   const MergeDesc* dd = (const MergeDesc*)(base + L.descs);
   for (int h = 1; h <= z.H; ++h) {
     const int a = T.hstart[h - 1], e = T.hstart[h];
-    if (h == P.fill_level) joined = start_fill(base, P, s, &join);
-    if (h == z.H && joined) hipStreamWaitEvent(s, join, 0);
+    const hipEvent_t ready = fill.before_level(base, P, s, h);
     int32_t lo = 0, hi = 0;
     LevelProbe lp{};
     const bool cand = hss_candidates(descs.data() + a, e - a, o, &lo, &hi);
     if (cand && make_probe(work, S, lo, hi, &lp) != 0) return PHDC_E_HIP;
-    launch_merge_level(dd + a, e - a, lm[h], S, o->gemm_mode, &SB, z.nsl, s, cand ? &lp : nullptr);
+    launch_merge_level(dd + a, e - a, lm[h], S, o->gemm_mode, &SB, z.nsl, s, cand ? &lp : nullptr, ready);
     if (!cand) continue;
     int rc = run_hss_level(descs.data() + a, dd + a, e - a, S, base + L.hss, L.hss_desc - L.hss, base + L.hss_desc,
                            z.hss_desc, o, s, work, &lp);
@@ -761,6 +817,14 @@ void phdc_opts_default(phdc_opts* o) {
 
 int phdc_version(void) { return 1; }
 
+}  // extern "C"
+
+size_t phdc::stedc_workspace_bytes(int64_t n, const phdc_opts* o, bool fill) {
+  return setup_for({n}, n * n, o, fill).L.total;
+}
+
+extern "C" {
+
 int phdc_stedc_workspace(int64_t n, const phdc_opts* o, size_t* bytes) {
   phdc_opts def;
   if (!o) { phdc_opts_default(&def); o = &def; }
@@ -793,7 +857,7 @@ int phdc::stedc_impl(int64_t n, const double* d, const double* e, double* lambda
   if (!work) return -7;
   if (!opts_ok(o)) return -9;
   if (n > (int64_t)1 << 30) return -1;
-  Setup SU = setup_for({n}, n * n, o);
+  Setup SU = setup_for({n}, n * n, o, !no_alloc);
   if (lwork < SU.L.total) return -8;
   if (((uintptr_t)work & (kAlign - 1)) != 0) return -7;
   if (n == 0) {
@@ -822,6 +886,8 @@ int phdc::stedc_impl(int64_t n, const double* d, const double* e, double* lambda
   BF.qoff = {0};
   BF.ld[0] = {ldq};
   BF.ld[1] = {n};
+  BF.q3 = (double*)(base + SU.L.qthird);
+  BF.q3off = SU.q3off;
   return run_solve(SU, BF, {n}, work, o, stream, false, no_alloc);
 }
 
@@ -960,6 +1026,8 @@ static int stedc_batched_impl(int64_t B, const int64_t* n_host, const int64_t* o
   }
   BF.ld[0] = n;
   BF.ld[1] = n;
+  BF.q3 = (double*)(base + SU.L.qthird);
+  BF.q3off = SU.q3off;
   return run_solve(SU, BF, n, work, o, (hipStream_t)stream, prepare_only);
 }
 
@@ -1173,7 +1241,7 @@ int phdc_merge_table(const void* work, int64_t max_rows, int32_t* table_host, in
     r[13] = c[i * kCounters + C_DROWS_LO];
     r[14] = c[i * kCounters + C_DROWS_HI];
     r[15] = d[i].root;
-    r[16] = (d[i].flags & kFlagPrefilled) ? 1 : 0;
+    r[16] = (d[i].flags & kFlagPrefilled) ? 2 : (d[i].flags & kFlagQuadFilled) ? 1 : 0;
     r[17] = c[i * kCounters + C_WROWS];
     r[18] = c[i * kCounters + C_WROWS + 1];
   }

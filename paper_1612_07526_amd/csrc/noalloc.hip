@@ -54,8 +54,9 @@ extern "C" int phdc_stedc_noalloc(int64_t n, const double* d, const double* e, d
   if (!info) return -7;
   if (o->gemm_mode == PHDC_GEMM_HSS) return -8;  // the HSS path uses pinned host memory
   size_t need = 0;
-  const int rc = phdc_stedc_workspace(n, o, &need);
+  const int rc = phdc_stedc_workspace(n, o, &need);  // (argument check)
   if (rc != 0) return rc == -2 ? -8 : -1;
+  need = stedc_workspace_bytes(n, o, false);  // this path takes no zero fill, hence no third buffer
   if (need > PHDC_NOALLOC_SCRATCH_BYTES) return -1;  // too large for the static workspace
   void* work = scratch_for_current_device();
   if (!work) return PHDC_E_HIP;

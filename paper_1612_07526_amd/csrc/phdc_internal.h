@@ -57,14 +57,16 @@ struct MergeDesc {
   int32_t root;         // 1: last merge of its matrix (every output entry is written, zeros included)
 };
 
-// One matrix whose caller-side eigenvector matrix is zero-filled in its two
-// off-diagonal quadrants (rows of one half of the split, columns of the other)
-// while the tree below runs: those entries are written only by the root merge,
-// and there they are zeros unless a deflated column's range reaches them.
+// One matrix whose caller-side eigenvector matrix is zero-filled, while the
+// tree below its root runs, before the root merge writes it: either the whole
+// matrix (k = 0; nothing below the root touches that Q: the even depths below
+// it use a workspace buffer of their own), or the two off-diagonal quadrants
+// (rows of one half of the split, columns of the other), which nothing below
+// the root touches either.
 struct FillDesc {
   double* q;  // the matrix's Q (column-major)
   int64_t ld;
-  int32_t n, k;  // size and first half (the root's n1)
+  int32_t n, k;  // size; 0, or the first half (the root's n1)
 };
 
 // One leaf solve (one wavefront).
@@ -167,11 +169,14 @@ constexpr int32_t kFlagNoSecularIters = 1;  // secular roots get no iterations (
 constexpr int32_t kFlagSmallMerge = 2;      // the whole merge runs in one workgroup (k_merge_small)
 constexpr int32_t kFlagPrepDeflate = 4;     // deflation's element-wise first steps run in k_deflate_prep
 constexpr int kDefPrepRows = 2048;          // merges from this size take kFlagPrepDeflate
-constexpr int32_t kFlagPrefilled = 8;       // root: Q's off-diagonal quadrants are already zero
-constexpr int kFillMinRows = 256;           // roots from this size take the off-block zero fill
+constexpr int32_t kFlagPrefilled = 8;       // root: the caller's Q was zero-filled beforehand
+constexpr int32_t kFlagQuadFilled = 16;     // root: only its off-diagonal quadrants were
+constexpr int32_t kFlagFilled = kFlagPrefilled | kFlagQuadFilled;
+constexpr int kFillMinRows = 256;           // roots from this size take the zero fill
 constexpr int kFillWideRows = 2048;         // matrices from this size fill a column per block (else per wave)
 // Merges of at most this many rows on the FP64 path run in one workgroup each.
 constexpr int kSmallMergeMax = 64;
+static_assert(kFillMinRows > kSmallMergeMax, "a zero-filled root is never a one-workgroup merge");
 
 // Kernel launchers (defined in the .hip files).  maxit: iteration cap per
 // eigenvalue of the leaf QL (0 under the PHDC_FAIL_LEAF test hook).
@@ -229,16 +234,21 @@ struct LevelProbe {
 };
 
 struct SplitBufs;
+// qout_ready: an event the level waits for before its first write of a
+// merge's output block (nullptr: none).
 void launch_merge_level(const MergeDesc* descs, int nm, const LevelMaps& maps, const Scratch& S,
                         int gemm_mode, const SplitBufs* split, int nsl, hipStream_t s,
-                        const LevelProbe* probe = nullptr);
-// Zero-fill the off-diagonal quadrants of the Q of nd matrices (cpfx: prefix of
-// their column counts, total = cpfx[nd]); wide: a block per column, else a wave
-// per column; at most max_blocks workgroups, looping over the columns.
-void launch_fill_offblocks(const FillDesc* fd, const int32_t* cpfx, int nd, int total, bool wide, int max_blocks,
-                           hipStream_t s);
-// Workgroup caps of the fill (a block per column / a wave per column): they set
-// how much bandwidth it takes from the latency-bound levels it runs beside.
+                        const LevelProbe* probe = nullptr, hipEvent_t qout_ready = nullptr);
+// Zero-fill the Q (or its off-diagonal quadrants, FillDesc) of nd matrices
+// (cpfx: prefix of their column counts, total = cpfx[nd]); wide: a block per
+// column, else a wave per column; at most max_blocks workgroups, looping over
+// the columns.
+void launch_fill_zero(const FillDesc* fd, const int32_t* cpfx, int nd, int total, bool wide, int max_blocks,
+                      hipStream_t s);
+// Workgroup size and caps of the fill (a block per column / a wave per
+// column): they set how many compute units it holds beside the levels it runs
+// with.
+constexpr int kFillThreads = 256;
 constexpr int kFillBlocksWide = 128;
 constexpr int kFillBlocksNarrow = 512;
 void launch_secular_standalone(int64_t K, const double* d, const double* z, double rho, int32_t* org,
@@ -248,6 +258,9 @@ void launch_secular_standalone(int64_t K, const double* d, const double* z, doub
 // pinned staging buffer), the call waits for it, and the HSS path is refused.
 int stedc_impl(int64_t n, const double* d, const double* e, double* lambda, double* Q, int64_t ldq, void* work,
                size_t lwork, const phdc_opts* o, hipStream_t s, bool no_alloc);
+// Workspace bytes of an n-row solve (o valid); fill: with the zero fill's third
+// eigenvector buffer (phdc_stedc), else without (no_alloc).
+size_t stedc_workspace_bytes(int64_t n, const phdc_opts* o, bool fill);
 
 // FP64 product for one merge whose HSS compression gave up (Sec. 2.2: Gu's
 // grouped products whenever HSS does not apply).  desc is the merge's device
