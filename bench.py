@@ -74,19 +74,17 @@ def algorithmic(table):
     copy_bytes: each deflated column read once over the rows it can be nonzero in and
                 written once over the same rows, or at the last merge of the matrix
                 (whose output is the caller's Q) over all m rows -- or, when that merge's
-                output was zero-filled beforehand, over the rows of its range only, or,
-                when its off-diagonal quadrants were, over the rows of its destination's
-                half and of its range -- 8 bytes per entry;
+                output was zero-filled beforehand, over the rows of its range only --
+                8 bytes per entry;
     root_copy_bytes: the same for the last merge only (the copy the library launches on
                 its own when a solve has a single root: the "copy" phase);
-    fill_bytes: 8 m^2 per last merge whose output was zero-filled, 16 n1 (m - n1) per
-                one whose off-diagonal quadrants were (the "fill" phase);
+    fill_bytes: 8 m^2 per last merge whose output was zero-filled (the "fill" phase);
     uhat_write_bytes: 8 K^2 bytes per merge.
     """
     t = table.astype(np.float64)
     m, n1, K, k1, k2, k3, nt1, nt2, path, root = (t[:, i] for i in (0, 1, 2, 3, 4, 5, 6, 7, 8, 15))
     rows = ((table[:, 13].astype(np.int64) & 0xFFFFFFFF) + (table[:, 14].astype(np.int64) << 32)).astype(np.float64)
-    pre, fmode = table[:, 16] > 0, table[:, 16]
+    pre = table[:, 16] > 0
     copied = ((table[:, 17].astype(np.int64) & 0xFFFFFFFF) + (table[:, 18].astype(np.int64) << 32)).astype(np.float64)
     n2 = m - n1
     plain = path == 0
@@ -96,7 +94,7 @@ def algorithmic(table):
         "gemm_flops": float(np.sum((2 * (n1 * (k1 + k2) + n2 * (k2 + k3)) * K)[plain])),
         "copy_bytes": float(np.sum(moved)),
         "root_copy_bytes": float(np.sum(moved[root > 0])),
-        "fill_bytes": float(np.sum(np.where(fmode == 2, 8 * m * m, np.where(fmode == 1, 16 * n1 * n2, 0)))),
+        "fill_bytes": float(np.sum((8 * m * m)[pre])),
         "uhat_write_bytes": float(np.sum(K * K * 8)),
     }
 

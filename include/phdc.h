@@ -229,11 +229,11 @@ int phdc_merge_stats(const void *work, int32_t *stats_host);
  * output ranks; "uhat-write" = column norms + Uhat + the deflated-column copy
  * ("uhat-norm" when the norms run first, for normalized Uhat); "copy" = the
  * deflated-column copy of a lone root merge (the caller's whole Q); "fill" =
- * the zero fill of the caller's Q (below 2048 rows all of it, else its
- * off-diagonal quadrants) for a root merge of at least 256 rows in the last
- * level, on a second stream while the levels below run (its events are
- * recorded on that stream); "rotate" and "rank" are no longer recorded
- * separately.
+ * the zero fill of the caller's Q for a root merge of at least 256 rows in the
+ * last level, on a second stream while the levels below run (from 2048 rows
+ * in two parts: the off-diagonal quadrants from the first levels, the diagonal
+ * halves from two levels before the root; its events are recorded on that
+ * stream); "rotate" and "rank" are no longer recorded separately.
  * Returns 0. */
 int phdc_profile_enable(int on);
 int phdc_profile_read(double *ms, int64_t *count, int nphase);
@@ -251,12 +251,9 @@ int phdc_profile_select(uint32_t mask);
  *  deflated columns nonzero in the Q1 rows only, in both halves, in the Q2 rows only,
  *  rows the deflated columns can be nonzero in, summed: low 32 bits (as unsigned), high bits,
  *  1 for the last merge of its matrix (which writes every row of its output) else 0,
- *  for a last merge whose output was zero-filled on a second stream while the
- *  tree below ran: 2 if all of it was (below 2048 rows; its deflated-column
- *  copy then writes the rows of each column's range only), 1 if its two
- *  off-diagonal quadrants were (rows of one half of its split, columns of the
- *  other; the copy writes the destination column's half and the part of the
- *  range outside it); else 0,
+ *  1 for a last merge whose output was zero-filled on a second stream while the
+ *  tree below ran (its deflated-column copy then writes the rows of each
+ *  column's range only), else 0,
  *  for such a merge: the rows its deflated-column copy writes, summed: low 32
  *  bits (as unsigned), high bits; else 0, 0}.
  * Rows are in the order the merges were planned (leaves upward, the root last).

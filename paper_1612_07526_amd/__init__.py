@@ -211,8 +211,7 @@ def merge_table(work: torch.Tensor):
     2 HSS), HSS rank, deflated columns nonzero in the Q1 rows only / both halves / the
     Q2 rows only, rows the deflated columns can be nonzero in (summed; low 32 bits as
     unsigned, then the high bits: see deflated_rows), 1 for the last merge of its matrix,
-    for a last merge zero-filled beforehand 2 (all of its output) or 1 (its off-diagonal
-    quadrants) else 0, and for
+    1 for a last merge whose output was zero-filled beforehand, and for
     such a merge the rows its deflated-column copy writes (summed, low / high bits: see
     copied_rows).  Rows follow the planning order (the root merge last)."""
     import numpy as np

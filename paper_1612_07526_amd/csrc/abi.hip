@@ -245,23 +245,24 @@ struct Probe {
 struct WorkState {
   Staging plan, hss;
   Probe probe;
-  hipEvent_t fill_fork = nullptr, fill_join = nullptr;  // the zero fill's second stream
+  hipEvent_t fill_ev[4] = {};  // the zero fill's second stream: fork and join of its two phases
 };
 std::mutex g_mu;
 std::unordered_map<const void*, WorkState> g_state;
 
-// Fork/join events of the zero fill of a workspace (created once; false if
-// they cannot be).
-bool fill_events(const void* work, hipEvent_t* fork, hipEvent_t* join) {
+// Fork and join events of phase `phase` (0 or 1) of the zero fill of a
+// workspace (created once; false if they cannot be).
+bool fill_events(const void* work, int phase, hipEvent_t* fork, hipEvent_t* join) {
   std::lock_guard<std::mutex> lk(g_mu);
   WorkState& w = g_state[work];
-  for (hipEvent_t* ev : {&w.fill_fork, &w.fill_join})
-    if (!*ev && hipEventCreateWithFlags(ev, hipEventDisableTiming) != hipSuccess) {
-      *ev = nullptr;
+  hipEvent_t* ev = w.fill_ev + 2 * phase;
+  for (int i = 0; i < 2; ++i)
+    if (!ev[i] && hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) != hipSuccess) {
+      ev[i] = nullptr;
       return false;
     }
-  *fork = w.fill_fork;
-  *join = w.fill_join;
+  *fork = ev[0];
+  *join = ev[1];
   return true;
 }
 
@@ -329,9 +330,9 @@ int64_t third_elems(int64_t m) {
   return m1 * m1 + (m - m1) * (m - m1);
 }
 
-// fill: roots of kFillMinRows to kFillWideRows - 1 rows in the last level are
-// zero-filled ahead of time (their matrices take the third buffer); off for
-// the allocation-free entry point, whose static workspace is sized without it.
+// fill: roots of at least kFillMinRows rows in the last level are zero-filled
+// ahead of time (their matrices take the third buffer); off for the
+// allocation-free entry point, whose static workspace is sized without it.
 Setup setup_for(const std::vector<int64_t>& n, int64_t q_total, const phdc_opts* o, bool fill = true) {
   Setup S;
   S.T = build_tree(n, o->leaf_size);
@@ -341,7 +342,7 @@ Setup setup_for(const std::vector<int64_t>& n, int64_t q_total, const phdc_opts*
   if (fill && H >= 1)
     for (int i = S.T.hstart[H - 1]; i < S.T.hstart[H]; ++i) {
       const Node& nd = S.T.merges[i];
-      if (nd.depth != 0 || nd.m < kFillMinRows || nd.m >= kFillWideRows) continue;
+      if (nd.depth != 0 || nd.m < kFillMinRows) continue;
       S.q3off[nd.b] = S.z.q3_total;
       S.z.q3_total += third_elems(nd.m);
     }
@@ -464,7 +465,8 @@ struct Prepared {
   int nleaves = 0, nmat = 0, ncols = 0;
   int nfill = 0, nfill_wide = 0;  // matrices of the off-block fill (the wide ones first)
   int fill_cols_wide = 0, fill_cols = 0;
-  int fill_level = 1;  // the fill starts before this level
+  int fill_level = 1;   // the fill starts before this level
+  int fill2_level = 1;  // its second phase (diagonal halves of the wide matrices) before this one
   phdc_opts o;
   const double* d = nullptr;  // inputs, for the optional non-finite scan
   const double* e = nullptr;
@@ -480,38 +482,44 @@ void forget_prepared(const void* work) {
 
 int leaf_iters(const phdc_opts* o) { return (o->force_fail & PHDC_FAIL_LEAF) ? 0 : kLeafMaxIters; }
 
-// Start the zero fill: on the auxiliary stream after what s has queued, its
-// completion recorded in *join (returns true: the last level waits for *join
-// before writing output blocks), or on s itself when no second stream or event
-// is available (returns false).
-bool start_fill(char* base, const Prepared& P, hipStream_t s, hipEvent_t* join) {
-  if (P.nfill <= 0) return false;
+// Start phase `phase` of the zero fill: on the auxiliary stream after what s
+// has queued, its completion recorded in *join (returns true: the last level
+// waits for *join before writing output blocks), or on s itself when no second
+// stream or event is available (returns false).  Phase 0: the off-diagonal
+// quadrants of the wide matrices (kFillWideRows rows and more) and all of the
+// narrow ones; phase 1: the diagonal halves of the wide ones.
+bool start_fill(char* base, const Prepared& P, hipStream_t s, int phase, hipEvent_t* join) {
   const FillDesc* fd = (const FillDesc*)(base + P.L.fill);
   const int32_t* pfx = (const int32_t*)(base + P.L.fill_pfx);
   hipStream_t a = aux_stream();
   hipEvent_t fork = nullptr;
-  const bool forked = a && fill_events(base, &fork, join) && hipEventRecord(fork, s) == hipSuccess &&
+  const bool forked = a && fill_events(base, phase, &fork, join) && hipEventRecord(fork, s) == hipSuccess &&
                       hipStreamWaitEvent(a, fork, 0) == hipSuccess;
   hipStream_t fs = forked ? a : s;
   {
     ProfScope p(PH_FILL, fs);
-    launch_fill_zero(fd, pfx, P.nfill_wide, P.fill_cols_wide, true, kFillBlocksWide, fs);
-    launch_fill_zero(fd + P.nfill_wide, pfx + P.nfill_wide + 1, P.nfill - P.nfill_wide,
-                     P.fill_cols - P.fill_cols_wide, false, kFillBlocksNarrow, fs);
+    launch_fill_zero(fd, pfx, P.nfill_wide, P.fill_cols_wide, true, phase == 1, kFillBlocksWide, fs);
+    if (phase == 0)
+      launch_fill_zero(fd + P.nfill_wide, pfx + P.nfill_wide + 1, P.nfill - P.nfill_wide,
+                       P.fill_cols - P.fill_cols_wide, false, false, kFillBlocksNarrow, fs);
   }
   return forked && hipEventRecord(*join, a) == hipSuccess;
 }
 
-// The zero fill around the levels of a solve: it starts before level
-// P.fill_level, and the last level waits for it before writing output blocks.
+// The zero fill around the levels of a solve: phase 0 starts before level
+// P.fill_level, phase 1 before level P.fill2_level (queued after phase 0 on
+// the same stream), and the last level waits for them before writing output
+// blocks.
 struct FillRun {
-  hipEvent_t join = nullptr;
-  bool joined = false;
+  hipEvent_t join[2] = {};
+  bool joined[2] = {false, false};
   // before launching level h; returns the level's qout_ready event
   hipEvent_t before_level(char* base, const Prepared& P, hipStream_t s, int h) {
     if (P.nfill <= 0) return nullptr;
-    if (h == P.fill_level) joined = start_fill(base, P, s, &join);
-    return h == P.z.H && joined ? join : nullptr;
+    if (h == P.fill_level) joined[0] = start_fill(base, P, s, 0, &join[0]);
+    if (h == P.fill2_level && P.nfill_wide > 0) joined[1] = start_fill(base, P, s, 1, &join[1]);
+    if (h != P.z.H) return nullptr;
+    return joined[1] ? join[1] : joined[0] ? join[0] : nullptr;  // (phase 1 runs after phase 0)
   }
 };
 
@@ -601,17 +609,15 @@ int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n,
     D.r0 = (int32_t)nd.r0;
     D.root = nd.depth == 0 ? 1 : 0;
   }
-  // Roots in the last level, zero-filled on a second stream while the tree
-  // below runs.  A root with a third buffer (Setup::q3off; below
-  // kFillWideRows rows): nothing but the root writes the caller's Q of its
-  // matrix, so the whole Q is filled and the root's copy of its deflated
-  // columns writes only the rows of each column's range.  A larger root: its
-  // off-diagonal quadrants (rows of one half, columns of the other), which
-  // every merge below leaves alone (they write and rotate in place only inside
-  // their own diagonal blocks); the copy then writes the rows of each
-  // column's half and range.  (Filling the whole of a large Q holds half the
-  // compute units for longer than the levels beside it can spare.)  Wide
-  // matrices first, then narrow ones.
+  // Roots in the last level with a third buffer (Setup::q3off): nothing but
+  // the root writes the caller's Q of such a matrix, so that Q is zero-filled
+  // on a second stream while the tree below runs, and the root's copy of its
+  // deflated columns then writes only the rows of each column's range.  The
+  // fill holds about half the compute units while it runs, which slows the
+  // levels beside it: a wide Q is filled in two phases, its off-diagonal
+  // quadrants from the first levels on and its diagonal halves only a few
+  // levels before the root, where they cost the least.  Wide matrices first,
+  // then narrow ones.
   std::vector<FillDesc> fills;
   int nfw = 0;
   if (!no_alloc && z.H >= 1) {
@@ -620,9 +626,8 @@ int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n,
         const Node& nd = T.merges[i];
         if (nd.depth != 0 || nd.m < kFillMinRows) continue;
         if ((nd.m >= kFillWideRows) != (pass == 0)) continue;
-        const bool full = BF.q3off[nd.b] >= 0;
-        descs[i].flags |= full ? kFlagPrefilled : kFlagQuadFilled;
-        fills.push_back(FillDesc{BF.q[0] + BF.qoff[nd.b], BF.ld[0][nd.b], nd.m, full ? 0 : nd.n1});
+        descs[i].flags |= kFlagPrefilled;
+        fills.push_back(FillDesc{BF.q[0] + BF.qoff[nd.b], BF.ld[0][nd.b], nd.m, pass == 0 ? nd.n1 : 0});
         if (pass == 0) ++nfw;
       }
   }
@@ -717,6 +722,7 @@ int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n,
   P.fill_level = 1;
   while (P.fill_level < z.H && lm[P.fill_level].maxm <= kSmallMergeMax && small_merge(lm[P.fill_level].maxm, o))
     ++P.fill_level;
+  P.fill2_level = std::max(P.fill_level, z.H - kFillLateLevels);
   if (prepare_only) {
     if (hipStreamSynchronize(s) != hipSuccess) return PHDC_E_HIP;
     if (hipMemcpy(base + plan0, plan.data(), plan.size(), hipMemcpyHostToDevice) != hipSuccess) return PHDC_E_HIP;
@@ -957,7 +963,7 @@ int phdc_release(void* work) {
     hipEventSynchronize(w.probe.done);
     hipEventDestroy(w.probe.done);
   }
-  for (hipEvent_t ev : {w.fill_fork, w.fill_join})
+  for (hipEvent_t ev : w.fill_ev)
     if (ev) {
       hipEventSynchronize(ev);
       hipEventDestroy(ev);
@@ -1241,7 +1247,7 @@ int phdc_merge_table(const void* work, int64_t max_rows, int32_t* table_host, in
     r[13] = c[i * kCounters + C_DROWS_LO];
     r[14] = c[i * kCounters + C_DROWS_HI];
     r[15] = d[i].root;
-    r[16] = (d[i].flags & kFlagPrefilled) ? 2 : (d[i].flags & kFlagQuadFilled) ? 1 : 0;
+    r[16] = (d[i].flags & kFlagPrefilled) ? 1 : 0;
     r[17] = c[i * kCounters + C_WROWS];
     r[18] = c[i * kCounters + C_WROWS + 1];
   }

@@ -1136,8 +1136,7 @@ __device__ void small_body(const MergeDesc& M, const Scratch& S, bool normalized
 // type-2 values are counted directly.
 // Item x of merge M (x < M.m).
 // Returns, for a deflated column of a zero-filled root, the rows its copy
-// writes (its range, or, with the quadrants only filled, its destination's
-// half and the part of its range outside it), else 0.
+// writes (its range), else 0.
 __device__ int rank_item(const MergeDesc& M, const Scratch& S, int x) {
   const int32_t* cnt = S.counters + (int64_t)M.id * kCounters;
   const int K = cnt[C_K], nd1 = cnt[C_ND1], nd2 = cnt[C_ND2];
@@ -1178,10 +1177,8 @@ __device__ int rank_item(const MergeDesc& M, const Scratch& S, int x) {
   RowRange g{0, M.m};  // roots fill every row of the block; deflated columns keep their range
   if (cls > 0) g = S.crng[so + (cls == 1 ? S.dfc1[so + idx] : S.dfc2[so + idx])];
   if (M.rout) M.rout[r] = RowRange{g.lo + M.r0, g.hi + M.r0};
-  if (cls == 0 || !(M.flags & kFlagFilled)) return 0;
-  if (M.flags & kFlagPrefilled) return g.hi - g.lo;
-  const int bl = r < M.n1 ? 0 : M.n1, bh = r < M.n1 ? M.n1 : M.m;
-  return (bh - bl) + max(0, min(g.hi, bl) - g.lo) + max(0, g.hi - max(g.lo, bh));
+  if (cls == 0 || !(M.flags & kFlagPrefilled)) return 0;
+  return g.hi - g.lo;
 }
 
 __device__ void rank_body(const BlockMap& bm, const Scratch& S, int b) {
@@ -1190,7 +1187,7 @@ __device__ void rank_body(const BlockMap& bm, const Scratch& S, int b) {
   const MergeDesc M = bm.descs[mi];
   const int x = lb * 256 + threadIdx.x;
   unsigned long long w = (x < M.m) ? (unsigned long long)rank_item(M, S, x) : 0ULL;
-  if (M.flags & kFlagFilled) {  // (block-uniform) one atomic per wave
+  if (M.flags & kFlagPrefilled) {  // (block-uniform) one atomic per wave
     for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o, 64);
     if ((threadIdx.x & 63) == 0 && w)
       atomicAdd((unsigned long long*)(S.counters + (int64_t)M.id * kCounters + C_WROWS), w);
@@ -1263,9 +1260,7 @@ __device__ void copy_body(const BlockMap& bm, const Scratch& S, int b) {
   const int64_t so = M.s_off;
   if (M.root) {
     // The caller's Q: every row is written -- rows [0, m), or, when Q was
-    // zero-filled beforehand, only the rows of the column's range, or, when
-    // its off-diagonal quadrants were, the rows of the destination column's
-    // half and of the column's range.  A
+    // zero-filled beforehand, only the rows of the column's range.  A
     // whole block per column (a wave per column below kCopyWideRows rows),
     // rows in pairs with 16-byte nontemporal stores (nothing here reads Q
     // again, so the lines need not stay in the caches).  On the short columns
@@ -1273,7 +1268,7 @@ __device__ void copy_body(const BlockMap& bm, const Scratch& S, int b) {
     // and the next column's list entry and destination are read while the
     // current one is in flight.
     const bool wide = m >= kCopyWideRows;
-    const bool full = (M.flags & kFlagPrefilled) != 0, quad = (M.flags & kFlagQuadFilled) != 0;
+    const bool pre = (M.flags & kFlagPrefilled) != 0;
     const int lane = wide ? threadIdx.x : (threadIdx.x & 63), step = wide ? 256 : 64;
     const int q0 = wide ? lb : lb * 4 + (threadIdx.x >> 6), qs = wide ? G : G * 4;
     auto entry = [&](int q, int& c, int& dst) {
@@ -1289,18 +1284,7 @@ __device__ void copy_body(const BlockMap& bm, const Scratch& S, int b) {
       const double* src = M.qin + (int64_t)c * M.ldin;
       double* out = M.qout + (int64_t)dst * M.ldout;
       auto val = [&](int r) { return (r >= g.lo && r < g.hi) ? src[r] : 0.0; };
-      // row intervals: [0, m); or the range; or the half [bl, bh) of the
-      // destination and the part of the range outside it
-      int bl = full ? g.lo : 0, bh = full ? g.hi : m;
-      if (quad) {
-        bl = dst < M.n1 ? 0 : M.n1;
-        bh = dst < M.n1 ? M.n1 : m;
-      }
-      for (int k = 0; k < (quad ? 3 : 1); ++k) {
-        const int x = k == 0 ? bl : k == 1 ? g.lo : max(g.lo, bh);
-        const int y = k == 0 ? bh : k == 1 ? min(g.hi, bl) : g.hi;
-        put_rows(out, x, y, lane, step, wide, val);
-      }
+      put_rows(out, pre ? g.lo : 0, pre ? g.hi : m, lane, step, wide, val);
       if (wide) {
         if (q + qs < nd) entry(q + qs, cn, dn);
       }
@@ -1375,13 +1359,14 @@ int map_blocks(int kind, int m, int n1, int gt, bool root, bool small, int nm) {
 }
 
 
-// Zero fill of the caller's Q (FillDesc): every row of every column, or the
-// off-diagonal quadrants (column c < k gets zeros in rows [k, n), column
-// c >= k in rows [0, k)).  A block of NT threads per column (wide) or a wave
-// per column; cpfx: prefix of the column counts of the nd matrices.
+// Zero fill of the caller's Q (FillDesc): every row of every column (k = 0),
+// or the off-diagonal quadrants (column c < k gets zeros in rows [k, n),
+// column c >= k in rows [0, k)), or with diag the diagonal halves (the other
+// rows).  A block of NT threads per column (wide) or a wave per column; cpfx:
+// prefix of the column counts of the nd matrices.
 template <int NT>
 __global__ void __launch_bounds__(NT) k_fill_zero(const FillDesc* __restrict__ fd, const int32_t* __restrict__ cpfx,
-                                                  int nd, int total, int wide) {
+                                                  int nd, int total, int wide, int diag) {
   constexpr int W = NT / 64;
   const int first = wide ? (int)blockIdx.x : (int)blockIdx.x * W + (int)(threadIdx.x >> 6);
   const int stride = wide ? (int)gridDim.x : (int)gridDim.x * W;
@@ -1398,18 +1383,18 @@ __global__ void __launch_bounds__(NT) k_fill_zero(const FillDesc* __restrict__ f
     const int c = col - cpfx[lo];
     double* out = F.q + (int64_t)c * F.ld;
     if (F.k == 0) put_rows(out, 0, F.n, lane, step, wide != 0, zero);
-    else if (c < F.k) put_rows(out, F.k, F.n, lane, step, wide != 0, zero);
+    else if ((c < F.k) != (diag != 0)) put_rows(out, F.k, F.n, lane, step, wide != 0, zero);
     else put_rows(out, 0, F.k, lane, step, wide != 0, zero);
   }
 }
 
-void launch_fill_zero(const FillDesc* fd, const int32_t* cpfx, int nd, int total, bool wide, int max_blocks,
-                      hipStream_t s) {
+void launch_fill_zero(const FillDesc* fd, const int32_t* cpfx, int nd, int total, bool wide, bool diag,
+                      int max_blocks, hipStream_t s) {
   if (nd <= 0 || total <= 0) return;
   constexpr int W = kFillThreads / 64;
   const int blocks = std::max(1, std::min(max_blocks, wide ? total : (total + W - 1) / W));
   hipLaunchKernelGGL(k_fill_zero<kFillThreads>, dim3(blocks), dim3(kFillThreads), 0, s, fd, cpfx, nd, total,
-                     wide ? 1 : 0);
+                     wide ? 1 : 0, diag ? 1 : 0);
 }
 
 __global__ void __launch_bounds__(256) k_copy_ints(const int32_t* __restrict__ src, int32_t* dst, int n) {

@@ -58,15 +58,15 @@ struct MergeDesc {
 };
 
 // One matrix whose caller-side eigenvector matrix is zero-filled, while the
-// tree below its root runs, before the root merge writes it: either the whole
-// matrix (k = 0; nothing below the root touches that Q: the even depths below
-// it use a workspace buffer of their own), or the two off-diagonal quadrants
-// (rows of one half of the split, columns of the other), which nothing below
-// the root touches either.
+// tree below its root runs, before the root merge writes it (nothing below the
+// root touches that Q: the even depths below it use a workspace buffer of
+// their own): all of it at once (k = 0), or in two parts split at row and
+// column k (the root's n1): the off-diagonal quadrants, then the diagonal
+// halves.
 struct FillDesc {
   double* q;  // the matrix's Q (column-major)
   int64_t ld;
-  int32_t n, k;  // size; 0, or the first half (the root's n1)
+  int32_t n, k;  // size; 0, or the first half
 };
 
 // One leaf solve (one wavefront).
@@ -170,10 +170,8 @@ constexpr int32_t kFlagSmallMerge = 2;      // the whole merge runs in one workg
 constexpr int32_t kFlagPrepDeflate = 4;     // deflation's element-wise first steps run in k_deflate_prep
 constexpr int kDefPrepRows = 2048;          // merges from this size take kFlagPrepDeflate
 constexpr int32_t kFlagPrefilled = 8;       // root: the caller's Q was zero-filled beforehand
-constexpr int32_t kFlagQuadFilled = 16;     // root: only its off-diagonal quadrants were
-constexpr int32_t kFlagFilled = kFlagPrefilled | kFlagQuadFilled;
 constexpr int kFillMinRows = 256;           // roots from this size take the zero fill
-constexpr int kFillWideRows = 2048;         // matrices from this size fill a column per block (else per wave)
+constexpr int kFillWideRows = 2048;         // matrices from this size fill in two phases, a column per block (else per wave)
 // Merges of at most this many rows on the FP64 path run in one workgroup each.
 constexpr int kSmallMergeMax = 64;
 static_assert(kFillMinRows > kSmallMergeMax, "a zero-filled root is never a one-workgroup merge");
@@ -239,16 +237,19 @@ struct SplitBufs;
 void launch_merge_level(const MergeDesc* descs, int nm, const LevelMaps& maps, const Scratch& S,
                         int gemm_mode, const SplitBufs* split, int nsl, hipStream_t s,
                         const LevelProbe* probe = nullptr, hipEvent_t qout_ready = nullptr);
-// Zero-fill the Q (or its off-diagonal quadrants, FillDesc) of nd matrices
-// (cpfx: prefix of their column counts, total = cpfx[nd]); wide: a block per
-// column, else a wave per column; at most max_blocks workgroups, looping over
-// the columns.
-void launch_fill_zero(const FillDesc* fd, const int32_t* cpfx, int nd, int total, bool wide, int max_blocks,
-                      hipStream_t s);
+// Zero-fill the Q of nd matrices (FillDesc; with k > 0 its off-diagonal
+// quadrants, or with diag its diagonal halves; cpfx: prefix of their column
+// counts, total = cpfx[nd]); wide: a block per column, else a wave per column;
+// at most max_blocks workgroups, looping over the columns.
+void launch_fill_zero(const FillDesc* fd, const int32_t* cpfx, int nd, int total, bool wide, bool diag,
+                      int max_blocks, hipStream_t s);
 // Workgroup size and caps of the fill (a block per column / a wave per
 // column): they set how many compute units it holds beside the levels it runs
 // with.
 constexpr int kFillThreads = 256;
+// The diagonal halves of a wide Q are filled from this many levels before the
+// root on.
+constexpr int kFillLateLevels = 3;
 constexpr int kFillBlocksWide = 128;
 constexpr int kFillBlocksNarrow = 512;
 void launch_secular_standalone(int64_t K, const double* d, const double* z, double rho, int32_t* org,

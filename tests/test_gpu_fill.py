@@ -1,10 +1,11 @@
 """Zero fill of the caller's eigenvector matrix ahead of a root merge (on the GPU).
 
 A root merge of at least 256 rows in the last level of the tree has its output
-zero-filled on a second stream while the levels below run: the whole of it
-below 2048 rows (the even depths below such a root keep their eigenvectors in a
-workspace buffer of their own), else its two off-diagonal quadrants.  The root
-then copies only the rows of each deflated column that can be nonzero.  Here
+zero-filled on a second stream while the levels below run (the even depths
+below such a root keep their eigenvectors in a workspace buffer of their own;
+from 2048 rows the fill comes in two parts: off-diagonal quadrants, then
+diagonal halves).  The root then copies only the rows of each deflated column
+that can be nonzero.  Here
 the caller's buffer starts out as NaN, so an entry that neither the fill nor
 the merge writes shows up in every check; deflation is made heavy (tiny
 couplings) so that most columns take the short copy.
@@ -64,24 +65,20 @@ def _check_solution(d, e, lam, Q, orc):
     assert np.abs(lh - lr).max() <= 1e-13 * np.abs(lr).max()
 
 
-@pytest.mark.parametrize("n,mode", [(300, 2), (1000, 2), (2047, 2), (2048, 1), (2500, 1)])
-def test_single_solve_over_poisoned_q(P, orc, n, mode):
+@pytest.mark.parametrize("n", [300, 1000, 2047, 2048, 2500])
+def test_single_solve_over_poisoned_q(P, orc, n):
     d, e = _deflating(n, seed=n)
     lam, Q, work = _solve_poisoned(P, d, e)
     tb = P.merge_table(work)
     root = tb[:, 15] > 0
-    assert root.sum() == 1 and tb[root, 16][0] == mode
+    assert root.sum() == 1 and tb[root, 16][0] == 1
     _check_solution(d, e, lam, Q, orc)
     # the root's copy wrote exactly the rows the fill left to it
     copied = int(P.copied_rows(tb)[root][0])
     ranged = int(P.deflated_rows(tb)[root][0])
     ndefl = int(tb[root, 6][0] + tb[root, 7][0])
     assert ndefl > n // 4
-    if mode == 2:
-        assert copied == ranged
-    else:
-        assert ranged <= copied <= ranged + ndefl * (n - n // 2)
-        assert copied >= ndefl * (n // 2)
+    assert copied == ranged
 
 
 def test_small_root_takes_no_fill(P, orc):
@@ -95,8 +92,8 @@ def test_small_root_takes_no_fill(P, orc):
 @pytest.mark.parametrize("sizes", [[2048, 1900, 1000, 300, 40], [1000, 700, 600, 40, 300, 1]])
 def test_batched_over_poisoned_q(P, orc, sizes):
     # Only the roots in the last level (the tallest trees: heights 7 and 6 at
-    # leaf size 16) are filled: 2048 by quadrants, 1900 whole; in the second
-    # batch 1000, 700 and 600 whole.
+    # leaf size 16) are filled: 2048 (in two parts) and 1900; in the second
+    # batch 1000, 700 and 600.
     lib = P.load()
     o = P.opts()
     mats = [_deflating(n, seed=100 + i) for i, n in enumerate(sizes)]
@@ -126,9 +123,9 @@ def test_batched_over_poisoned_q(P, orc, sizes):
         if n < 256:
             assert modes.get(n, 0) == 0
     if max(sizes) == 2048:
-        assert modes[2048] == 1 and modes[1900] == 2 and modes[1000] == 0 and modes[300] == 0
+        assert modes[2048] == 1 and modes[1900] == 1 and modes[1000] == 0 and modes[300] == 0
     else:
-        assert modes[1000] == 2 and modes[700] == 2 and modes[600] == 2 and modes[300] == 0
+        assert modes[1000] == 1 and modes[700] == 1 and modes[600] == 1 and modes[300] == 0
     for b, n in enumerate(sizes):
         Qb = Q[qoff[b]:qoff[b] + n * n].view(n, n).t()
         _check_solution(mats[b][0], mats[b][1], lam[off[b]:off[b] + n], Qb, orc)
