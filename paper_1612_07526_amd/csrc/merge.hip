@@ -190,6 +190,70 @@ __global__ void __launch_bounds__(kPrepThreads) k_deflate_prep(BlockMap bm, Scra
   }
 }
 
+// The partial |z|^2, max |D| and sortedness flags of k_deflate_prep's blocks,
+// combined by wave 0 in one fixed order, so that every kernel that combines
+// them gets the same bits; sh2 and shu are LDS scratch.  All threads call it.
+__device__ void prep_totals(const MergeDesc& M, const Scratch& S, double* sh2, int* shu, double* zz, double* dmx,
+                            int* uns) {
+  const int t = threadIdx.x;
+  if (t < 64) {
+    const int64_t so = M.s_off;
+    const int nb = cdiv_d(M.m, kPrepThreads);
+    double a = 0.0, b = 0.0;
+    int u = 0;
+    for (int i = t; i < nb; i += 64) {
+      a += S.tau[so + i];
+      b = fmax(b, S.dorg[so + i]);
+      u |= S.org[so + i];
+    }
+    // (an xor butterfly leaves the same bits in every lane: IEEE addition commutes)
+    for (int o = 32; o > 0; o >>= 1) {
+      a += __shfl_xor(a, o, 64);
+      b = fmax(b, __shfl_xor(b, o, 64));
+      u |= __shfl_xor(u, o, 64);
+    }
+    if (t == 0) {
+      sh2[0] = a;
+      sh2[1] = b;
+      *shu = u;
+    }
+  }
+  __syncthreads();
+  *zz = sh2[0];
+  *dmx = sh2[1];
+  *uns = *shu;
+  __syncthreads();
+}
+
+// Type-1 deflation of merges of at least kDefPrepRows rows across many
+// workgroups (after k_deflate_prep): kDefT1Threads pole positions per
+// workgroup.  Every workgroup combines the prep partials (prep_totals) into
+// rho and the tolerance exactly as the one-workgroup deflation does, tests the
+// positions before its own for survivors itself (a short redundant read, so
+// that no workgroup waits for another), and writes its survivors (surv) and
+// type-1 deflations (dfv1, dfc1) straight to their places in pole order.  It
+// leaves normalised z in zhat (pole order), the 0/1 flags, and per workgroup
+// j: its survivors (dest[j]), its deflations (destd1[j]), their counts by
+// half (destd2[j]: Q1 rows only + 65536 x Q2 rows only) and their rows in
+// range (cnorm[j]).  Workgroup 0 leaves rho, the tolerance and 1 (done) in
+// the merge's mparam slots 0-2.  Input that is unsorted or not finite is left
+// to the one-workgroup deflation (slot 2 = 0), which then does every step as
+// for small merges.
+constexpr int kDefT1Threads = 1024;
+constexpr int kDefT1Loads = 16;  // loads of preceding z issued together per thread
+
+template <int NT>
+__device__ int block_isum(int v, int* sh) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  int r = 0;
+  for (int i = 0; i < NT / 64; ++i) r += sh[i];
+  return r;
+}
+
 // sdl: LDS for D, used by the merge-path searches when m <= lds_cap.  UN: the
 // elements per thread (chunks of 64 per wave) whose loads each pass issues
 // together (more registers); 1 where a merge fits one pass anyway.
@@ -204,7 +268,7 @@ __device__ void deflate_body(const MergeDesc& M, const Scratch& S, int lds_cap, 
   const int64_t so = M.s_off;
   int32_t* cnt = S.counters + (int64_t)M.id * kCounters;
   double* dv = S.dv + so;
-  double* zv = S.zv + so;
+  double* zv = S.zv + so;  // (zhat after the many-workgroup type-1 deflation)
   int32_t* col = S.col + so;
   int32_t* part = S.part + so;
   int32_t* flag = S.flag + so;
@@ -226,15 +290,13 @@ __device__ void deflate_body(const MergeDesc& M, const Scratch& S, int lds_cap, 
   double zz = 0.0, dmx = 0.0;
   int uns = 0;  // bit 0: a descending step inside D1 or D2; bit 1: a NaN or Inf pole
   const bool prepared = (M.flags & kFlagPrepDeflate) != 0;  // block-uniform
+  // k_deflate_t1 did step 3 (and left rho and the tolerance) unless the input
+  // was unsorted or not finite
+  const double* mp = S.mparam + (int64_t)M.id * 4;
+  const bool split1 = prepared && mp[2] != 0.0;  // block-uniform
   constexpr int U1 = UN;  // loads of UN indices issued before their uses
-  if (prepared) {
-    const int nb = (m + kPrepThreads - 1) / kPrepThreads;
-    for (int b = t; b < nb; b += NT) {
-      zz += S.tau[so + b];
-      dmx = fmax(dmx, S.dorg[so + b]);
-      uns |= S.org[so + b];
-    }
-  }
+  __shared__ double sh2[2];
+  if (prepared && !split1) prep_totals(M, S, sh2, &shi[1], &zz, &dmx, &uns);
   for (int i0 = t; !prepared && i0 < m; i0 += U1 * NT) {
     double zi[U1], di[U1], dprev[U1];
 #pragma unroll
@@ -267,8 +329,10 @@ __device__ void deflate_body(const MergeDesc& M, const Scratch& S, int lds_cap, 
       }
     }
   }
-  zz = block_sum<NT>(zz, shd);
-  dmx = block_max<NT>(dmx, shd);
+  if (!prepared) {
+    zz = block_sum<NT>(zz, shd);
+    dmx = block_max<NT>(dmx, shd);
+  }
   __syncthreads();
   if (t == 0) shi[0] = 0;
   __syncthreads();
@@ -276,10 +340,10 @@ __device__ void deflate_body(const MergeDesc& M, const Scratch& S, int lds_cap, 
   __syncthreads();
   uns = shi[0];
   if (!isfinite(zz) || !isfinite(rho0)) uns |= 2;  // block-uniform
-  const double rho = rho0 * zz;
+  const double rho = split1 ? mp[0] : rho0 * zz;
   const double zn = sqrt(zz);
-  const double tol = 8.0 * kUnitRoundoff * fmax(dmx, rho);
-  if (t == 0) {
+  const double tol = split1 ? mp[1] : 8.0 * kUnitRoundoff * fmax(dmx, rho);
+  if (t == 0 && !split1) {
     S.mparam[(int64_t)M.id * 4 + 0] = rho;
     S.mparam[(int64_t)M.id * 4 + 1] = tol;
     if (uns & 2) set_status(S.status, PHDC_ERR_NONFINITE);
@@ -289,9 +353,10 @@ __device__ void deflate_body(const MergeDesc& M, const Scratch& S, int lds_cap, 
   // 2. merge the two ascending runs (ties: D1 first) and normalise z.  For
   // valid input the positions form a permutation of [0, m); otherwise keep the
   // input order so every slot is still written exactly once.  (Prepared merges:
-  // already placed, z normalised in step 3's first pass; placed again here in
-  // input order if the runs were not ascending.)
-  const bool norm_in_pass = prepared && !uns;
+  // already placed by k_deflate_prep, and step 3 done by k_deflate_t1, which
+  // left normalised z in zhat; placed again here in input order if the runs
+  // were not ascending, and every step done here.)
+  if (split1) zv = S.zhat + so;
   auto place = [&](const double* D) {
     for (int i = t; i < m; i += NT) {
       const double di = D[i];
@@ -302,7 +367,7 @@ __device__ void deflate_body(const MergeDesc& M, const Scratch& S, int lds_cap, 
       part[pos] = (i < n1) ? 1 : 3;
     }
   };
-  if (norm_in_pass) {
+  if (split1) {
   } else if (m <= lds_cap) {
     for (int i = t; i < m; i += NT) sdl[i] = M.lin[i];
     __syncthreads();
@@ -317,10 +382,29 @@ __device__ void deflate_body(const MergeDesc& M, const Scratch& S, int lds_cap, 
   const int seg = ((m + NW - 1) / NW + 63) / 64 * 64;
   const int seg0 = min(m, wv * seg), seg1 = min(m, seg0 + seg);
   int ns, nd1;
+  int t1dp1 = 0, t1dp3 = 0;  // (split1) type-1 deflations by half, rows in range
+  double t1rows = 0.0;
   // The passes below load UC chunks of 64 before using any of them (the chunks
   // are then consumed in order), so a wave waits on memory once per UC chunks.
   constexpr int UC = UN;
-  {
+  if (split1) {  // k_deflate_t1's per-workgroup totals
+    const int nb1 = cdiv_d(m, kDefT1Threads);
+    int a = 0, b = 0, h1 = 0, h3 = 0;
+    double r = 0.0;
+    for (int j = t; j < nb1; j += NT) {
+      a += S.dest[so + j];
+      b += S.destd1[so + j];
+      const int h = S.destd2[so + j];
+      h1 += h & 0xFFFF;
+      h3 += h >> 16;
+      r += S.cnorm[so + j];
+    }
+    ns = block_isum<NT>(a, shc[0]);
+    nd1 = block_isum<NT>(b, shc[1]);
+    t1dp1 = block_isum<NT>(h1, shc[2]);
+    t1dp3 = block_isum<NT>(h3, shc[3]);
+    t1rows = block_sum<NT>(r, shd);
+  } else {
     int c[2] = {0, 0}, pre[2], tot[2];
     for (int b0 = seg0; b0 < seg1; b0 += 64 * UC) {
       double zk[UC];
@@ -329,15 +413,6 @@ __device__ void deflate_body(const MergeDesc& M, const Scratch& S, int lds_cap, 
         const int k = b0 + u * 64 + lane;
         zk[u] = (k < seg1) ? zv[k] : 0.0;
       }
-      if (norm_in_pass)
-#pragma unroll
-        for (int u = 0; u < UC; ++u) {
-          const int k = b0 + u * 64 + lane;
-          if (k < seg1) {
-            zk[u] = (zn > 0.0) ? zk[u] / zn : 0.0;
-            zv[k] = zk[u];
-          }
-        }
 #pragma unroll
       for (int u = 0; u < UC; ++u) {
         const int k = b0 + u * 64 + lane;
@@ -482,15 +557,32 @@ __device__ void deflate_body(const MergeDesc& M, const Scratch& S, int lds_cap, 
   // 5. final survivors in pole order, Gu's grouping by part (Sec. 1): rows of
   // Uhat ordered [part 1 | part 2 | part 3]; the Q1-row product uses columns of
   // parts 1,2 and the Q2-row product those of parts 2,3.  Type-2 deflated list.
+  // (split1: only the survivors of step 3 are visited, through surv; the type-1
+  // deflations were counted by k_deflate_t1.)
+  const int n5 = split1 ? ns : m;
+  const int sg5 = ((n5 + NW - 1) / NW + 63) / 64 * 64;
+  const int s50 = min(n5, wv * sg5), s51 = min(n5, s50 + sg5);
+  auto pole = [&](int i) { return split1 ? surv[i] : i; };
+  // a wave whose segment is one batch keeps its indices, flags and halves in
+  // registers for the second pass (block-uniform)
+  const bool one5 = sg5 <= 64 * UC;
+  int kA[UC], fA[UC], pA[UC];
   int c[7] = {0, 0, 0, 0, 0, 0, 0}, pre[7], tot[7];
-  for (int b0 = seg0; b0 < seg1; b0 += 64 * UC) {
-    int fu[UC], pu[UC];
+  for (int b0 = s50; b0 < s51; b0 += 64 * UC) {
+    int fu[UC], pu[UC], ku[UC];
 #pragma unroll
     for (int u = 0; u < UC; ++u) {
-      const int k = b0 + u * 64 + lane;
-      const bool valid = k < seg1;
-      fu[u] = valid ? flag[k] : -1;
-      pu[u] = valid ? part[k] : 0;
+      const int i = b0 + u * 64 + lane;
+      ku[u] = (i < s51) ? pole(i) : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < UC; ++u) {
+      const int k = ku[u];
+      fu[u] = (k >= 0) ? flag[k] : -1;
+      pu[u] = (k >= 0) ? part[k] : 0;
+      kA[u] = k;
+      fA[u] = fu[u];
+      pA[u] = pu[u];
     }
 #pragma unroll
     for (int u = 0; u < UC; ++u) {
@@ -506,21 +598,39 @@ __device__ void deflate_body(const MergeDesc& M, const Scratch& S, int lds_cap, 
   }
   wave_prefix<7, NW>(c, pre, tot, shc);
   const int k1 = tot[0], k2 = tot[1], k3 = tot[2], nd2 = tot[3];
-  const int dp1 = tot[4], dp2 = tot[5], dp3 = tot[6];
+  const int dp1 = tot[4] + t1dp1, dp2 = tot[5], dp3 = tot[6] + t1dp3;
   const int K = k1 + k2 + k3;
   double drows = 0.0;  // rows in range over the deflated columns (exact: integers below 2^53)
   {
     int b1 = pre[0], b2 = pre[1], b3 = pre[2], b4 = pre[3];
-    for (int b0 = seg0; b0 < seg1; b0 += 64 * UC) {
-      int fu[UC], pu[UC], cu[UC];
+    for (int b0 = s50; b0 < s51; b0 += 64 * UC) {
+      int fu[UC], pu[UC], cu[UC], ku[UC];
       double du[UC], zu[UC];
       RowRange gu[UC];
+      if (one5) {
+#pragma unroll
+        for (int u = 0; u < UC; ++u) {
+          ku[u] = kA[u];
+          fu[u] = fA[u];
+          pu[u] = pA[u];
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < UC; ++u) {
+          const int i = b0 + u * 64 + lane;
+          ku[u] = (i < s51) ? pole(i) : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < UC; ++u) {
+          const int k = ku[u];
+          fu[u] = (k >= 0) ? flag[k] : -1;
+          pu[u] = (k >= 0) ? part[k] : 0;
+        }
+      }
 #pragma unroll
       for (int u = 0; u < UC; ++u) {
-        const int k = b0 + u * 64 + lane;
-        const bool valid = k < seg1;
-        fu[u] = valid ? flag[k] : -1;
-        pu[u] = valid ? part[k] : 0;
+        const int k = ku[u];
+        const bool valid = k >= 0;
         cu[u] = valid ? col[k] : 0;
         du[u] = valid ? dv[k] : 0.0;
         zu[u] = valid ? zv[k] : 0.0;
@@ -571,7 +681,7 @@ __device__ void deflate_body(const MergeDesc& M, const Scratch& S, int lds_cap, 
       }
     }
   }
-  drows = block_sum<NT>(drows, shd);
+  drows = block_sum<NT>(drows, shd) + t1rows;
   if (t == 0) {
     const int64_t dr = (int64_t)drows;
     cnt[C_DROWS_LO] = (int32_t)(uint32_t)(dr & 0xffffffffLL);
@@ -592,6 +702,95 @@ __device__ void deflate_body(const MergeDesc& M, const Scratch& S, int lds_cap, 
     cnt[C_WROWS] = 0;
     cnt[C_WROWS + 1] = 0;
   }
+}
+
+__global__ void __launch_bounds__(kDefT1Threads) k_deflate_t1(BlockMap bm, Scratch S) {
+  constexpr int NT = kDefT1Threads, NW = NT / 64;
+  static_assert(NW <= kDefWaves, "wave_prefix covers at most kDefWaves waves");
+  __shared__ double shd[NW];
+  __shared__ double sh2[2];
+  __shared__ int shu;
+  __shared__ int shc[2][kDefWaves];
+  __shared__ int shs[4][NW];
+  const int mi = find_merge(bm, blockIdx.x);
+  const int lb = blockIdx.x - merge_first_block(bm, mi);
+  const MergeDesc M = bm.descs[mi];
+  if (!(M.flags & kFlagPrepDeflate)) return;  // (the one-workgroup deflation does every step)
+  const int m = M.m, t = threadIdx.x, lane = t & 63;
+  const int64_t so = M.s_off;
+  double zz, dmx;
+  int uns;
+  prep_totals(M, S, sh2, &shu, &zz, &dmx, &uns);
+  double rho0 = M.rho;
+  if (M.ecoup != nullptr) rho0 = fabs(*M.ecoup);
+  if (!isfinite(zz) || !isfinite(rho0)) uns |= 2;
+  // exactly the one-workgroup deflation's rho, normalisation and test
+  const double rho = rho0 * zz;
+  const double zn = sqrt(zz);
+  const double tol = 8.0 * kUnitRoundoff * fmax(dmx, rho);
+  if (lb == 0 && t == 0) {
+    double* mp = S.mparam + (int64_t)M.id * 4;
+    mp[0] = rho;
+    mp[1] = tol;
+    mp[2] = uns ? 0.0 : 1.0;
+  }
+  if (uns) return;  // (block-uniform)
+  auto znorm = [&](double z) { return (zn > 0.0) ? z / zn : 0.0; };
+
+  // survivors among the positions before this workgroup's
+  const int k0 = lb * NT;
+  int cs = 0;
+  for (int b0 = t; b0 < k0; b0 += NT * kDefT1Loads) {
+    double zb[kDefT1Loads];
+#pragma unroll
+    for (int u = 0; u < kDefT1Loads; ++u) {
+      const int k = b0 + u * NT;
+      zb[u] = (k < k0) ? S.zv[so + k] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kDefT1Loads; ++u)
+      if (b0 + u * NT < k0 && !(rho * fabs(znorm(zb[u])) <= tol)) ++cs;
+  }
+  const int pre_s = block_isum<NT>(cs, shs[0]), pre_d = k0 - pre_s;
+
+  // this workgroup's positions
+  const int k = k0 + t;
+  const bool valid = k < m;
+  double zk = 0.0, dk = 0.0;
+  int ck = 0, pk = 0;
+  if (valid) {
+    zk = znorm(S.zv[so + k]);
+    dk = S.dv[so + k];
+    ck = S.col[so + k];
+    pk = S.part[so + k];
+  }
+  const bool dfl = valid && rho * fabs(zk) <= tol;
+  if (valid) {
+    S.zhat[so + k] = zk;
+    S.flag[so + k] = dfl ? 1 : 0;
+  }
+  const uint64_t ms = __ballot(valid && !dfl), md = __ballot(dfl);
+  int cw[2] = {(int)__popcll(ms), (int)__popcll(md)}, pre[2], tot[2];
+  wave_prefix<2, NW>(cw, pre, tot, shc);
+  if (valid && !dfl) S.surv[so + pre_s + pre[0] + lanes_below(ms)] = k;
+  double rows = 0.0;
+  if (dfl) {
+    const int q = pre_d + pre[1] + lanes_below(md);
+    S.dfv1[so + q] = dk;
+    S.dfc1[so + q] = ck;
+    const RowRange g = S.crng[so + ck];
+    rows = (double)(g.hi - g.lo);
+  }
+  const int h1 = block_isum<NT>(dfl && pk == 1 ? 1 : 0, shs[1]);
+  const int h3 = block_isum<NT>(dfl && pk == 3 ? 1 : 0, shs[2]);
+  rows = block_sum<NT>(rows, shd);
+  if (t == 0) {
+    S.dest[so + lb] = tot[0];
+    S.destd1[so + lb] = tot[1];
+    S.destd2[so + lb] = h1 | (h3 << 16);
+    S.cnorm[so + lb] = rows;
+  }
+  (void)lane;
 }
 
 template <int NT>
@@ -1354,6 +1553,7 @@ int map_blocks(int kind, int m, int n1, int gt, bool root, bool small, int nm) {
     case MAP_SPLITA: return cdiv(m, 256) * kSplitKGroups;
     case MAP_SPLITB: return cdiv(m + 8, 256) * kSplitRGroups;
     case MAP_PREP: return m >= kDefPrepRows ? cdiv(m, kPrepThreads) : 0;
+    case MAP_DEFL1: return m >= kDefPrepRows ? cdiv(m, kDefT1Threads) : 0;
   }
   return 0;
 }
@@ -1585,6 +1785,8 @@ void launch_merge_level(const MergeDesc* descs, int nm, const LevelMaps& maps, c
   { ProfScope p(PH_DEFLATE, s);
     if (maps.total[MAP_PREP] > 0)
       hipLaunchKernelGGL(k_deflate_prep, dim3(maps.total[MAP_PREP]), dim3(kPrepThreads), 0, s, bmap(MAP_PREP), S);
+    if (maps.total[MAP_DEFL1] > 0)
+      hipLaunchKernelGGL(k_deflate_t1, dim3(maps.total[MAP_DEFL1]), dim3(kDefT1Threads), 0, s, bmap(MAP_DEFL1), S);
     const int cap = maps.maxm <= kDefLdsMax ? maps.maxm : 0;
     if (maps.maxm <= kDefSmall)
       hipLaunchKernelGGL(k_deflate<256>, dim3(nm), dim3(256), (size_t)cap * sizeof(double), s, descs, S, cap);
@@ -1594,7 +1796,7 @@ void launch_merge_level(const MergeDesc* descs, int nm, const LevelMaps& maps, c
   if (probe && probe->count > 0) {
     hipLaunchKernelGGL(k_copy_ints, dim3((probe->count + 255) / 256), dim3(256), 0, s, probe->src, probe->dst,
                        probe->count);
-    hipEventRecord(probe->done, s);
+    (void)hipEventRecord(probe->done, s);
   }
   const int nrot = maps.total[MAP_ROT];
   const int ncopy = maps.total[MAP_COPY];
@@ -1616,7 +1818,7 @@ void launch_merge_level(const MergeDesc* descs, int nm, const LevelMaps& maps, c
     const int nc = maps.copy_alone ? 0 : ncopy;
     // the launches below write output blocks: a zero fill of a root's output
     // (rows >= kFillMinRows, so never in the small branches above) ends first
-    if (qout_ready) hipStreamWaitEvent(s, qout_ready, 0);
+    if (qout_ready) (void)hipStreamWaitEvent(s, qout_ready, 0);
     if (normalized) {
       { ProfScope p(PH_UNORM, s);
         hipLaunchKernelGGL(k_stage_uhat, dim3(nitem), dim3(256), 0, s, none, 0, none, 0, bmap(MAP_ROOTS16), S, 1); }

@@ -168,7 +168,7 @@ __device__ inline void set_status(int32_t* status, int code) {
 constexpr int32_t kFlagNoSecularIters = 1;  // secular roots get no iterations (test hook)
 constexpr int32_t kFlagSmallMerge = 2;      // the whole merge runs in one workgroup (k_merge_small)
 constexpr int32_t kFlagPrepDeflate = 4;     // deflation's element-wise first steps run in k_deflate_prep
-constexpr int kDefPrepRows = 2048;          // merges from this size take kFlagPrepDeflate
+constexpr int kDefPrepRows = 4096;          // merges from this size take kFlagPrepDeflate
 constexpr int32_t kFlagPrefilled = 8;       // root: the caller's Q was zero-filled beforehand
 constexpr int kFillMinRows = 256;           // roots from this size take the zero fill
 constexpr int kFillWideRows = 2048;         // matrices from this size fill in two phases, a column per block (else per wave)
@@ -191,7 +191,7 @@ hipStream_t aux_stream();
 // Block maps of one merge level (device prefix arrays, nm + 1 entries each).
 enum MapKind {
   MAP_SECULAR = 0, MAP_ROOTS16, MAP_ROWS256, MAP_ROT, MAP_UWRITE, MAP_GEMM, MAP_COPY, MAP_SPLITA, MAP_SPLITB, MAP_SMALL,
-  MAP_PREP, MAP_COUNT
+  MAP_PREP, MAP_DEFL1, MAP_COUNT
 };
 struct LevelMaps {
   const int32_t* pfx[MAP_COUNT];

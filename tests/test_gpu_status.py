@@ -96,6 +96,40 @@ def test_status_nonfinite_in_poles(P):
     assert P.status(work) == P.STATUS_NONFINITE
 
 
+@pytest.mark.parametrize("case", ["ok", "unsorted", "nan_z", "inf_d"])
+def test_status_large_merge(P, case):
+    # merges of 4096 rows and more deflate across many workgroups; bad input is
+    # handed back to the one-workgroup path, which reports it
+    D, z, rho, Q1, Q2 = W.random_merge(2048, 2048, seed=11)
+    if case == "unsorted":
+        D[100], D[101] = D[101], D[100] + 1.0
+    elif case == "nan_z":
+        z[3000] = np.nan
+    elif case == "inf_d":
+        D[2500] = np.inf
+    lam, Q, work = P.merge(D, z, rho, torch.tensor(Q1), torch.tensor(Q2), check=False, return_work=True)
+    st = P.status(work)
+    if case == "ok":
+        # each eigenvalue sits where the secular function counts it (a Sturm-type
+        # count over the poles, as in the full-size merge test); orthogonality
+        assert st == P.STATUS_OK
+        lh = _np(lam)
+        order = np.argsort(D, kind="stable")
+        ds, zs = D[order], z[order] / np.linalg.norm(z)
+        r = rho * float(np.dot(z, z))
+        delta = 1e-13 * np.abs(lh).max()
+
+        def below(x):
+            j = int(np.searchsorted(ds, x, side="left"))
+            return 0 if j == 0 else j - 1 + (1 if 1.0 + r * np.sum(zs * zs / (ds - x)) > 0 else 0)
+
+        for k in np.random.default_rng(2).choice(D.size, 32, replace=False):
+            assert below(lh[k] - delta) <= k and below(lh[k] + delta) >= k + 1
+        assert orth(_np(Q)) <= 1e-12
+    else:
+        assert st == (P.STATUS_UNSORTED if case == "unsorted" else P.STATUS_NONFINITE)
+
+
 def test_status_nonfinite_in_stedc_input(P):
     # without the scan a NaN in d is caught by the first kernel that meets it
     d, e = W.uniform(300, 6)
