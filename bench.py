@@ -165,7 +165,7 @@ def reference_copy_gbs():
 # Kernel phase -> (counter summary under profiles/, source file the kernel is built from).
 TRAFFIC_SUMMARIES = {
     "copy": ("profiles/k_stage_uhat_root_copy_uniform_n16384_traffic.md", "paper_1612_07526_amd/csrc/merge.hip"),
-    "fill": ("profiles/k_fill_offblocks_uniform_n16384_traffic.md", "paper_1612_07526_amd/csrc/merge.hip"),
+    "fill": ("profiles/k_fill_zero_uniform_n16384_traffic.md", "paper_1612_07526_amd/csrc/merge.hip"),
 }
 
 
@@ -649,8 +649,9 @@ def main():
                     help="comma list of sections: merge_gemm,merge32k,toeplitz,examples,example1,split,batch,adjoint,cpu")
     ap.add_argument("--skip-paths", default="", help="comma list of update paths to leave out: hss,split")
     ap.add_argument("--only-value", action="store_true", help="time the headline solve only (profiling runs)")
-    ap.add_argument("--leaf", type=int, default=16,
-                    help="leaf size of the headline solve (16: fastest in a sweep over 8..64 on this GPU)")
+    ap.add_argument("--leaf", type=int, default=8,
+                    help="leaf size of the headline solve (8: fastest in a sweep over 8..32 on this GPU; the "
+                         "library's default, 16, is faster for the batch)")
     ap.add_argument("--chosen-only", action="store_true",
                     help="time the chosen-form headline solve only (no plain, leaf-32 or graph timings): counter runs")
     ap.add_argument("--calib-copy", action="store_true",

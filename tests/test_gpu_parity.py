@@ -222,10 +222,10 @@ def test_stedc_decoupled(P, orc):
     _check_eig(d, e, _np(lam), _np(Q), lref)
 
 
-@pytest.mark.parametrize("leaf", [32, 16])
+@pytest.mark.parametrize("leaf", [32, 16, 8])
 def test_stedc_uniform_16384_full_size(P, orc, leaf):
     # the headline workload: n = 16384, d, e ~ U[-1, 1], at the library's default leaf
-    # size and at the benchmarked one; eigenvalues vs the oracle (same split tree),
+    # size (16), the benchmarked one (8) and 32; eigenvalues vs the oracle (same split tree),
     # orthogonality and residual of the full Q on the GPU, sampled isolated columns vs
     # the oracle
     n = 16384
