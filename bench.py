@@ -649,9 +649,9 @@ def main():
                     help="comma list of sections: merge_gemm,merge32k,toeplitz,examples,example1,split,batch,adjoint,cpu")
     ap.add_argument("--skip-paths", default="", help="comma list of update paths to leave out: hss,split")
     ap.add_argument("--only-value", action="store_true", help="time the headline solve only (profiling runs)")
-    ap.add_argument("--leaf", type=int, default=8,
-                    help="leaf size of the headline solve (8: fastest in a sweep over 8..32 on this GPU; the "
-                         "library's default, 16, is faster for the batch)")
+    ap.add_argument("--leaf", type=int, default=16,
+                    help="leaf size of the headline solve (16: fastest for the chosen form; the plain form "
+                         "and graph replay are faster at 8)")
     ap.add_argument("--chosen-only", action="store_true",
                     help="time the chosen-form headline solve only (no plain, leaf-32 or graph timings): counter runs")
     ap.add_argument("--calib-copy", action="store_true",
