@@ -677,6 +677,9 @@ int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n,
     // the split-precision slicer, or the HSS sampling of a level with candidates
     lm[h].uhat_normalized = o->gemm_mode == PHDC_GEMM_SPLIT || (hss_threshold(o) > 0 && lm[h].maxm >= hss_threshold(o));
     lm[h].copy_alone = (e - a == 1) && T.merges[a].depth == 0;
+    int64_t rows = 0;
+    for (int i = a; i < e; ++i) rows += T.merges[i].m;
+    lm[h].sec_wide = rows <= kSecWideRows;
     for (int k = 0; k < MAP_COUNT; ++k) {
       const size_t at = maps.size();
       int32_t acc = 0, first = -1;
@@ -684,7 +687,7 @@ int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n,
       maps.push_back(0);
       for (int i = a; i < e; ++i) {
         const int32_t bl = map_blocks(k, T.merges[i].m, T.merges[i].n1, lm[h].gemm_tile, T.merges[i].depth == 0,
-                                      small_merge(T.merges[i].m, o), e - a);
+                                      small_merge(T.merges[i].m, o), e - a, lm[h].sec_wide);
         if (first < 0) first = bl;
         else if (bl != first) equal = false;
         acc += bl;
@@ -1148,9 +1151,10 @@ int phdc_merge(int64_t n1, int64_t n2, const double* D, const double* z, double 
   lm.gemm_tile = (o->gemm_mode == PHDC_GEMM_SPLIT) ? 128 : gemm_tile_for(m);
   lm.uhat_normalized = o->gemm_mode == PHDC_GEMM_SPLIT || (hss_threshold(o) > 0 && m >= hss_threshold(o));
   lm.copy_alone = true;
+  lm.sec_wide = m <= kSecWideRows;
   for (int k = 0; k < MAP_COUNT; ++k) {
     lm.pfx[k] = (const int32_t*)(base + L.maps) + maps.size();
-    lm.total[k] = map_blocks(k, (int)m, (int)n1, lm.gemm_tile, true, small_merge((int)m, o));
+    lm.total[k] = map_blocks(k, (int)m, (int)n1, lm.gemm_tile, true, small_merge((int)m, o), 1, lm.sec_wide);
     lm.per[k] = lm.total[k] > 0 ? lm.total[k] : 0;
     maps.push_back(0);
     maps.push_back(lm.total[k]);

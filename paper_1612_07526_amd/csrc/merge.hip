@@ -925,10 +925,17 @@ constexpr int kDppRowMirror = 0x140;     // lane i <-> 15 - i within each 16 lan
 // the mirrored quad and the mirrored half-row: the same pairing tree as xor 1,
 // 2, 4, 8 (quads hold equal values by then), so the result does not depend on
 // which form runs, and IEEE addition being commutative every lane holds the
-// identical total.  G = 4 takes the first two steps.
+// identical total.  G = 4 takes the first two steps; G = 32 adds the totals
+// of its two rows (in either order: the same bits).
 template <int G>
 __device__ inline double group_sum(double v) {
-  if constexpr (G == 16 || G == 4) {
+  if constexpr (G == 32) {
+    v += dpp_row<kDppQuadXor1>(v);
+    v += dpp_row<kDppQuadXor2>(v);
+    v += dpp_row<kDppRowHalfMirror>(v);
+    v += dpp_row<kDppRowMirror>(v);
+    v += __shfl_xor(v, 16, 64);
+  } else if constexpr (G == 16 || G == 4) {
     v += dpp_row<kDppQuadXor1>(v);
     v += dpp_row<kDppQuadXor2>(v);
     if constexpr (G == 16) {
@@ -1059,7 +1066,9 @@ __device__ __forceinline__ bool secular_root(int K, const double* __restrict__ d
 
 constexpr int kSecThreads = 256;  // threads per block
 constexpr int kSecLds = 2048;     // largest number of poles staged in LDS (d_i and z_i^2: 32 KB)
-constexpr int kSecG = 16;         // lanes per root
+constexpr int kSecG = 16;         // lanes per root (crowded levels, small merges, standalone roots)
+constexpr int kSecGWide = 32;     // lanes per root in levels of at most kSecWideRows rows (fastest of 4..64
+                                  // on a random n = 16384 solve)
 
 // The roots of one block: G lanes per root, kSecThreads / G roots per block.
 // Merges with K <= cap stage the poles and squared weights in LDS once (cap:
@@ -1103,12 +1112,13 @@ __device__ __forceinline__ void secular_block(const MergeDesc& M, const Scratch&
   }
 }
 
+template <int G>
 __device__ void secular_body(const BlockMap& bm, const Scratch& S, int b, double* sd, double* sz, int cap) {
   const int mi = find_merge(bm, b);
   const int lb = b - merge_first_block(bm, mi);
   const MergeDesc M = bm.descs[mi];
   const int K = S.counters[(int64_t)M.id * kCounters + C_K];
-  secular_block<kSecG>(M, S, K, lb, merge_blocks(bm, mi), sd, sz, cap);
+  secular_block<G>(M, S, K, lb, merge_blocks(bm, mi), sd, sz, cap);
 }
 
 __global__ void __launch_bounds__(64) k_secular_raw(int K, const double* d, const double* z, double rho,
@@ -1527,7 +1537,7 @@ bool small_merge(int m, const phdc_opts* o) {
   return !(o->gemm_mode == PHDC_GEMM_HSS && m >= std::max<int64_t>(o->hss_min_K, 1));
 }
 
-int map_blocks(int kind, int m, int n1, int gt, bool root, bool small, int nm) {
+int map_blocks(int kind, int m, int n1, int gt, bool root, bool small, int nm, bool sec_wide) {
   auto cdiv = [](int a, int b) { return (a + b - 1) / b; };
   if (small || kind == MAP_SMALL) return (small && kind == MAP_SMALL) ? 1 : 0;
   const int share = cdiv(kLevelBlocks, std::max(nm, 1));  // this merge's part of a full level launch
@@ -1535,7 +1545,7 @@ int map_blocks(int kind, int m, int n1, int gt, bool root, bool small, int nm) {
     return full <= share ? full : unit * std::max(1, share / unit);
   };
   switch (kind) {
-    case MAP_SECULAR: return trim(cdiv(m, kSecThreads / kSecG), 1);
+    case MAP_SECULAR: return trim(cdiv(m, kSecThreads / (sec_wide ? kSecGWide : kSecG)), 1);
     case MAP_ROOTS16: return trim(cdiv(m, kItemsPerBlock), 1);
     case MAP_ROWS256: return cdiv(m, 256);
     case MAP_ROT: return trim(cdiv(m, 256) * std::max(1, std::min(m / 2, kRotGroups)), cdiv(m, 256));
@@ -1616,10 +1626,11 @@ __global__ void __launch_bounds__(256) k_copy_ints(const int32_t* __restrict__ s
 // split-precision path), the norms come first in a launch of their own.
 
 // Dynamic LDS: 2 cap doubles, cap = min(largest merge of the level, kSecLds).
+template <int G>
 __global__ void __launch_bounds__(256) k_stage_roots(BlockMap sec, int nsec, BlockMap rot, Scratch S, int cap) {
   HIP_DYNAMIC_SHARED(double, lds)
   const int b = blockIdx.x;
-  if (b < nsec) secular_body(sec, S, b, lds, lds + cap, cap);
+  if (b < nsec) secular_body<G>(sec, S, b, lds, lds + cap, cap);
   else rotate_body(rot, S, b - nsec);
 }
 
@@ -1810,8 +1821,12 @@ void launch_merge_level(const MergeDesc* descs, int nm, const LevelMaps& maps, c
     const int nuw = maps.total[MAP_UWRITE];
     { ProfScope p(PH_SECULAR, s);
       const int cap = std::min(maps.maxm, kSecLds);
-      hipLaunchKernelGGL(k_stage_roots, dim3(nsec + nrot), dim3(256), (size_t)2 * cap * sizeof(double), s,
-                         bmap(MAP_SECULAR), nsec, bmap(MAP_ROT), S, cap); }
+      if (maps.sec_wide)
+        hipLaunchKernelGGL(k_stage_roots<kSecGWide>, dim3(nsec + nrot), dim3(256), (size_t)2 * cap * sizeof(double),
+                           s, bmap(MAP_SECULAR), nsec, bmap(MAP_ROT), S, cap);
+      else
+        hipLaunchKernelGGL(k_stage_roots<kSecG>, dim3(nsec + nrot), dim3(256), (size_t)2 * cap * sizeof(double), s,
+                           bmap(MAP_SECULAR), nsec, bmap(MAP_ROT), S, cap); }
     { ProfScope p(PH_LOWNER, s);
       hipLaunchKernelGGL(k_stage_lowner, dim3(nitem + nrank), dim3(256), 0, s, bmap(MAP_ROOTS16), nitem,
                          bmap(MAP_ROWS256), S); }

@@ -201,6 +201,7 @@ struct LevelMaps {
   int32_t gemm_tile = 128;  // output tile edge of the FP64 update GEMM (64 or 128)
   bool uhat_normalized = false;  // Uhat written with unit columns (else the GEMM epilogue scales them)
   bool copy_alone = false;       // the deflated-column copy gets a launch of its own (a lone root merge)
+  bool sec_wide = false;         // 32 lanes per secular root (levels of at most kSecWideRows rows), else 16
 };
 // Blocks of one merge for a kernel class; gt is the FP64 GEMM tile edge (MAP_GEMM);
 // root: the merge is the last one of its matrix (MAP_COPY: one column per block);
@@ -211,7 +212,11 @@ struct LevelMaps {
 // than kLevelBlocks (levels of many small merges: the trimmed blocks would
 // mostly find no work, yet each costs a dispatch).
 constexpr int kLevelBlocks = 16384;
-int map_blocks(int kind, int m, int n1, int gt, bool root, bool small = false, int nm = 1);
+// Levels of at most this many rows over all their merges give each secular
+// root 32 lanes (short latency per root); crowded levels give it 16 (more roots
+// in flight).
+constexpr int kSecWideRows = 65536;
+int map_blocks(int kind, int m, int n1, int gt, bool root, bool small = false, int nm = 1, bool sec_wide = false);
 // Whether a merge of m rows takes the one-workgroup path for these options.
 bool small_merge(int m, const phdc_opts* o);
 constexpr int kGemmBlockCap = 1024;      // blocks per merge of the update GEMMs (they loop over tiles)
