@@ -668,7 +668,9 @@ int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n,
   put(plan, L.canon_pfx - plan0, cpfx.data(), cpfx.size());
 
   std::vector<int32_t> maps;
+  maps.reserve((size_t)z.map_ints);
   std::vector<LevelMaps> lm(z.H + 1);
+  std::vector<int32_t> blk;  // blocks per merge of a level, kind-major
   for (int h = 1; h <= z.H; ++h) {
     const int a = T.hstart[h - 1], e = T.hstart[h];
     for (int i = a; i < e; ++i) lm[h].maxm = std::max(lm[h].maxm, T.merges[i].m);
@@ -680,14 +682,26 @@ int run_solve(const Setup& SU, const Buffers& BF, const std::vector<int64_t>& n,
     int64_t rows = 0;
     for (int i = a; i < e; ++i) rows += T.merges[i].m;
     lm[h].sec_wide = rows <= kSecWideRows;
+    // a merge's block counts depend on its size, split and depth (and the
+    // level): merges of a level mostly share them, so they are reused
+    const int nm = e - a;
+    blk.assign((size_t)MAP_COUNT * nm, 0);
+    for (int i = a; i < e; ++i) {
+      const Node& nd = T.merges[i];
+      const bool same = i > a && nd.m == T.merges[i - 1].m && nd.n1 == T.merges[i - 1].n1 &&
+                        (nd.depth == 0) == (T.merges[i - 1].depth == 0);
+      for (int k = 0; k < MAP_COUNT; ++k)
+        blk[(size_t)k * nm + (i - a)] =
+            same ? blk[(size_t)k * nm + (i - a - 1)]
+                 : map_blocks(k, nd.m, nd.n1, lm[h].gemm_tile, nd.depth == 0, small_merge(nd.m, o), nm, lm[h].sec_wide);
+    }
     for (int k = 0; k < MAP_COUNT; ++k) {
       const size_t at = maps.size();
       int32_t acc = 0, first = -1;
       bool equal = true;
       maps.push_back(0);
-      for (int i = a; i < e; ++i) {
-        const int32_t bl = map_blocks(k, T.merges[i].m, T.merges[i].n1, lm[h].gemm_tile, T.merges[i].depth == 0,
-                                      small_merge(T.merges[i].m, o), e - a, lm[h].sec_wide);
+      for (int i = 0; i < nm; ++i) {
+        const int32_t bl = blk[(size_t)k * nm + i];
         if (first < 0) first = bl;
         else if (bl != first) equal = false;
         acc += bl;
