@@ -232,7 +232,7 @@ int phdc_merge_stats(const void *work, int32_t *stats_host);
  * the zero fill of the caller's Q for a root merge of at least 256 rows in the
  * last level, on a second stream while the levels below run (from 2048 rows
  * in two parts: the off-diagonal quadrants from the first levels, the diagonal
- * halves from two levels before the root; its events are recorded on that
+ * halves from four levels before the root; its events are recorded on that
  * stream); "rotate" and "rank" are no longer recorded separately.
  * Returns 0. */
 int phdc_profile_enable(int on);

@@ -254,7 +254,7 @@ void launch_fill_zero(const FillDesc* fd, const int32_t* cpfx, int nd, int total
 constexpr int kFillThreads = 256;
 // The diagonal halves of a wide Q are filled from this many levels before the
 // root on.
-constexpr int kFillLateLevels = 3;
+constexpr int kFillLateLevels = 4;
 constexpr int kFillBlocksWide = 128;
 constexpr int kFillBlocksNarrow = 512;
 void launch_secular_standalone(int64_t K, const double* d, const double* z, double rho, int32_t* org,
