@@ -658,7 +658,7 @@ def main():
                     help="first run a plain 1 GiB device copy (reference kernel for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: the solver runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU sharding is a design, not an implementation", file=sys.stderr)
         sys.exit(2)
     args.skip = set(x for x in args.skip.split(",") if x)
