@@ -111,6 +111,10 @@ int phdc_version(void);
  *   Q       device, ldq*n doubles, output eigenvectors (column j for lambda[j])
  *   ldq     leading dimension of Q, ldq >= max(1, n)
  *   work    device workspace of lwork bytes (phdc_stedc_workspace), 256-byte aligned
+ *           (about 2.5 n^2 doubles for large n: a second eigenvector buffer of
+ *           n^2, a third of about n^2/2 for the even depths below a root that
+ *           is zero-filled ahead of time (n >= 256), Uhat of the largest
+ *           level, about n^2, and O(n) scratch)
  * Returns 0, -(argument index) or PHDC_E_HIP. */
 int phdc_stedc_workspace(int64_t n, const phdc_opts *o, size_t *bytes);
 int phdc_stedc(int64_t n, const double *d, const double *e, double *lambda, double *Q, int64_t ldq,
