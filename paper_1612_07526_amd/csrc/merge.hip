@@ -1143,11 +1143,12 @@ __global__ void __launch_bounds__(64) k_secular_raw(int K, const double* d, cons
 // for i <= j < K-1 (d_i - lambda_j)/(d_i - d_{j+1}), times lambda_{K-1} - d_i.
 template <int G>
 __device__ inline double group_prod(double v) {
-  if constexpr (G == 16) {
+  if constexpr (G == 16 || G == 32) {
     v *= dpp_row<kDppQuadXor1>(v);
     v *= dpp_row<kDppQuadXor2>(v);
     v *= dpp_row<kDppRowHalfMirror>(v);
     v *= dpp_row<kDppRowMirror>(v);
+    if constexpr (G == 32) v *= __shfl_xor(v, 16, 64);  // (the two rows' products, in either order)
   } else {
 #pragma unroll
     for (int o = 1; o < G; o <<= 1) v *= __shfl_xor(v, o, 64);
@@ -1155,14 +1156,14 @@ __device__ inline double group_prod(double v) {
   return v;
 }
 
-// Both kernels: 256-lane blocks, 16 items per block, 16 lanes per item each
-// taking every 16th term, two terms in flight per lane.
+// Both kernels: 256-lane blocks, IG lanes per item (16, or 32 in levels of at
+// most kSecWideRows rows, as for the secular roots) each taking every IG-th
+// term, two terms in flight per lane.
 constexpr int kItemG = 16;
-constexpr int kItemsPerBlock = kSecThreads / kItemG;
 
 // A lane's partial product is a product of factors in (0, 1], so none
 // underflows before the full product does.  Item i0 of a merge with K poles,
-// computed by the 16 lanes of a group (sub = lane within the group).
+// computed by the IG lanes of a group (sub = lane within the group).
 template <int IG = kItemG>
 __device__ inline void lowner_item(const MergeDesc& M, const Scratch& S, int K, int i0, int sub) {
   const bool active = i0 < K;
@@ -1196,14 +1197,16 @@ __device__ inline void lowner_item(const MergeDesc& M, const Scratch& S, int K, 
   }
 }
 
+template <int IG>
 __device__ void lowner_body(const BlockMap& bm, const Scratch& S, int b) {
+  constexpr int IPB = kSecThreads / IG;  // items per block
   const int mi = find_merge(bm, b);
   const int lb = b - merge_first_block(bm, mi);
   const MergeDesc M = bm.descs[mi];
   const int K = S.counters[(int64_t)M.id * kCounters + C_K];
   const int G = merge_blocks(bm, mi);
-  for (int i0 = lb * kItemsPerBlock; i0 < K; i0 += G * kItemsPerBlock)  // (block-uniform bound)
-    lowner_item(M, S, K, i0 + (int)threadIdx.x / kItemG, threadIdx.x % kItemG);
+  for (int i0 = lb * IPB; i0 < K; i0 += G * IPB)  // (block-uniform bound)
+    lowner_item<IG>(M, S, K, i0 + (int)threadIdx.x / IG, threadIdx.x % IG);
 }
 
 // Reciprocal 2-norms of the columns zhat_i / (d_i - lambda_j) of Uhat (Eq. (4)).
@@ -1231,14 +1234,16 @@ __device__ inline void unorm_item(const MergeDesc& M, const Scratch& S, int K, i
   if (active && sub == 0) S.cnorm[so + j] = 1.0 / sqrt(s);
 }
 
+template <int IG>
 __device__ void unorm_body(const BlockMap& bm, const Scratch& S, int b) {
+  constexpr int IPB = kSecThreads / IG;  // items per block
   const int mi = find_merge(bm, b);
   const int lb = b - merge_first_block(bm, mi);
   const MergeDesc M = bm.descs[mi];
   const int K = S.counters[(int64_t)M.id * kCounters + C_K];
   const int G = merge_blocks(bm, mi);
-  for (int j0 = lb * kItemsPerBlock; j0 < K; j0 += G * kItemsPerBlock)  // (block-uniform bound)
-    unorm_item(M, S, K, j0 + (int)threadIdx.x / kItemG, threadIdx.x % kItemG);
+  for (int j0 = lb * IPB; j0 < K; j0 += G * IPB)  // (block-uniform bound)
+    unorm_item<IG>(M, S, K, j0 + (int)threadIdx.x / IG, threadIdx.x % IG);
 }
 
 // ... then the entries, written row-major (row g = grouped row, ld = K) so that
@@ -1546,7 +1551,7 @@ int map_blocks(int kind, int m, int n1, int gt, bool root, bool small, int nm, b
   };
   switch (kind) {
     case MAP_SECULAR: return trim(cdiv(m, kSecThreads / (sec_wide ? kSecGWide : kSecG)), 1);
-    case MAP_ROOTS16: return trim(cdiv(m, kItemsPerBlock), 1);
+    case MAP_ROOTS16: return trim(cdiv(m, kSecThreads / (sec_wide ? kSecGWide : kItemG)), 1);
     case MAP_ROWS256: return cdiv(m, 256);
     case MAP_ROT: return trim(cdiv(m, 256) * std::max(1, std::min(m / 2, kRotGroups)), cdiv(m, 256));
     case MAP_UWRITE: return trim(cdiv(m, 256) * std::max(1, std::min(m, kUwRowGroups)), cdiv(m, 256));
@@ -1759,18 +1764,20 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(5))) k_
   small_update<NT>(M, S, cl, rl);
 }
 
+template <int IG>
 __global__ void __launch_bounds__(256) k_stage_lowner(BlockMap low, int nlow, BlockMap rank, Scratch S) {
   const int b = blockIdx.x;
-  if (b < nlow) lowner_body(low, S, b);
+  if (b < nlow) lowner_body<IG>(low, S, b);
   else rank_body(rank, S, b - nlow);
 }
 
+template <int IG>
 __global__ void __launch_bounds__(256) k_stage_uhat(BlockMap cp, int ncp, BlockMap uw, int nuw, BlockMap un, Scratch S,
                                                     int normalized) {
   const int b = blockIdx.x;
   if (b < ncp) copy_body(cp, S, b);
   else if (b < ncp + nuw) uwrite_body(uw, S, b - ncp, normalized != 0);
-  else unorm_body(un, S, b - ncp - nuw);
+  else unorm_body<IG>(un, S, b - ncp - nuw);
 }
 
 void launch_merge_level(const MergeDesc* descs, int nm, const LevelMaps& maps, const Scratch& S, int gemm_mode,
@@ -1815,10 +1822,13 @@ void launch_merge_level(const MergeDesc* descs, int nm, const LevelMaps& maps, c
     { ProfScope p(PH_SECULAR, s);
       hipLaunchKernelGGL(k_stage_small, dim3(nm), dim3(kStageSmallThreads), 0, s, descs, S, normalized); }
     { ProfScope p(PH_UWRITE, s);  // (the copy phase times the lone root copy only)
-      hipLaunchKernelGGL(k_stage_uhat, dim3(ncopy), dim3(256), 0, s, bmap(MAP_COPY), ncopy, none, 0, none, S, 0); }
+      hipLaunchKernelGGL(k_stage_uhat<kItemG>, dim3(ncopy), dim3(256), 0, s, bmap(MAP_COPY), ncopy, none, 0, none, S, 0); }
   } else {
     const int nsec = maps.total[MAP_SECULAR], nitem = maps.total[MAP_ROOTS16], nrank = maps.total[MAP_ROWS256];
     const int nuw = maps.total[MAP_UWRITE];
+    // items (Loewner z, column norms) take as many lanes as the level's secular roots
+    const auto k_lowner = maps.sec_wide ? k_stage_lowner<kSecGWide> : k_stage_lowner<kItemG>;
+    const auto k_uhat = maps.sec_wide ? k_stage_uhat<kSecGWide> : k_stage_uhat<kItemG>;
     { ProfScope p(PH_SECULAR, s);
       const int cap = std::min(maps.maxm, kSecLds);
       if (maps.sec_wide)
@@ -1828,7 +1838,7 @@ void launch_merge_level(const MergeDesc* descs, int nm, const LevelMaps& maps, c
         hipLaunchKernelGGL(k_stage_roots<kSecG>, dim3(nsec + nrot), dim3(256), (size_t)2 * cap * sizeof(double), s,
                            bmap(MAP_SECULAR), nsec, bmap(MAP_ROT), S, cap); }
     { ProfScope p(PH_LOWNER, s);
-      hipLaunchKernelGGL(k_stage_lowner, dim3(nitem + nrank), dim3(256), 0, s, bmap(MAP_ROOTS16), nitem,
+      hipLaunchKernelGGL(k_lowner, dim3(nitem + nrank), dim3(256), 0, s, bmap(MAP_ROOTS16), nitem,
                          bmap(MAP_ROWS256), S); }
     const int nc = maps.copy_alone ? 0 : ncopy;
     // the launches below write output blocks: a zero fill of a root's output
@@ -1836,18 +1846,18 @@ void launch_merge_level(const MergeDesc* descs, int nm, const LevelMaps& maps, c
     if (qout_ready) (void)hipStreamWaitEvent(s, qout_ready, 0);
     if (normalized) {
       { ProfScope p(PH_UNORM, s);
-        hipLaunchKernelGGL(k_stage_uhat, dim3(nitem), dim3(256), 0, s, none, 0, none, 0, bmap(MAP_ROOTS16), S, 1); }
+        hipLaunchKernelGGL(k_uhat, dim3(nitem), dim3(256), 0, s, none, 0, none, 0, bmap(MAP_ROOTS16), S, 1); }
       { ProfScope p(PH_UWRITE, s);
-        hipLaunchKernelGGL(k_stage_uhat, dim3(nc + nuw), dim3(256), 0, s, bmap(MAP_COPY), nc, bmap(MAP_UWRITE), nuw,
+        hipLaunchKernelGGL(k_uhat, dim3(nc + nuw), dim3(256), 0, s, bmap(MAP_COPY), nc, bmap(MAP_UWRITE), nuw,
                            none, S, 1); }
     } else {
       ProfScope p(PH_UWRITE, s);
-      hipLaunchKernelGGL(k_stage_uhat, dim3(nc + nuw + nitem), dim3(256), 0, s, bmap(MAP_COPY), nc, bmap(MAP_UWRITE),
+      hipLaunchKernelGGL(k_uhat, dim3(nc + nuw + nitem), dim3(256), 0, s, bmap(MAP_COPY), nc, bmap(MAP_UWRITE),
                          nuw, bmap(MAP_ROOTS16), S, 0);
     }
     if (maps.copy_alone) {
       ProfScope p(PH_COPY, s);
-      hipLaunchKernelGGL(k_stage_uhat, dim3(ncopy), dim3(256), 0, s, bmap(MAP_COPY), ncopy, none, 0, none, S, 0);
+      hipLaunchKernelGGL(k_stage_uhat<kItemG>, dim3(ncopy), dim3(256), 0, s, bmap(MAP_COPY), ncopy, none, 0, none, S, 0);
     }
   }
   { ProfScope p(PH_GEMM, s);
@@ -1872,7 +1882,7 @@ void launch_fp64_fallback(const MergeDesc* desc, const MergeDesc& M, const Scrat
   const int ngm = map_blocks(MAP_GEMM, M.m, M.n1, tile, M.root != 0);
   const BlockMap none{desc, nullptr, 1, 1};
   hipLaunchKernelGGL(k_mark_fallback, dim3(1), dim3(1), 0, s, desc, S.counters);
-  hipLaunchKernelGGL(k_stage_uhat, dim3(nuw), dim3(256), 0, s, none, 0, BlockMap{desc, nullptr, 1, nuw}, nuw, none,
+  hipLaunchKernelGGL(k_stage_uhat<kItemG>, dim3(nuw), dim3(256), 0, s, none, 0, BlockMap{desc, nullptr, 1, nuw}, nuw, none,
                      S, 1);  // Uhat only
   launch_merge_gemm_f64(BlockMap{desc, nullptr, 1, ngm}, ngm, S, tile, false, s);
 }
